@@ -1,0 +1,292 @@
+"""Seeded synthetic workloads for the mapping evaluator (inputs only).
+
+This module builds candidate descriptors; it evaluates nothing.  It is shared by
+the tests, the benchmark and both sides of every parity check (the CPU oracle and
+the HIP library), so it holds none of the evaluation arithmetic: no projection, no
+inverse chain, no ghost or tile counting, no objective.  Lists of factorizations
+are passed in by the caller (each side enumerates its own).
+
+Workloads (shapes follow the paper's stencil and matmul studies, Sec. 4.1, 6.3 and
+App. A.1; all data synthetic):
+  c1  2-D 64x64 on 2 nodes x 4 GPUs, 4 factorizations x 4 chains, 5-point h=1
+  c2  3-D 512^3 on 16 x 8, 36 factorizations x 6 chains, star h=2
+  c3  random batch: ranks 2-3, extents log-uniform 32..1023, nodes 1..64,
+      GPUs/node in {1,2,4,8}, 0-4 random transformations (gen.c)
+  c4  matmul task space 256^3 on 16 x 4, 28 factorizations x 2 chains + Cannon
+  c5  search instances: every factorization x a fixed menu of chains
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+SPLIT, MERGE, SWAP, BALANCE_SPLIT, DECOMPOSE = 1, 2, 3, 4, 5
+BLOCK, CYCLIC = 0, 1
+
+OP_DTYPE = np.dtype([("kind", "<i4"), ("a", "<i4"), ("b", "<i4"), ("nf", "<i4"),
+                     ("f", "<i4", (4,))])
+CAND_DTYPE = np.dtype([("lrank", "<i4"), ("nodes", "<i4"), ("gpus", "<i4"), ("nops", "<i4"),
+                       ("extent", "<i8", (4,)), ("ops", OP_DTYPE, (8,)),
+                       ("mrank", "<i4"), ("pad0", "<i4"),
+                       ("proj_src", "i1", (8,)), ("proj_mode", "i1", (8,))])
+STENCIL_DTYPE = np.dtype([("lrank", "<i4"), ("elem_bytes", "<i4"), ("halo", "<i4", (4,))])
+assert CAND_DTYPE.itemsize == 328 and STENCIL_DTYPE.itemsize == 24
+
+
+def split(i, d):
+    return (SPLIT, i, d, ())
+
+
+def merge(p, q):
+    return (MERGE, p, q, ())
+
+
+def swap(p, q):
+    return (SWAP, p, q, ())
+
+
+def balance_split(i, d):
+    return (BALANCE_SPLIT, i, d, ())
+
+
+def decompose(i, factors):
+    return (DECOMPOSE, i, 0, tuple(int(x) for x in factors))
+
+
+def _rank_after(ops):
+    """Rank of the processor space after the ops (grammar bookkeeping only)."""
+    r = 2
+    for kind, _a, _b, f in ops:
+        if kind in (SPLIT, BALANCE_SPLIT):
+            r += 1
+        elif kind == MERGE:
+            r -= 1
+        elif kind == DECOMPOSE:
+            r += len(f) - 1
+    return r
+
+
+def candidate(extent, nodes, gpus, ops, proj=None):
+    """One candidate record.  proj: list of (src_dim, mode) per final dim; default
+    BLOCK with src_j = j over a final space of the launch rank."""
+    rec = np.zeros((), dtype=CAND_DTYPE)
+    rec["lrank"] = len(extent)
+    for d, l in enumerate(extent):
+        rec["extent"][d] = l
+    rec["nodes"], rec["gpus"] = nodes, gpus
+    if len(ops) > 8:
+        raise ValueError("at most 8 ops")
+    rec["nops"] = len(ops)
+    for t, (kind, a, b, f) in enumerate(ops):
+        rec["ops"][t]["kind"], rec["ops"][t]["a"], rec["ops"][t]["b"] = kind, a, b
+        rec["ops"][t]["nf"] = len(f)
+        for m, x in enumerate(f):
+            rec["ops"][t]["f"][m] = x
+    if proj is None:
+        proj = [(j, BLOCK) for j in range(_rank_after(ops))]
+    rec["mrank"] = len(proj)
+    for j, (src, mode) in enumerate(proj):
+        rec["proj_src"][j], rec["proj_mode"][j] = src, mode
+    return rec
+
+
+def batch(records):
+    out = np.zeros(len(records), dtype=CAND_DTYPE)
+    for i, r in enumerate(records):
+        out[i] = r
+    return out
+
+
+def stencil(halo, elem_bytes=8):
+    st = np.zeros((), dtype=STENCIL_DTYPE)
+    st["lrank"] = len(halo)
+    st["elem_bytes"] = elem_bytes
+    for d, h in enumerate(halo):
+        st["halo"][d] = h
+    return st
+
+
+# ---------------------------------------------------------------- named workloads
+
+def c1_chains():
+    """The four chain tails of the 64x64 workload, applied after merge(0,1) +
+    decompose(0, F): identity, swap, re-split by 4, balance_split by 3."""
+    return [[], [swap(0, 1)], [merge(0, 1), split(0, 4)], [merge(0, 1), balance_split(0, 3)]]
+
+
+C1_FACTORIZATIONS = [(1, 8), (2, 4), (4, 2), (8, 1)]  # every ordered 2-factorization of 8
+
+
+def c1_candidates(factorizations=C1_FACTORIZATIONS, extent=(64, 64), nodes=2, gpus=4):
+    recs = []
+    for f in factorizations:
+        for tail in c1_chains():
+            recs.append(candidate(extent, nodes, gpus, [merge(0, 1), decompose(0, f)] + tail))
+    return batch(recs)
+
+
+def c1_stencil():
+    return stencil((1, 1), 8)
+
+
+def c2_chains(f):
+    """Six chain tails after merge(0,1) + decompose(0, F) on a 3-factorization."""
+    return [[], [swap(0, 1)], [swap(1, 2)], [swap(0, 2)],
+            [merge(0, 1), split(0, int(f[1]))], [merge(1, 2), split(1, int(f[2]))]]
+
+
+def c2_candidates(factorizations, extent=(512, 512, 512), nodes=16, gpus=8):
+    recs = []
+    for f in factorizations:
+        for tail in c2_chains(f):
+            recs.append(candidate(extent, nodes, gpus, [merge(0, 1), decompose(0, f)] + tail))
+    return batch(recs)
+
+
+def c2_stencil():
+    return stencil((2, 2, 2), 8)
+
+
+C4_TILE_BYTES = 1024 * 1024 * 8  # one 1024x1024 fp64 tile
+
+
+def c4_candidates(factorizations, extent=(256, 256, 256), nodes=16, gpus=4):
+    """Every 3-factorization of 64 (block, with and without swap(0,1)), plus the
+    hierarchical Cannon mapper of App. A.1: node grid from decompose of the node
+    dim, GPU grid from decompose of the GPU dim, nodes blocked and GPUs cyclic,
+    k unmapped."""
+    recs = []
+    for f in factorizations:
+        recs.append(candidate(extent, nodes, gpus, [merge(0, 1), decompose(0, f)]))
+        recs.append(candidate(extent, nodes, gpus, [merge(0, 1), decompose(0, f), swap(0, 1)]))
+    recs.append(cannon_candidate(extent, nodes, gpus))
+    return batch(recs)
+
+
+def cannon_candidate(extent, nodes, gpus, node_grid=None, gpu_grid=None):
+    node_grid = node_grid or _square_pair(nodes)
+    gpu_grid = gpu_grid or _square_pair(gpus)
+    ops = [decompose(0, node_grid), decompose(2, gpu_grid)]
+    proj = [(0, BLOCK), (1, BLOCK), (0, CYCLIC), (1, CYCLIC)]
+    return candidate(extent, nodes, gpus, ops, proj)
+
+
+def _square_pair(v):
+    a = int(round(v ** 0.5))
+    while v % a:
+        a -= 1
+    return (max(a, v // a), min(a, v // a))
+
+
+# ---------------------------------------------------------------- random batches
+
+_gen = None
+
+
+def _genlib():
+    global _gen
+    if _gen is None:
+        so = os.path.join(HERE, "libtmgen.so")
+        if not os.path.exists(so):
+            build()
+        _gen = ctypes.CDLL(so)
+        _gen.gen_random_candidates.restype = ctypes.c_int
+        _gen.gen_random_candidates.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64] + \
+            [ctypes.c_int32] * 7 + [ctypes.c_void_p]
+        assert _gen.gen_sizeof_candidate() == CAND_DTYPE.itemsize
+    return _gen
+
+
+def build():
+    so = os.path.join(HERE, "libtmgen.so")
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", so + ".tmp",
+                           os.path.join(HERE, "gen.c")])
+    os.replace(so + ".tmp", so)
+
+
+C3_SEED = 17087
+
+
+def random_candidates(n, seed=C3_SEED, first=0, ranks=(2, 3), octaves=(5, 9), nodes_max=64,
+                      gpus=(1, 2, 4, 8), max_ops=4, cyclic_pct=0):
+    """n random candidates (c3 recipe by default); candidate i depends only on
+    (seed, first + i)."""
+    out = np.zeros(n, dtype=CAND_DTYPE)
+    kmask = sum(1 << k for k in ranks)
+    gmask = sum(1 << (int(g).bit_length() - 1) for g in gpus)
+    rc = _genlib().gen_random_candidates(seed, first, n, kmask, octaves[0], octaves[1], nodes_max,
+                                         gmask, max_ops, cyclic_pct, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad generator arguments")
+    return out
+
+
+def c3_candidates(n=4096, seed=C3_SEED, **kw):
+    return random_candidates(n, seed=seed, **kw)
+
+
+def c3_stencil(lrank):
+    return stencil((1,) * lrank, 8)
+
+
+def split_by_rank(cands):
+    """c3 mixes ranks 2 and 3; a stencil fixes the rank, so batches are evaluated per
+    rank.  Returns {rank: index array}."""
+    return {int(k): np.nonzero(cands["lrank"] == k)[0] for k in np.unique(cands["lrank"])}
+
+
+# ---------------------------------------------------------------- search instances
+
+def chain_menu(k):
+    """A fixed menu of 32 chains (each a function of the factorization F) applied to
+    Machine(GPU); each returns the full op list.  Node-major / GPU-major bases, the
+    factor order permutations that swaps reach, re-splits and balance_splits."""
+    menu = []
+    bases = ([merge(0, 1)], [swap(0, 1), merge(0, 1)])
+    tails = []
+    if k == 2:
+        tails = [lambda f: [], lambda f: [swap(0, 1)],
+                 lambda f: [merge(0, 1), split(0, f[1])],
+                 lambda f: [merge(0, 1), balance_split(0, max(1, f[0] - 1))],
+                 lambda f: [merge(0, 1), balance_split(0, f[0] + 1)],
+                 lambda f: [swap(0, 1), merge(0, 1), split(0, f[0])],
+                 lambda f: [merge(0, 1), split(0, f[0] * f[1])],
+                 lambda f: [merge(0, 1), split(0, 1)]]
+    else:
+        tails = [lambda f: [], lambda f: [swap(0, 1)], lambda f: [swap(1, 2)], lambda f: [swap(0, 2)],
+                 lambda f: [swap(0, 1), swap(1, 2)], lambda f: [swap(1, 2), swap(0, 1)],
+                 lambda f: [merge(0, 1), split(0, f[1])], lambda f: [merge(1, 2), split(1, f[2])],
+                 lambda f: [merge(0, 1), balance_split(0, f[0] + 1)],
+                 lambda f: [merge(1, 2), balance_split(1, f[1] + 1)],
+                 lambda f: [merge(0, 2), split(0, f[2]), swap(1, 2)],
+                 lambda f: [merge(0, 1), split(0, 1), swap(0, 2)],
+                 lambda f: [swap(0, 2), swap(0, 1)],
+                 lambda f: [merge(0, 1), balance_split(0, max(1, f[0] * f[1] - 1))],
+                 lambda f: [merge(1, 2), split(1, f[2]), swap(0, 1)],
+                 lambda f: [merge(0, 1), split(0, f[1]), swap(1, 2)]]
+    for base in bases:
+        for t in tails:
+            menu.append((base, t))
+    return menu
+
+
+def instance_candidates(extent, nodes, gpus, factorizations, menu=None):
+    """Every factorization x every menu chain, in that order."""
+    k = len(extent)
+    menu = menu or chain_menu(k)
+    recs = []
+    for f in factorizations:
+        for base, tail in menu:
+            recs.append(candidate(extent, nodes, gpus, base + [decompose(0, f)] + tail(tuple(f))))
+    return batch(recs)
+
+
+def random_instances(n, seed=2, first=0, octaves=(5, 9), nodes_max=64, gpus=(1, 2, 4, 8)):
+    """Search instances (extent, nodes, gpus) with launch rank 3: the domain, the
+    machine and the stencil of a random candidate; the chain is not used."""
+    cs = random_candidates(n, seed=seed, first=first, ranks=(3,), octaves=octaves,
+                           nodes_max=nodes_max, gpus=gpus, max_ops=0)
+    return [(tuple(int(x) for x in c["extent"][:3]), int(c["nodes"]), int(c["gpus"])) for c in cs]
