@@ -1,0 +1,233 @@
+/*
+ * taskmap.h -- C ABI of libtaskmap: exact, batched evaluation of index-task
+ * mappings on an AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Mapple, arXiv 2507.17087, Sec. 3): an index launch has a task
+ * space (launch domain) of k dimensions; the machine is the processor space
+ * Machine(GPU) = (nodes, GPUs per node) (Sec. 3.2.1).  A mapping transforms the
+ * processor space with a chain of primitives -- split, merge, swap (Sec. 3.3,
+ * Fig. 6), decompose (Sec. 4.2) and balance_split (named in the paper's listings,
+ * never defined; reading below) -- and projects every launch point onto the final
+ * space, by blocks (Fig. 1 / Fig. 3: point * size / space) or round robin
+ * (Fig. 4).  The processor of a point is found by inverting the chain, last
+ * transformation first (Sec. 5.2).  The library returns the processor of every
+ * point and the communication the mapping induces:
+ *   - stencil ghost volume: for every cell, the distinct processors that own one of
+ *     its star neighbours (halo width h_m along dim m) other than its own owner,
+ *     split into intra- and inter-node transfers (Sec. 4.1, Sec. 4.2 volume model,
+ *     App. A.3 anisotropic halos);
+ *   - matmul tile fetches: distinct A[i,k], B[k,j], C[i,j] tiles per processor for a
+ *     task space (i,j,k) (the matmul mappers of Sec. 6 and App. A.1);
+ *   - decompose's search (Sec. 4.3): every ordered factorization, the exact argmin
+ *     of the objective, the greedy grid of Alg. A1, and a learned ranker that
+ *     prunes candidate lists before exact evaluation.
+ *
+ * Readings where the paper is silent:
+ *   - balance_split(i,d) on a dim of size s: shape (.., d, ceil(s/d), ..); the
+ *     inverse folds v = a_i + a_{i+1}*d onto b_i = floor(v*s / (d*ceil(s/d))).
+ *     Equal to split(i,d) when d divides s; processor loads differ by at most one.
+ *   - decompose(i,F) = split(i,F0), split(i+1,F1), ..., so F0 varies fastest.
+ *   - processor id = node * gpus_per_node + gpu.
+ *   - ghost volume counts distinct (receiving processor, cell) pairs; the domain is
+ *     not periodic; a transfer is inter-node when the receiver's node differs from
+ *     the node owning the cell.
+ *   - all integer division is floor division of non-negative values.
+ *
+ * Conventions
+ *   - Every entry point returns TM_OK (0) or a negative TM_E* code; the message of
+ *     the last failure on the calling thread is returned by tm_last_error().
+ *   - Validation is complete before anything is enqueued: on error nothing is
+ *     launched and no output is touched.
+ *   - "host" pointers are read before the call returns; "device" pointers are
+ *     caller-owned device memory (e.g. torch tensors) of the current HIP device and
+ *     are written by work enqueued on `stream` (a hipStream_t; NULL = the null
+ *     stream).  Results are valid once the stream reaches that work.
+ *   - Opaque handles (tm_plan, tm_ranker) are created and destroyed only here.
+ *   - Calls on different streams are independent; one handle must not be used by
+ *     two threads at once.
+ */
+#ifndef TASKMAP_H
+#define TASKMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TM_ABI_VERSION 1
+
+enum { TM_MAX_LRANK = 4, TM_MAX_MRANK = 8, TM_MAX_OPS = 8 };
+/* Largest processor-space volume (product of its shape) after any transformation. */
+#define TM_MAX_VOLUME (1LL << 24)
+#define TM_MAX_EXTENT 2147483647LL
+#define TM_MAX_POINTS (1LL << 40)
+#define TM_MAX_HALO 65535
+
+enum tm_status {
+    TM_OK = 0,
+    TM_EINVAL = -1,    /* malformed descriptor or argument */
+    TM_EOVERFLOW = -2, /* a size exceeds the documented limits */
+    TM_ECAPACITY = -3, /* output buffer too small; *count holds the size needed */
+    TM_ENOMEM = -4,    /* host or device allocation failed */
+    TM_EDEVICE = -5,   /* a HIP call failed (message in tm_last_error) */
+    TM_ENOTSUP = -6    /* valid input outside what the GPU kernels handle */
+};
+
+enum tm_op_kind { TM_SPLIT = 1, TM_MERGE = 2, TM_SWAP = 3, TM_BALANCE_SPLIT = 4, TM_DECOMPOSE = 5 };
+enum tm_proj_mode { TM_BLOCK = 0, TM_CYCLIC = 1 };
+
+/* One transformation of the processor space (Fig. 6, Sec. 4.2).
+ *   split(i=a, d=b)        (.., s_i, ..) -> (.., d, s_i/d, ..); requires d | s_i
+ *   merge(p=a, q=b)        p < q; dims p, q fused at p (p fastest), q removed
+ *   swap(p=a, q=b)         p != q; the two dims exchanged
+ *   balance_split(i=a,d=b) (.., s_i, ..) -> (.., d, ceil(s_i/d), ..)
+ *   decompose(i=a, f[0..nf)) s_i replaced by f[0..nf); product of f must be s_i */
+typedef struct {
+    int32_t kind, a, b, nf;
+    int32_t f[TM_MAX_LRANK];
+} tm_op;
+
+/* A candidate mapping: 328 bytes, little-endian, 8-byte aligned.
+ *   lrank        launch rank k, 1..4
+ *   nodes, gpus_per_node  Machine(GPU) = (nodes, gpus_per_node); product <= 2^24
+ *   nops         number of transformations applied to Machine(GPU), 0..8
+ *   extent[d]    launch domain 0 <= ip[d] < extent[d]; points in C order (last dim
+ *                fastest); product <= 2^40
+ *   mrank        rank of the final processor space (checked)
+ *   proj_src[j]  launch dim projected onto final dim j
+ *   proj_mode[j] TM_BLOCK: a_j = floor(ip[src]*s_j / extent[src]);
+ *                TM_CYCLIC: a_j = ip[src] mod s_j  */
+typedef struct {
+    int32_t lrank, nodes, gpus_per_node, nops;
+    int64_t extent[TM_MAX_LRANK];
+    tm_op ops[TM_MAX_OPS];
+    int32_t mrank, reserved;
+    int8_t proj_src[TM_MAX_MRANK];
+    int8_t proj_mode[TM_MAX_MRANK];
+} tm_candidate;
+
+/* Star stencil, non-periodic: halo[d] cells along each axis (0..65535), elements of
+ * elem_bytes bytes.  lrank must equal the candidates' launch rank. */
+typedef struct {
+    int32_t lrank, elem_bytes;
+    int32_t halo[TM_MAX_LRANK];
+} tm_stencil;
+
+/* ghost_cells = sum over cells of the distinct other owners of a star neighbour;
+ * inter_cells = the part whose receiver is on another node; bytes = cells * elem_bytes. */
+typedef struct {
+    int64_t ghost_cells, inter_cells, bytes, inter_bytes;
+} tm_stencil_cost;
+
+/* Matmul task space (i,j,k) = extent[0..2]; each task touches A[i,k], B[k,j], C[i,j]. */
+typedef struct {
+    int64_t tile_bytes;
+} tm_matmul;
+
+/* tiles[m]: sum over processors of distinct tiles of matrix m (A, B, C);
+ * max_tiles[m]: largest per-processor count; bytes = sum(tiles) * tile_bytes. */
+typedef struct {
+    int64_t tiles[3], max_tiles[3], bytes;
+} tm_matmul_cost;
+
+int tm_abi_version(void);
+int tm_candidate_size(void); /* sizeof(tm_candidate) */
+/* Message of the last failed call on this thread ("" if none). */
+const char* tm_last_error(void);
+
+/* ---------------------------------------------------------------- host calls */
+
+/* Checks one candidate (host).  On TM_OK writes the final shape (up to 8 entries)
+ * and its rank.  Errors: TM_EINVAL (bad kind, index, factor, projection or rank),
+ * TM_EOVERFLOW (size limits). */
+int tm_validate(const tm_candidate* c, int32_t* final_shape, int32_t* final_rank);
+
+/* decompose's search space (Sec. 4.3): all ordered k-tuples (1 <= k <= 4) of
+ * positive integers with product P (1 <= P <= 2^24), lexicographic ascending,
+ * written row-major to out[count][k] (host).  *count always receives the number of
+ * tuples; TM_ECAPACITY if it exceeds cap (out may be NULL when cap == 0). */
+int tm_enumerate_factorizations(int64_t P, int32_t k, int32_t* out, int64_t cap, int64_t* count);
+
+/* decompose's choice (Sec. 4.2, App. A.3): the factorization F of P minimising
+ * sum_m halo[m] * F[m] * prod_{j != m} extent[j], compared exactly; ties go to the
+ * lexicographically smallest F (host). */
+int tm_decompose_argmin(int64_t P, int32_t k, const int64_t* extent, const int32_t* halo,
+                        int32_t* out_f);
+
+/* Alg. A1 (App. A.2): primes of P ascending, each multiplied into the smallest
+ * current factor (lowest index on ties), result sorted descending (host). */
+int tm_greedy_grid(int64_t P, int32_t k, int32_t* out_f);
+
+/* The workload greedy of Sec. 4.3: primes ascending, each to the dimension that
+ * minimises max(w) - min(w), w_m = extent[m] / F[m], exactly (host). */
+int tm_workload_greedy(int64_t P, int32_t k, const int64_t* extent, int32_t* out_f);
+
+/* ---------------------------------------------------------------- device calls */
+
+/* Processor id of every coordinate of the final space of c (C order), computed on
+ * the GPU: d_out (device, int32[cap]).  *count (host) receives the volume;
+ * TM_ECAPACITY if cap is smaller. */
+int tm_chain_table(const tm_candidate* c, int32_t* d_out, int64_t cap, int64_t* count,
+                   void* stream);
+
+/* Processor id of every launch point of c, C order: d_map (device, int32[len]),
+ * len must equal the number of points (else TM_ECAPACITY). */
+int tm_proc_map(const tm_candidate* c, int32_t* d_map, int64_t len, void* stream);
+
+/* Stencil cost of n candidates (host array) sharing one stencil (host); results to
+ * d_out (device, tm_stencil_cost[n]).  All candidates must have launch rank
+ * st->lrank.  TM_ENOTSUP if a halo exceeds 4 or a candidate's tables exceed the
+ * per-workgroup LDS budget (32768 words of final-space volume + extents). */
+int tm_eval_stencil_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
+                          tm_stencil_cost* d_out, void* stream);
+
+/* Matmul tile fetches of n rank-3 candidates: d_per_proc (device, int64[sum P_c][3],
+ * candidates back to back, may be NULL) and d_out (device, tm_matmul_cost[n]).
+ * TM_ENOTSUP if a candidate has more than 1024 processors. */
+int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_matmul* mm,
+                         int64_t* d_per_proc, tm_matmul_cost* d_out, void* stream);
+
+/* Selection over a cost array (device): for each of nseg segments
+ * [seg[s], seg[s+1]) of d_costs (seg is a host int64[nseg+1]), the index (relative to
+ * the segment start) minimising (bytes, inter_bytes, index) -> d_best (device,
+ * int64[nseg]).  Empty segments give -1. */
+int tm_select_best(const tm_stencil_cost* d_costs, const int64_t* seg, int64_t nseg,
+                   int64_t* d_best, void* stream);
+
+/* ---------------------------------------------------------------- batch plans
+ * A plan owns device memory for up to max_cands candidates and max_words table
+ * words.  tm_plan_load validates a batch on the host and uploads its descriptors
+ * (asynchronously, on `stream`); tm_plan_run replays one hipGraph per (launch
+ * rank, halo, table size) class: reset -> table build -> one persistent counting
+ * launch over a work queue of (candidate, row block) items -> bytes + selection.
+ * d_out: tm_stencil_cost[n]; d_best: int64[1] (may be NULL).  Work items hold
+ * cells_per_item cells (0 = autotuned default). */
+typedef struct tm_plan tm_plan;
+
+int tm_plan_create(int64_t max_cands, int64_t max_words, tm_plan** out);
+int tm_plan_load(tm_plan* p, const tm_candidate* c, int64_t n, const tm_stencil* st,
+                 int64_t cells_per_item, void* stream);
+int tm_plan_run(tm_plan* p, tm_stencil_cost* d_out, int64_t* d_best, void* stream);
+/* stage 0: reset + table build; 1: counting; 2: bytes + selection (same work as
+ * tm_plan_run, one stage at a time, each replayed from its own graph). */
+int tm_plan_run_stage(tm_plan* p, int32_t stage, tm_stencil_cost* d_out, int64_t* d_best,
+                      void* stream);
+/* Processor map of candidate *d_index (device int64; index into the loaded batch),
+ * or of host_index when d_index is NULL, into d_map (device int32[cap]); cap must
+ * hold the largest candidate of the batch. */
+int tm_plan_materialize(tm_plan* p, const int64_t* d_index, int64_t host_index, int32_t* d_map,
+                        int64_t cap, void* stream);
+/* Times cells_per_item and grid variants of the loaded batch, keeps the fastest;
+ * writes the chosen cells_per_item and workgroups per CU (host pointers, nullable). */
+int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cells_per_item,
+                     int32_t* wg_per_cu, void* stream);
+/* Counts of the loaded batch: candidates, work items, total points (host, nullable). */
+int tm_plan_info(const tm_plan* p, int64_t* n, int64_t* items, int64_t* points);
+int tm_plan_destroy(tm_plan* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TASKMAP_H */

@@ -1,0 +1,653 @@
+// tm_device.cpp -- device entry points of libtaskmap: single-shot evaluation calls
+// and batch plans (persistent counting launch replayed from hipGraphs).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "tm_internal.h"
+
+namespace tmk {
+
+#define TM_HIP(expr)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) return set_error(TM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int64_t kDefaultCellsPerItem = 1 << 17;
+
+// ------------------------------------------------------------------ batch compilation
+
+struct Compiled {
+    std::vector<DevCand> cands;
+    DevHeader hdr{};
+    int64_t arena_words = 0, items = 0, points = 0, max_points = 0;
+    int32_t max_words = 0;
+    int K = 0, H = 1;
+};
+
+static int64_t rows_per_item_for(const DevCand& d, int64_t cells_per_item) {
+    const int64_t rpi = std::max<int64_t>(1, cells_per_item / std::max<int32_t>(d.L, 1));
+    return std::min<int64_t>(rpi, std::max<int64_t>(d.rows, 1));
+}
+
+static void layout_items(Compiled& cp, int64_t cells_per_item) {
+    int64_t items = 0;
+    for (auto& d : cp.cands) {
+        const int64_t rpi = rows_per_item_for(d, cells_per_item);
+        d.rows_per_item = (int32_t)rpi;
+        d.item_first = items;
+        items += (d.rows + rpi - 1) / rpi;
+    }
+    cp.items = items;
+    cp.hdr.total_items = items;
+}
+
+// Validates and compiles n candidates.  st == nullptr: tables without halo flags.
+// need_lds: every candidate's tables must fit the LDS budget of the kernels.
+static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st, int64_t cells_per_item,
+                         bool need_lds, Compiled& cp) {
+    if (n < 0) return set_error(TM_EINVAL, "n = %lld", (long long)n);
+    if (n > 0 && !c) return set_error(TM_EINVAL, "null candidate array");
+    cp.cands.resize((size_t)n);
+    cp.hdr = DevHeader{};
+    cp.hdr.n = n;
+    if (st) {
+        if (st->lrank < 1 || st->lrank > TM_MAX_LRANK) return set_error(TM_EINVAL, "stencil lrank %d", st->lrank);
+        if (st->elem_bytes < 0) return set_error(TM_EINVAL, "elem_bytes %d", st->elem_bytes);
+        int hmax = 0;
+        for (int d = 0; d < st->lrank; ++d) {
+            if (st->halo[d] < 0 || st->halo[d] > TM_MAX_HALO) return set_error(TM_EINVAL, "halo[%d] = %d", d, st->halo[d]);
+            hmax = std::max(hmax, st->halo[d]);
+            cp.hdr.halo[d] = st->halo[d];
+        }
+        if (hmax > kMaxHalo) return set_error(TM_ENOTSUP, "halo %d above the kernels' limit of %d", hmax, kMaxHalo);
+        cp.K = st->lrank;
+        cp.H = std::max(1, hmax);
+        cp.hdr.elem_bytes = st->elem_bytes;
+        cp.hdr.lrank = st->lrank;
+    }
+    int64_t words = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        Shapes sh;
+        int rc = validate_shapes(&c[i], &sh);
+        if (rc != TM_OK) return set_error(rc, "candidate %lld: %s", (long long)i, tm_last_error());
+        if (st && c[i].lrank != st->lrank)
+            return set_error(TM_EINVAL, "candidate %lld: lrank %d but the stencil has %d", (long long)i, c[i].lrank,
+                             st->lrank);
+        DevCand& d = cp.cands[(size_t)i];
+        rc = fill_devcand(&c[i], sh, &d);
+        if (rc != TM_OK) return set_error(rc, "candidate %lld: tables too large", (long long)i);
+        if (need_lds && d.words > kMaxLdsWords)
+            return set_error(TM_ENOTSUP, "candidate %lld: %d table words exceed the LDS budget of %d", (long long)i,
+                             d.words, kMaxLdsWords);
+        if (d.rows > INT32_MAX) return set_error(TM_ENOTSUP, "candidate %lld: more than 2^31 rows", (long long)i);
+        d.arena_off = words;
+        words += d.words;
+        cp.max_words = std::max(cp.max_words, d.words);
+        cp.points += d.npoints;
+        cp.max_points = std::max(cp.max_points, d.npoints);
+    }
+    cp.arena_words = words;
+    cp.hdr.max_words = cp.max_words;
+    layout_items(cp, cells_per_item > 0 ? cells_per_item : kDefaultCellsPerItem);
+    return TM_OK;
+}
+
+// ------------------------------------------------------------------ staging
+
+// Per-thread pinned staging for descriptor uploads; reused once the previous copy
+// out of it has completed.
+struct Staging {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    int device = -1;
+    bool pending = false;
+};
+static thread_local Staging g_stage;
+
+static int staging_acquire(size_t bytes, void** out) {
+    int dev = 0;
+    TM_HIP(hipGetDevice(&dev));
+    if (g_stage.pending) {
+        TM_HIP(hipEventSynchronize(g_stage.ev));
+        g_stage.pending = false;
+    }
+    if (g_stage.device != dev) {
+        if (g_stage.ev) (void)hipEventDestroy(g_stage.ev);
+        g_stage.ev = nullptr;
+        g_stage.device = dev;
+    }
+    if (!g_stage.ev) TM_HIP(hipEventCreateWithFlags(&g_stage.ev, hipEventDisableTiming));
+    if (g_stage.cap < bytes) {
+        if (g_stage.ptr) TM_HIP(hipHostFree(g_stage.ptr));
+        g_stage.ptr = nullptr;
+        g_stage.cap = 0;
+        const size_t cap = std::max<size_t>(bytes, 1 << 20);
+        if (hipHostMalloc(&g_stage.ptr, cap, hipHostMallocDefault) != hipSuccess)
+            return set_error(TM_ENOMEM, "pinned staging of %zu bytes", cap);
+        g_stage.cap = cap;
+    }
+    *out = g_stage.ptr;
+    return TM_OK;
+}
+
+static int staging_release(hipStream_t s) {
+    TM_HIP(hipEventRecord(g_stage.ev, s));
+    g_stage.pending = true;
+    return TM_OK;
+}
+
+// Device copies of a compiled batch in stream-ordered allocations.
+struct DeviceBatch {
+    DevCand* cands = nullptr;
+    DevHeader* hdr = nullptr;
+    int32_t* arena = nullptr;
+    unsigned long long* counter = nullptr;
+};
+
+static int upload_batch(const Compiled& cp, DeviceBatch& db, hipStream_t s) {
+    const size_t nc = cp.cands.size() * sizeof(DevCand);
+    TM_HIP(hipMallocAsync((void**)&db.cands, std::max<size_t>(nc, 64), s));
+    TM_HIP(hipMallocAsync((void**)&db.hdr, sizeof(DevHeader) + 64, s));
+    TM_HIP(hipMallocAsync((void**)&db.arena, std::max<size_t>((size_t)cp.arena_words * 4, 64), s));
+    TM_HIP(hipMallocAsync((void**)&db.counter, 64, s));
+    void* stg = nullptr;
+    int rc = staging_acquire(nc + sizeof(DevHeader), &stg);
+    if (rc != TM_OK) return rc;
+    std::memcpy(stg, &cp.hdr, sizeof(DevHeader));
+    if (nc) std::memcpy((char*)stg + sizeof(DevHeader), cp.cands.data(), nc);
+    TM_HIP(hipMemcpyAsync(db.hdr, stg, sizeof(DevHeader), hipMemcpyHostToDevice, s));
+    if (nc) TM_HIP(hipMemcpyAsync(db.cands, (char*)stg + sizeof(DevHeader), nc, hipMemcpyHostToDevice, s));
+    return staging_release(s);
+}
+
+static void free_batch(DeviceBatch& db, hipStream_t s) {
+    if (db.cands) (void)hipFreeAsync(db.cands, s);
+    if (db.hdr) (void)hipFreeAsync(db.hdr, s);
+    if (db.arena) (void)hipFreeAsync(db.arena, s);
+    if (db.counter) (void)hipFreeAsync(db.counter, s);
+    db = DeviceBatch{};
+}
+
+static int num_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
+}
+
+static int count_grid(int K, int H, int lds_words, int64_t items, int wg_per_cu) {
+    int per_cu = 0;
+    if (count_kernel_occupancy(K, H, lds_words, &per_cu) != 0 || per_cu < 1) per_cu = 1;
+    if (wg_per_cu > 0) per_cu = std::min(per_cu, wg_per_cu);
+    const int64_t g = (int64_t)per_cu * num_cus();
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, items));
+}
+
+}  // namespace tmk
+
+using namespace tmk;
+
+// ------------------------------------------------------------------ single-shot calls
+
+extern "C" int tm_chain_table(const tm_candidate* c, int32_t* d_out, int64_t cap, int64_t* count, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    Compiled cp;
+    int rc = compile_batch(c, 1, nullptr, 0, false, cp);
+    if (rc != TM_OK) return rc;
+    if (count) *count = cp.cands[0].vol;
+    if (cap < cp.cands[0].vol) return set_error(TM_ECAPACITY, "chain table has %d entries", cp.cands[0].vol);
+    if (!d_out) return set_error(TM_EINVAL, "null output");
+    DeviceBatch db;
+    rc = upload_batch(cp, db, s);
+    if (rc == TM_OK) {
+        hipError_t e = launch_build_tables(db.hdr, db.cands, 1, db.arena, 0, s);
+        if (e == hipSuccess) e = launch_chain_table(db.cands, db.arena, d_out, s);
+        if (e != hipSuccess) rc = set_error(TM_EDEVICE, "chain table launch: %s", hipGetErrorString(e));
+    }
+    free_batch(db, s);
+    return rc;
+}
+
+extern "C" int tm_proc_map(const tm_candidate* c, int32_t* d_map, int64_t len, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    Compiled cp;
+    int rc = compile_batch(c, 1, nullptr, 0, true, cp);
+    if (rc != TM_OK) return rc;
+    if (len != cp.cands[0].npoints)
+        return set_error(TM_ECAPACITY, "map length %lld but the domain has %lld points", (long long)len,
+                         (long long)cp.cands[0].npoints);
+    if (!d_map) return set_error(TM_EINVAL, "null output");
+    DeviceBatch db;
+    rc = upload_batch(cp, db, s);
+    if (rc == TM_OK) {
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((cp.cands[0].rows + 3) / 4, num_cus() * 8));
+        hipError_t e = launch_build_tables(db.hdr, db.cands, 1, db.arena, 0, s);
+        if (e == hipSuccess) e = launch_map(db.cands, 1, db.arena, nullptr, 0, d_map, grid, cp.max_words, s);
+        if (e != hipSuccess) rc = set_error(TM_EDEVICE, "map launch: %s", hipGetErrorString(e));
+    }
+    free_batch(db, s);
+    return rc;
+}
+
+extern "C" int tm_eval_stencil_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
+                                     tm_stencil_cost* d_out, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (!st) return set_error(TM_EINVAL, "null stencil");
+    Compiled cp;
+    int rc = compile_batch(c, n, st, 0, true, cp);
+    if (rc != TM_OK) return rc;
+    if (n == 0) return TM_OK;
+    if (!d_out) return set_error(TM_EINVAL, "null output");
+    DeviceBatch db;
+    rc = upload_batch(cp, db, s);
+    if (rc == TM_OK) {
+        const int grid = count_grid(cp.K, cp.H, cp.max_words, cp.items, 0);
+        hipError_t e = launch_reset(db.hdr, db.counter, d_out, n, s);
+        if (e == hipSuccess) e = launch_build_tables(db.hdr, db.cands, n, db.arena, 1, s);
+        if (e == hipSuccess)
+            e = launch_count(cp.K, cp.H, db.hdr, db.cands, db.arena, db.counter, d_out, grid, cp.max_words, s);
+        if (e == hipSuccess) e = launch_finalize_select(db.hdr, d_out, nullptr, s);
+        if (e != hipSuccess) rc = set_error(TM_EDEVICE, "stencil launch: %s", hipGetErrorString(e));
+    }
+    free_batch(db, s);
+    return rc;
+}
+
+extern "C" int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_matmul* mm, int64_t* d_per_proc,
+                                    tm_matmul_cost* d_out, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (!mm || mm->tile_bytes < 0) return set_error(TM_EINVAL, "bad matmul descriptor");
+    Compiled cp;
+    int rc = compile_batch(c, n, nullptr, 0, true, cp);
+    if (rc != TM_OK) return rc;
+    if (n == 0) return TM_OK;
+    if (!d_out) return set_error(TM_EINVAL, "null output");
+    std::vector<int64_t> proc_off((size_t)n + 1), block_first((size_t)n + 1);
+    int64_t procs = 0, blocks = 0;
+    int pmax = 0;
+    const int64_t per = 256 * 16;
+    for (int64_t i = 0; i < n; ++i) {
+        const DevCand& d = cp.cands[(size_t)i];
+        if (d.lrank != 3) return set_error(TM_EINVAL, "candidate %lld: matmul needs launch rank 3", (long long)i);
+        const int64_t P = (int64_t)d.nodes * d.gpus;
+        if (P > 1024) return set_error(TM_ENOTSUP, "candidate %lld: %lld processors (limit 1024)", (long long)i, (long long)P);
+        if (d.extent[0] * d.extent[1] > INT32_MAX || d.extent[1] * d.extent[2] > INT32_MAX ||
+            d.extent[0] * d.extent[2] > INT32_MAX)
+            return set_error(TM_ENOTSUP, "candidate %lld: more than 2^31 tiles in a matrix", (long long)i);
+        pmax = std::max<int>(pmax, (int)P);
+        proc_off[(size_t)i] = procs;
+        block_first[(size_t)i] = blocks;
+        procs += P;
+        blocks += (d.extent[0] * d.extent[2] + per - 1) / per + (d.extent[2] * d.extent[1] + per - 1) / per +
+                  (d.extent[0] * d.extent[1] + per - 1) / per;
+    }
+    proc_off[(size_t)n] = procs;
+    block_first[(size_t)n] = blocks;
+    DeviceBatch db;
+    rc = upload_batch(cp, db, s);
+    int64_t *d_off = nullptr, *d_bf = nullptr;
+    unsigned long long* d_pp = nullptr;
+    if (rc == TM_OK) {
+        hipError_t e = hipMallocAsync((void**)&d_off, (size_t)(n + 1) * 8, s);
+        if (e == hipSuccess) e = hipMallocAsync((void**)&d_bf, (size_t)(n + 1) * 8, s);
+        if (e == hipSuccess) e = hipMallocAsync((void**)&d_pp, (size_t)std::max<int64_t>(procs, 1) * 24, s);
+        void* stg = nullptr;
+        if (e == hipSuccess) {
+            // the descriptor upload above used the staging buffer; reuse waits for it
+            rc = staging_acquire((size_t)(n + 1) * 16, &stg);
+            if (rc == TM_OK) {
+                std::memcpy(stg, proc_off.data(), (size_t)(n + 1) * 8);
+                std::memcpy((char*)stg + (n + 1) * 8, block_first.data(), (size_t)(n + 1) * 8);
+                e = hipMemcpyAsync(d_off, stg, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(d_bf, (char*)stg + (n + 1) * 8, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, s);
+                if (e == hipSuccess) rc = staging_release(s);
+            }
+        }
+        if (rc == TM_OK && e == hipSuccess) e = hipMemsetAsync(d_pp, 0, (size_t)std::max<int64_t>(procs, 1) * 24, s);
+        if (rc == TM_OK && e == hipSuccess) e = launch_build_tables(db.hdr, db.cands, n, db.arena, 0, s);
+        if (rc == TM_OK && e == hipSuccess)
+            e = launch_matmul(db.cands, n, db.arena, cp.max_words, pmax, d_off, d_pp, blocks, d_bf, s);
+        if (rc == TM_OK && e == hipSuccess)
+            e = launch_matmul_finalize(db.cands, n, d_off, d_pp, mm->tile_bytes, d_out, d_per_proc, s);
+        if (rc == TM_OK && e != hipSuccess) rc = set_error(TM_EDEVICE, "matmul launch: %s", hipGetErrorString(e));
+    }
+    if (d_off) (void)hipFreeAsync(d_off, s);
+    if (d_bf) (void)hipFreeAsync(d_bf, s);
+    if (d_pp) (void)hipFreeAsync(d_pp, s);
+    free_batch(db, s);
+    return rc;
+}
+
+extern "C" int tm_select_best(const tm_stencil_cost* d_costs, const int64_t* seg, int64_t nseg, int64_t* d_best,
+                              void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (nseg < 0 || (nseg > 0 && (!seg || !d_best))) return set_error(TM_EINVAL, "bad segments");
+    if (nseg == 0) return TM_OK;
+    for (int64_t i = 0; i < nseg; ++i)
+        if (seg[i] < 0 || seg[i + 1] < seg[i]) return set_error(TM_EINVAL, "segment %lld is not ordered", (long long)i);
+    if (seg[nseg] > 0 && !d_costs) return set_error(TM_EINVAL, "null costs");
+    int64_t* d_seg = nullptr;
+    TM_HIP(hipMallocAsync((void**)&d_seg, (size_t)(nseg + 1) * 8, s));
+    void* stg = nullptr;
+    int rc = staging_acquire((size_t)(nseg + 1) * 8, &stg);
+    if (rc == TM_OK) {
+        std::memcpy(stg, seg, (size_t)(nseg + 1) * 8);
+        hipError_t e = hipMemcpyAsync(d_seg, stg, (size_t)(nseg + 1) * 8, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) rc = staging_release(s);
+        if (rc == TM_OK && e == hipSuccess) e = launch_select_segments(d_costs, d_seg, nseg, d_best, s);
+        if (rc == TM_OK && e != hipSuccess) rc = set_error(TM_EDEVICE, "select launch: %s", hipGetErrorString(e));
+    }
+    (void)hipFreeAsync(d_seg, s);
+    return rc;
+}
+
+// ------------------------------------------------------------------ batch plans
+
+struct tm_plan {
+    int device = 0;
+    int64_t cap_cands = 0, cap_words = 0;
+    DevCand* d_cands = nullptr;
+    int32_t* d_arena = nullptr;
+    DevHeader* d_hdr = nullptr;
+    unsigned long long* d_counter = nullptr;
+    DevCand* h_cands = nullptr;  // pinned staging
+    DevHeader* h_hdr = nullptr;
+    hipEvent_t up_ev = nullptr;
+    bool up_pending = false;
+    hipStream_t cap_stream = nullptr;
+    Compiled cp;  // the loaded batch
+    bool loaded = false;
+    int64_t cells_per_item = 0;
+    int wg_per_cu = 0;
+    // graph cache: one entry
+    bool g_valid = false;
+    int g_grid = 0;
+    void* g_out = nullptr;
+    void* g_best = nullptr;
+    hipGraphExec_t g_full = nullptr, g_stage[3] = {nullptr, nullptr, nullptr};
+};
+
+namespace tmk {
+
+static void plan_drop_graphs(tm_plan* p) {
+    if (p->g_full) (void)hipGraphExecDestroy(p->g_full);
+    for (auto& g : p->g_stage)
+        if (g) (void)hipGraphExecDestroy(g);
+    p->g_full = nullptr;
+    for (auto& g : p->g_stage) g = nullptr;
+    p->g_valid = false;
+}
+
+static void plan_free(tm_plan* p) {
+    plan_drop_graphs(p);
+    if (p->d_cands) (void)hipFree(p->d_cands);
+    if (p->d_arena) (void)hipFree(p->d_arena);
+    if (p->d_hdr) (void)hipFree(p->d_hdr);
+    if (p->d_counter) (void)hipFree(p->d_counter);
+    if (p->h_cands) (void)hipHostFree(p->h_cands);
+    if (p->h_hdr) (void)hipHostFree(p->h_hdr);
+    p->d_cands = nullptr;
+    p->d_arena = nullptr;
+    p->d_hdr = nullptr;
+    p->d_counter = nullptr;
+    p->h_cands = nullptr;
+    p->h_hdr = nullptr;
+}
+
+static int plan_alloc(tm_plan* p, int64_t cands, int64_t words) {
+    plan_free(p);
+    cands = std::max<int64_t>(cands, 1);
+    words = std::max<int64_t>(words, 1);
+    if (hipMalloc((void**)&p->d_cands, (size_t)cands * sizeof(DevCand)) != hipSuccess ||
+        hipMalloc((void**)&p->d_arena, (size_t)words * 4) != hipSuccess ||
+        hipMalloc((void**)&p->d_hdr, sizeof(DevHeader)) != hipSuccess ||
+        hipMalloc((void**)&p->d_counter, 256) != hipSuccess ||
+        hipHostMalloc((void**)&p->h_cands, (size_t)cands * sizeof(DevCand), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&p->h_hdr, sizeof(DevHeader), hipHostMallocDefault) != hipSuccess) {
+        plan_free(p);
+        return set_error(TM_ENOMEM, "plan buffers for %lld candidates / %lld words", (long long)cands,
+                         (long long)words);
+    }
+    p->cap_cands = cands;
+    p->cap_words = words;
+    return TM_OK;
+}
+
+static int plan_upload(tm_plan* p, hipStream_t s) {
+    if (p->up_pending) {
+        TM_HIP(hipEventSynchronize(p->up_ev));
+        p->up_pending = false;
+    }
+    const size_t nc = p->cp.cands.size() * sizeof(DevCand);
+    std::memcpy(p->h_hdr, &p->cp.hdr, sizeof(DevHeader));
+    if (nc) std::memcpy(p->h_cands, p->cp.cands.data(), nc);
+    TM_HIP(hipMemcpyAsync(p->d_hdr, p->h_hdr, sizeof(DevHeader), hipMemcpyHostToDevice, s));
+    if (nc) TM_HIP(hipMemcpyAsync(p->d_cands, p->h_cands, nc, hipMemcpyHostToDevice, s));
+    TM_HIP(hipEventRecord(p->up_ev, s));
+    p->up_pending = true;
+    return TM_OK;
+}
+
+// Enqueues one stage of a run on stream s (direct launches; also used for capture).
+static hipError_t plan_enqueue(tm_plan* p, int stage, tm_stencil_cost* out, int64_t* best, int grid, hipStream_t s) {
+    const Compiled& cp = p->cp;
+    hipError_t e = hipSuccess;
+    if (stage == 0 || stage < 0) {
+        e = launch_reset(p->d_hdr, p->d_counter, out, cp.hdr.n, s);
+        if (e == hipSuccess) e = launch_build_tables(p->d_hdr, p->d_cands, cp.hdr.n, p->d_arena, 1, s);
+        if (e != hipSuccess) return e;
+    }
+    if (stage == 1 || stage < 0) {
+        e = launch_count(cp.K, cp.H, p->d_hdr, p->d_cands, p->d_arena, p->d_counter, out, grid, cp.max_words, s);
+        if (e != hipSuccess) return e;
+    }
+    if (stage == 2 || stage < 0) e = launch_finalize_select(p->d_hdr, out, best, s);
+    return e;
+}
+
+static int capture(tm_plan* p, int stage, tm_stencil_cost* out, int64_t* best, int grid, hipGraphExec_t* exec) {
+    hipGraph_t g = nullptr;
+    TM_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t e = plan_enqueue(p, stage, out, best, grid, p->cap_stream);
+    const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return set_error(TM_EDEVICE, "capture: %s", hipGetErrorString(e));
+    }
+    TM_HIP(e2);
+    const hipError_t e3 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    TM_HIP(e3);
+    return TM_OK;
+}
+
+static int plan_graphs(tm_plan* p, tm_stencil_cost* out, int64_t* best) {
+    const int grid = count_grid(p->cp.K, p->cp.H, p->cp.max_words, p->cp.items, p->wg_per_cu);
+    if (p->g_valid && p->g_grid == grid && p->g_out == out && p->g_best == best) return TM_OK;
+    plan_drop_graphs(p);
+    int rc = capture(p, -1, out, best, grid, &p->g_full);
+    for (int st = 0; st < 3 && rc == TM_OK; ++st) rc = capture(p, st, out, best, grid, &p->g_stage[st]);
+    if (rc != TM_OK) {
+        plan_drop_graphs(p);
+        return rc;
+    }
+    p->g_valid = true;
+    p->g_grid = grid;
+    p->g_out = out;
+    p->g_best = best;
+    return TM_OK;
+}
+
+}  // namespace tmk
+
+extern "C" int tm_plan_create(int64_t max_cands, int64_t max_words, tm_plan** out) {
+    if (!out) return set_error(TM_EINVAL, "null output");
+    *out = nullptr;
+    tm_plan* p = new (std::nothrow) tm_plan();
+    if (!p) return set_error(TM_ENOMEM, "plan");
+    (void)hipGetDevice(&p->device);
+    int rc = plan_alloc(p, max_cands, max_words);
+    if (rc == TM_OK && hipEventCreateWithFlags(&p->up_ev, hipEventDisableTiming) != hipSuccess)
+        rc = set_error(TM_EDEVICE, "event");
+    if (rc == TM_OK && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        rc = set_error(TM_EDEVICE, "capture stream");
+    if (rc != TM_OK) {
+        tm_plan_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return TM_OK;
+}
+
+extern "C" int tm_plan_destroy(tm_plan* p) {
+    if (!p) return TM_OK;
+    if (p->up_pending) (void)hipEventSynchronize(p->up_ev);
+    (void)hipDeviceSynchronize();
+    plan_free(p);
+    if (p->up_ev) (void)hipEventDestroy(p->up_ev);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    delete p;
+    return TM_OK;
+}
+
+extern "C" int tm_plan_load(tm_plan* p, const tm_candidate* c, int64_t n, const tm_stencil* st,
+                            int64_t cells_per_item, void* stream) {
+    if (!p) return set_error(TM_EINVAL, "null plan");
+    if (!st) return set_error(TM_EINVAL, "null stencil");
+    if (cells_per_item < 0) return set_error(TM_EINVAL, "cells_per_item %lld", (long long)cells_per_item);
+    hipStream_t s = (hipStream_t)stream;
+    Compiled cp;
+    int rc = compile_batch(c, n, st, cells_per_item > 0 ? cells_per_item : p->cells_per_item, true, cp);
+    if (rc != TM_OK) return rc;
+    if (n > p->cap_cands || cp.arena_words > p->cap_words) {
+        // grow: wait for work that may still read the old buffers
+        TM_HIP(hipStreamSynchronize(s));
+        rc = plan_alloc(p, std::max(n, p->cap_cands), std::max(cp.arena_words, p->cap_words));
+        if (rc != TM_OK) return rc;
+        p->up_pending = false;
+    }
+    if (cells_per_item > 0) p->cells_per_item = cells_per_item;
+    p->cp = std::move(cp);
+    p->loaded = true;
+    plan_drop_graphs(p);
+    return plan_upload(p, s);
+}
+
+extern "C" int tm_plan_run(tm_plan* p, tm_stencil_cost* d_out, int64_t* d_best, void* stream) {
+    if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
+    if (p->cp.hdr.n > 0 && !d_out) return set_error(TM_EINVAL, "null output");
+    if (p->cp.hdr.n == 0) return TM_OK;
+    int rc = plan_graphs(p, d_out, d_best);
+    if (rc != TM_OK) return rc;
+    TM_HIP(hipGraphLaunch(p->g_full, (hipStream_t)stream));
+    return TM_OK;
+}
+
+extern "C" int tm_plan_run_stage(tm_plan* p, int32_t stage, tm_stencil_cost* d_out, int64_t* d_best,
+                                 void* stream) {
+    if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
+    if (stage < 0 || stage > 2) return set_error(TM_EINVAL, "stage %d", stage);
+    if (p->cp.hdr.n > 0 && !d_out) return set_error(TM_EINVAL, "null output");
+    if (p->cp.hdr.n == 0) return TM_OK;
+    int rc = plan_graphs(p, d_out, d_best);
+    if (rc != TM_OK) return rc;
+    TM_HIP(hipGraphLaunch(p->g_stage[stage], (hipStream_t)stream));
+    return TM_OK;
+}
+
+extern "C" int tm_plan_materialize(tm_plan* p, const int64_t* d_index, int64_t host_index, int32_t* d_map,
+                                   int64_t cap, void* stream) {
+    if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
+    if (!d_map) return set_error(TM_EINVAL, "null output");
+    const Compiled& cp = p->cp;
+    if (cp.hdr.n == 0) return set_error(TM_EINVAL, "empty batch");
+    int64_t need = cp.max_points;
+    int64_t rows = 0;
+    if (!d_index) {
+        if (host_index < 0 || host_index >= cp.hdr.n) return set_error(TM_EINVAL, "index %lld", (long long)host_index);
+        need = cp.cands[(size_t)host_index].npoints;
+        rows = cp.cands[(size_t)host_index].rows;
+    } else {
+        for (auto& d : cp.cands) rows = std::max(rows, d.rows);
+    }
+    if (cap < need) return set_error(TM_ECAPACITY, "map needs %lld entries", (long long)need);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((rows + 3) / 4, num_cus() * 8));
+    const hipError_t e = launch_map(p->d_cands, cp.hdr.n, p->d_arena, d_index, host_index, d_map, grid, cp.max_words,
+                                    (hipStream_t)stream);
+    if (e != hipSuccess) return set_error(TM_EDEVICE, "map launch: %s", hipGetErrorString(e));
+    return TM_OK;
+}
+
+extern "C" int tm_plan_info(const tm_plan* p, int64_t* n, int64_t* items, int64_t* points) {
+    if (!p) return set_error(TM_EINVAL, "null plan");
+    if (n) *n = p->loaded ? p->cp.hdr.n : 0;
+    if (items) *items = p->loaded ? p->cp.items : 0;
+    if (points) *points = p->loaded ? p->cp.points : 0;
+    return TM_OK;
+}
+
+extern "C" int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cells_per_item, int32_t* wg_per_cu,
+                                void* stream) {
+    if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
+    if (p->cp.hdr.n == 0) return TM_OK;
+    if (!d_out) return set_error(TM_EINVAL, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    TM_HIP(hipEventCreate(&e0));
+    TM_HIP(hipEventCreate(&e1));
+    const int64_t cells_opts[] = {1 << 15, 1 << 17, 1 << 19};
+    const int wg_opts[] = {0, 2, 1};
+    float best_ms = 1e30f;
+    int64_t best_c = kDefaultCellsPerItem;
+    int best_w = 0;
+    int rc = TM_OK;
+    for (int64_t cpi : cells_opts) {
+        layout_items(p->cp, cpi);
+        rc = plan_upload(p, s);
+        if (rc != TM_OK) break;
+        // tables once per layout (they do not depend on it)
+        if (plan_enqueue(p, 0, d_out, nullptr, 1, s) != hipSuccess) {
+            rc = set_error(TM_EDEVICE, "autotune build");
+            break;
+        }
+        for (int w : wg_opts) {
+            const int grid = count_grid(p->cp.K, p->cp.H, p->cp.max_words, p->cp.items, w);
+            float tot = 0.f;
+            for (int rep = 0; rep < 3 && rc == TM_OK; ++rep) {
+                hipError_t e = launch_reset(p->d_hdr, p->d_counter, d_out, p->cp.hdr.n, s);
+                if (e == hipSuccess) e = hipEventRecord(e0, s);
+                if (e == hipSuccess) e = plan_enqueue(p, 1, d_out, nullptr, grid, s);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) rc = set_error(TM_EDEVICE, "autotune: %s", hipGetErrorString(e));
+                if (rep > 0) tot += ms;
+            }
+            if (rc != TM_OK) break;
+            if (tot < best_ms) {
+                best_ms = tot;
+                best_c = cpi;
+                best_w = w;
+            }
+        }
+        if (rc != TM_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != TM_OK) return rc;
+    p->cells_per_item = best_c;
+    p->wg_per_cu = best_w;
+    layout_items(p->cp, best_c);
+    plan_drop_graphs(p);
+    rc = plan_upload(p, s);
+    if (cells_per_item) *cells_per_item = best_c;
+    if (wg_per_cu) *wg_per_cu = best_w;
+    return rc;
+}

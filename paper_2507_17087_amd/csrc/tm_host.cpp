@@ -1,0 +1,378 @@
+// tm_host.cpp -- host side of libtaskmap: validation, decompose's search,
+// descriptor compilation, batch plans and the C entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <functional>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "tm_internal.h"
+
+namespace tmk {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define TM_HIP(expr)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) return set_error(TM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ validation
+
+// Forward shape rules of Fig. 6 (split, merge, swap), Sec. 4.2 (decompose) and the
+// balance_split reading, from Machine(GPU) = (nodes, gpus).  Records the shape
+// before every op (the table-build kernel inverts the ops with them).
+int validate_shapes(const tm_candidate* c, Shapes* sh) {
+    if (!c) return set_error(TM_EINVAL, "null candidate");
+    if (c->lrank < 1 || c->lrank > TM_MAX_LRANK) return set_error(TM_EINVAL, "lrank %d not in 1..4", c->lrank);
+    if (c->nodes < 1 || c->gpus_per_node < 1) return set_error(TM_EINVAL, "machine (%d, %d)", c->nodes, c->gpus_per_node);
+    if ((int64_t)c->nodes * c->gpus_per_node > TM_MAX_VOLUME)
+        return set_error(TM_EOVERFLOW, "more than 2^24 processors");
+    if (c->nops < 0 || c->nops > TM_MAX_OPS) return set_error(TM_EINVAL, "nops %d", c->nops);
+    int64_t pts = 1;
+    for (int d = 0; d < c->lrank; ++d) {
+        const int64_t l = c->extent[d];
+        if (l < 1 || l > TM_MAX_EXTENT) return set_error(TM_EINVAL, "extent[%d] = %lld", d, (long long)l);
+        if (pts > TM_MAX_POINTS / l) return set_error(TM_EOVERFLOW, "more than 2^40 points");
+        pts *= l;
+    }
+    sh->rank[0] = 2;
+    sh->size[0][0] = c->nodes;
+    sh->size[0][1] = c->gpus_per_node;
+    for (int t = 0; t < c->nops; ++t) {
+        const tm_op& op = c->ops[t];
+        const int r = sh->rank[t];
+        const int64_t* s = sh->size[t];
+        int64_t* o = sh->size[t + 1];
+        int nr = r;
+        switch (op.kind) {
+            case TM_SPLIT: {
+                const int i = op.a;
+                const int64_t d = op.b;
+                if (i < 0 || i >= r) return set_error(TM_EINVAL, "op %d: split dim %d of rank %d", t, i, r);
+                if (d < 1 || s[i] % d) return set_error(TM_EINVAL, "op %d: split factor %lld does not divide %lld", t, (long long)d, (long long)s[i]);
+                if (r + 1 > TM_MAX_MRANK) return set_error(TM_EINVAL, "op %d: rank above 8", t);
+                nr = r + 1;
+                for (int u = 0; u < i; ++u) o[u] = s[u];
+                o[i] = d;
+                o[i + 1] = s[i] / d;
+                for (int u = i + 1; u < r; ++u) o[u + 1] = s[u];
+                break;
+            }
+            case TM_MERGE: {
+                const int p = op.a, q = op.b;
+                if (p < 0 || p >= q || q >= r) return set_error(TM_EINVAL, "op %d: merge(%d,%d) on rank %d", t, p, q, r);
+                nr = r - 1;
+                int w = 0;
+                for (int u = 0; u < r; ++u)
+                    if (u != q) o[w++] = u == p ? s[p] * s[q] : s[u];
+                break;
+            }
+            case TM_SWAP: {
+                const int p = op.a, q = op.b;
+                if (p < 0 || q < 0 || p >= r || q >= r || p == q)
+                    return set_error(TM_EINVAL, "op %d: swap(%d,%d) on rank %d", t, p, q, r);
+                for (int u = 0; u < r; ++u) o[u] = s[u];
+                std::swap(o[p], o[q]);
+                break;
+            }
+            case TM_BALANCE_SPLIT: {
+                const int i = op.a;
+                const int64_t d = op.b;
+                if (i < 0 || i >= r || d < 1) return set_error(TM_EINVAL, "op %d: balance_split(%d,%lld)", t, i, (long long)d);
+                if (d > TM_MAX_VOLUME) return set_error(TM_EOVERFLOW, "op %d: balance_split factor too large", t);
+                if (r + 1 > TM_MAX_MRANK) return set_error(TM_EINVAL, "op %d: rank above 8", t);
+                nr = r + 1;
+                for (int u = 0; u < i; ++u) o[u] = s[u];
+                o[i] = d;
+                o[i + 1] = (s[i] + d - 1) / d;
+                for (int u = i + 1; u < r; ++u) o[u + 1] = s[u];
+                break;
+            }
+            case TM_DECOMPOSE: {
+                const int i = op.a, k = op.nf;
+                if (i < 0 || i >= r || k < 1 || k > TM_MAX_LRANK)
+                    return set_error(TM_EINVAL, "op %d: decompose dim %d with %d factors", t, i, k);
+                if (r + k - 1 > TM_MAX_MRANK) return set_error(TM_EINVAL, "op %d: rank above 8", t);
+                int64_t prod = 1;
+                for (int m = 0; m < k; ++m) {
+                    if (op.f[m] < 1) return set_error(TM_EINVAL, "op %d: factor %d", t, op.f[m]);
+                    prod *= op.f[m];
+                    if (prod > s[i]) return set_error(TM_EINVAL, "op %d: factors exceed %lld", t, (long long)s[i]);
+                }
+                if (prod != s[i]) return set_error(TM_EINVAL, "op %d: factor product %lld != %lld", t, (long long)prod, (long long)s[i]);
+                nr = r + k - 1;
+                for (int u = 0; u < i; ++u) o[u] = s[u];
+                for (int m = 0; m < k; ++m) o[i + m] = op.f[m];
+                for (int u = i + 1; u < r; ++u) o[u + k - 1] = s[u];
+                break;
+            }
+            default:
+                return set_error(TM_EINVAL, "op %d: unknown kind %d", t, op.kind);
+        }
+        sh->rank[t + 1] = nr;
+        int64_t vol = 1;
+        for (int u = 0; u < nr; ++u) vol *= o[u];
+        if (vol > TM_MAX_VOLUME) return set_error(TM_EOVERFLOW, "op %d: processor space volume above 2^24", t);
+    }
+    const int fr = sh->rank[c->nops];
+    if (c->mrank != fr) return set_error(TM_EINVAL, "mrank %d but the final rank is %d", c->mrank, fr);
+    for (int j = 0; j < fr; ++j) {
+        if (c->proj_src[j] < 0 || c->proj_src[j] >= c->lrank)
+            return set_error(TM_EINVAL, "proj_src[%d] = %d", j, (int)c->proj_src[j]);
+        if (c->proj_mode[j] != TM_BLOCK && c->proj_mode[j] != TM_CYCLIC)
+            return set_error(TM_EINVAL, "proj_mode[%d] = %d", j, (int)c->proj_mode[j]);
+    }
+    return TM_OK;
+}
+
+static int bits_for(int64_t g) {
+    int b = 0;
+    while ((int64_t(1) << b) < g) ++b;
+    return b;
+}
+
+int fill_devcand(const tm_candidate* c, const Shapes& sh, DevCand* d) {
+    std::memset(d, 0, sizeof(*d));
+    d->lrank = c->lrank;
+    d->nops = c->nops;
+    d->nodes = c->nodes;
+    d->gpus = c->gpus_per_node;
+    d->gbits = bits_for(c->gpus_per_node);
+    const int fr = sh.rank[c->nops];
+    d->frank = fr;
+    int64_t vol = 1;
+    for (int j = fr - 1; j >= 0; --j) {
+        d->fshape[j] = (int32_t)sh.size[c->nops][j];
+        d->fstride[j] = (int32_t)vol;
+        vol *= sh.size[c->nops][j];
+    }
+    d->vol = (int32_t)vol;
+    int64_t words = vol, pts = 1;
+    for (int k = 0; k < c->lrank; ++k) {
+        d->extent[k] = c->extent[k];
+        d->coord_off[k] = (int32_t)std::min<int64_t>(words, INT32_MAX);
+        words += c->extent[k];
+        pts *= c->extent[k];
+    }
+    d->words = (int32_t)std::min<int64_t>(words, INT32_MAX);
+    d->npoints = pts;
+    d->L = (int32_t)c->extent[c->lrank - 1];
+    d->rows = pts / c->extent[c->lrank - 1];
+    for (int j = 0; j < fr; ++j) {
+        d->proj_src[j] = c->proj_src[j];
+        d->proj_mode[j] = c->proj_mode[j];
+    }
+    for (int t = 0; t < c->nops; ++t) {
+        d->rank[t] = sh.rank[t];
+        for (int u = 0; u < sh.rank[t]; ++u) d->shape[t][u] = (int32_t)sh.size[t][u];
+        d->op_kind[t] = c->ops[t].kind;
+        d->op_a[t] = c->ops[t].a;
+        d->op_b[t] = c->ops[t].b;
+        d->op_nf[t] = c->ops[t].nf;
+        for (int m = 0; m < TM_MAX_LRANK; ++m) d->op_f[t][m] = c->ops[t].f[m];
+    }
+    return words > INT32_MAX ? TM_EOVERFLOW : TM_OK;
+}
+
+// ------------------------------------------------------------------ decompose's search
+
+static int check_pk(int64_t P, int32_t k) {
+    if (P < 1 || P > TM_MAX_VOLUME) return set_error(TM_EINVAL, "P = %lld not in 1..2^24", (long long)P);
+    if (k < 1 || k > TM_MAX_LRANK) return set_error(TM_EINVAL, "k = %d not in 1..4", k);
+    return TM_OK;
+}
+
+// Prime factorization P = prod p_j^{a_j} (trial division), primes ascending.
+static void factorize(int64_t P, std::vector<std::pair<int64_t, int>>& pe) {
+    pe.clear();
+    for (int64_t p = 2; p * p <= P; ++p) {
+        int e = 0;
+        while (P % p == 0) {
+            P /= p;
+            ++e;
+        }
+        if (e) pe.push_back({p, e});
+    }
+    if (P > 1) pe.push_back({P, 1});
+}
+
+// Sec. 4.3: distribute each prime's exponent over the k dims (stars and bars) and
+// take the Cartesian product over primes; then sort lexicographically.
+static void all_factorizations(int64_t P, int k, std::vector<std::array<int32_t, 4>>& out) {
+    std::vector<std::pair<int64_t, int>> pe;
+    factorize(P, pe);
+    out.assign(1, {1, 1, 1, 1});
+    for (auto& [p, a] : pe) {
+        // all compositions of a into k non-negative parts
+        std::vector<std::array<int, 4>> comps;
+        std::array<int, 4> cur{0, 0, 0, 0};
+        std::function<void(int, int)> rec = [&](int pos, int left) {
+            if (pos == k - 1) {
+                cur[pos] = left;
+                comps.push_back(cur);
+                return;
+            }
+            for (int x = 0; x <= left; ++x) {
+                cur[pos] = x;
+                rec(pos + 1, left - x);
+            }
+        };
+        rec(0, a);
+        std::vector<std::array<int32_t, 4>> next;
+        next.reserve(out.size() * comps.size());
+        for (auto& f : out)
+            for (auto& cp : comps) {
+                std::array<int32_t, 4> g = f;
+                for (int m = 0; m < k; ++m)
+                    for (int e = 0; e < cp[m]; ++e) g[m] *= (int32_t)p;
+                next.push_back(g);
+            }
+        out.swap(next);
+    }
+    std::sort(out.begin(), out.end(), [k](const std::array<int32_t, 4>& x, const std::array<int32_t, 4>& y) {
+        for (int m = 0; m < k; ++m)
+            if (x[m] != y[m]) return x[m] < y[m];
+        return false;
+    });
+}
+
+}  // namespace tmk
+
+using namespace tmk;
+
+extern "C" {
+
+int tm_abi_version(void) { return TM_ABI_VERSION; }
+int tm_candidate_size(void) { return (int)sizeof(tm_candidate); }
+const char* tm_last_error(void) { return g_err; }
+
+int tm_validate(const tm_candidate* c, int32_t* final_shape, int32_t* final_rank) {
+    Shapes sh;
+    const int rc = validate_shapes(c, &sh);
+    if (rc != TM_OK) return rc;
+    const int fr = sh.rank[c->nops];
+    if (final_rank) *final_rank = fr;
+    if (final_shape)
+        for (int j = 0; j < fr; ++j) final_shape[j] = (int32_t)sh.size[c->nops][j];
+    return TM_OK;
+}
+
+int tm_enumerate_factorizations(int64_t P, int32_t k, int32_t* out, int64_t cap, int64_t* count) {
+    int rc = check_pk(P, k);
+    if (rc != TM_OK) return rc;
+    if (cap < 0 || (cap > 0 && !out)) return set_error(TM_EINVAL, "bad output buffer");
+    std::vector<std::array<int32_t, 4>> all;
+    all_factorizations(P, k, all);
+    if (count) *count = (int64_t)all.size();
+    if ((int64_t)all.size() > cap)
+        return set_error(TM_ECAPACITY, "%zu factorizations, capacity %lld", all.size(), (long long)cap);
+    for (size_t i = 0; i < all.size(); ++i)
+        for (int m = 0; m < k; ++m) out[i * k + m] = all[i][m];
+    return TM_OK;
+}
+
+int tm_decompose_argmin(int64_t P, int32_t k, const int64_t* extent, const int32_t* halo, int32_t* out_f) {
+    int rc = check_pk(P, k);
+    if (rc != TM_OK) return rc;
+    if (!extent || !halo || !out_f) return set_error(TM_EINVAL, "null argument");
+    for (int m = 0; m < k; ++m) {
+        if (extent[m] < 1 || extent[m] > TM_MAX_EXTENT) return set_error(TM_EINVAL, "extent[%d]", m);
+        if (halo[m] < 0 || halo[m] > TM_MAX_HALO) return set_error(TM_EINVAL, "halo[%d]", m);
+    }
+    std::vector<std::array<int32_t, 4>> all;
+    all_factorizations(P, k, all);
+    // objective sum_m h_m f_m prod_{j!=m} l_j, exact in 128 bits; enumeration order is
+    // lexicographic, so the first minimum is the lexicographically smallest
+    __int128 best = 0;
+    int64_t bi = -1;
+    for (size_t i = 0; i < all.size(); ++i) {
+        __int128 v = 0;
+        for (int m = 0; m < k; ++m) {
+            __int128 term = (__int128)halo[m] * all[i][m];
+            for (int j = 0; j < k; ++j)
+                if (j != m && __builtin_mul_overflow(term, (__int128)extent[j], &term))
+                    return set_error(TM_EOVERFLOW, "objective overflows 128 bits");
+            if (__builtin_add_overflow(v, term, &v)) return set_error(TM_EOVERFLOW, "objective overflows 128 bits");
+        }
+        if (bi < 0 || v < best) {
+            best = v;
+            bi = (int64_t)i;
+        }
+    }
+    for (int m = 0; m < k; ++m) out_f[m] = all[bi][m];
+    return TM_OK;
+}
+
+int tm_greedy_grid(int64_t P, int32_t k, int32_t* out_f) {
+    int rc = check_pk(P, k);
+    if (rc != TM_OK) return rc;
+    if (!out_f) return set_error(TM_EINVAL, "null argument");
+    std::vector<std::pair<int64_t, int>> pe;
+    factorize(P, pe);
+    int64_t f[4] = {1, 1, 1, 1};
+    for (auto& [p, a] : pe)
+        for (int e = 0; e < a; ++e) {
+            int j = 0;
+            for (int m = 1; m < k; ++m)
+                if (f[m] < f[j]) j = m;
+            f[j] *= p;
+        }
+    std::sort(f, f + k, [](int64_t x, int64_t y) { return x > y; });
+    for (int m = 0; m < k; ++m) out_f[m] = (int32_t)f[m];
+    return TM_OK;
+}
+
+int tm_workload_greedy(int64_t P, int32_t k, const int64_t* extent, int32_t* out_f) {
+    int rc = check_pk(P, k);
+    if (rc != TM_OK) return rc;
+    if (!extent || !out_f) return set_error(TM_EINVAL, "null argument");
+    for (int m = 0; m < k; ++m)
+        if (extent[m] < 1 || extent[m] > TM_MAX_EXTENT) return set_error(TM_EINVAL, "extent[%d]", m);
+    std::vector<std::pair<int64_t, int>> pe;
+    factorize(P, pe);
+    int64_t f[4] = {1, 1, 1, 1};
+    // w_m = l_m / f_m as exact fractions; spread = max w - min w
+    auto less = [](__int128 an, __int128 ad, __int128 bn, __int128 bd) { return an * bd < bn * ad; };
+    for (auto& [p, a] : pe)
+        for (int e = 0; e < a; ++e) {
+            int bj = -1;
+            __int128 bn = 0, bd = 1;
+            for (int j = 0; j < k; ++j) {
+                int64_t g[4];
+                for (int m = 0; m < k; ++m) g[m] = f[m];
+                g[j] *= p;
+                int hi = 0, lo = 0;
+                for (int m = 1; m < k; ++m) {
+                    if (less(extent[hi], g[hi], extent[m], g[m])) hi = m;
+                    if (less(extent[m], g[m], extent[lo], g[lo])) lo = m;
+                }
+                const __int128 dn = (__int128)extent[hi] * g[lo] - (__int128)extent[lo] * g[hi];
+                const __int128 dd = (__int128)g[hi] * g[lo];
+                if (bj < 0 || less(dn, dd, bn, bd)) {
+                    bj = j;
+                    bn = dn;
+                    bd = dd;
+                }
+            }
+            f[bj] *= p;
+        }
+    for (int m = 0; m < k; ++m) out_f[m] = (int32_t)f[m];
+    return TM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// tm_internal.h -- structures shared by the host side and the kernels of libtaskmap.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/taskmap.h"
+
+namespace tmk {
+
+// Compiled candidate as the kernels read it.  The host fills in the shapes of the
+// processor space before every transformation (validation computes them anyway);
+// the table-build kernel derives everything per coordinate from these.
+struct DevCand {
+    int32_t lrank, nops, nodes, gpus;
+    int32_t gbits, frank, vol, words;   // gpu bits of the owner key; final rank and volume; table words
+    int64_t extent[TM_MAX_LRANK];
+    int64_t npoints;
+    int64_t arena_off;                  // word offset of this candidate's tables
+    int64_t item_first;                 // first work item of this candidate
+    int64_t rows;                       // points / extent[lrank-1]
+    int32_t rows_per_item, L;           // rows per work item; row length = last extent
+    int32_t coord_off[TM_MAX_LRANK];    // table offsets of the per-dim coordinate tables
+    int32_t fshape[TM_MAX_MRANK], fstride[TM_MAX_MRANK];
+    int8_t proj_src[TM_MAX_MRANK], proj_mode[TM_MAX_MRANK];
+    int32_t rank[TM_MAX_OPS];                    // rank before op t
+    int32_t shape[TM_MAX_OPS][TM_MAX_MRANK];     // shape before op t
+    int32_t op_kind[TM_MAX_OPS], op_a[TM_MAX_OPS], op_b[TM_MAX_OPS], op_nf[TM_MAX_OPS];
+    int32_t op_f[TM_MAX_OPS][TM_MAX_LRANK];
+};
+
+// Batch header: one per plan, in device memory, read by every kernel of a replay.
+struct DevHeader {
+    int64_t n;            // candidates
+    int64_t total_items;  // work items over all candidates
+    int32_t halo[TM_MAX_LRANK];
+    int32_t elem_bytes, lrank;
+    int32_t max_words, pad;
+};
+
+// Host-side result of validation.
+struct Shapes {
+    int32_t rank[TM_MAX_OPS + 1];
+    int64_t size[TM_MAX_OPS + 1][TM_MAX_MRANK];
+};
+
+// Word layout of an entry of a per-dim coordinate table: bits 0..30 hold the
+// contribution of that coordinate to the linear final-space index, bit 31 is set
+// when some star neighbour along that dim (within the halo) has a different
+// contribution.
+constexpr uint32_t kFlagBit = 0x80000000u;
+constexpr uint32_t kValMask = 0x7fffffffu;
+// Largest table (final-space volume + sum of extents) that the counting and map
+// kernels stage in LDS.
+constexpr int32_t kMaxLdsWords = 32768;
+constexpr int kMaxHalo = 4;
+
+int set_error(int code, const char* fmt, ...);
+int validate_shapes(const tm_candidate* c, Shapes* sh);
+int fill_devcand(const tm_candidate* c, const Shapes& sh, DevCand* d);
+
+// Kernel launchers (tm_kernels.hip).  All enqueue on `s` and return hipError_t.
+hipError_t launch_build_tables(const DevHeader* hdr, const DevCand* cands, int64_t n, int32_t* arena,
+                               int32_t mode_halo, hipStream_t s);
+hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_cost* out, int64_t n,
+                        hipStream_t s);
+hipError_t launch_count(int K, int H, const DevHeader* hdr, const DevCand* cands, const int32_t* arena,
+                        unsigned long long* counter, tm_stencil_cost* out, int grid, int lds_words,
+                        hipStream_t s);
+hipError_t launch_finalize_select(const DevHeader* hdr, tm_stencil_cost* out, int64_t* best,
+                                  hipStream_t s);
+hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* seg, int64_t nseg,
+                                  int64_t* best, hipStream_t s);
+hipError_t launch_map(const DevCand* cands, int64_t n, const int32_t* arena, const int64_t* d_index,
+                      int64_t index, int32_t* out, int grid, int lds_words, hipStream_t s);
+hipError_t launch_chain_table(const DevCand* cand, const int32_t* arena, int32_t* out, hipStream_t s);
+hipError_t launch_matmul(const DevCand* cands, int64_t n, const int32_t* arena, int words_max,
+                         int pmax, const int64_t* proc_off, unsigned long long* per_proc,
+                         int64_t total_blocks, const int64_t* block_first, hipStream_t s);
+hipError_t launch_matmul_finalize(const DevCand* cands, int64_t n, const int64_t* proc_off,
+                                  const unsigned long long* per_proc, int64_t tile_bytes,
+                                  tm_matmul_cost* out, int64_t* out_per_proc, hipStream_t s);
+int count_kernel_occupancy(int K, int H, int lds_words, int* blocks_per_cu);
+
+}  // namespace tmk

@@ -1,0 +1,834 @@
+// tm_kernels.hip -- gfx950 kernels of libtaskmap.
+//
+// Data layout.  For each candidate the table-build kernel writes, into a device
+// arena, (1) the chain table T[v]: the owner of every coordinate v of the final
+// processor space (C order), found by inverting the transformation chain last to
+// first (Fig. 6 formulas, decompose as composed splits per Sec. 4.2, balance_split
+// as the fold described in taskmap.h), stored as the key (node << gbits) | gpu so
+// that owner identity and node are both one integer operation away; and (2) one
+// coordinate table per launch dim d: C_d[x] = sum over final dims j projected
+// from d of a_j(x) * stride_j (block: floor(x*s_j/l_d), cyclic: x mod s_j), with
+// bit 31 set when a star neighbour within the halo along d has a different value.
+// The linear final coordinate of point q is then v(q) = sum_d C_d[q_d] and its
+// owner is T[v(q)]: the chain is evaluated once per coordinate, not per point.
+//
+// Kernels: table build; processor map (streaming int32 writes); stencil counting
+// (persistent, work queue over (candidate, row block) items, tables in LDS); bytes
+// and selection; matmul tile bitmaps.  All arithmetic is exact integer.
+#include <hip/hip_runtime.h>
+
+#include "tm_internal.h"
+
+namespace tmk {
+
+// ------------------------------------------------------------------ helpers
+
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int32_t uniform32(int32_t x) {
+    return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Copy a DevCand into LDS with all threads of the block (it is read many times).
+__device__ __forceinline__ void stage_cand(DevCand* dst, const DevCand* src) {
+    const int32_t* s = reinterpret_cast<const int32_t*>(src);
+    int32_t* d = reinterpret_cast<int32_t*>(dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(DevCand) / 4); i += blockDim.x) d[i] = s[i];
+}
+
+// Owner key of final-space coordinate v: decode v (C order), then undo the ops.
+__device__ int32_t owner_key(const DevCand& c, int32_t v) {
+    int32_t a[TM_MAX_MRANK], b[TM_MAX_MRANK];
+    for (int j = c.frank - 1; j >= 0; --j) {
+        const int32_t s = c.fshape[j];
+        a[j] = v % s;
+        v /= s;
+    }
+    for (int t = c.nops - 1; t >= 0; --t) {
+        const int r = c.rank[t];
+        const int32_t* s = c.shape[t];
+        const int pa = c.op_a[t], pb = c.op_b[t];
+        switch (c.op_kind[t]) {
+            case TM_SPLIT:
+                for (int u = 0; u < pa; ++u) b[u] = a[u];
+                b[pa] = a[pa] + a[pa + 1] * pb;
+                for (int u = pa + 1; u < r; ++u) b[u] = a[u + 1];
+                break;
+            case TM_MERGE:
+                for (int u = 0; u < r; ++u) {
+                    if (u < pa || (u > pa && u < pb)) b[u] = a[u];
+                    else if (u == pa) b[u] = a[pa] % s[pa];
+                    else if (u == pb) b[u] = a[pa] / s[pa];
+                    else b[u] = a[u - 1];
+                }
+                break;
+            case TM_SWAP:
+                for (int u = 0; u < r; ++u) b[u] = a[u];
+                b[pa] = a[pb];
+                b[pb] = a[pa];
+                break;
+            case TM_BALANCE_SPLIT: {
+                const int64_t si = s[pa];
+                const int64_t cc = (si + pb - 1) / pb;
+                const int64_t vv = (int64_t)a[pa] + (int64_t)a[pa + 1] * pb;
+                for (int u = 0; u < pa; ++u) b[u] = a[u];
+                b[pa] = (int32_t)((vv * si) / ((int64_t)pb * cc));
+                for (int u = pa + 1; u < r; ++u) b[u] = a[u + 1];
+                break;
+            }
+            default: {  // TM_DECOMPOSE
+                const int k = c.op_nf[t];
+                int32_t acc = 0;
+                for (int m = k - 1; m >= 0; --m) acc = acc * c.op_f[t][m] + a[pa + m];
+                for (int u = 0; u < pa; ++u) b[u] = a[u];
+                b[pa] = acc;
+                for (int u = pa + 1; u < r; ++u) b[u] = a[u + k - 1];
+                break;
+            }
+        }
+        for (int u = 0; u < r; ++u) a[u] = b[u];
+    }
+    return (a[0] << c.gbits) | a[1];
+}
+
+// Contribution of coordinate x of launch dim d to the linear final index.
+__device__ int32_t coord_value(const DevCand& c, int d, int64_t x) {
+    int32_t v = 0;
+    for (int j = 0; j < c.frank; ++j) {
+        if (c.proj_src[j] != d) continue;
+        const int64_t s = c.fshape[j];
+        const int64_t a = c.proj_mode[j] == TM_BLOCK ? (x * s) / c.extent[d] : x % s;
+        v += (int32_t)a * c.fstride[j];
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------ table build
+
+// One workgroup per candidate (grid-stride over candidates).
+__global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restrict__ hdr,
+                                                      const DevCand* __restrict__ cands,
+                                                      int32_t* __restrict__ arena, int use_halo) {
+    __shared__ DevCand sc;
+    const int64_t n = hdr->n;
+    for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
+        __syncthreads();
+        stage_cand(&sc, &cands[ci]);
+        __syncthreads();
+        int32_t* base = arena + sc.arena_off;
+        for (int32_t v = threadIdx.x; v < sc.vol; v += blockDim.x) base[v] = owner_key(sc, v);
+        for (int d = 0; d < sc.lrank; ++d) {
+            const int64_t l = sc.extent[d];
+            const int h = use_halo ? hdr->halo[d] : 0;
+            int32_t* ct = base + sc.coord_off[d];
+            for (int64_t x = threadIdx.x; x < l; x += blockDim.x) {
+                const int32_t val = coord_value(sc, d, x);
+                bool flag = false;
+                for (int s = 1; s <= h && !flag; ++s) {
+                    if (x - s >= 0 && coord_value(sc, d, x - s) != val) flag = true;
+                    if (x + s < l && coord_value(sc, d, x + s) != val) flag = true;
+                }
+                ct[x] = (int32_t)((uint32_t)val | (flag ? kFlagBit : 0u));
+            }
+        }
+    }
+}
+
+hipError_t launch_build_tables(const DevHeader* hdr, const DevCand* cands, int64_t n, int32_t* arena,
+                               int32_t use_halo, hipStream_t s) {
+    const int64_t grid = n < 65536 ? (n > 0 ? n : 1) : 65536;
+    hipLaunchKernelGGL(k_build_tables, dim3((unsigned)grid), dim3(256), 0, s, hdr, cands, arena, use_halo);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ reset
+
+__global__ void k_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_cost* out, int64_t cap) {
+    const int64_t n = hdr->n < cap ? hdr->n : cap;
+    int64_t* o = reinterpret_cast<int64_t*>(out);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 4 * n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        o[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0ull;
+}
+
+hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_cost* out, int64_t n,
+                        hipStream_t s) {
+    int64_t grid = (4 * n + 255) / 256;
+    if (grid < 1) grid = 1;
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(k_reset, dim3((unsigned)grid), dim3(256), 0, s, hdr, counter, out, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ stencil counting
+//
+// A work item is a block of consecutive rows (all launch dims but the last fixed)
+// of one candidate.  A workgroup takes items from a global atomic counter (the
+// next one is requested while the current one runs), stages the candidate's tables
+// in LDS when the candidate changes, and gives each wave whole rows.  For a row,
+// the outer coordinates fix a base index and tell whether the row lies within a
+// halo of a block boundary of an outer dim (row flag).
+//   - Rows without the row flag: a cell can only have foreign neighbours along the
+//     last dim, which is the case exactly when its last-dim table entry carries the
+//     flag.  Each cell is tested; flagged cells are compacted into a per-wave LDS
+//     queue (ballot + prefix count) and evaluated 64 at a time with all lanes busy.
+//   - Rows with the row flag: the distinct non-zero index offsets to the outer
+//     neighbours are the same for every cell of the row; every cell looks up its
+//     owner and those neighbours' owners, plus its last-dim neighbours if flagged.
+// Per cell the owners of the candidate neighbours are de-duplicated exactly and
+// counted (and those on another node); lanes sum in registers, waves reduce, and
+// one 64-bit atomic per wave and item adds to the candidate's totals.
+
+template <int K, int H>
+struct CountCfg {
+    static constexpr int NO = K > 1 ? 2 * H * (K - 1) : 1;  // outer neighbour slots
+    static constexpr int NL = 2 * H;                         // last-dim neighbour slots
+};
+
+constexpr int kQueueCap = 128;
+
+// De-duplicate a static list of owner keys against the cell owner o; every slot
+// whose neighbour is absent holds o itself.
+template <int N>
+__device__ __forceinline__ void count_distinct(const int32_t (&c)[N], int32_t o, int gbits, int& cnt,
+                                               int& icnt) {
+    const int32_t onode = o >> gbits;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        bool fresh = c[j] != o;
+#pragma unroll
+        for (int i = 0; i < j; ++i) fresh = fresh && (c[i] != c[j]);
+        cnt += fresh ? 1 : 0;
+        icnt += (fresh && ((c[j] >> gbits) != onode)) ? 1 : 0;
+    }
+}
+
+// Owners of the last-dim neighbours of cell (v, x) into c[0..NL).
+template <int H>
+__device__ __forceinline__ void last_dim_owners(const int32_t* __restrict__ T, const int32_t* __restrict__ CL,
+                                                int32_t v, int32_t x, int32_t ev, int L, int h, int32_t o,
+                                                int32_t (&c)[2 * H]) {
+#pragma unroll
+    for (int s = 1; s <= H; ++s) {
+#pragma unroll
+        for (int dir = 0; dir < 2; ++dir) {
+            const int xx = dir ? x + s : x - s;
+            int32_t own = o;
+            if (s <= h && xx >= 0 && xx < L) {
+                const int32_t dv = (CL[xx] & (int32_t)kValMask) - ev;
+                if (dv != 0) own = T[v + dv];
+            }
+            c[2 * (s - 1) + dir] = own;
+        }
+    }
+}
+
+template <int K, int H>
+__global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr,
+                                               const DevCand* __restrict__ cands,
+                                               const int32_t* __restrict__ arena,
+                                               unsigned long long* __restrict__ counter,
+                                               tm_stencil_cost* __restrict__ out) {
+    using Cfg = CountCfg<K, H>;
+    extern __shared__ int32_t lds[];
+    __shared__ long long s_item;
+    __shared__ int32_t s_qv[4][kQueueCap], s_qx[4][kQueueCap];
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t total = uniform64(hdr->total_items);
+    const int64_t n = uniform64(hdr->n);
+    int hal[K];
+#pragma unroll
+    for (int d = 0; d < K; ++d) hal[d] = uniform32(hdr->halo[d]);
+
+    int64_t cur = -1;
+    int32_t L = 0, gbits = 0, rpi = 1;
+    int64_t rows = 0, ifirst = 0;
+    int32_t off[K], ext[K];
+#pragma unroll
+    for (int d = 0; d < K; ++d) off[d] = ext[d] = 0;
+
+    int32_t* qv = s_qv[wid];
+    int32_t* qx = s_qx[wid];
+
+    unsigned long long next = 0;
+    if (tid == 0) next = atomicAdd(counter, 1ull);
+    for (;;) {
+        if (tid == 0) s_item = (long long)next;
+        __syncthreads();
+        const int64_t item = uniform64(s_item);
+        __syncthreads();
+        if (item >= total) break;
+        if (tid == 0) next = atomicAdd(counter, 1ull);
+
+        // candidate owning this item (binary search over item_first)
+        int64_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (cands[mid].item_first <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        lo = uniform64(lo);
+        if (lo != cur) {
+            const DevCand* c = &cands[lo];
+            const int32_t words = uniform32(c->words);
+            const int32_t* src = arena + c->arena_off;
+            for (int i = tid; i < words; i += 256) lds[i] = src[i];
+            L = uniform32(c->L);
+            gbits = uniform32(c->gbits);
+            rpi = uniform32(c->rows_per_item);
+            rows = uniform64(c->rows);
+            ifirst = uniform64(c->item_first);
+#pragma unroll
+            for (int d = 0; d < K; ++d) {
+                off[d] = uniform32(c->coord_off[d]);
+                ext[d] = uniform32((int32_t)c->extent[d]);
+            }
+            cur = lo;
+            __syncthreads();
+        }
+        const int32_t* T = lds;
+        const int32_t* CL = lds + off[K - 1];
+        const int hL = hal[K - 1];
+
+        const int64_t r0 = (item - ifirst) * rpi;
+        const int64_t r1 = r0 + rpi < rows ? r0 + rpi : rows;
+        int cnt = 0, icnt = 0;
+        int qn = 0;  // wave-uniform queue length
+
+        for (int64_t r = r0 + wid; r < r1; r += 4) {
+            // outer coordinates of row r
+            int32_t q[K > 1 ? K - 1 : 1];
+            {
+                uint32_t rr = (uint32_t)r;
+#pragma unroll
+                for (int d = K - 2; d >= 0; --d) {
+                    q[d] = (int32_t)(rr % (uint32_t)ext[d]);
+                    rr /= (uint32_t)ext[d];
+                }
+            }
+            int32_t base = 0;
+            bool rflag = false;
+            int32_t oe[K > 1 ? K - 1 : 1];
+#pragma unroll
+            for (int d = 0; d < K - 1; ++d) {
+                oe[d] = T[off[d] + q[d]];
+                base += oe[d] & (int32_t)kValMask;
+                rflag = rflag || (oe[d] < 0);
+            }
+            if (!rflag) {
+                // ---- sparse path: only flagged last-dim cells can see another owner
+                for (int xb = 0; xb < L; xb += 64) {
+                    const int x = xb + lane;
+                    const int32_t e = x < L ? CL[x] : 0;
+                    const bool hit = e < 0;
+                    const uint64_t m = __ballot(hit);
+                    if (m == 0ull) continue;
+                    const int pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    if (hit) {
+                        qv[pos] = base + (e & (int32_t)kValMask);
+                        qx[pos] = x;
+                    }
+                    qn += __popcll(m);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (qn >= 64) {
+                        const int32_t v = qv[lane], xq = qx[lane];
+                        const int32_t o = T[v];
+                        int32_t cand[Cfg::NL];
+                        last_dim_owners<H>(T, CL, v, xq, CL[xq] & (int32_t)kValMask, L, hL, o, cand);
+                        count_distinct<Cfg::NL>(cand, o, gbits, cnt, icnt);
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        if (lane < qn - 64) {
+                            qv[lane] = qv[lane + 64];
+                            qx[lane] = qx[lane + 64];
+                        }
+                        qn -= 64;
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
+                }
+            } else {
+                // ---- dense path: distinct non-zero offsets to the outer neighbours
+                int32_t od[Cfg::NO];
+                bool ok[Cfg::NO];
+#pragma unroll
+                for (int j = 0; j < Cfg::NO; ++j) {
+                    od[j] = 0;
+                    ok[j] = false;
+                }
+#pragma unroll
+                for (int d = 0; d < K - 1; ++d) {
+#pragma unroll
+                    for (int s = 1; s <= H; ++s) {
+#pragma unroll
+                        for (int dir = 0; dir < 2; ++dir) {
+                            const int slot = (d * H + (s - 1)) * 2 + dir;
+                            const int xx = dir ? q[d] + s : q[d] - s;
+                            int32_t dv = 0;
+                            if (oe[d] < 0 && s <= hal[d] && xx >= 0 && xx < ext[d])
+                                dv = (T[off[d] + xx] & (int32_t)kValMask) - (oe[d] & (int32_t)kValMask);
+                            od[slot] = dv;
+                            bool fresh = dv != 0;
+#pragma unroll
+                            for (int i = 0; i < slot; ++i) fresh = fresh && (od[i] != dv);
+                            ok[slot] = fresh;
+                        }
+                    }
+                }
+                for (int xb = 0; xb < L; xb += 64) {
+                    const int x = xb + lane;
+                    if (x >= L) continue;
+                    const int32_t e = CL[x];
+                    const int32_t ev = e & (int32_t)kValMask;
+                    const int32_t v = base + ev;
+                    const int32_t o = T[v];
+                    if (e >= 0) {
+                        int32_t cand[Cfg::NO];
+#pragma unroll
+                        for (int j = 0; j < Cfg::NO; ++j) cand[j] = ok[j] ? T[v + od[j]] : o;
+                        count_distinct<Cfg::NO>(cand, o, gbits, cnt, icnt);
+                    } else {
+                        int32_t cand[Cfg::NO + Cfg::NL];
+#pragma unroll
+                        for (int j = 0; j < Cfg::NO; ++j) cand[j] = ok[j] ? T[v + od[j]] : o;
+                        int32_t cl[Cfg::NL];
+                        last_dim_owners<H>(T, CL, v, x, ev, L, hL, o, cl);
+#pragma unroll
+                        for (int j = 0; j < Cfg::NL; ++j) cand[Cfg::NO + j] = cl[j];
+                        count_distinct<Cfg::NO + Cfg::NL>(cand, o, gbits, cnt, icnt);
+                    }
+                }
+            }
+        }
+        // drain the queue
+        if (qn > 0) {
+            if (lane < qn) {
+                const int32_t v = qv[lane], xq = qx[lane];
+                const int32_t o = T[v];
+                int32_t cand[Cfg::NL];
+                last_dim_owners<H>(T, CL, v, xq, CL[xq] & (int32_t)kValMask, L, hL, o, cand);
+                count_distinct<Cfg::NL>(cand, o, gbits, cnt, icnt);
+            }
+            qn = 0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        cnt = wave_sum(cnt);
+        icnt = wave_sum(icnt);
+        if (lane == 0 && (cnt | icnt)) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].ghost_cells), (unsigned long long)cnt);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].inter_cells), (unsigned long long)icnt);
+        }
+    }
+}
+
+template <int K, int H>
+static void* count_fn() {
+    return reinterpret_cast<void*>(&k_count<K, H>);
+}
+
+static void* pick_count(int K, int H) {
+#define TM_PICK(k)                              \
+    if (K == k) {                               \
+        if (H == 1) return count_fn<k, 1>();    \
+        if (H == 2) return count_fn<k, 2>();    \
+        if (H == 3) return count_fn<k, 3>();    \
+        if (H == 4) return count_fn<k, 4>();    \
+    }
+    TM_PICK(1) TM_PICK(2) TM_PICK(3) TM_PICK(4)
+#undef TM_PICK
+    return nullptr;
+}
+
+int count_kernel_occupancy(int K, int H, int lds_words, int* blocks_per_cu) {
+    void* fn = pick_count(K, H);
+    if (!fn) return -1;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, (size_t)lds_words * 4) != hipSuccess)
+        return -1;
+    *blocks_per_cu = nb;
+    return 0;
+}
+
+hipError_t launch_count(int K, int H, const DevHeader* hdr, const DevCand* cands, const int32_t* arena,
+                        unsigned long long* counter, tm_stencil_cost* out, int grid, int lds_words,
+                        hipStream_t s) {
+    void* fn = pick_count(K, H);
+    if (!fn) return hipErrorInvalidValue;
+    void* args[] = {(void*)&hdr, (void*)&cands, (void*)&arena, (void*)&counter, (void*)&out};
+    return hipLaunchKernel(fn, dim3(grid), dim3(256), args, (size_t)lds_words * 4, s);
+}
+
+// ------------------------------------------------------------------ bytes + selection
+
+// One workgroup: bytes from cell counts, then the minimum of (bytes, inter_bytes, index).
+__global__ __launch_bounds__(1024) void k_finalize_select(const DevHeader* __restrict__ hdr,
+                                                          tm_stencil_cost* __restrict__ out,
+                                                          int64_t* __restrict__ best) {
+    __shared__ int64_t sb[1024], si[1024], sx[1024];
+    const int64_t n = hdr->n;
+    const int64_t eb = hdr->elem_bytes;
+    int64_t kb = INT64_MAX, ki = INT64_MAX, kx = INT64_MAX;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        tm_stencil_cost c = out[i];
+        c.bytes = c.ghost_cells * eb;
+        c.inter_bytes = c.inter_cells * eb;
+        out[i] = c;
+        if (c.bytes < kb || (c.bytes == kb && (c.inter_bytes < ki || (c.inter_bytes == ki && i < kx)))) {
+            kb = c.bytes;
+            ki = c.inter_bytes;
+            kx = i;
+        }
+    }
+    sb[threadIdx.x] = kb;
+    si[threadIdx.x] = ki;
+    sx[threadIdx.x] = kx;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const int o = threadIdx.x + w;
+            if (sb[o] < sb[threadIdx.x] ||
+                (sb[o] == sb[threadIdx.x] &&
+                 (si[o] < si[threadIdx.x] || (si[o] == si[threadIdx.x] && sx[o] < sx[threadIdx.x])))) {
+                sb[threadIdx.x] = sb[o];
+                si[threadIdx.x] = si[o];
+                sx[threadIdx.x] = sx[o];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && best) *best = n > 0 ? sx[0] : -1;
+}
+
+hipError_t launch_finalize_select(const DevHeader* hdr, tm_stencil_cost* out, int64_t* best, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_select, dim3(1), dim3(1024), 0, s, hdr, out, best);
+    return hipGetLastError();
+}
+
+// One workgroup per segment.
+__global__ __launch_bounds__(256) void k_select_segments(const tm_stencil_cost* __restrict__ costs,
+                                                         const int64_t* __restrict__ seg,
+                                                         int64_t* __restrict__ best) {
+    __shared__ int64_t sb[256], si[256], sx[256];
+    const int64_t a = seg[blockIdx.x], e = seg[blockIdx.x + 1];
+    int64_t kb = INT64_MAX, ki = INT64_MAX, kx = INT64_MAX;
+    for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
+        const int64_t b = costs[i].bytes, ib = costs[i].inter_bytes;
+        if (b < kb || (b == kb && (ib < ki || (ib == ki && i < kx)))) {
+            kb = b;
+            ki = ib;
+            kx = i;
+        }
+    }
+    sb[threadIdx.x] = kb;
+    si[threadIdx.x] = ki;
+    sx[threadIdx.x] = kx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const int o = threadIdx.x + w;
+            if (sb[o] < sb[threadIdx.x] ||
+                (sb[o] == sb[threadIdx.x] &&
+                 (si[o] < si[threadIdx.x] || (si[o] == si[threadIdx.x] && sx[o] < sx[threadIdx.x])))) {
+                sb[threadIdx.x] = sb[o];
+                si[threadIdx.x] = si[o];
+                sx[threadIdx.x] = sx[o];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) best[blockIdx.x] = e > a ? sx[0] - a : -1;
+}
+
+hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* seg, int64_t nseg,
+                                  int64_t* best, hipStream_t s) {
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select_segments, dim3((unsigned)nseg), dim3(256), 0, s, costs, seg, best);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ processor map
+//
+// Rows of the launch domain are spread over the workgroups; each wave writes whole
+// rows.  A lane produces four consecutive points (one 16-byte non-temporal store)
+// when the row start is 16-byte aligned, else single points.  The candidate's
+// tables sit in LDS.
+
+__global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, int64_t n,
+                                             const int32_t* __restrict__ arena,
+                                             const int64_t* __restrict__ d_index, int64_t index,
+                                             int32_t* __restrict__ out) {
+    extern __shared__ int32_t lds[];
+    __shared__ DevCand sc;
+    const int64_t ci = d_index ? uniform64(*d_index) : index;
+    if (ci < 0 || ci >= n) return;  // no candidate selected (empty batch)
+    stage_cand(&sc, &cands[ci]);
+    __syncthreads();
+    const int32_t words = sc.words;
+    const int32_t* src = arena + sc.arena_off;
+    for (int i = threadIdx.x; i < words; i += blockDim.x) lds[i] = src[i];
+    __syncthreads();
+
+    const int K = sc.lrank;
+    const int32_t L = sc.L;
+    const int64_t rows = sc.rows;
+    const int32_t gb = sc.gbits, g = sc.gpus, gmask = (1 << sc.gbits) - 1;
+    const int32_t* T = lds;
+    const int32_t* CL = lds + sc.coord_off[K - 1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const bool vec = (L & 3) == 0 && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
+    for (int64_t r = (int64_t)blockIdx.x * 4 + wid; r < rows; r += nw) {
+        uint32_t rr = (uint32_t)r;
+        int32_t base = 0;
+        for (int d = K - 2; d >= 0; --d) {
+            const uint32_t e = (uint32_t)sc.extent[d];
+            base += lds[sc.coord_off[d] + (int32_t)(rr % e)] & (int32_t)kValMask;
+            rr /= e;
+        }
+        int32_t* row = out + r * (int64_t)L;
+        if (vec) {
+            for (int x = lane * 4; x < L; x += 256) {
+                i32x4 key;
+                key.x = T[base + (CL[x] & (int32_t)kValMask)];
+                key.y = T[base + (CL[x + 1] & (int32_t)kValMask)];
+                key.z = T[base + (CL[x + 2] & (int32_t)kValMask)];
+                key.w = T[base + (CL[x + 3] & (int32_t)kValMask)];
+                const i32x4 p = (key >> gb) * g + (key & gmask);
+                __builtin_nontemporal_store(p, reinterpret_cast<i32x4*>(row + x));
+            }
+        } else {
+            for (int x = lane; x < L; x += 64) {
+                const int32_t key = T[base + (CL[x] & (int32_t)kValMask)];
+                __builtin_nontemporal_store((key >> gb) * g + (key & gmask), row + x);
+            }
+        }
+    }
+}
+
+hipError_t launch_map(const DevCand* cands, int64_t n, const int32_t* arena, const int64_t* d_index,
+                      int64_t index, int32_t* out, int grid, int lds_words, hipStream_t s) {
+    hipLaunchKernelGGL(k_map, dim3(grid), dim3(256), (size_t)lds_words * 4, s, cands, n, arena, d_index, index,
+                       out);
+    return hipGetLastError();
+}
+
+// Chain table as processor ids (for inspection and tests).
+__global__ void k_chain_table(const DevCand* __restrict__ cand, const int32_t* __restrict__ arena,
+                              int32_t* __restrict__ out) {
+    const DevCand& c = *cand;
+    const int32_t gmask = (1 << c.gbits) - 1;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < c.vol; v += gridDim.x * blockDim.x) {
+        const int32_t key = arena[c.arena_off + v];
+        out[v] = (key >> c.gbits) * c.gpus + (key & gmask);
+    }
+}
+
+hipError_t launch_chain_table(const DevCand* cand, const int32_t* arena, int32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_chain_table, dim3(256), dim3(256), 0, s, cand, arena, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ matmul tiles
+//
+// Work block = (candidate, matrix m in {A,B,C}, 16 x 256 consecutive tiles).  A thread
+// owns one tile and walks the reduction index (j for A[i,k], i for B[k,j], k for
+// C[i,j]), OR-ing the owner's bit into a processor bitmap of W 64-bit words held in
+// registers.  Per-processor counts come from wave ballots over the bitmaps; lane p
+// of the wave keeps processor (64*w + p)'s count, and one atomic per wave and word
+// adds it to the global per-processor totals.
+
+constexpr int kMatmulChunks = 16;  // a work block covers 16 x 256 tiles of one matrix
+
+template <int W>
+__global__ __launch_bounds__(256) void k_matmul(const DevCand* __restrict__ cands, int64_t n,
+                                                const int32_t* __restrict__ arena,
+                                                const int64_t* __restrict__ proc_off,
+                                                unsigned long long* __restrict__ per_proc,
+                                                const int64_t* __restrict__ block_first, int64_t total_blocks) {
+    extern __shared__ int32_t lds[];
+    __shared__ DevCand sc;
+    const int lane = threadIdx.x & 63;
+    int64_t cur = -1;
+    for (int64_t blk = blockIdx.x; blk < total_blocks; blk += gridDim.x) {
+        int64_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (block_first[mid] <= blk) lo = mid;
+            else hi = mid - 1;
+        }
+        if (lo != cur) {
+            __syncthreads();
+            stage_cand(&sc, &cands[lo]);
+            __syncthreads();
+            const int32_t* src = arena + sc.arena_off;
+            for (int i = threadIdx.x; i < sc.words; i += blockDim.x) lds[i] = src[i];
+            __syncthreads();
+            cur = lo;
+        }
+        const int64_t Ti = sc.extent[0], Tj = sc.extent[1], Tk = sc.extent[2];
+        const int64_t nA = Ti * Tk, nB = Tk * Tj, nC = Ti * Tj;
+        const int64_t per = 256 * kMatmulChunks;
+        const int64_t bA = (nA + per - 1) / per, bB = (nB + per - 1) / per;
+        int64_t local = blk - block_first[lo];
+        int m;
+        if (local < bA) m = 0;
+        else if (local < bA + bB) { m = 1; local -= bA; }
+        else { m = 2; local -= bA + bB; }
+        const int64_t ntile = m == 0 ? nA : (m == 1 ? nB : nC);
+        const int32_t* T = lds;
+        const int32_t* C0 = lds + sc.coord_off[0];
+        const int32_t* C1 = lds + sc.coord_off[1];
+        const int32_t* C2 = lds + sc.coord_off[2];
+        const int32_t gb = sc.gbits, g = sc.gpus, gmask = (1 << sc.gbits) - 1;
+        uint32_t mine[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) mine[w] = 0;
+        for (int ch = 0; ch < kMatmulChunks; ++ch) {
+            const int64_t tile = (local * kMatmulChunks + ch) * 256 + threadIdx.x;
+            if (tile - threadIdx.x >= ntile) break;  // uniform: chunk past the end
+            uint64_t bm[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) bm[w] = 0;
+            if (tile < ntile) {
+                int32_t fixed;
+                const int32_t* red;
+                int64_t nred;
+                if (m == 0) {  // A[i,k]: tile = i*Tk + k, reduce over j
+                    const int64_t i = tile / Tk, k = tile % Tk;
+                    fixed = (C0[i] & (int32_t)kValMask) + (C2[k] & (int32_t)kValMask);
+                    red = C1;
+                    nred = Tj;
+                } else if (m == 1) {  // B[k,j]: tile = k*Tj + j, reduce over i
+                    const int64_t k = tile / Tj, j = tile % Tj;
+                    fixed = (C2[k] & (int32_t)kValMask) + (C1[j] & (int32_t)kValMask);
+                    red = C0;
+                    nred = Ti;
+                } else {  // C[i,j]: tile = i*Tj + j, reduce over k
+                    const int64_t i = tile / Tj, j = tile % Tj;
+                    fixed = (C0[i] & (int32_t)kValMask) + (C1[j] & (int32_t)kValMask);
+                    red = C2;
+                    nred = Tk;
+                }
+                for (int64_t t = 0; t < nred; ++t) {
+                    const int32_t key = T[fixed + (red[t] & (int32_t)kValMask)];
+                    const int32_t p = (key >> gb) * g + (key & gmask);
+                    const uint64_t bit = 1ull << (p & 63);
+                    if (W == 1) {
+                        bm[0] |= bit;
+                    } else {
+#pragma unroll
+                        for (int w = 0; w < W; ++w) bm[w] |= ((p >> 6) == w) ? bit : 0ull;
+                    }
+                }
+            }
+            // lane b of the wave counts processor 64*w + b
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                for (int b = 0; b < 64; ++b) {
+                    const uint64_t mask = __ballot((bm[w] >> b) & 1ull);
+                    if (lane == b) mine[w] += (uint32_t)__popcll(mask);
+                }
+            }
+        }
+        const int64_t P = (int64_t)sc.nodes * sc.gpus;
+        unsigned long long* dst = per_proc + proc_off[lo] * 3;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const int64_t p = (int64_t)w * 64 + lane;
+            if (mine[w] && p < P) atomicAdd(&dst[p * 3 + m], (unsigned long long)mine[w]);
+        }
+    }
+}
+
+hipError_t launch_matmul(const DevCand* cands, int64_t n, const int32_t* arena, int words_max, int pmax,
+                         const int64_t* proc_off, unsigned long long* per_proc, int64_t total_blocks,
+                         const int64_t* block_first, hipStream_t s) {
+    const int W = (pmax + 63) / 64;
+    int64_t grid = total_blocks < 8192 ? total_blocks : 8192;
+    if (grid < 1) grid = 1;
+    const size_t lds = (size_t)words_max * 4;
+#define TM_MM(w)                                                                                        \
+    if (W <= w) {                                                                                       \
+        hipLaunchKernelGGL(k_matmul<w>, dim3((unsigned)grid), dim3(256), lds, s, cands, n, arena, proc_off, \
+                           per_proc, block_first, total_blocks);                                        \
+        return hipGetLastError();                                                                       \
+    }
+    TM_MM(1) TM_MM(2) TM_MM(4) TM_MM(8) TM_MM(16)
+#undef TM_MM
+    return hipErrorInvalidValue;
+}
+
+// Totals, maxima and bytes per candidate; optional copy of the per-processor counts.
+__global__ __launch_bounds__(256) void k_matmul_finalize(const DevCand* __restrict__ cands,
+                                                         const int64_t* __restrict__ proc_off,
+                                                         const unsigned long long* __restrict__ per_proc,
+                                                         int64_t tile_bytes, tm_matmul_cost* __restrict__ out,
+                                                         int64_t* __restrict__ out_per_proc) {
+    __shared__ unsigned long long st[3][256], sm[3][256];
+    const int64_t c = blockIdx.x;
+    const int64_t P = (int64_t)cands[c].nodes * cands[c].gpus;
+    const unsigned long long* src = per_proc + proc_off[c] * 3;
+    unsigned long long t[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+    for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
+        for (int m = 0; m < 3; ++m) {
+            const unsigned long long v = src[p * 3 + m];
+            t[m] += v;
+            mx[m] = v > mx[m] ? v : mx[m];
+            if (out_per_proc) out_per_proc[(proc_off[c] + p) * 3 + m] = (int64_t)v;
+        }
+    }
+    for (int m = 0; m < 3; ++m) {
+        st[m][threadIdx.x] = t[m];
+        sm[m][threadIdx.x] = mx[m];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int m = 0; m < 3; ++m) {
+                st[m][threadIdx.x] += st[m][threadIdx.x + w];
+                sm[m][threadIdx.x] = sm[m][threadIdx.x + w] > sm[m][threadIdx.x] ? sm[m][threadIdx.x + w]
+                                                                                  : sm[m][threadIdx.x];
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        tm_matmul_cost r;
+        for (int m = 0; m < 3; ++m) {
+            r.tiles[m] = (int64_t)st[m][0];
+            r.max_tiles[m] = (int64_t)sm[m][0];
+        }
+        r.bytes = (r.tiles[0] + r.tiles[1] + r.tiles[2]) * tile_bytes;
+        out[c] = r;
+    }
+}
+
+hipError_t launch_matmul_finalize(const DevCand* cands, int64_t n, const int64_t* proc_off,
+                                  const unsigned long long* per_proc, int64_t tile_bytes, tm_matmul_cost* out,
+                                  int64_t* out_per_proc, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_matmul_finalize, dim3((unsigned)n), dim3(256), 0, s, cands, proc_off, per_proc,
+                       tile_bytes, out, out_per_proc);
+    return hipGetLastError();
+}
+
+}  // namespace tmk

@@ -1,0 +1,102 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared entry
+point, and its host calls agree with the oracle (no GPU needed for these)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from workloads import balance_split, decompose, merge, split, swap
+
+tm = pytest.importorskip("paper_2507_17087_amd")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(tm_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = tm.lib()
+    names = declared_symbols()
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert tm.tm_abi_version() == 1
+
+
+def test_validate_matches_oracle_random_and_corrupted():
+    rng = np.random.default_rng(0)
+    cs = W.random_candidates(400, seed=99, ranks=(1, 2, 3, 4), octaves=(1, 6), nodes_max=40,
+                             max_ops=5, cyclic_pct=20)
+    bad = cs.copy()
+    for c in bad:  # corrupt one field at random
+        t = int(rng.integers(0, 7))
+        if t == 0:
+            c["ops"][int(rng.integers(0, 8))]["kind"] = int(rng.integers(0, 7))
+        elif t == 1:
+            c["ops"][int(rng.integers(0, max(int(c["nops"]), 1)))]["a"] += int(rng.integers(-2, 3))
+        elif t == 2:
+            c["ops"][int(rng.integers(0, max(int(c["nops"]), 1)))]["b"] += int(rng.integers(-2, 3))
+        elif t == 3:
+            c["mrank"] += int(rng.integers(-1, 2))
+        elif t == 4:
+            c["proj_src"][int(rng.integers(0, 8))] = int(rng.integers(-1, 5))
+        elif t == 5:
+            c["extent"][int(rng.integers(0, 4))] = int(rng.integers(-1, 3))
+        else:
+            c["nops"] = int(rng.integers(0, 9))
+    nbad = 0
+    for c in np.concatenate([cs, bad]):
+        a, b = tm.tm_validate(c), oracle.validate(c)
+        assert a[0] == b[0]
+        if a[0] == 0:
+            assert a[1] == b[1]
+        else:
+            nbad += 1
+    assert nbad > 100
+
+
+@pytest.mark.parametrize("P", [1, 6, 8, 12, 48, 64, 72, 97, 128, 360, 480, 512, 1 << 20, 720720])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_enumeration_matches_oracle(P, k):
+    if P > 100000 and k > 3:
+        pytest.skip("large")
+    assert tm.tm_enumerate_factorizations(P, k) == oracle.enumerate_factorizations(P, k)
+
+
+def test_argmin_and_greedy_match_oracle():
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        k = int(rng.integers(1, 5))
+        P = int(rng.integers(1, 600))
+        ext = tuple(int(x) for x in rng.integers(1, 2000, size=k))
+        halo = tuple(int(x) for x in rng.integers(0, 4, size=k))
+        assert tm.tm_decompose_argmin(P, ext, halo) == oracle.decompose_argmin(P, ext, halo)
+        assert tm.tm_greedy_grid(P, k) == oracle.greedy_grid(P, k)
+        assert tm.tm_workload_greedy(P, ext) == oracle.workload_greedy(P, ext)
+
+
+def test_error_codes_and_messages():
+    with pytest.raises(tm.TaskmapError) as e:
+        tm.tm_enumerate_factorizations(0, 2)
+    assert e.value.code == tm.TM_EINVAL
+    with pytest.raises(tm.TaskmapError) as e:
+        tm.tm_greedy_grid(8, 5)
+    assert e.value.code == tm.TM_EINVAL
+    c = W.candidate((4, 4), 2, 4, [split(0, 3)])
+    rc, _ = tm.tm_validate(c)
+    assert rc == tm.TM_EINVAL
+    assert b"split" in tm.lib().tm_last_error()
+    cnt = ctypes.c_int64()
+    rc = tm.lib().tm_enumerate_factorizations(128, 3, None, 0, ctypes.byref(cnt))
+    assert rc == tm.TM_ECAPACITY and cnt.value == 36

@@ -1,0 +1,312 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element, on
+seeded inputs.  Integer results must be bit-exact."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from workloads import balance_split, decompose, merge, split, swap
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def tm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2507_17087_amd as m
+    m.lib()
+    return m
+
+
+def gpu_costs(tm, cands, st):
+    import torch
+    out = tm.tm_eval_stencil_batch(cands, st)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def by_rank(cands):
+    for k, idx in W.split_by_rank(cands).items():
+        yield k, idx, cands[idx]
+
+
+# ---------------------------------------------------------------- c1: 64x64 on 2 x 4
+
+def test_c1_costs_maps_tables(tm):
+    import torch
+    say("c1 16 candidates")
+    c1 = W.c1_candidates(oracle.enumerate_factorizations(8, 2))
+    st = W.c1_stencil()
+    exp = oracle.stencil_cost_batch(c1, st)
+    got = gpu_costs(tm, c1, st)
+    assert (got == exp).all()
+    for c in c1:
+        assert (tm.tm_proc_map(c).cpu().numpy() == oracle.proc_map(c)).all()
+        assert (tm.tm_chain_table(c).cpu().numpy() == oracle.chain_table(c)).all()
+    best = tm.tm_select_best(torch.from_numpy(got).cuda(), [0, len(c1)]).cpu().numpy()
+    assert best[0] == oracle.select_best(exp)
+
+
+# ---------------------------------------------------------------- random chains, edges
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_random_small_parity(tm, seed):
+    say("random small seed", seed)
+    cs = W.random_candidates(240, seed=seed, ranks=(1, 2, 3), octaves=(0, 5), nodes_max=24,
+                             max_ops=4, cyclic_pct=25)
+    rng = np.random.default_rng(seed)
+    for k, idx, sub in by_rank(cs):
+        for h in [tuple(int(x) for x in rng.integers(0, 5, size=k)), (1,) * k]:
+            st = W.stencil(h, 4)
+            say("  rank", k, "halo", h, "n", len(sub))
+            assert (gpu_costs(tm, sub, st) == oracle.stencil_cost_batch(sub, st)).all()
+    for c in cs[:80]:
+        assert (tm.tm_proc_map(c).cpu().numpy() == oracle.proc_map(c)).all()
+
+
+def test_rank4_and_ragged(tm):
+    say("rank 4 and ragged extents")
+    cs = W.random_candidates(60, seed=7, ranks=(4,), octaves=(0, 3), nodes_max=12, max_ops=4,
+                             cyclic_pct=30)
+    for st in [W.stencil((1, 2, 1, 1), 8), W.stencil((2, 2, 2, 2), 8)]:
+        assert (gpu_costs(tm, cs, st) == oracle.stencil_cost_batch(cs, st)).all()
+    odd = [W.candidate((1, 1), 1, 1, [merge(0, 1), decompose(0, (1, 1))]),
+           W.candidate((3, 1), 2, 3, [merge(0, 1), decompose(0, (3, 2))]),
+           W.candidate((1, 70), 2, 3, [merge(0, 1), decompose(0, (2, 3))]),
+           W.candidate((130, 67), 5, 7, [merge(0, 1), decompose(0, (5, 7)), swap(0, 1)]),
+           W.candidate((9, 200), 64, 8, [merge(0, 1), decompose(0, (32, 16))]),
+           W.candidate((200, 3), 6, 1, [merge(0, 1), balance_split(0, 5)])]
+    odd = W.batch(odd)
+    for h in [(0, 0), (1, 1), (4, 3), (2, 4)]:
+        st = W.stencil(h, 8)
+        assert (gpu_costs(tm, odd, st) == oracle.stencil_cost_batch(odd, st)).all()
+    for c in odd:
+        assert (tm.tm_proc_map(c).cpu().numpy() == oracle.proc_map(c)).all()
+    one_d = W.batch([W.candidate((5000,), 7, 3, [merge(0, 1)]),
+                     W.candidate((333,), 4, 4, [merge(0, 1)], proj=[(0, W.CYCLIC)])])
+    st = W.stencil((3,), 8)
+    assert (gpu_costs(tm, one_d, st) == oracle.stencil_cost_batch(one_d, st)).all()
+
+
+def test_empty_batch_and_invalid_input(tm):
+    import torch
+    say("empty and invalid")
+    out = torch.full((2, 4), -7, dtype=torch.int64, device="cuda")
+    empty = np.zeros(0, dtype=W.CAND_DTYPE)
+    tm.tm_eval_stencil_batch(empty, W.stencil((1, 1)), out)
+    bad = W.batch([W.candidate((8, 8), 2, 2, [merge(0, 1), decompose(0, (2, 2))]),
+                   W.candidate((8, 8), 2, 2, [split(0, 3)])])
+    with pytest.raises(tm.TaskmapError) as e:
+        tm.tm_eval_stencil_batch(bad, W.stencil((1, 1)), out)
+    assert e.value.code == tm.TM_EINVAL
+    with pytest.raises(tm.TaskmapError) as e:
+        tm.tm_eval_stencil_batch(bad[:1], W.stencil((5, 1)), out)
+    assert e.value.code == tm.TM_ENOTSUP
+    torch.cuda.synchronize()
+    assert (out.cpu() == -7).all()  # nothing was launched
+
+
+# ---------------------------------------------------------------- c2: 512^3 on 16 x 8
+
+def test_c2_scaled_all_candidates(tm):
+    say("c2 at 64^3, 216 candidates")
+    cands = W.c2_candidates(oracle.enumerate_factorizations(128, 3), extent=(64, 64, 64))
+    st = W.c2_stencil()
+    assert (gpu_costs(tm, cands, st) == oracle.stencil_cost_batch(cands, st)).all()
+
+
+def test_c2_full_size_plan(tm):
+    import torch
+    say("c2 full 512^3 plan")
+    fs = oracle.enumerate_factorizations(128, 3)
+    cands = W.c2_candidates(fs)
+    st = W.c2_stencil()
+    plan = tm.Plan(len(cands), 1)
+    plan.load(cands, st)
+    out = torch.empty((len(cands), 4), dtype=torch.int64, device="cuda")
+    best = torch.empty(1, dtype=torch.int64, device="cuda")
+    plan.run(out, best)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    # identity chains: every block is 512/f >= 4 >= h wide, so the closed form holds
+    for i, f in enumerate(fs):
+        row = got[6 * i]
+        assert row[0] == sum(2 * 2 * (fm - 1) * 512 * 512 for fm in f)
+        assert row[2] == 8 * row[0]
+    # one full-size candidate through the oracle, cell by cell
+    i = fs.index((4, 4, 8)) * 6
+    say("  oracle on candidate", i, "(134M points)")
+    assert tuple(got[i]) == oracle.stencil_cost(cands[i], st)
+    b = int(best.cpu()[0])
+    assert b == oracle.select_best(got)
+    # materialised map of the selected candidate at sampled points
+    m = torch.empty(512 ** 3, dtype=torch.int32, device="cuda")
+    plan.materialize(m, d_index=best)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    pts = rng.integers(0, 512, size=(3000, 3))
+    mm = m.view(512, 512, 512)
+    idx = torch.from_numpy(pts).cuda()
+    vals = mm[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    g = int(cands[b]["gpus"])
+    for p, v in zip(pts, vals):
+        nd, gp = oracle.point_owner(cands[b], tuple(int(x) for x in p))
+        assert v == nd * g + gp
+    # every processor gets exactly 512^3/128 points (bijective block chain, f | 512)
+    counts = torch.bincount(m.long(), minlength=128).cpu().numpy()
+    assert (counts == 512 ** 3 // 128).all()
+    plan.close()
+
+
+# ---------------------------------------------------------------- c3: random batch
+
+def test_c3_scaled_all(tm):
+    say("c3 4096 candidates at scaled extents")
+    cs = W.c3_candidates(4096, octaves=(1, 4), nodes_max=64)
+    for k, idx, sub in by_rank(cs):
+        st = W.c3_stencil(k)
+        assert (gpu_costs(tm, sub, st) == oracle.stencil_cost_batch(sub, st)).all()
+
+
+def test_c3_full_extents_subset(tm):
+    say("c3 full-extent subset")
+    cs = W.c3_candidates(4096)
+    pts = np.prod(np.where(np.arange(4)[None, :] < cs["lrank"][:, None], cs["extent"], 1), axis=1)
+    rng = np.random.default_rng(17087)
+    small = np.nonzero(pts <= 3_000_000)[0]
+    pick = np.sort(rng.choice(small, size=24, replace=False))
+    sub = cs[pick]
+    for k, idx, s in by_rank(sub):
+        st = W.c3_stencil(k)
+        assert (gpu_costs(tm, s, st) == oracle.stencil_cost_batch(s, st)).all()
+
+
+# ---------------------------------------------------------------- c4: matmul
+
+def matmul_gpu(tm, cands, tile_bytes):
+    import torch
+    pp, out = tm.tm_eval_matmul_batch(cands, tile_bytes)
+    torch.cuda.synchronize()
+    return pp.cpu().numpy(), out.cpu().numpy()
+
+
+def test_c4_scaled_all(tm):
+    say("c4 at 32^3 tiles, 57 candidates")
+    cands = W.c4_candidates(oracle.enumerate_factorizations(64, 3), extent=(32, 32, 32))
+    pp, out = matmul_gpu(tm, cands, W.C4_TILE_BYTES)
+    off = 0
+    for i, c in enumerate(cands):
+        P = int(c["nodes"]) * int(c["gpus"])
+        per, tot = oracle.matmul_cost(c, W.C4_TILE_BYTES)
+        assert (pp[off:off + P] == per).all()
+        assert tuple(out[i]) == tot
+        off += P
+
+
+def test_c4_full_size(tm):
+    say("c4 at 256^3 tiles")
+    fs = oracle.enumerate_factorizations(64, 3)
+    cands = W.c4_candidates(fs)
+    pp, out = matmul_gpu(tm, cands, W.C4_TILE_BYTES)
+    T = 256
+    for i, f in enumerate(fs):
+        nA = (T // f[0]) * (T // f[2])
+        nB = (T // f[2]) * (T // f[1])
+        nC = (T // f[0]) * (T // f[1])
+        assert tuple(out[2 * i][:3]) == (64 * nA, 64 * nB, 64 * nC)
+        assert tuple(out[2 * i][3:6]) == (nA, nB, nC)
+    i881 = fs.index((8, 8, 1))
+    assert tuple(out[-1][:6]) == tuple(out[2 * i881][:6])  # Cannon = (8,8,1) counts
+    say("  oracle on one full candidate (16.7M tasks)")
+    per, tot = oracle.matmul_cost(cands[-1], W.C4_TILE_BYTES)
+    assert tuple(out[-1]) == tot
+    assert (pp[-64:] == per).all()
+
+
+def test_matmul_many_processors(tm):
+    say("matmul P > 64")
+    cs = W.batch([W.candidate((12, 10, 9), 40, 5, [merge(0, 1), decompose(0, (10, 5, 4))]),
+                  W.candidate((7, 16, 5), 30, 8, [merge(0, 1), decompose(0, (6, 8, 5)), swap(0, 2)]),
+                  W.candidate((9, 9, 9), 100, 10, [merge(0, 1), decompose(0, (10, 10, 10))],
+                              proj=[(0, W.CYCLIC), (1, W.BLOCK), (2, W.CYCLIC)])])
+    pp, out = matmul_gpu(tm, cs, 3)
+    off = 0
+    for i, c in enumerate(cs):
+        P = int(c["nodes"]) * int(c["gpus"])
+        per, tot = oracle.matmul_cost(c, 3)
+        assert (pp[off:off + P] == per).all() and tuple(out[i]) == tot
+        off += P
+
+
+# ---------------------------------------------------------------- plans and graphs
+
+def test_plan_graph_replay_deterministic(tm):
+    import torch
+    say("plan graph replay, layouts")
+    cs = W.c3_candidates(1500, seed=3, ranks=(3,), octaves=(3, 6))
+    st = W.c3_stencil(3)
+    exp = oracle.stencil_cost_batch(cs[:300], st)
+    ref = None
+    for cpi in [0, 4096, 1 << 15, 1 << 20]:
+        plan = tm.Plan(16, 16)  # grows on load
+        plan.load(cs, st, cells_per_item=cpi)
+        out = torch.empty((len(cs), 4), dtype=torch.int64, device="cuda")
+        best = torch.empty(1, dtype=torch.int64, device="cuda")
+        for rep in range(3):
+            plan.run(out, best)
+            torch.cuda.synchronize()
+            got = out.cpu().numpy().copy()
+            _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+            if ref is None:
+                ref = got
+                assert (got[:300] == exp).all()
+            assert (got == ref).all()
+        for stage in (0, 1, 2):
+            plan.run_stage(stage, out, best)
+        torch.cuda.synchronize()
+        assert (out.cpu().numpy() == ref).all()
+        assert int(best.cpu()[0]) == oracle.select_best(ref)
+        plan.close()
+    one = gpu_costs(tm, cs, st)
+    assert (one == ref).all()
+
+
+def test_plan_autotune_keeps_results(tm):
+    import torch
+    say("plan autotune")
+    cands = W.c2_candidates(oracle.enumerate_factorizations(128, 3), extent=(128, 96, 64))
+    st = W.c2_stencil()
+    plan = tm.Plan(len(cands), 1)
+    plan.load(cands, st)
+    out = torch.empty((len(cands), 4), dtype=torch.int64, device="cuda")
+    plan.run(out)
+    torch.cuda.synchronize()
+    a = out.cpu().numpy().copy()
+    cpi, wg = plan.autotune(out)
+    say("  chose", cpi, wg)
+    plan.run(out)
+    torch.cuda.synchronize()
+    assert (out.cpu().numpy() == a).all()
+    assert (a == oracle.stencil_cost_batch(cands, st)).all()
+    plan.close()
+
+
+def test_select_segments(tm):
+    import torch
+    say("segmented select")
+    rng = np.random.default_rng(0)
+    costs = np.zeros((1000, 4), np.int64)
+    costs[:, 2] = rng.integers(0, 5, size=1000)
+    costs[:, 3] = rng.integers(0, 3, size=1000)
+    seg = [0, 10, 10, 300, 999, 1000]
+    got = tm.tm_select_best(torch.from_numpy(costs).cuda(), seg).cpu().numpy()
+    for s in range(len(seg) - 1):
+        a, b = seg[s], seg[s + 1]
+        assert got[s] == (oracle.select_best(costs[a:b]) if b > a else -1)
