@@ -226,6 +226,58 @@ int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cells_per_item
 int tm_plan_info(const tm_plan* p, int64_t* n, int64_t* items, int64_t* points);
 int tm_plan_destroy(tm_plan* p);
 
+/* ---------------------------------------------------------------- learned ranker
+ * A surrogate of the exact cost that prunes decompose's candidate space before
+ * exact evaluation (the search of Sec. 4.3 over factorizations, widened to
+ * transformation chains).  Model: 64 features -> 3 hidden layers of width 256
+ * (ReLU) -> 2 outputs, BF16 weights and activations with FP32 accumulation on the
+ * matrix cores, FP32 master weights trained with Adam on the mean squared error
+ * against standardised log2(1 + bytes) and log2(1 + inter-node bytes) of exact
+ * costs.  Parameters are one flat fp32 vector of tm_ranker_param_count() values:
+ * W1[64][256], b1[256], W2[256][256], b2, W3[256][256], b3, W4[256][2], b4[2]
+ * (row-major, inputs along rows). */
+typedef struct tm_ranker tm_ranker;
+
+int tm_ranker_param_count(void);
+int tm_ranker_feature_count(void);
+/* He-normal initial weights from `seed`, zero biases. */
+int tm_ranker_create(uint64_t seed, tm_ranker** out);
+int tm_ranker_destroy(tm_ranker* r);
+/* Copies of the fp32 parameter vector (device pointers, param_count floats). */
+int tm_ranker_get_params(tm_ranker* r, float* d_out, void* stream);
+int tm_ranker_set_params(tm_ranker* r, const float* d_in, void* stream);
+/* mu_sigma (host, 4 floats) = {mu0, sigma0, mu1, sigma1} of the target scaling. */
+int tm_ranker_get_scaling(const tm_ranker* r, float* mu_sigma);
+/* Features of every candidate loaded in plan p (device fp32 [n][64]). */
+int tm_ranker_features(const tm_plan* p, float* d_feat, void* stream);
+/* Network outputs for n feature rows (device fp32 [n][64] -> [n][2]); inputs are
+ * rounded to bf16 first. */
+int tm_ranker_forward(tm_ranker* r, const float* d_feat, int64_t n, float* d_out, void* stream);
+/* Gradient of the mean squared error over n rows and both outputs against
+ * d_target (device fp32 [n][2], already standardised) -> d_grad (device fp32
+ * [param_count]); parameters are not changed. */
+int tm_ranker_grad(tm_ranker* r, const float* d_feat, const float* d_target, int64_t n, float* d_grad, void* stream);
+/* Trains on n rows: features d_feat (device fp32 [n][64]) and exact costs d_cost
+ * (device tm_stencil_cost[n]); sets the target scaling from the data; `epochs`
+ * passes in shuffled minibatches of `batch` rows, Adam with cosine-decayed lr.
+ * h_loss (host, nullable, [epochs]) receives the loss of each epoch's first batch.
+ * Synchronous with respect to the host. */
+int tm_ranker_train(tm_ranker* r, const float* d_feat, const tm_stencil_cost* d_cost, int64_t n, int32_t epochs,
+                    int32_t batch, float lr, uint64_t seed, float* h_loss, void* stream);
+int tm_ranker_save(const tm_ranker* r, const char* path);
+int tm_ranker_load(const char* path, tm_ranker** out);
+
+/* Search over the batch loaded in plan p, split into nseg instances by seg (host
+ * int64[nseg+1], seg[0] = 0, seg[nseg] = n).  For each instance, d_best (device
+ * int64[nseg]) receives the index (relative to the instance) of the candidate
+ * minimising (bytes, inter_bytes, index) and d_best_cost (device, nullable) its
+ * cost.  r == NULL: every candidate is evaluated exactly.  Otherwise the ranker
+ * scores every candidate (y0 + lambda * y1), the topk lowest per instance are
+ * evaluated exactly on the GPU, and the best of those is returned.  Everything
+ * after the segment upload runs on the device, on `stream`. */
+int tm_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t topk, float lambda,
+              int64_t* d_best, tm_stencil_cost* d_best_cost, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

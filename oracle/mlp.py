@@ -1,0 +1,162 @@
+"""Float64 reference of the learned ranker -- TEST INFRASTRUCTURE ONLY.
+
+Plain numpy, written independently of the HIP kernels: the feature encoding of a
+candidate, the 64 -> 256 -> 256 -> 256 -> 2 ReLU network, its mean-squared-error
+gradient by hand-written backpropagation, and one Adam step.  Only the tests and
+the benchmark's CPU leg use it.
+
+Parameter vector layout (flat): W1[64][256], b1[256], W2[256][256], b2[256],
+W3[256][256], b3[256], W4[256][2], b4[2]; rows index inputs.
+
+The ranker is not described by the paper (it is this build's learned pruning of
+decompose's search space); its feature encoding below is a definition, so the
+feature function is checked only against values worked out by hand in the tests
+("parity unpinned" beyond those).
+"""
+import math
+
+import numpy as np
+
+F, W, O = 64, 256, 2
+SPLIT, MERGE, SWAP, BALANCE_SPLIT, DECOMPOSE = 1, 2, 3, 4, 5
+
+
+def layout():
+    off, L = 0, {}
+    for name, size in [("w1", F * W), ("b1", W), ("w2", W * W), ("b2", W), ("w3", W * W), ("b3", W),
+                       ("w4", W * O), ("b4", O)]:
+        L[name] = (off, off + size)
+        off += size
+    L["count"] = off
+    return L
+
+
+def unpack(p):
+    L = layout()
+    g = lambda k: np.asarray(p[L[k][0]:L[k][1]], dtype=np.float64)
+    return (g("w1").reshape(F, W), g("b1"), g("w2").reshape(W, W), g("b2"), g("w3").reshape(W, W), g("b3"),
+            g("w4").reshape(W, O), g("b4"))
+
+
+def bf16_round(x):
+    """Round float32 values to bfloat16 (nearest even), returned as float64."""
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
+
+
+def forward(p, X):
+    w1, b1, w2, b2, w3, b3, w4, b4 = unpack(p)
+    z1 = X @ w1 + b1
+    h1 = np.maximum(z1, 0)
+    z2 = h1 @ w2 + b2
+    h2 = np.maximum(z2, 0)
+    z3 = h2 @ w3 + b3
+    h3 = np.maximum(z3, 0)
+    y = h3 @ w4 + b4
+    return y, (X, h1, h2, h3)
+
+
+def loss_and_grad(p, X, T):
+    """Mean over rows and outputs of (y - t)^2, and its gradient (flat)."""
+    w1, b1, w2, b2, w3, b3, w4, b4 = unpack(p)
+    y, (x, h1, h2, h3) = forward(p, X)
+    n = X.shape[0]
+    d = y - T
+    loss = float((d * d).sum() / (n * O))
+    dy = 2.0 * d / (n * O)
+    gw4 = h3.T @ dy
+    gb4 = dy.sum(0)
+    dh3 = (dy @ w4.T) * (h3 > 0)
+    gw3 = h2.T @ dh3
+    gb3 = dh3.sum(0)
+    dh2 = (dh3 @ w3.T) * (h2 > 0)
+    gw2 = h1.T @ dh2
+    gb2 = dh2.sum(0)
+    dh1 = (dh2 @ w2.T) * (h1 > 0)
+    gw1 = x.T @ dh1
+    gb1 = dh1.sum(0)
+    g = np.concatenate([gw1.ravel(), gb1, gw2.ravel(), gb2, gw3.ravel(), gb3, gw4.ravel(), gb4])
+    return loss, g
+
+
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    p = p - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)
+    return p, m, v
+
+
+def final_shape_and_blocks(c):
+    """Shapes after every op (forward rules) -> final shape, and the number of final
+    coordinates projected from each launch dim."""
+    s = [int(c["nodes"]), int(c["gpus"])]
+    for t in range(int(c["nops"])):
+        op = c["ops"][t]
+        k, a, b = int(op["kind"]), int(op["a"]), int(op["b"])
+        if k == SPLIT:
+            s = s[:a] + [b, s[a] // b] + s[a + 1:]
+        elif k == BALANCE_SPLIT:
+            s = s[:a] + [b, -(-s[a] // b)] + s[a + 1:]
+        elif k == MERGE:
+            s = s[:a] + [s[a] * s[b]] + s[a + 1:b] + s[b + 1:]
+        elif k == SWAP:
+            s = list(s)
+            s[a], s[b] = s[b], s[a]
+        elif k == DECOMPOSE:
+            f = [int(x) for x in op["f"][: int(op["nf"])]]
+            s = s[:a] + f + s[a + 1:]
+    blocks = [1.0] * 4
+    for j, sz in enumerate(s):
+        blocks[int(c["proj_src"][j])] *= sz
+    return s, blocks
+
+
+def features(c, halo):
+    """The 64 ranker features of one candidate (float64)."""
+    f = np.zeros(F)
+    k = int(c["lrank"])
+    f[k - 1] = 1
+    s, blocks = final_shape_and_blocks(c)
+    F_ = [1, 1, 1, 1]
+    nf = 0
+    ops = c["ops"][: int(c["nops"])]
+    for op in ops:
+        if int(op["kind"]) == DECOMPOSE:
+            nf = int(op["nf"])
+            F_ = [int(x) for x in op["f"][:4]]
+            break
+    vb = vf = 0.0
+    for d in range(k):
+        l = float(c["extent"][d])
+        f[4 + d] = math.log2(l) / 10
+        f[15 + d] = math.log2(blocks[d]) / 9
+        f[19 + d] = (math.log2(l) - math.log2(blocks[d])) / 10
+        vb += 2.0 * halo[d] * (blocks[d] - 1.0) / l
+        if d < nf:
+            vf += 2.0 * halo[d] * (F_[d] - 1.0) / l
+        f[54 + d] = halo[d] / 4
+    n, g = int(c["nodes"]), int(c["gpus"])
+    f[8] = math.log2(n) / 6
+    f[9] = math.log2(g) / 3
+    f[10] = math.log2(n * g) / 9
+    for m in range(min(nf, 4)):
+        f[11 + m] = math.log2(F_[m]) / 9
+    f[23] = math.log2(1 + vb) / 4
+    f[24] = math.log2(1 + vf) / 4
+    for t, op in enumerate(ops):
+        kd = int(op["kind"])
+        if 1 <= kd <= 5:
+            f[25 + kd - 1] += 0.25
+        if t < 6:
+            f[30 + t] = kd / 5
+            f[36 + t] = int(op["a"]) / 8
+            f[42 + t] = 0.0 if kd == DECOMPOSE else math.log2(1 + int(op["b"])) / 9
+    f[48] = 1.0 if len(ops) and int(ops[0]["kind"]) == SWAP else 0.0
+    for j in range(min(len(s), 4)):
+        f[49 + j] = 1.0 if int(c["proj_mode"][j]) else 0.0
+    f[53] = len(s) / 8
+    f[58] = math.ceil(math.log2(g)) / 3 if g > 1 else 0.0
+    f[59] = 1.0
+    return f

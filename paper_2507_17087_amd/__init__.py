@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-from . import _ranker_api  # noqa: F401  (ranker entry points, see ranker.py)
+from . import _ranker_api  # ctypes signatures of the ranker and search entry points
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtaskmap.so")
@@ -299,3 +299,93 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- learned ranker
+
+def tm_ranker_param_count():
+    return lib().tm_ranker_param_count()
+
+
+def tm_ranker_features(plan):
+    """fp32 [n, 64] features of the batch loaded in `plan` (device tensor)."""
+    import torch
+    out = torch.empty((max(plan.n, 1), lib().tm_ranker_feature_count()), dtype=torch.float32, device="cuda")
+    _check(lib().tm_ranker_features(plan._p, _dev_ptr(out, torch.float32), _stream()))
+    return out[: plan.n]
+
+
+class Ranker:
+    """tm_ranker: BF16-MFMA MLP surrogate of the exact cost (see taskmap.h)."""
+
+    def __init__(self, seed=0, path=None):
+        self._r = ctypes.c_void_p()
+        if path is None:
+            _check(lib().tm_ranker_create(seed, ctypes.byref(self._r)))
+        else:
+            _check(lib().tm_ranker_load(os.fsencode(path), ctypes.byref(self._r)))
+        self.param_count = lib().tm_ranker_param_count()
+
+    def get_params(self):
+        import torch
+        out = torch.empty(self.param_count, dtype=torch.float32, device="cuda")
+        _check(lib().tm_ranker_get_params(self._r, _dev_ptr(out, torch.float32), _stream()))
+        return out
+
+    def set_params(self, p):
+        import torch
+        _check(lib().tm_ranker_set_params(self._r, _dev_ptr(p, torch.float32, self.param_count), _stream()))
+
+    def scaling(self):
+        a = (ctypes.c_float * 4)()
+        _check(lib().tm_ranker_get_scaling(self._r, a))
+        return tuple(a)
+
+    def forward(self, feat):
+        import torch
+        n = feat.shape[0]
+        out = torch.empty((max(n, 1), 2), dtype=torch.float32, device="cuda")
+        _check(lib().tm_ranker_forward(self._r, _dev_ptr(feat, torch.float32), n, _dev_ptr(out, torch.float32),
+                                       _stream()))
+        return out[:n]
+
+    def grad(self, feat, target):
+        import torch
+        g = torch.empty(self.param_count, dtype=torch.float32, device="cuda")
+        _check(lib().tm_ranker_grad(self._r, _dev_ptr(feat, torch.float32), _dev_ptr(target, torch.float32),
+                                    feat.shape[0], _dev_ptr(g, torch.float32), _stream()))
+        return g
+
+    def train(self, feat, costs, epochs=4, batch=4096, lr=2e-3, seed=1):
+        import torch
+        losses = (ctypes.c_float * max(epochs, 1))()
+        _check(lib().tm_ranker_train(self._r, _dev_ptr(feat, torch.float32), _dev_ptr(costs, torch.int64),
+                                     feat.shape[0], epochs, batch, lr, seed, losses, _stream()))
+        return list(losses)[:epochs]
+
+    def save(self, path):
+        _check(lib().tm_ranker_save(self._r, os.fsencode(path)))
+
+    def close(self):
+        if self._r:
+            lib().tm_ranker_destroy(self._r)
+            self._r = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tm_search(plan, ranker, seg, topk=64, lam=0.05):
+    """Per instance [seg[s], seg[s+1]) of the batch loaded in `plan`: (best index
+    relative to the instance, its cost) as device tensors.  ranker None = exhaustive."""
+    import torch
+    sg = np.ascontiguousarray(seg, dtype=np.int64)
+    nseg = len(sg) - 1
+    best = torch.empty(max(nseg, 1), dtype=torch.int64, device="cuda")
+    cost = torch.empty((max(nseg, 1), 4), dtype=torch.int64, device="cuda")
+    _check(lib().tm_search(plan._p, ranker._r if ranker is not None else None, sg.ctypes.data, nseg, topk, lam,
+                           _dev_ptr(best, torch.int64), _dev_ptr(cost, torch.int64), _stream()))
+    return best[:nseg], cost[:nseg]

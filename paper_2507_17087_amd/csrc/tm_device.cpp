@@ -7,6 +7,8 @@
 #include <vector>
 
 #include "tm_internal.h"
+#include "tm_plan.h"
+#include "tm_ranker.h"
 
 namespace tmk {
 
@@ -20,17 +22,52 @@ constexpr int64_t kDefaultCellsPerItem = 1 << 17;
 
 // ------------------------------------------------------------------ batch compilation
 
-struct Compiled {
-    std::vector<DevCand> cands;
-    DevHeader hdr{};
-    int64_t arena_words = 0, items = 0, points = 0, max_points = 0;
-    int32_t max_words = 0;
-    int K = 0, H = 1;
-};
-
 static int64_t rows_per_item_for(const DevCand& d, int64_t cells_per_item) {
     const int64_t rpi = std::max<int64_t>(1, cells_per_item / std::max<int32_t>(d.L, 1));
     return std::min<int64_t>(rpi, std::max<int64_t>(d.rows, 1));
+}
+
+static int64_t up4(int64_t x) { return (x + 3) & ~int64_t(3); }
+
+// Arena layout of one candidate: owner table T, the last dim's coordinate table
+// (16-byte aligned, read four entries at a time), the other coordinate tables --
+// the prefix staged in LDS -- then the last dim's offset lists (also staged when
+// they fit the LDS budget, else read from global memory), then the other dims'
+// offset lists (read from global memory once per row).  H = 0: no offset lists.
+static int layout_tables(DevCand& d, int H) {
+    const int K = d.lrank;
+    int64_t off = up4(d.vol);
+    d.coord_off[K - 1] = (int32_t)off;
+    off += (d.extent[K - 1] + 255) & ~int64_t(255);  // zero-padded to whole 256-entry chunks
+    for (int k = 0; k < K - 1; ++k) {
+        d.coord_off[k] = (int32_t)std::min<int64_t>(off, INT32_MAX);
+        off += d.extent[k];
+    }
+    d.hstride = 2 * H;
+    int64_t staged;
+    if (H > 0) {
+        off = up4(off);
+        const int64_t tables = off + 4;  // slack for the last four-entry read of a ragged row
+        d.dl_off[K - 1] = (int32_t)std::min<int64_t>(off, INT32_MAX);
+        off += 2 * H * d.extent[K - 1];
+        off = up4(off);
+        // the last dim's offset lists join the LDS prefix when they fit
+        d.dl_lds = off + 4 <= kMaxLdsWords ? 1 : 0;
+        staged = d.dl_lds ? off + 4 : tables;
+        for (int k = 0; k < K - 1; ++k) {
+            d.dl_off[k] = (int32_t)std::min<int64_t>(off, INT32_MAX);
+            off += 2 * H * d.extent[k];
+        }
+    } else {
+        for (int k = 0; k < K; ++k) d.dl_off[k] = 0;
+        d.dl_lds = 0;
+        staged = up4(off) + 4;
+    }
+    const int64_t words = std::max(off, staged);
+    if (words > INT32_MAX) return TM_EOVERFLOW;
+    d.lds_words = (int32_t)staged;
+    d.words = (int32_t)words;
+    return TM_OK;
 }
 
 static void layout_items(Compiled& cp, int64_t cells_per_item) {
@@ -68,6 +105,7 @@ static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
         cp.H = std::max(1, hmax);
         cp.hdr.elem_bytes = st->elem_bytes;
         cp.hdr.lrank = st->lrank;
+        cp.hdr.H = cp.H;
     }
     int64_t words = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -79,14 +117,16 @@ static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
                              st->lrank);
         DevCand& d = cp.cands[(size_t)i];
         rc = fill_devcand(&c[i], sh, &d);
+        if (rc == TM_OK) rc = layout_tables(d, st ? cp.H : 0);
         if (rc != TM_OK) return set_error(rc, "candidate %lld: tables too large", (long long)i);
-        if (need_lds && d.words > kMaxLdsWords)
+        if (need_lds && d.lds_words > kMaxLdsWords)
             return set_error(TM_ENOTSUP, "candidate %lld: %d table words exceed the LDS budget of %d", (long long)i,
-                             d.words, kMaxLdsWords);
+                             d.lds_words, kMaxLdsWords);
         if (d.rows > INT32_MAX) return set_error(TM_ENOTSUP, "candidate %lld: more than 2^31 rows", (long long)i);
         d.arena_off = words;
         words += d.words;
-        cp.max_words = std::max(cp.max_words, d.words);
+        cp.max_words = std::max(cp.max_words, d.lds_words);
+        cp.max_all_words = std::max(cp.max_all_words, d.words);
         cp.points += d.npoints;
         cp.max_points = std::max(cp.max_points, d.npoints);
     }
@@ -349,30 +389,6 @@ extern "C" int tm_select_best(const tm_stencil_cost* d_costs, const int64_t* seg
 
 // ------------------------------------------------------------------ batch plans
 
-struct tm_plan {
-    int device = 0;
-    int64_t cap_cands = 0, cap_words = 0;
-    DevCand* d_cands = nullptr;
-    int32_t* d_arena = nullptr;
-    DevHeader* d_hdr = nullptr;
-    unsigned long long* d_counter = nullptr;
-    DevCand* h_cands = nullptr;  // pinned staging
-    DevHeader* h_hdr = nullptr;
-    hipEvent_t up_ev = nullptr;
-    bool up_pending = false;
-    hipStream_t cap_stream = nullptr;
-    Compiled cp;  // the loaded batch
-    bool loaded = false;
-    int64_t cells_per_item = 0;
-    int wg_per_cu = 0;
-    // graph cache: one entry
-    bool g_valid = false;
-    int g_grid = 0;
-    void* g_out = nullptr;
-    void* g_best = nullptr;
-    hipGraphExec_t g_full = nullptr, g_stage[3] = {nullptr, nullptr, nullptr};
-};
-
 namespace tmk {
 
 static void plan_drop_graphs(tm_plan* p) {
@@ -384,37 +400,64 @@ static void plan_drop_graphs(tm_plan* p) {
     p->g_valid = false;
 }
 
+static void search_free(SearchBufs& b) {
+    void* ptrs[] = {b.X, b.Y, b.score, b.scratch, b.seg, b.sel, b.sub, b.map, b.sub_seg, b.sub_hdr,
+                    b.sub_arena, b.sub_counter, b.sub_out, b.sub_best, b.all_out};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    b = SearchBufs{};
+}
+
 static void plan_free(tm_plan* p) {
     plan_drop_graphs(p);
+    search_free(p->sb);
     if (p->d_cands) (void)hipFree(p->d_cands);
     if (p->d_arena) (void)hipFree(p->d_arena);
     if (p->d_hdr) (void)hipFree(p->d_hdr);
     if (p->d_counter) (void)hipFree(p->d_counter);
     if (p->h_cands) (void)hipHostFree(p->h_cands);
     if (p->h_hdr) (void)hipHostFree(p->h_hdr);
+    if (p->h_seg) (void)hipHostFree(p->h_seg);
     p->d_cands = nullptr;
     p->d_arena = nullptr;
     p->d_hdr = nullptr;
     p->d_counter = nullptr;
     p->h_cands = nullptr;
     p->h_hdr = nullptr;
+    p->h_seg = nullptr;
+    p->cap_hseg = 0;
+    p->cap_cands = 0;
+    p->cap_words = 0;
 }
 
-static int plan_alloc(tm_plan* p, int64_t cands, int64_t words) {
+// Descriptor buffers for up to `cands` candidates (the table arena is allocated
+// separately, on first use, by plan_ensure_arena).
+static int plan_alloc(tm_plan* p, int64_t cands) {
     plan_free(p);
     cands = std::max<int64_t>(cands, 1);
-    words = std::max<int64_t>(words, 1);
     if (hipMalloc((void**)&p->d_cands, (size_t)cands * sizeof(DevCand)) != hipSuccess ||
-        hipMalloc((void**)&p->d_arena, (size_t)words * 4) != hipSuccess ||
         hipMalloc((void**)&p->d_hdr, sizeof(DevHeader)) != hipSuccess ||
         hipMalloc((void**)&p->d_counter, 256) != hipSuccess ||
         hipHostMalloc((void**)&p->h_cands, (size_t)cands * sizeof(DevCand), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&p->h_hdr, sizeof(DevHeader), hipHostMallocDefault) != hipSuccess) {
         plan_free(p);
-        return set_error(TM_ENOMEM, "plan buffers for %lld candidates / %lld words", (long long)cands,
-                         (long long)words);
+        return set_error(TM_ENOMEM, "plan buffers for %lld candidates", (long long)cands);
     }
     p->cap_cands = cands;
+    return TM_OK;
+}
+
+// Table arena of the whole loaded batch; grows (after draining `s`) when needed.
+static int plan_ensure_arena(tm_plan* p, hipStream_t s) {
+    const int64_t words = std::max<int64_t>(p->cp.arena_words, 1);
+    if (p->d_arena && p->cap_words >= words) return TM_OK;
+    TM_HIP(hipStreamSynchronize(s));
+    if (p->d_arena) (void)hipFree(p->d_arena);
+    p->d_arena = nullptr;
+    p->cap_words = 0;
+    plan_drop_graphs(p);
+    if (hipMalloc((void**)&p->d_arena, (size_t)words * 4) != hipSuccess)
+        return set_error(TM_ENOMEM, "table arena of %lld words", (long long)words);
     p->cap_words = words;
     return TM_OK;
 }
@@ -492,7 +535,11 @@ extern "C" int tm_plan_create(int64_t max_cands, int64_t max_words, tm_plan** ou
     tm_plan* p = new (std::nothrow) tm_plan();
     if (!p) return set_error(TM_ENOMEM, "plan");
     (void)hipGetDevice(&p->device);
-    int rc = plan_alloc(p, max_cands, max_words);
+    int rc = plan_alloc(p, max_cands);
+    if (rc == TM_OK && max_words > 0) {
+        if (hipMalloc((void**)&p->d_arena, (size_t)max_words * 4) != hipSuccess) rc = set_error(TM_ENOMEM, "arena");
+        else p->cap_words = max_words;
+    }
     if (rc == TM_OK && hipEventCreateWithFlags(&p->up_ev, hipEventDisableTiming) != hipSuccess)
         rc = set_error(TM_EDEVICE, "event");
     if (rc == TM_OK && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
@@ -525,10 +572,10 @@ extern "C" int tm_plan_load(tm_plan* p, const tm_candidate* c, int64_t n, const 
     Compiled cp;
     int rc = compile_batch(c, n, st, cells_per_item > 0 ? cells_per_item : p->cells_per_item, true, cp);
     if (rc != TM_OK) return rc;
-    if (n > p->cap_cands || cp.arena_words > p->cap_words) {
+    if (n > p->cap_cands) {
         // grow: wait for work that may still read the old buffers
         TM_HIP(hipStreamSynchronize(s));
-        rc = plan_alloc(p, std::max(n, p->cap_cands), std::max(cp.arena_words, p->cap_words));
+        rc = plan_alloc(p, std::max(n, p->cap_cands));
         if (rc != TM_OK) return rc;
         p->up_pending = false;
     }
@@ -543,7 +590,8 @@ extern "C" int tm_plan_run(tm_plan* p, tm_stencil_cost* d_out, int64_t* d_best, 
     if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
     if (p->cp.hdr.n > 0 && !d_out) return set_error(TM_EINVAL, "null output");
     if (p->cp.hdr.n == 0) return TM_OK;
-    int rc = plan_graphs(p, d_out, d_best);
+    int rc = plan_ensure_arena(p, (hipStream_t)stream);
+    if (rc == TM_OK) rc = plan_graphs(p, d_out, d_best);
     if (rc != TM_OK) return rc;
     TM_HIP(hipGraphLaunch(p->g_full, (hipStream_t)stream));
     return TM_OK;
@@ -555,7 +603,8 @@ extern "C" int tm_plan_run_stage(tm_plan* p, int32_t stage, tm_stencil_cost* d_o
     if (stage < 0 || stage > 2) return set_error(TM_EINVAL, "stage %d", stage);
     if (p->cp.hdr.n > 0 && !d_out) return set_error(TM_EINVAL, "null output");
     if (p->cp.hdr.n == 0) return TM_OK;
-    int rc = plan_graphs(p, d_out, d_best);
+    int rc = plan_ensure_arena(p, (hipStream_t)stream);
+    if (rc == TM_OK) rc = plan_graphs(p, d_out, d_best);
     if (rc != TM_OK) return rc;
     TM_HIP(hipGraphLaunch(p->g_stage[stage], (hipStream_t)stream));
     return TM_OK;
@@ -577,6 +626,8 @@ extern "C" int tm_plan_materialize(tm_plan* p, const int64_t* d_index, int64_t h
         for (auto& d : cp.cands) rows = std::max(rows, d.rows);
     }
     if (cap < need) return set_error(TM_ECAPACITY, "map needs %lld entries", (long long)need);
+    if (!p->d_arena || p->cap_words < cp.arena_words)
+        return set_error(TM_EINVAL, "no tables yet: run the plan before materialising a map");
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((rows + 3) / 4, num_cus() * 8));
     const hipError_t e = launch_map(p->d_cands, cp.hdr.n, p->d_arena, d_index, host_index, d_map, grid, cp.max_words,
                                     (hipStream_t)stream);
@@ -598,6 +649,8 @@ extern "C" int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cel
     if (p->cp.hdr.n == 0) return TM_OK;
     if (!d_out) return set_error(TM_EINVAL, "null output");
     hipStream_t s = (hipStream_t)stream;
+    int arc = plan_ensure_arena(p, s);
+    if (arc != TM_OK) return arc;
     hipEvent_t e0, e1;
     TM_HIP(hipEventCreate(&e0));
     TM_HIP(hipEventCreate(&e1));
@@ -651,3 +704,189 @@ extern "C" int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cel
     if (wg_per_cu) *wg_per_cu = best_w;
     return rc;
 }
+
+// ------------------------------------------------------------------ search support
+
+namespace tmk {
+
+int64_t plan_size(const tm_plan* p) { return p->cp.hdr.n; }
+const DevCand* plan_cands(const tm_plan* p) { return p->d_cands; }
+const int32_t* plan_halo(const tm_plan* p) { return p->d_hdr->halo; }
+const DevHeader* plan_hdr(const tm_plan* p) { return p->d_hdr; }
+int64_t plan_cells_per_item(const tm_plan* p) {
+    return p->cells_per_item > 0 ? p->cells_per_item : kDefaultCellsPerItem;
+}
+
+int plan_features(const tm_plan* p, float* d_feat, hipStream_t s) {
+    if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
+    if (!d_feat) return set_error(TM_EINVAL, "null output");
+    tm_plan* q = const_cast<tm_plan*>(p);
+    SearchBufs& b = q->sb;
+    const int64_t n = p->cp.hdr.n;
+    if (b.cap_n < n) {
+        TM_HIP(hipStreamSynchronize(s));
+        if (b.X) (void)hipFree(b.X);
+        b.X = nullptr;
+        b.cap_n = 0;
+        if (b.Y) (void)hipFree(b.Y);
+        if (b.score) (void)hipFree(b.score);
+        if (b.scratch) (void)hipFree(b.scratch);
+        b.Y = b.score = b.scratch = nullptr;
+        if (hipMalloc((void**)&b.X, (size_t)std::max<int64_t>(n, 1) * kFeat * 2) != hipSuccess ||
+            hipMalloc((void**)&b.Y, (size_t)std::max<int64_t>(n, 1) * kOut * 4) != hipSuccess ||
+            hipMalloc((void**)&b.score, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
+            hipMalloc((void**)&b.scratch, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess)
+            return set_error(TM_ENOMEM, "feature buffers");
+        b.cap_n = n;
+    }
+    TM_HIP(launch_features(p->d_cands, n, p->d_hdr->halo, b.X, d_feat, s));
+    return TM_OK;
+}
+
+// Uploads the instance segments and sizes the search buffers.
+int plan_search_prepare(tm_plan* p, const int64_t* seg, int64_t nseg, int32_t topk, bool ranked, SearchBufs** out,
+                        hipStream_t s) {
+    if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
+    if (nseg < 1 || !seg) return set_error(TM_EINVAL, "no segments");
+    const int64_t n = p->cp.hdr.n;
+    if (seg[0] != 0 || seg[nseg] != n) return set_error(TM_EINVAL, "segments must cover the loaded batch");
+    for (int64_t i = 0; i < nseg; ++i)
+        if (seg[i + 1] < seg[i]) return set_error(TM_EINVAL, "segment %lld is not ordered", (long long)i);
+    if (ranked && (topk < 1 || topk > 4096)) return set_error(TM_EINVAL, "topk %d not in 1..4096", topk);
+    SearchBufs& b = p->sb;
+    const int64_t nsel = ranked ? nseg * (int64_t)topk : 0;
+    const int64_t words = nsel * std::max<int64_t>(p->cp.max_all_words, 1);
+    auto grow = [&](bool need) -> int {
+        if (!need) return TM_OK;
+        TM_HIP(hipStreamSynchronize(s));
+        return TM_OK;
+    };
+    if (ranked) {
+        if (b.cap_n < n) {
+            int rc = grow(true);
+            if (rc != TM_OK) return rc;
+            if (b.X) (void)hipFree(b.X);
+            if (b.Y) (void)hipFree(b.Y);
+            if (b.score) (void)hipFree(b.score);
+            if (b.scratch) (void)hipFree(b.scratch);
+            b.X = nullptr;
+            b.Y = b.score = b.scratch = nullptr;
+            b.cap_n = 0;
+            if (hipMalloc((void**)&b.X, (size_t)std::max<int64_t>(n, 1) * kFeat * 2) != hipSuccess ||
+                hipMalloc((void**)&b.Y, (size_t)std::max<int64_t>(n, 1) * kOut * 4) != hipSuccess ||
+                hipMalloc((void**)&b.score, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
+                hipMalloc((void**)&b.scratch, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess)
+                return set_error(TM_ENOMEM, "score buffers");
+            b.cap_n = n;
+        }
+        if (b.cap_sel < nsel || b.cap_words < words) {
+            int rc = grow(true);
+            if (rc != TM_OK) return rc;
+            void* ptrs[] = {b.sel, b.sub, b.map, b.sub_arena, b.sub_out};
+            for (void* q : ptrs)
+                if (q) (void)hipFree(q);
+            b.sel = nullptr;
+            b.sub = nullptr;
+            b.map = nullptr;
+            b.sub_arena = nullptr;
+            b.sub_out = nullptr;
+            b.cap_sel = b.cap_words = 0;
+            if (hipMalloc((void**)&b.sel, (size_t)nsel * 8) != hipSuccess ||
+                hipMalloc((void**)&b.sub, (size_t)nsel * sizeof(DevCand)) != hipSuccess ||
+                hipMalloc((void**)&b.map, (size_t)nsel * 8) != hipSuccess ||
+                hipMalloc((void**)&b.sub_arena, (size_t)std::max<int64_t>(words, 1) * 4) != hipSuccess ||
+                hipMalloc((void**)&b.sub_out, (size_t)nsel * sizeof(tm_stencil_cost)) != hipSuccess)
+                return set_error(TM_ENOMEM, "survivor buffers");
+            b.cap_sel = nsel;
+            b.cap_words = words;
+        }
+        if (!b.sub_hdr) {
+            if (hipMalloc((void**)&b.sub_hdr, sizeof(DevHeader)) != hipSuccess ||
+                hipMalloc((void**)&b.sub_counter, 256) != hipSuccess)
+                return set_error(TM_ENOMEM, "survivor header");
+        }
+    } else if (b.cap_all < n) {
+        int rc = grow(b.all_out != nullptr);
+        if (rc != TM_OK) return rc;
+        if (b.all_out) (void)hipFree(b.all_out);
+        b.all_out = nullptr;
+        b.cap_all = 0;
+        if (hipMalloc((void**)&b.all_out, (size_t)std::max<int64_t>(n, 1) * sizeof(tm_stencil_cost)) != hipSuccess)
+            return set_error(TM_ENOMEM, "cost buffer");
+        b.cap_all = n;
+    }
+    if (b.cap_seg < nseg + 1) {
+        int rc = grow(true);
+        if (rc != TM_OK) return rc;
+        if (b.seg) (void)hipFree(b.seg);
+        if (b.sub_seg) (void)hipFree(b.sub_seg);
+        if (b.sub_best) (void)hipFree(b.sub_best);
+        b.seg = b.sub_seg = b.sub_best = nullptr;
+        b.cap_seg = 0;
+        if (hipMalloc((void**)&b.seg, (size_t)(nseg + 1) * 8) != hipSuccess ||
+            hipMalloc((void**)&b.sub_seg, (size_t)(nseg + 1) * 8) != hipSuccess ||
+            hipMalloc((void**)&b.sub_best, (size_t)(nseg + 1) * 8) != hipSuccess)
+            return set_error(TM_ENOMEM, "segment buffers");
+        b.cap_seg = nseg + 1;
+    }
+    // segments: copy only when they changed (pinned staging, ordered on s)
+    if (b.nseg != nseg || !p->h_seg || std::memcmp(p->h_seg, seg, (size_t)(nseg + 1) * 8) != 0) {
+        if (p->up_pending) {
+            TM_HIP(hipEventSynchronize(p->up_ev));
+            p->up_pending = false;
+        }
+        if (p->cap_hseg < nseg + 1) {
+            if (p->h_seg) (void)hipHostFree(p->h_seg);
+            p->h_seg = nullptr;
+            if (hipHostMalloc((void**)&p->h_seg, (size_t)(nseg + 1) * 8, hipHostMallocDefault) != hipSuccess)
+                return set_error(TM_ENOMEM, "segment staging");
+            p->cap_hseg = nseg + 1;
+        }
+        std::memcpy(p->h_seg, seg, (size_t)(nseg + 1) * 8);
+        TM_HIP(hipMemcpyAsync(b.seg, p->h_seg, (size_t)(nseg + 1) * 8, hipMemcpyHostToDevice, s));
+        TM_HIP(hipEventRecord(p->up_ev, s));
+        p->up_pending = true;
+    }
+    b.nseg = nseg;
+    b.k = topk;
+    *out = &b;
+    return TM_OK;
+}
+
+// Exact costs of the survivors gathered in sb (descriptors and header on device).
+hipError_t plan_eval_sub(tm_plan* p, SearchBufs* sb, hipStream_t s) {
+    const int64_t nsel = sb->nseg * sb->k;
+    const Compiled& cp = p->cp;
+    hipError_t e = launch_reset(sb->sub_hdr, sb->sub_counter, sb->sub_out, nsel, s);
+    if (e == hipSuccess) e = launch_build_tables(sb->sub_hdr, sb->sub, nsel, sb->sub_arena, 1, s);
+    if (e == hipSuccess) {
+        // survivors' work items are bounded by the batch's largest candidate
+        int64_t max_items = 0;
+        for (const auto& d : cp.cands) {
+            const int64_t rpi = std::max<int64_t>(1, plan_cells_per_item(p) / std::max<int32_t>(d.L, 1));
+            max_items = std::max<int64_t>(max_items, (d.rows + rpi - 1) / rpi);
+        }
+        const int grid = count_grid(cp.K, cp.H, cp.max_words, std::max<int64_t>(1, max_items * nsel), p->wg_per_cu);
+        e = launch_count(cp.K, cp.H, sb->sub_hdr, sb->sub, sb->sub_arena, sb->sub_counter, sb->sub_out, grid,
+                         cp.max_words, s);
+    }
+    if (e == hipSuccess) e = launch_finalize_select(sb->sub_hdr, sb->sub_out, nullptr, s);
+    return e;
+}
+
+int plan_exhaustive_search(tm_plan* p, const int64_t* seg, int64_t nseg, int64_t* d_best,
+                           tm_stencil_cost* d_best_cost, hipStream_t s) {
+    if (!d_best) return set_error(TM_EINVAL, "null output");
+    SearchBufs* sb = nullptr;
+    int rc = plan_search_prepare(p, seg, nseg, 0, false, &sb, s);
+    if (rc == TM_OK) rc = plan_ensure_arena(p, s);
+    if (rc != TM_OK) return rc;
+    const int grid = count_grid(p->cp.K, p->cp.H, p->cp.max_words, p->cp.items, p->wg_per_cu);
+    hipError_t e = plan_enqueue(p, -1, sb->all_out, nullptr, grid, s);
+    if (e == hipSuccess) e = launch_select_segments(sb->all_out, sb->seg, nseg, d_best, s);
+    if (e == hipSuccess) e = launch_pick_costs(d_best, sb->seg, sb->all_out, nseg, d_best_cost, s);
+    if (e != hipSuccess) return set_error(TM_EDEVICE, "exhaustive search: %s", hipGetErrorString(e));
+    return TM_OK;
+}
+
+}  // namespace tmk

@@ -23,6 +23,9 @@ struct DevCand {
     int64_t rows;                       // points / extent[lrank-1]
     int32_t rows_per_item, L;           // rows per work item; row length = last extent
     int32_t coord_off[TM_MAX_LRANK];    // table offsets of the per-dim coordinate tables
+    int32_t dl_off[TM_MAX_LRANK];       // table offsets of the per-dim neighbour-offset lists
+    int32_t lds_words, hstride;         // leading words staged in LDS; list stride (2*H)
+    int32_t dl_lds, pad1;               // last dim's offset lists are in the staged prefix
     int32_t fshape[TM_MAX_MRANK], fstride[TM_MAX_MRANK];
     int8_t proj_src[TM_MAX_MRANK], proj_mode[TM_MAX_MRANK];
     int32_t rank[TM_MAX_OPS];                    // rank before op t
@@ -37,7 +40,7 @@ struct DevHeader {
     int64_t total_items;  // work items over all candidates
     int32_t halo[TM_MAX_LRANK];
     int32_t elem_bytes, lrank;
-    int32_t max_words, pad;
+    int32_t max_words, H;  // largest staged table; max halo (0: no neighbour lists)
 };
 
 // Host-side result of validation.
@@ -46,14 +49,13 @@ struct Shapes {
     int64_t size[TM_MAX_OPS + 1][TM_MAX_MRANK];
 };
 
-// Word layout of an entry of a per-dim coordinate table: bits 0..30 hold the
-// contribution of that coordinate to the linear final-space index, bit 31 is set
-// when some star neighbour along that dim (within the halo) has a different
-// contribution.
-constexpr uint32_t kFlagBit = 0x80000000u;
-constexpr uint32_t kValMask = 0x7fffffffu;
-// Largest table (final-space volume + sum of extents) that the counting and map
-// kernels stage in LDS.
+// Word layout of an entry of a per-dim coordinate table: bits 0..23 hold the
+// contribution of that coordinate to the linear final-space index (volumes are at
+// most 2^24), bits 24..27 the number of distinct non-zero index offsets from that
+// coordinate to its star neighbours along the dim (within the halo).  That list of
+// offsets is stored separately, 2*H words per coordinate, zero-padded.
+constexpr int32_t kValMask = 0x00ffffff;
+constexpr int kCntShift = 24;
 constexpr int32_t kMaxLdsWords = 32768;
 constexpr int kMaxHalo = 4;
 

@@ -116,7 +116,10 @@ __device__ int32_t coord_value(const DevCand& c, int d, int64_t x) {
 
 // ------------------------------------------------------------------ table build
 
-// One workgroup per candidate (grid-stride over candidates).
+// One workgroup per candidate (grid-stride over candidates).  With halos (use_halo),
+// each coordinate x of launch dim d also gets the list of distinct non-zero offsets
+// C_d[x +- s] - C_d[x] (1 <= s <= h_d, in-domain neighbours), and its count in the
+// coordinate entry.
 __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restrict__ hdr,
                                                       const DevCand* __restrict__ cands,
                                                       int32_t* __restrict__ arena, int use_halo) {
@@ -128,19 +131,31 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
         __syncthreads();
         int32_t* base = arena + sc.arena_off;
         for (int32_t v = threadIdx.x; v < sc.vol; v += blockDim.x) base[v] = owner_key(sc, v);
+        const int hs = sc.hstride;
         for (int d = 0; d < sc.lrank; ++d) {
             const int64_t l = sc.extent[d];
             const int h = use_halo ? hdr->halo[d] : 0;
             int32_t* ct = base + sc.coord_off[d];
+            int32_t* dl = base + sc.dl_off[d];
             for (int64_t x = threadIdx.x; x < l; x += blockDim.x) {
                 const int32_t val = coord_value(sc, d, x);
-                bool flag = false;
-                for (int s = 1; s <= h && !flag; ++s) {
-                    if (x - s >= 0 && coord_value(sc, d, x - s) != val) flag = true;
-                    if (x + s < l && coord_value(sc, d, x + s) != val) flag = true;
+                int cnt = 0;
+                for (int s = 1; s <= h; ++s) {
+                    for (int dir = 0; dir < 2; ++dir) {
+                        const int64_t xx = dir ? x + s : x - s;
+                        if (xx < 0 || xx >= l) continue;
+                        const int32_t dv = coord_value(sc, d, xx) - val;
+                        if (dv == 0) continue;
+                        bool seen = false;
+                        for (int i = 0; i < cnt; ++i) seen = seen || (dl[x * hs + i] == dv);
+                        if (!seen) dl[x * hs + cnt++] = dv;
+                    }
                 }
-                ct[x] = (int32_t)((uint32_t)val | (flag ? kFlagBit : 0u));
+                for (int i = cnt; i < hs; ++i) dl[x * hs + i] = 0;
+                ct[x] = val | (cnt << kCntShift);
             }
+            if (d == sc.lrank - 1)  // zero entries up to a multiple of 256 (scanned four per lane)
+                for (int64_t x = l + threadIdx.x; x < ((l + 255) & ~int64_t(255)); x += blockDim.x) ct[x] = 0;
         }
     }
 }
@@ -176,61 +191,56 @@ hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_
 //
 // A work item is a block of consecutive rows (all launch dims but the last fixed)
 // of one candidate.  A workgroup takes items from a global atomic counter (the
-// next one is requested while the current one runs), stages the candidate's tables
-// in LDS when the candidate changes, and gives each wave whole rows.  For a row,
-// the outer coordinates fix a base index and tell whether the row lies within a
-// halo of a block boundary of an outer dim (row flag).
-//   - Rows without the row flag: a cell can only have foreign neighbours along the
-//     last dim, which is the case exactly when its last-dim table entry carries the
-//     flag.  Each cell is tested; flagged cells are compacted into a per-wave LDS
-//     queue (ballot + prefix count) and evaluated 64 at a time with all lanes busy.
-//   - Rows with the row flag: the distinct non-zero index offsets to the outer
-//     neighbours are the same for every cell of the row; every cell looks up its
-//     owner and those neighbours' owners, plus its last-dim neighbours if flagged.
-// Per cell the owners of the candidate neighbours are de-duplicated exactly and
-// counted (and those on another node); lanes sum in registers, waves reduce, and
-// one 64-bit atomic per wave and item adds to the candidate's totals.
-
-template <int K, int H>
-struct CountCfg {
-    static constexpr int NO = K > 1 ? 2 * H * (K - 1) : 1;  // outer neighbour slots
-    static constexpr int NL = 2 * H;                         // last-dim neighbour slots
-};
+// next one is requested while the current one runs), stages the candidate's owner
+// table, coordinate tables and last-dim offset lists in LDS when the candidate
+// changes, and gives each wave whole rows.  Every cell is examined: a lane reads
+// the coordinate entries of four consecutive cells with one LDS load.
+//   - The outer coordinates of a row fix a base index and the row's list of
+//     distinct offsets to outer neighbours (usually empty: the row lies inside a
+//     block along every outer dim).
+//   - Rows with an empty list: a cell can have a foreign neighbour only along the
+//     last dim, i.e. when its entry's offset count is non-zero.  Groups of four
+//     cells holding such a cell are compacted into a per-wave LDS queue (ballot +
+//     prefix count) and evaluated 64 groups at a time with every lane busy.
+//   - Rows with a non-empty list: every cell is evaluated.
+// Evaluating a cell: its owner o = T[v], then the owners T[v + delta] over the row
+// list and the cell's own last-dim list; the distinct ones other than o are
+// counted (and those on another node).  Lanes count in registers, waves reduce,
+// and one 64-bit atomic per wave and item adds to the candidate's totals.
 
 constexpr int kQueueCap = 128;
 
-// De-duplicate a static list of owner keys against the cell owner o; every slot
-// whose neighbour is absent holds o itself.
-template <int N>
-__device__ __forceinline__ void count_distinct(const int32_t (&c)[N], int32_t o, int gbits, int& cnt,
-                                               int& icnt) {
-    const int32_t onode = o >> gbits;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        bool fresh = c[j] != o;
-#pragma unroll
-        for (int i = 0; i < j; ++i) fresh = fresh && (c[i] != c[j]);
-        cnt += fresh ? 1 : 0;
-        icnt += (fresh && ((c[j] >> gbits) != onode)) ? 1 : 0;
-    }
+__device__ __forceinline__ int32_t cval(int32_t e) { return e & kValMask; }
+__device__ __forceinline__ int32_t ccnt(int32_t e) { return (e >> kCntShift) & 0xf; }
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Owners of the last-dim neighbours of cell (v, x) into c[0..NL).
-template <int H>
-__device__ __forceinline__ void last_dim_owners(const int32_t* __restrict__ T, const int32_t* __restrict__ CL,
-                                                int32_t v, int32_t x, int32_t ev, int L, int h, int32_t o,
-                                                int32_t (&c)[2 * H]) {
-#pragma unroll
-    for (int s = 1; s <= H; ++s) {
-#pragma unroll
-        for (int dir = 0; dir < 2; ++dir) {
-            const int xx = dir ? x + s : x - s;
-            int32_t own = o;
-            if (s <= h && xx >= 0 && xx < L) {
-                const int32_t dv = (CL[xx] & (int32_t)kValMask) - ev;
-                if (dv != 0) own = T[v + dv];
+// Distinct owners, other than o, among T[v + delta] for delta in rl[0..nr) then
+// xl[0..nx).  Offsets repeat nothing within one list; equal owners are merged.
+__device__ __forceinline__ void eval_cell(const int32_t* __restrict__ T, int32_t v, int32_t o,
+                                          const int32_t* rl, int nr, const int32_t* xl, int nx, int gbits,
+                                          int& cnt, int& icnt) {
+    const int n = nr + nx;
+    const int32_t onode = o >> gbits;
+    for (int t = 0; t < n; ++t) {
+        const int32_t dt = t < nr ? rl[t] : xl[t - nr];
+        const int32_t ot = T[v + dt];
+        if (ot == o) continue;
+        bool fresh = true;
+        for (int s = 0; s < t; ++s) {
+            const int32_t ds = s < nr ? rl[s] : xl[s - nr];
+            if (T[v + ds] == ot) {
+                fresh = false;
+                break;
             }
-            c[2 * (s - 1) + dir] = own;
+        }
+        if (fresh) {
+            ++cnt;
+            icnt += ((ot >> gbits) != onode) ? 1 : 0;
         }
     }
 }
@@ -241,27 +251,29 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
                                                const int32_t* __restrict__ arena,
                                                unsigned long long* __restrict__ counter,
                                                tm_stencil_cost* __restrict__ out) {
-    using Cfg = CountCfg<K, H>;
+    constexpr int HS = 2 * H;  // offsets per coordinate
+    constexpr int KO = K > 1 ? K - 1 : 1;
     extern __shared__ int32_t lds[];
     __shared__ long long s_item;
     __shared__ int32_t s_qv[4][kQueueCap], s_qx[4][kQueueCap];
+    __shared__ int32_t s_rl[4][32];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t total = uniform64(hdr->total_items);
     const int64_t n = uniform64(hdr->n);
-    int hal[K];
-#pragma unroll
-    for (int d = 0; d < K; ++d) hal[d] = uniform32(hdr->halo[d]);
 
     int64_t cur = -1;
     int32_t L = 0, gbits = 0, rpi = 1;
     int64_t rows = 0, ifirst = 0;
-    int32_t off[K], ext[K];
+    int32_t off[K], ext[K], dlo[K];
+    const int32_t* garena = arena;
+    const int32_t* DL = arena;  // last dim's offset lists: LDS when staged, else global
 #pragma unroll
-    for (int d = 0; d < K; ++d) off[d] = ext[d] = 0;
+    for (int d = 0; d < K; ++d) off[d] = ext[d] = dlo[d] = 0;
 
     int32_t* qv = s_qv[wid];
     int32_t* qx = s_qx[wid];
+    int32_t* rl = s_rl[wid];
 
     unsigned long long next = 0;
     if (tid == 0) next = atomicAdd(counter, 1ull);
@@ -283,9 +295,10 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
         lo = uniform64(lo);
         if (lo != cur) {
             const DevCand* c = &cands[lo];
-            const int32_t words = uniform32(c->words);
+            const int32_t words = uniform32(c->lds_words);
             const int32_t* src = arena + c->arena_off;
             for (int i = tid; i < words; i += 256) lds[i] = src[i];
+            garena = src;
             L = uniform32(c->L);
             gbits = uniform32(c->gbits);
             rpi = uniform32(c->rows_per_item);
@@ -295,125 +308,127 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
             for (int d = 0; d < K; ++d) {
                 off[d] = uniform32(c->coord_off[d]);
                 ext[d] = uniform32((int32_t)c->extent[d]);
+                dlo[d] = uniform32(c->dl_off[d]);
             }
+            DL = uniform32(c->dl_lds) ? lds + dlo[K - 1] : src + dlo[K - 1];
             cur = lo;
             __syncthreads();
         }
         const int32_t* T = lds;
         const int32_t* CL = lds + off[K - 1];
-        const int hL = hal[K - 1];
 
+        // this wave's contiguous share of the item's rows
         const int64_t r0 = (item - ifirst) * rpi;
         const int64_t r1 = r0 + rpi < rows ? r0 + rpi : rows;
+        const int64_t nrw = (r1 - r0 + 3) >> 2;
+        const int64_t ra = r0 + wid * nrw;
+        const int64_t rb = ra + nrw < r1 ? ra + nrw : r1;
         int cnt = 0, icnt = 0;
         int qn = 0;  // wave-uniform queue length
 
-        for (int64_t r = r0 + wid; r < r1; r += 4) {
-            // outer coordinates of row r
-            int32_t q[K > 1 ? K - 1 : 1];
+        if (ra < rb) {
+            // outer coordinates of the first row (one division per dim, then stepping)
+            int32_t q[KO];
             {
-                uint32_t rr = (uint32_t)r;
+                uint32_t rr = (uint32_t)ra;
 #pragma unroll
                 for (int d = K - 2; d >= 0; --d) {
                     q[d] = (int32_t)(rr % (uint32_t)ext[d]);
                     rr /= (uint32_t)ext[d];
                 }
             }
-            int32_t base = 0;
-            bool rflag = false;
-            int32_t oe[K > 1 ? K - 1 : 1];
+            // prefix over dims 0..K-3: base index and offsets, refreshed on carries
+            int32_t base_o = 0, no = 0;
+            auto load_prefix = [&]() {
+                base_o = 0;
+                no = 0;
 #pragma unroll
-            for (int d = 0; d < K - 1; ++d) {
-                oe[d] = T[off[d] + q[d]];
-                base += oe[d] & (int32_t)kValMask;
-                rflag = rflag || (oe[d] < 0);
-            }
-            if (!rflag) {
-                // ---- sparse path: only flagged last-dim cells can see another owner
-                for (int xb = 0; xb < L; xb += 64) {
-                    const int x = xb + lane;
-                    const int32_t e = x < L ? CL[x] : 0;
-                    const bool hit = e < 0;
-                    const uint64_t m = __ballot(hit);
-                    if (m == 0ull) continue;
-                    const int pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    if (hit) {
-                        qv[pos] = base + (e & (int32_t)kValMask);
-                        qx[pos] = x;
+                for (int d = 0; d < K - 2; ++d) {
+                    const int32_t e = uniform32(T[off[d] + q[d]]);
+                    base_o += cval(e);
+                    const int nd = ccnt(e);
+                    if (nd) {
+                        if (lane < nd) rl[no + lane] = garena[dlo[d] + q[d] * HS + lane];
+                        no += nd;
                     }
-                    qn += __popcll(m);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    if (qn >= 64) {
-                        const int32_t v = qv[lane], xq = qx[lane];
-                        const int32_t o = T[v];
-                        int32_t cand[Cfg::NL];
-                        last_dim_owners<H>(T, CL, v, xq, CL[xq] & (int32_t)kValMask, L, hL, o, cand);
-                        count_distinct<Cfg::NL>(cand, o, gbits, cnt, icnt);
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                        if (lane < qn - 64) {
-                            qv[lane] = qv[lane + 64];
-                            qx[lane] = qx[lane + 64];
+                }
+            };
+            load_prefix();
+            for (int64_t r = ra; r < rb; ++r) {
+                int32_t base = base_o, nr = no;
+                if (K > 1) {
+                    const int32_t e = uniform32(T[off[K - 2] + q[K - 2]]);
+                    base += cval(e);
+                    const int nd = ccnt(e);
+                    if (nd) {
+                        if (lane < nd) rl[no + lane] = garena[dlo[K - 2] + q[K - 2] * HS + lane];
+                        nr += nd;
+                    }
+                }
+                if (nr == 0) {
+                    // ---- sparse row: groups of four cells with last-dim offsets go to the queue
+                    for (int xb = 0; xb < L; xb += 256) {
+                        const int x0 = xb + 4 * lane;
+                        const i32x4 e4 = *reinterpret_cast<const i32x4*>(CL + x0);  // zero-padded past L
+                        const bool hit = (uint32_t)(e4.x | e4.y | e4.z | e4.w) > (uint32_t)kValMask;
+                        const uint64_t m = __ballot(hit);
+                        if (m == 0ull) continue;
+                        const int pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        if (hit) {
+                            qv[pos] = base;
+                            qx[pos] = x0;
                         }
-                        qn -= 64;
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    }
-                }
-            } else {
-                // ---- dense path: distinct non-zero offsets to the outer neighbours
-                int32_t od[Cfg::NO];
-                bool ok[Cfg::NO];
+                        qn += __popcll(m);
+                        wave_sync_lds();
+                        if (qn >= 64) {
+                            const int32_t bq = qv[lane], xq = qx[lane];
+                            const i32x4 g4 = *reinterpret_cast<const i32x4*>(CL + xq);
 #pragma unroll
-                for (int j = 0; j < Cfg::NO; ++j) {
-                    od[j] = 0;
-                    ok[j] = false;
-                }
-#pragma unroll
-                for (int d = 0; d < K - 1; ++d) {
-#pragma unroll
-                    for (int s = 1; s <= H; ++s) {
-#pragma unroll
-                        for (int dir = 0; dir < 2; ++dir) {
-                            const int slot = (d * H + (s - 1)) * 2 + dir;
-                            const int xx = dir ? q[d] + s : q[d] - s;
-                            int32_t dv = 0;
-                            if (oe[d] < 0 && s <= hal[d] && xx >= 0 && xx < ext[d])
-                                dv = (T[off[d] + xx] & (int32_t)kValMask) - (oe[d] & (int32_t)kValMask);
-                            od[slot] = dv;
-                            bool fresh = dv != 0;
-#pragma unroll
-                            for (int i = 0; i < slot; ++i) fresh = fresh && (od[i] != dv);
-                            ok[slot] = fresh;
+                            for (int j = 0; j < 4; ++j) {
+                                const int32_t e = j == 0 ? g4.x : (j == 1 ? g4.y : (j == 2 ? g4.z : g4.w));
+                                const int nx = ccnt(e);
+                                if (nx == 0) continue;
+                                const int32_t v = bq + cval(e);
+                                eval_cell(T, v, T[v], rl, 0, DL + (xq + j) * HS, nx, gbits, cnt, icnt);
+                            }
+                            wave_sync_lds();
+                            if (lane < qn - 64) {
+                                qv[lane] = qv[lane + 64];
+                                qx[lane] = qx[lane + 64];
+                            }
+                            qn -= 64;
+                            wave_sync_lds();
                         }
                     }
+                } else {
+                    // ---- dense row: every cell sees the outer neighbours of the row
+                    wave_sync_lds();
+                    for (int xb = 0; xb < L; xb += 256) {
+                        const int x0 = xb + 4 * lane;
+                        const i32x4 e4 = *reinterpret_cast<const i32x4*>(CL + x0);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int x = x0 + j;
+                            if (x >= L) continue;
+                            const int32_t e = j == 0 ? e4.x : (j == 1 ? e4.y : (j == 2 ? e4.z : e4.w));
+                            const int32_t v = base + cval(e);
+                            eval_cell(T, v, T[v], rl, nr, DL + x * HS, ccnt(e), gbits, cnt, icnt);
+                        }
+                    }
+                    wave_sync_lds();
                 }
-                for (int xb = 0; xb < L; xb += 64) {
-                    const int x = xb + lane;
-                    if (x >= L) continue;
-                    const int32_t e = CL[x];
-                    const int32_t ev = e & (int32_t)kValMask;
-                    const int32_t v = base + ev;
-                    const int32_t o = T[v];
-                    if (e >= 0) {
-                        int32_t cand[Cfg::NO];
+                // next row: step the outer coordinates
+                if (K > 1) {
+                    if (++q[K - 2] == ext[K - 2]) {
+                        q[K - 2] = 0;
 #pragma unroll
-                        for (int j = 0; j < Cfg::NO; ++j) cand[j] = ok[j] ? T[v + od[j]] : o;
-                        count_distinct<Cfg::NO>(cand, o, gbits, cnt, icnt);
-                    } else {
-                        int32_t cand[Cfg::NO + Cfg::NL];
-#pragma unroll
-                        for (int j = 0; j < Cfg::NO; ++j) cand[j] = ok[j] ? T[v + od[j]] : o;
-                        int32_t cl[Cfg::NL];
-                        last_dim_owners<H>(T, CL, v, x, ev, L, hL, o, cl);
-#pragma unroll
-                        for (int j = 0; j < Cfg::NL; ++j) cand[Cfg::NO + j] = cl[j];
-                        count_distinct<Cfg::NO + Cfg::NL>(cand, o, gbits, cnt, icnt);
+                        for (int d = K - 3; d >= 0; --d) {
+                            if (++q[d] < ext[d]) break;
+                            q[d] = 0;
+                        }
+                        load_prefix();
+                        wave_sync_lds();
                     }
                 }
             }
@@ -421,16 +436,19 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
         // drain the queue
         if (qn > 0) {
             if (lane < qn) {
-                const int32_t v = qv[lane], xq = qx[lane];
-                const int32_t o = T[v];
-                int32_t cand[Cfg::NL];
-                last_dim_owners<H>(T, CL, v, xq, CL[xq] & (int32_t)kValMask, L, hL, o, cand);
-                count_distinct<Cfg::NL>(cand, o, gbits, cnt, icnt);
+                const int32_t bq = qv[lane], xq = qx[lane];
+                const i32x4 g4 = *reinterpret_cast<const i32x4*>(CL + xq);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int32_t e = j == 0 ? g4.x : (j == 1 ? g4.y : (j == 2 ? g4.z : g4.w));
+                    const int nx = ccnt(e);
+                    if (nx == 0) continue;
+                    const int32_t v = bq + cval(e);
+                    eval_cell(T, v, T[v], rl, 0, DL + (xq + j) * HS, nx, gbits, cnt, icnt);
+                }
             }
             qn = 0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_sync_lds();
         }
         cnt = wave_sum(cnt);
         icnt = wave_sum(icnt);
@@ -583,7 +601,7 @@ __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, 
     if (ci < 0 || ci >= n) return;  // no candidate selected (empty batch)
     stage_cand(&sc, &cands[ci]);
     __syncthreads();
-    const int32_t words = sc.words;
+    const int32_t words = sc.lds_words;
     const int32_t* src = arena + sc.arena_off;
     for (int i = threadIdx.x; i < words; i += blockDim.x) lds[i] = src[i];
     __syncthreads();
@@ -602,23 +620,23 @@ __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, 
         int32_t base = 0;
         for (int d = K - 2; d >= 0; --d) {
             const uint32_t e = (uint32_t)sc.extent[d];
-            base += lds[sc.coord_off[d] + (int32_t)(rr % e)] & (int32_t)kValMask;
+            base += lds[sc.coord_off[d] + (int32_t)(rr % e)] & kValMask;
             rr /= e;
         }
         int32_t* row = out + r * (int64_t)L;
         if (vec) {
             for (int x = lane * 4; x < L; x += 256) {
                 i32x4 key;
-                key.x = T[base + (CL[x] & (int32_t)kValMask)];
-                key.y = T[base + (CL[x + 1] & (int32_t)kValMask)];
-                key.z = T[base + (CL[x + 2] & (int32_t)kValMask)];
-                key.w = T[base + (CL[x + 3] & (int32_t)kValMask)];
+                key.x = T[base + (CL[x] & kValMask)];
+                key.y = T[base + (CL[x + 1] & kValMask)];
+                key.z = T[base + (CL[x + 2] & kValMask)];
+                key.w = T[base + (CL[x + 3] & kValMask)];
                 const i32x4 p = (key >> gb) * g + (key & gmask);
                 __builtin_nontemporal_store(p, reinterpret_cast<i32x4*>(row + x));
             }
         } else {
             for (int x = lane; x < L; x += 64) {
-                const int32_t key = T[base + (CL[x] & (int32_t)kValMask)];
+                const int32_t key = T[base + (CL[x] & kValMask)];
                 __builtin_nontemporal_store((key >> gb) * g + (key & gmask), row + x);
             }
         }
@@ -681,7 +699,7 @@ __global__ __launch_bounds__(256) void k_matmul(const DevCand* __restrict__ cand
             stage_cand(&sc, &cands[lo]);
             __syncthreads();
             const int32_t* src = arena + sc.arena_off;
-            for (int i = threadIdx.x; i < sc.words; i += blockDim.x) lds[i] = src[i];
+            for (int i = threadIdx.x; i < sc.lds_words; i += blockDim.x) lds[i] = src[i];
             __syncthreads();
             cur = lo;
         }
@@ -715,22 +733,22 @@ __global__ __launch_bounds__(256) void k_matmul(const DevCand* __restrict__ cand
                 int64_t nred;
                 if (m == 0) {  // A[i,k]: tile = i*Tk + k, reduce over j
                     const int64_t i = tile / Tk, k = tile % Tk;
-                    fixed = (C0[i] & (int32_t)kValMask) + (C2[k] & (int32_t)kValMask);
+                    fixed = (C0[i] & kValMask) + (C2[k] & kValMask);
                     red = C1;
                     nred = Tj;
                 } else if (m == 1) {  // B[k,j]: tile = k*Tj + j, reduce over i
                     const int64_t k = tile / Tj, j = tile % Tj;
-                    fixed = (C2[k] & (int32_t)kValMask) + (C1[j] & (int32_t)kValMask);
+                    fixed = (C2[k] & kValMask) + (C1[j] & kValMask);
                     red = C0;
                     nred = Ti;
                 } else {  // C[i,j]: tile = i*Tj + j, reduce over k
                     const int64_t i = tile / Tj, j = tile % Tj;
-                    fixed = (C0[i] & (int32_t)kValMask) + (C1[j] & (int32_t)kValMask);
+                    fixed = (C0[i] & kValMask) + (C1[j] & kValMask);
                     red = C2;
                     nred = Tk;
                 }
                 for (int64_t t = 0; t < nred; ++t) {
-                    const int32_t key = T[fixed + (red[t] & (int32_t)kValMask)];
+                    const int32_t key = T[fixed + (red[t] & kValMask)];
                     const int32_t p = (key >> gb) * g + (key & gmask);
                     const uint64_t bit = 1ull << (p & 63);
                     if (W == 1) {

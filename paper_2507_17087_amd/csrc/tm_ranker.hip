@@ -1,0 +1,681 @@
+// tm_ranker.hip -- learned ranker kernels (gfx950): candidate features, a 3-layer
+// BF16 MLP (MFMA v_mfma_f32_16x16x32_bf16, FP32 accumulation) forward / backward,
+// Adam, per-segment top-k, and the on-device gather of the survivors for exact
+// re-evaluation.
+//
+// MFMA fragment layout used throughout (16x16x32, one wave): lane l holds row
+// (l % 16) of A and column (l % 16) of B, eight consecutive k values starting at
+// 8 * (l / 16); the result holds rows 4 * (l / 16) + r (r = 0..3) of column l % 16.
+#include <hip/hip_runtime.h>
+
+#include "tm_internal.h"
+#include "tm_ranker.h"
+
+namespace tmk {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
+
+__device__ __forceinline__ f32x4 mfma16(u16x8 a, u16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a), as_bf(b), c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------ features
+
+__device__ __forceinline__ float lg2(double x) { return (float)log2(x); }
+
+// One thread per candidate; writes kFeat bf16 values (row of X) and, when
+// feat_f32 is given, the same values in fp32.
+__global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ cands, int64_t n,
+                                                  const int32_t* __restrict__ halo, uint16_t* __restrict__ X,
+                                                  float* __restrict__ feat_f32) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const DevCand& c = cands[i];
+    float f[kFeat];
+#pragma unroll
+    for (int t = 0; t < kFeat; ++t) f[t] = 0.f;
+    const int k = c.lrank;
+    f[k - 1] = 1.f;
+    double blocks[4] = {1, 1, 1, 1};
+    for (int j = 0; j < c.frank; ++j) blocks[c.proj_src[j]] *= c.fshape[j];
+    double vol_b = 0, vol_f = 0;
+    int32_t F[4] = {1, 1, 1, 1};
+    int nf = 0;
+    for (int t = 0; t < c.nops; ++t)
+        if (c.op_kind[t] == TM_DECOMPOSE) {
+            nf = c.op_nf[t];
+            for (int m = 0; m < nf; ++m) F[m] = c.op_f[t][m];
+            break;
+        }
+    for (int d = 0; d < k; ++d) {
+        const double l = (double)c.extent[d];
+        f[4 + d] = lg2(l) / 10.f;
+        f[15 + d] = lg2(blocks[d]) / 9.f;
+        f[19 + d] = (lg2(l) - lg2(blocks[d])) / 10.f;
+        vol_b += 2.0 * halo[d] * (blocks[d] - 1.0) / l;
+        if (d < nf) vol_f += 2.0 * halo[d] * (F[d] - 1.0) / l;
+        f[54 + d] = halo[d] / 4.f;
+    }
+    f[8] = lg2((double)c.nodes) / 6.f;
+    f[9] = lg2((double)c.gpus) / 3.f;
+    f[10] = lg2((double)c.nodes * c.gpus) / 9.f;
+    for (int m = 0; m < nf && m < 4; ++m) f[11 + m] = lg2((double)F[m]) / 9.f;
+    f[23] = lg2(1.0 + vol_b) / 4.f;
+    f[24] = lg2(1.0 + vol_f) / 4.f;
+    for (int t = 0; t < c.nops; ++t) {
+        const int kd = c.op_kind[t];
+        if (kd >= 1 && kd <= 5) f[25 + kd - 1] += 0.25f;
+        if (t < 6) {
+            f[30 + t] = kd / 5.f;
+            f[36 + t] = c.op_a[t] / 8.f;
+            f[42 + t] = kd == TM_DECOMPOSE ? 0.f : lg2(1.0 + (double)c.op_b[t]) / 9.f;
+        }
+    }
+    f[48] = (c.nops > 0 && c.op_kind[0] == TM_SWAP) ? 1.f : 0.f;
+    for (int j = 0; j < c.frank && j < 4; ++j) f[49 + j] = c.proj_mode[j] ? 1.f : 0.f;
+    f[53] = c.frank / 8.f;
+    f[58] = c.gbits / 3.f;
+    f[59] = 1.f;
+    uint16_t* row = X + i * kFeat;
+#pragma unroll
+    for (int t = 0; t < kFeat; ++t) {
+        row[t] = f2bf(f[t]);
+        if (feat_f32) feat_f32[i * kFeat + t] = f[t];
+    }
+}
+
+// ------------------------------------------------------------------ fused forward
+//
+// A workgroup (4 waves) takes 64 rows.  Activations stay in LDS (bf16, padded row
+// stride); wave w computes output columns [64w, 64w + 64) of each hidden layer as
+// 4 x 4 MFMA tiles, reading weight fragments straight from the transposed bf16
+// weights Wt[n][k] (16 contiguous bytes per lane).  Epilogue: bias, ReLU, round to
+// bf16; optionally the activations are stored for the backward pass.  The head
+// (256 -> 2) is a pair of FP32 dot products per row.
+
+constexpr int kRowsFwd = 64;
+constexpr int kLdsStride = kWidth + 8;  // bf16 elements per LDS row (breaks bank aliasing)
+
+template <int KIN>
+__device__ __forceinline__ void layer_fwd(const uint16_t* __restrict__ in_lds, uint16_t* __restrict__ out_lds,
+                                          const uint16_t* __restrict__ Wt, const float* __restrict__ bias,
+                                          int lane, int wid) {
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll
+    for (int k0 = 0; k0 < KIN; k0 += 32) {
+        u16x8 bf[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int ncol = wid * 64 + b * 16 + r16;
+            bf[b] = *reinterpret_cast<const u16x8*>(Wt + (size_t)ncol * KIN + k0 + kq);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const u16x8 af = *reinterpret_cast<const u16x8*>(in_lds + (a * 16 + r16) * kLdsStride + k0 + kq);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(af, bf[b], acc[a][b]);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int col = wid * 64 + b * 16 + r16;
+        const float bb = bias[col];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = a * 16 + (lane >> 4) * 4 + r;
+                const float v = fmaxf(acc[a][b][r] + bb, 0.f);
+                out_lds[row * kLdsStride + col] = f2bf(v);
+            }
+    }
+}
+
+__device__ __forceinline__ void store_act(const uint16_t* __restrict__ lds_act, uint16_t* __restrict__ g,
+                                          int64_t row0, int64_t n, int tid) {
+    // 64 rows x 256 bf16: each thread moves 8 bf16 per step
+    for (int i = tid; i < kRowsFwd * (kWidth / 8); i += 256) {
+        const int r = i / (kWidth / 8), c8 = (i % (kWidth / 8)) * 8;
+        if (row0 + r < n)
+            *reinterpret_cast<u16x8*>(g + (row0 + r) * kWidth + c8) =
+                *reinterpret_cast<const u16x8*>(lds_act + r * kLdsStride + c8);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t* __restrict__ X, int64_t n,
+                                                     const RankerWeights W, float* __restrict__ Y,
+                                                     uint16_t* __restrict__ H1, uint16_t* __restrict__ H2,
+                                                     uint16_t* __restrict__ H3) {
+    __shared__ __attribute__((aligned(16))) uint16_t sa[kRowsFwd * kLdsStride];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[kRowsFwd * kLdsStride];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int64_t row0 = (int64_t)blockIdx.x * kRowsFwd; row0 < n; row0 += (int64_t)gridDim.x * kRowsFwd) {
+        __syncthreads();
+        // X tile -> sa (64 x 64 bf16), zero rows past n
+        for (int i = tid; i < kRowsFwd * (kFeat / 8); i += 256) {
+            const int r = i / (kFeat / 8), c8 = (i % (kFeat / 8)) * 8;
+            u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (row0 + r < n) v = *reinterpret_cast<const u16x8*>(X + (row0 + r) * kFeat + c8);
+            *reinterpret_cast<u16x8*>(sa + r * kLdsStride + c8) = v;
+        }
+        __syncthreads();
+        layer_fwd<kFeat>(sa, sb, W.w1t, W.b1, lane, wid);
+        __syncthreads();
+        if (H1) store_act(sb, H1, row0, n, tid);
+        layer_fwd<kWidth>(sb, sa, W.w2t, W.b2, lane, wid);
+        __syncthreads();
+        if (H2) store_act(sa, H2, row0, n, tid);
+        layer_fwd<kWidth>(sa, sb, W.w3t, W.b3, lane, wid);
+        __syncthreads();
+        if (H3) store_act(sb, H3, row0, n, tid);
+        // head: thread t -> row t/4, output (t/2)%2, half (t%2) of the k range
+        {
+            const int r = tid >> 2, h = (tid >> 1) & 1, half = tid & 1;
+            float s = 0.f;
+            for (int k = half * (kWidth / 2); k < (half + 1) * (kWidth / 2); ++k)
+                s += bf2f(sb[r * kLdsStride + k]) * bf2f(W.w4[k * kOut + h]);
+            s += __shfl_xor(s, 1, 64);
+            if (half == 0 && row0 + r < n) Y[(row0 + r) * kOut + h] = s + W.b4[h];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ backward pieces
+
+// dY = scale_h * (Y - T) (per head weights already in scale), and the head's input
+// gradient dH3 = (dY W4^T) * [H3 > 0], bf16.
+__global__ __launch_bounds__(256) void k_head_backward(const float* __restrict__ Y, const float* __restrict__ Tg,
+                                                       int64_t n, float s0, float s1, const RankerWeights W,
+                                                       const uint16_t* __restrict__ H3, float* __restrict__ dY,
+                                                       uint16_t* __restrict__ dH3) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n * kWidth) return;
+    const int64_t r = idx / kWidth;
+    const int k = (int)(idx % kWidth);
+    const float d0 = s0 * (Y[r * kOut] - Tg[r * kOut]);
+    const float d1 = s1 * (Y[r * kOut + 1] - Tg[r * kOut + 1]);
+    if (k == 0) {
+        dY[r * kOut] = d0;
+        dY[r * kOut + 1] = d1;
+    }
+    const float g = d0 * bf2f(W.w4[k * kOut]) + d1 * bf2f(W.w4[k * kOut + 1]);
+    dH3[idx] = bf2f(H3[idx]) > 0.f ? f2bf(g) : (uint16_t)0;
+}
+
+// dIn = (dOut M) * [Act > 0] where the layer computed Out = In Wf: M = Wf^T, so
+// B-fragments come from Wf stored row-major [kin][kout] (k = kout contiguous).
+// 64 rows per workgroup, KOUT = 256 reduction, output columns KIN.
+template <int KIN>
+__global__ __launch_bounds__(256) void k_backward_data(const uint16_t* __restrict__ dOut, int64_t n,
+                                                       const uint16_t* __restrict__ Wf,
+                                                       const uint16_t* __restrict__ Act,
+                                                       uint16_t* __restrict__ dIn) {
+    __shared__ __attribute__((aligned(16))) uint16_t sa[kRowsFwd * kLdsStride];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    constexpr int NT = KIN / 64;  // column tiles of 16 per wave
+    for (int64_t row0 = (int64_t)blockIdx.x * kRowsFwd; row0 < n; row0 += (int64_t)gridDim.x * kRowsFwd) {
+        __syncthreads();
+        for (int i = tid; i < kRowsFwd * (kWidth / 8); i += 256) {
+            const int r = i / (kWidth / 8), c8 = (i % (kWidth / 8)) * 8;
+            u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (row0 + r < n) v = *reinterpret_cast<const u16x8*>(dOut + (row0 + r) * kWidth + c8);
+            *reinterpret_cast<u16x8*>(sa + r * kLdsStride + c8) = v;
+        }
+        __syncthreads();
+        f32x4 acc[4][NT];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < NT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k0 = 0; k0 < kWidth; k0 += 32) {
+            u16x8 bf[NT];
+#pragma unroll
+            for (int b = 0; b < NT; ++b) {
+                const int ncol = wid * (KIN / 4) + b * 16 + r16;
+                bf[b] = *reinterpret_cast<const u16x8*>(Wf + (size_t)ncol * kWidth + k0 + kq);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const u16x8 af = *reinterpret_cast<const u16x8*>(sa + (a * 16 + r16) * kLdsStride + k0 + kq);
+#pragma unroll
+                for (int b = 0; b < NT; ++b) acc[a][b] = mfma16(af, bf[b], acc[a][b]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+            const int col = wid * (KIN / 4) + b * 16 + r16;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row0 + a * 16 + (lane >> 4) * 4 + r;
+                    if (row < n) {
+                        const bool on = Act ? bf2f(Act[row * KIN + col]) > 0.f : true;
+                        dIn[row * KIN + col] = on ? f2bf(acc[a][b][r]) : (uint16_t)0;
+                    }
+                }
+        }
+    }
+}
+
+// Weight gradient partials: P[split][KIN][KOUT] = In[rows of split]^T dOut[rows].
+// Workgroup = (64 x 64 output tile, split).  Chunks of 32 rows are staged in LDS
+// transposed (k-major) so that both MFMA operands read 16 contiguous bytes.
+template <int KIN>
+__global__ __launch_bounds__(256) void k_wgrad(const uint16_t* __restrict__ In, const uint16_t* __restrict__ dOut,
+                                               int64_t n, int64_t rows_per_split, float* __restrict__ P) {
+    __shared__ __attribute__((aligned(16))) uint16_t sI[64][40];  // [kin][row] (32 rows + pad)
+    __shared__ __attribute__((aligned(16))) uint16_t sO[64][40];  // [kout][row]
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tiles_n = kWidth / 64;
+    const int ti = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;  // output tile (kin, kout)
+    const int split = blockIdx.y;
+    const int64_t ra = split * rows_per_split;
+    const int64_t rb = ra + rows_per_split < n ? ra + rows_per_split : n;
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    const int wa = wid >> 1, wb = wid & 1;  // wave's 32 x 32 quadrant
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t r0 = ra; r0 < rb; r0 += 32) {
+        __syncthreads();
+        // 32 rows x 64 columns of each operand, transposed into LDS
+        for (int i = tid; i < 32 * 64; i += 256) {
+            const int rr = i / 64, cc = i % 64;
+            const int64_t row = r0 + rr;
+            uint16_t vi = 0, vo = 0;
+            if (row < rb) {
+                vi = In[row * KIN + ti * 64 + cc];
+                vo = dOut[row * kWidth + tn * 64 + cc];
+            }
+            sI[cc][rr] = vi;
+            sO[cc][rr] = vo;
+        }
+        __syncthreads();
+        const u16x8 a0 = *reinterpret_cast<const u16x8*>(&sI[wa * 32 + r16][kq]);
+        const u16x8 a1 = *reinterpret_cast<const u16x8*>(&sI[wa * 32 + 16 + r16][kq]);
+        const u16x8 b0 = *reinterpret_cast<const u16x8*>(&sO[wb * 32 + r16][kq]);
+        const u16x8 b1 = *reinterpret_cast<const u16x8*>(&sO[wb * 32 + 16 + r16][kq]);
+        acc[0][0] = mfma16(a0, b0, acc[0][0]);
+        acc[0][1] = mfma16(a0, b1, acc[0][1]);
+        acc[1][0] = mfma16(a1, b0, acc[1][0]);
+        acc[1][1] = mfma16(a1, b1, acc[1][1]);
+    }
+    float* out = P + (size_t)split * KIN * kWidth;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ti * 64 + wa * 32 + a * 16 + (lane >> 4) * 4 + r;
+                const int col = tn * 64 + wb * 32 + b * 16 + r16;
+                out[row * kWidth + col] = acc[a][b][r];
+            }
+}
+
+// Column sums of a bf16 [n x N] matrix per split (bias gradients), fp32 partials.
+__global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ A, int64_t n, int N,
+                                                int64_t rows_per_split, float* __restrict__ P) {
+    const int split = blockIdx.y;
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= N) return;
+    const int64_t ra = split * rows_per_split;
+    const int64_t rb = ra + rows_per_split < n ? ra + rows_per_split : n;
+    float s = 0.f;
+    for (int64_t r = ra; r < rb; ++r) s += bf2f(A[r * N + col]);
+    P[(size_t)split * N + col] = s;
+}
+
+// Head gradients: dW4[k][h] = sum_r H3[r][k] dY[r][h], db4[h] = sum_r dY[r][h].
+__global__ __launch_bounds__(256) void k_head_wgrad(const uint16_t* __restrict__ H3, const float* __restrict__ dY,
+                                                    int64_t n, int64_t rows_per_split, float* __restrict__ P) {
+    const int split = blockIdx.y;
+    const int t = threadIdx.x;  // k index
+    const int64_t ra = split * rows_per_split;
+    const int64_t rb = ra + rows_per_split < n ? ra + rows_per_split : n;
+    float s0 = 0.f, s1 = 0.f, b0 = 0.f, b1 = 0.f;
+    for (int64_t r = ra; r < rb; ++r) {
+        const float h = bf2f(H3[r * kWidth + t]);
+        s0 += h * dY[r * kOut];
+        s1 += h * dY[r * kOut + 1];
+        if (t == 0) {
+            b0 += dY[r * kOut];
+            b1 += dY[r * kOut + 1];
+        }
+    }
+    float* o = P + (size_t)split * (kWidth * kOut + kOut);
+    o[t * kOut] = s0;
+    o[t * kOut + 1] = s1;
+    if (t == 0) {
+        o[kWidth * kOut] = b0;
+        o[kWidth * kOut + 1] = b1;
+    }
+}
+
+// Sum split partials (fixed order: deterministic) into dst[count].
+__global__ __launch_bounds__(256) void k_reduce_splits(const float* __restrict__ P, int splits, int64_t count,
+                                                       float* __restrict__ dst) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.f;
+    for (int sp = 0; sp < splits; ++sp) s += P[(size_t)sp * count + i];
+    dst[i] = s;
+}
+
+// Adam on the fp32 master copy; refreshes the bf16 copies (row-major and
+// transposed) of the matrices.  Parameter layout: see RankerLayout.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, int64_t count,
+                                              float lr, float b1, float b2, float eps, float c1, float c2,
+                                              const RankerWeights W) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    publish_param(i, pi, W);
+}
+
+// Refresh all bf16 copies from the fp32 master (after loading or setting params).
+__global__ __launch_bounds__(256) void k_publish(const float* __restrict__ p, int64_t count, const RankerWeights W) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    publish_param(i, p[i], W);
+}
+
+// ------------------------------------------------------------------ top-k per segment
+//
+// One workgroup per segment: k rounds of a block-wide argmin over (score, index),
+// the winner marked taken (NaN) in the scratch copy.  Output: global candidate
+// indices, ascending by (score, index); -1 past the end of a shorter segment.
+
+__global__ __launch_bounds__(256) void k_topk(const float* __restrict__ score, const int64_t* __restrict__ seg,
+                                              int k, float* __restrict__ scratch, int64_t* __restrict__ sel) {
+    __shared__ float sv[256];
+    __shared__ int64_t si[256];
+    const int64_t a = seg[blockIdx.x], e = seg[blockIdx.x + 1];
+    for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) scratch[i] = score[i];
+    __syncthreads();
+    const float taken = __builtin_nanf("");  // never wins a comparison
+    for (int round = 0; round < k; ++round) {
+        float bv = INFINITY;
+        int64_t bi = INT64_MAX;
+        for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
+            const float s = scratch[i];
+            if (s < bv || (s == bv && i < bi)) {
+                bv = s;
+                bi = i;
+            }
+        }
+        sv[threadIdx.x] = bv;
+        si[threadIdx.x] = bi;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                const float ov = sv[threadIdx.x + w];
+                const int64_t oi = si[threadIdx.x + w];
+                if (ov < sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+                    sv[threadIdx.x] = ov;
+                    si[threadIdx.x] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        const int64_t win = si[0];
+        __syncthreads();
+        if (win == INT64_MAX) {  // segment exhausted
+            for (int rr = round + threadIdx.x; rr < k; rr += blockDim.x) sel[blockIdx.x * (int64_t)k + rr] = -1;
+            break;
+        }
+        if (threadIdx.x == 0) {
+            sel[blockIdx.x * (int64_t)k + round] = win;
+            scratch[win] = taken;
+        }
+        __syncthreads();
+    }
+}
+
+// Ranking score from the two heads: s = y0 + lambda * y1.
+__global__ void k_combine(const float* __restrict__ Y, int64_t n, float lambda, float* __restrict__ s) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) s[i] = Y[i * kOut] + lambda * Y[i * kOut + 1];
+}
+
+// ------------------------------------------------------------------ survivors
+
+// Builds the sub-batch of selected candidates on the device: copies their compiled
+// descriptors, lays out their tables and work items (prefix sums in one workgroup)
+// and writes the sub-batch header.  sel[s] < 0 entries are skipped; map[j] gives
+// the original index of sub-batch entry j and seg_out the sub-batch segments.
+__global__ __launch_bounds__(1024) void k_gather(const DevCand* __restrict__ cands, const int64_t* __restrict__ sel,
+                                                 int64_t nsel, int k, int64_t cells_per_item,
+                                                 DevCand* __restrict__ sub, int64_t* __restrict__ map,
+                                                 int64_t* __restrict__ seg_out, DevHeader* __restrict__ hdr,
+                                                 const DevHeader* __restrict__ proto) {
+    __shared__ int64_t s_words[1024], s_items[1024], s_cnt[1024];
+    __shared__ int64_t carry_w, carry_i, carry_c;
+    if (threadIdx.x == 0) {
+        carry_w = 0;
+        carry_i = 0;
+        carry_c = 0;
+    }
+    __syncthreads();
+    for (int64_t base = 0; base < nsel; base += blockDim.x) {
+        const int64_t s = base + threadIdx.x;
+        int64_t words = 0, items = 0, present = 0;
+        int64_t ci = -1;
+        if (s < nsel) {
+            ci = sel[s];
+            if (ci >= 0) {
+                const DevCand& c = cands[ci];
+                const int64_t rpi0 = cells_per_item / (c.L > 0 ? c.L : 1);
+                const int64_t rpi = rpi0 < 1 ? 1 : (rpi0 > c.rows ? (c.rows > 0 ? c.rows : 1) : rpi0);
+                words = c.words;
+                items = (c.rows + rpi - 1) / rpi;
+                present = 1;
+            }
+        }
+        s_words[threadIdx.x] = words;
+        s_items[threadIdx.x] = items;
+        s_cnt[threadIdx.x] = present;
+        __syncthreads();
+        for (int o = 1; o < (int)blockDim.x; o <<= 1) {  // inclusive scans
+            int64_t aw = 0, ai = 0, ac = 0;
+            if ((int)threadIdx.x >= o) {
+                aw = s_words[threadIdx.x - o];
+                ai = s_items[threadIdx.x - o];
+                ac = s_cnt[threadIdx.x - o];
+            }
+            __syncthreads();
+            s_words[threadIdx.x] += aw;
+            s_items[threadIdx.x] += ai;
+            s_cnt[threadIdx.x] += ac;
+            __syncthreads();
+        }
+        if (present) {
+            const int64_t j = carry_c + s_cnt[threadIdx.x] - 1;
+            DevCand c = cands[ci];
+            const int64_t rpi0 = cells_per_item / (c.L > 0 ? c.L : 1);
+            c.rows_per_item = (int32_t)(rpi0 < 1 ? 1 : (rpi0 > c.rows ? (c.rows > 0 ? c.rows : 1) : rpi0));
+            c.arena_off = carry_w + s_words[threadIdx.x] - words;
+            c.item_first = carry_i + s_items[threadIdx.x] - items;
+            sub[j] = c;
+            map[j] = ci;
+        }
+        // segment starts: first slot of each segment of k
+        if (s < nsel && (s % k) == 0) seg_out[s / k] = carry_c + s_cnt[threadIdx.x] - present;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) {
+            carry_w += s_words[threadIdx.x];
+            carry_i += s_items[threadIdx.x];
+            carry_c += s_cnt[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        seg_out[(nsel + k - 1) / k] = carry_c;
+        DevHeader h = *proto;
+        h.n = carry_c;
+        h.total_items = carry_i;
+        *hdr = h;
+    }
+}
+
+// best[s] = map[sub_best[s] + seg[s]] (original candidate index) and its cost.
+__global__ void k_map_best(const int64_t* __restrict__ sub_best, const int64_t* __restrict__ seg,
+                           const int64_t* __restrict__ map, const tm_stencil_cost* __restrict__ sub_cost,
+                           int64_t nseg, const int64_t* __restrict__ orig_seg, int64_t* __restrict__ best,
+                           tm_stencil_cost* __restrict__ best_cost) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    const int64_t b = sub_best[s];
+    if (b < 0) {
+        best[s] = -1;
+        if (best_cost) best_cost[s] = tm_stencil_cost{-1, -1, -1, -1};
+        return;
+    }
+    const int64_t j = seg[s] + b;
+    best[s] = map[j] - orig_seg[s];
+    if (best_cost) best_cost[s] = sub_cost[j];
+}
+
+// Exhaustive path: best index is already relative; copy costs out.
+__global__ void k_pick_costs(const int64_t* __restrict__ best, const int64_t* __restrict__ seg,
+                             const tm_stencil_cost* __restrict__ cost, int64_t nseg,
+                             tm_stencil_cost* __restrict__ best_cost) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= nseg || !best_cost) return;
+    best_cost[s] = best[s] < 0 ? tm_stencil_cost{-1, -1, -1, -1} : cost[seg[s] + best[s]];
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_halo, uint16_t* X, float* f32,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cands, n, d_halo, X, f32);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const uint16_t* X, int64_t n, const RankerWeights& W, float* Y, uint16_t* H1,
+                              uint16_t* H2, uint16_t* H3, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t grid = (n + kRowsFwd - 1) / kRowsFwd;
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)grid), dim3(256), 0, s, X, n, W, Y, H1, H2, H3);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(const RankerBuffers& B, const RankerWeights& W, int64_t n, float s0, float s1,
+                           hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t rows_per_split = ((n + kSplits - 1) / kSplits + 31) / 32 * 32;
+    const int splits = (int)((n + rows_per_split - 1) / rows_per_split);
+    hipLaunchKernelGGL(k_head_backward, dim3((unsigned)((n * kWidth + 255) / 256)), dim3(256), 0, s, B.Y, B.T, n, s0,
+                       s1, W, B.H3, B.dY, B.dH3);
+    hipLaunchKernelGGL(k_head_wgrad, dim3(1, splits), dim3(kWidth), 0, s, B.H3, B.dY, n, rows_per_split, B.part);
+    hipLaunchKernelGGL(k_reduce_splits, dim3((kWidth * kOut + kOut + 255) / 256), dim3(256), 0, s, B.part, splits,
+                       (int64_t)(kWidth * kOut + kOut), B.grad + W.layout.w4);
+    int64_t grid = (n + kRowsFwd - 1) / kRowsFwd;
+    if (grid > 8192) grid = 8192;
+    // layer 3
+    hipLaunchKernelGGL(k_wgrad<kWidth>, dim3(16, splits), dim3(256), 0, s, B.H2, B.dH3, n, rows_per_split, B.part);
+    hipLaunchKernelGGL(k_reduce_splits, dim3((kWidth * kWidth + 255) / 256), dim3(256), 0, s, B.part, splits,
+                       (int64_t)kWidth * kWidth, B.grad + W.layout.w3);
+    hipLaunchKernelGGL(k_colsum, dim3(1, splits), dim3(kWidth), 0, s, B.dH3, n, kWidth, rows_per_split, B.part);
+    hipLaunchKernelGGL(k_reduce_splits, dim3(1), dim3(256), 0, s, B.part, splits, (int64_t)kWidth, B.grad + W.layout.b3);
+    hipLaunchKernelGGL(k_backward_data<kWidth>, dim3((unsigned)grid), dim3(256), 0, s, B.dH3, n, W.w3, B.H2, B.dH2);
+    // layer 2
+    hipLaunchKernelGGL(k_wgrad<kWidth>, dim3(16, splits), dim3(256), 0, s, B.H1, B.dH2, n, rows_per_split, B.part);
+    hipLaunchKernelGGL(k_reduce_splits, dim3((kWidth * kWidth + 255) / 256), dim3(256), 0, s, B.part, splits,
+                       (int64_t)kWidth * kWidth, B.grad + W.layout.w2);
+    hipLaunchKernelGGL(k_colsum, dim3(1, splits), dim3(kWidth), 0, s, B.dH2, n, kWidth, rows_per_split, B.part);
+    hipLaunchKernelGGL(k_reduce_splits, dim3(1), dim3(256), 0, s, B.part, splits, (int64_t)kWidth, B.grad + W.layout.b2);
+    hipLaunchKernelGGL(k_backward_data<kWidth>, dim3((unsigned)grid), dim3(256), 0, s, B.dH2, n, W.w2, B.H1, B.dH1);
+    // layer 1
+    hipLaunchKernelGGL(k_wgrad<kFeat>, dim3(4, splits), dim3(256), 0, s, B.X, B.dH1, n, rows_per_split, B.part);
+    hipLaunchKernelGGL(k_reduce_splits, dim3((kFeat * kWidth + 255) / 256), dim3(256), 0, s, B.part, splits,
+                       (int64_t)kFeat * kWidth, B.grad + W.layout.w1);
+    hipLaunchKernelGGL(k_colsum, dim3(1, splits), dim3(kWidth), 0, s, B.dH1, n, kWidth, rows_per_split, B.part);
+    hipLaunchKernelGGL(k_reduce_splits, dim3(1), dim3(256), 0, s, B.part, splits, (int64_t)kWidth, B.grad + W.layout.b1);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2,
+                       float eps, int64_t t, const RankerWeights& W, hipStream_t s) {
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, g, m, v, count, lr, b1, b2,
+                       eps, c1, c2, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_publish(const float* p, int64_t count, const RankerWeights& W, hipStream_t s) {
+    hipLaunchKernelGGL(k_publish, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk(const float* score, const int64_t* seg, int64_t nseg, int k, float* scratch, int64_t* sel,
+                       hipStream_t s) {
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_topk, dim3((unsigned)nseg), dim3(256), 0, s, score, seg, k, scratch, sel);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const float* Y, int64_t n, float lambda, float* s, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Y, n, lambda, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const DevCand* cands, const int64_t* sel, int64_t nsel, int k, int64_t cells_per_item,
+                         DevCand* sub, int64_t* map, int64_t* seg_out, DevHeader* hdr, const DevHeader* proto,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_gather, dim3(1), dim3(1024), 0, s, cands, sel, nsel, k, cells_per_item, sub, map, seg_out,
+                       hdr, proto);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_best(const int64_t* sub_best, const int64_t* seg, const int64_t* map,
+                           const tm_stencil_cost* sub_cost, int64_t nseg, const int64_t* orig_seg, int64_t* best,
+                           tm_stencil_cost* best_cost, hipStream_t s) {
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_map_best, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, s, sub_best, seg, map, sub_cost,
+                       nseg, orig_seg, best, best_cost);
+    return hipGetLastError();
+}
+
+hipError_t launch_pick_costs(const int64_t* best, const int64_t* seg, const tm_stencil_cost* cost, int64_t nseg,
+                             tm_stencil_cost* best_cost, hipStream_t s) {
+    if (nseg <= 0 || !best_cost) return hipSuccess;
+    hipLaunchKernelGGL(k_pick_costs, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, s, best, seg, cost, nseg,
+                       best_cost);
+    return hipGetLastError();
+}
+
+}  // namespace tmk

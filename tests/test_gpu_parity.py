@@ -93,6 +93,12 @@ def test_rank4_and_ragged(tm):
                      W.candidate((333,), 4, 4, [merge(0, 1)], proj=[(0, W.CYCLIC)])])
     st = W.stencil((3,), 8)
     assert (gpu_costs(tm, one_d, st) == oracle.stencil_cost_batch(one_d, st)).all()
+    # rows too long for the last dim's offset lists to sit in LDS (read from global)
+    long_rows = W.batch([W.candidate((3, 9001), 5, 4, [merge(0, 1), decompose(0, (2, 10))]),
+                         W.candidate((4, 7000), 6, 2, [merge(0, 1), decompose(0, (3, 4))],
+                                     proj=[(0, W.BLOCK), (1, W.CYCLIC)])])
+    st = W.stencil((2, 4), 8)
+    assert (gpu_costs(tm, long_rows, st) == oracle.stencil_cost_batch(long_rows, st)).all()
 
 
 def test_empty_batch_and_invalid_input(tm):

@@ -1,0 +1,217 @@
+"""GPU tests of the learned ranker and the ranked search: features, forward and
+gradient against the float64 reference (same bf16-rounded operands), one Adam step,
+training progress, save/load, and search quality against exhaustive search."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def tm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2507_17087_amd as m
+    m.lib()
+    return m
+
+
+def loaded_plan(tm, cands, st):
+    p = tm.Plan(len(cands), 1)
+    p.load(cands, st)
+    return p
+
+
+def exact_costs(tm, cands, st):
+    import torch
+    p = loaded_plan(tm, cands, st)
+    out = torch.empty((len(cands), 4), dtype=torch.int64, device="cuda")
+    p.run(out)
+    torch.cuda.synchronize()
+    return p, out
+
+
+def test_features_parity(tm):
+    import torch
+    say("features")
+    cs = np.concatenate([W.random_candidates(300, seed=41, ranks=(3,), octaves=(2, 9), nodes_max=64, max_ops=4,
+                                             cyclic_pct=20),
+                         W.c2_candidates(oracle.enumerate_factorizations(128, 3), extent=(96, 200, 64))])
+    st = W.stencil((2, 1, 3), 8)
+    p = loaded_plan(tm, cs, st)
+    got = tm.tm_ranker_features(p).cpu().numpy()
+    exp = np.stack([mlp.features(c, (2, 1, 3)) for c in cs])
+    assert np.abs(got - exp).max() < 1e-5
+
+
+def _bf16_params(r):
+    return mlp.bf16_round(r.get_params().cpu().numpy())
+
+
+def _exact_params(r):
+    """bf16 weight matrices, fp32 biases: what the kernels compute with."""
+    p = r.get_params().cpu().numpy().astype(np.float64)
+    L = mlp.layout()
+    q = p.copy()
+    for k in ("w1", "w2", "w3", "w4"):
+        a, b = L[k]
+        q[a:b] = mlp.bf16_round(p[a:b].astype(np.float32))
+    return q
+
+
+def test_forward_parity(tm):
+    import torch
+    say("forward")
+    r = tm.Ranker(seed=3)
+    rng = np.random.default_rng(0)
+    X = rng.uniform(-1, 1, size=(333, mlp.F)).astype(np.float32)
+    y = r.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    ref, _ = mlp.forward(_exact_params(r), mlp.bf16_round(X))
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(y - ref).max() <= 0.03 * scale
+    assert np.corrcoef(y.ravel(), ref.ravel())[0, 1] > 0.999
+
+
+def test_gradient_parity(tm):
+    import torch
+    say("gradient")
+    r = tm.Ranker(seed=5)
+    rng = np.random.default_rng(1)
+    X = rng.uniform(-1, 1, size=(1000, mlp.F)).astype(np.float32)
+    T = rng.normal(0, 1, size=(1000, mlp.O)).astype(np.float32)
+    g = r.grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()).cpu().numpy().astype(np.float64)
+    _, ref = mlp.loss_and_grad(_exact_params(r), mlp.bf16_round(X), T.astype(np.float64))
+    L = mlp.layout()
+    for k in ("w1", "b1", "w2", "b2", "w3", "b3", "w4", "b4"):
+        a, b = L[k]
+        d = np.linalg.norm(g[a:b] - ref[a:b]) / max(np.linalg.norm(ref[a:b]), 1e-12)
+        cos = float(g[a:b] @ ref[a:b] / max(np.linalg.norm(g[a:b]) * np.linalg.norm(ref[a:b]), 1e-30))
+        say(f"  {k}: rel {d:.4f} cos {cos:.6f}")
+        assert d < 0.05 and cos > 0.998
+
+
+def test_one_adam_step(tm):
+    import torch
+    say("adam step")
+    r = tm.Ranker(seed=9)
+    p0 = r.get_params().cpu().numpy().astype(np.float64)
+    cands = W.random_candidates(700, seed=9, ranks=(3,), octaves=(3, 5), nodes_max=16, max_ops=3)
+    st = W.c3_stencil(3)
+    plan, costs = exact_costs(tm, cands, st)
+    feat = tm.tm_ranker_features(plan)
+    twin = tm.Ranker(seed=9)
+    r.train(feat, costs, epochs=1, batch=len(cands), lr=1e-3, seed=1)
+    mu0, s0, mu1, s1 = r.scaling()
+    c = costs.cpu().numpy().astype(np.float64)
+    T = np.stack([(np.log2(1 + c[:, 2]) - mu0) / s0, (np.log2(1 + c[:, 3]) - mu1) / s1], 1).astype(np.float32)
+    g = twin.grad(feat, torch.from_numpy(T).cuda()).cpu().numpy().astype(np.float64)
+    exp, _, _ = mlp.adam_step(p0, g, np.zeros_like(p0), np.zeros_like(p0), 1, 1e-3)
+    got = r.get_params().cpu().numpy().astype(np.float64)
+    assert np.abs(got - exp).max() < 1e-5
+
+
+def search_instances(tm, count, seed, octaves, min_cands=1024, fact=None):
+    fact = fact or tm.tm_enumerate_factorizations
+    out = []
+    first = 0
+    while len(out) < count:
+        for ext, n, g in W.random_instances(64, seed=seed, first=first, octaves=octaves):
+            fs = fact(n * g, 3)
+            if len(fs) * 32 >= min_cands:
+                out.append((ext, n, g, fs))
+                if len(out) == count:
+                    break
+        first += 64
+    return out
+
+
+def build_batch(instances):
+    cands, seg = [], [0]
+    for ext, n, g, fs in instances:
+        c = W.instance_candidates(ext, n, g, fs)
+        cands.append(c)
+        seg.append(seg[-1] + len(c))
+    return np.concatenate(cands), np.array(seg, np.int64)
+
+
+@pytest.fixture(scope="module")
+def trained(tm):
+    import torch
+    say("training set")
+    inst = search_instances(tm, 48, seed=1, octaves=(3, 6))
+    cands, _ = build_batch(inst)
+    st = W.c3_stencil(3)
+    plan, costs = exact_costs(tm, cands, st)
+    feat = tm.tm_ranker_features(plan)
+    r = tm.Ranker(seed=1)
+    say(f"  training on {len(cands)} candidates")
+    losses = r.train(feat, costs, epochs=12, batch=4096, lr=2e-3, seed=1)
+    say("  losses", [round(x, 4) for x in losses])
+    torch.cuda.synchronize()
+    return r, losses
+
+
+def test_training_reduces_loss(tm, trained):
+    r, losses = trained
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_save_load_roundtrip(tm, trained):
+    import torch
+    r, _ = trained
+    X = torch.rand((200, 64), device="cuda") * 2 - 1
+    a = r.forward(X).cpu().numpy()
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ranker.bin")
+        r.save(path)
+        r2 = tm.Ranker(path=path)
+        b = r2.forward(X).cpu().numpy()
+        assert r2.scaling() == r.scaling()
+    assert (a == b).all()
+
+
+def test_search_matches_exhaustive_when_topk_covers(tm, trained):
+    say("search, topk covers every instance")
+    r, _ = trained
+    inst = search_instances(tm, 3, seed=7, octaves=(3, 5), min_cands=0)
+    cands, seg = build_batch(inst)
+    plan = loaded_plan(tm, cands, W.c3_stencil(3))
+    b_ex, c_ex = tm.tm_search(plan, None, seg)
+    b_rk, c_rk = tm.tm_search(plan, r, seg, topk=int(np.diff(seg).max()))
+    assert (b_ex.cpu() == b_rk.cpu()).all() and (c_ex.cpu() == c_rk.cpu()).all()
+    # the exhaustive search against the oracle on the smallest instance
+    s = int(np.argmin(np.diff(seg)))
+    sub = cands[seg[s]:seg[s + 1]]
+    exp = oracle.stencil_cost_batch(sub, W.c3_stencil(3))
+    e = oracle.select_best(exp)
+    assert int(b_ex.cpu()[s]) == e and tuple(c_ex.cpu().numpy()[s]) == tuple(exp[e])
+
+
+def test_ranked_search_quality(tm, trained):
+    import torch
+    say("ranked search quality")
+    r, _ = trained
+    inst = search_instances(tm, 64, seed=2, octaves=(3, 6))
+    cands, seg = build_batch(inst)
+    plan = loaded_plan(tm, cands, W.c3_stencil(3))
+    b_ex, c_ex = tm.tm_search(plan, None, seg)
+    b_rk, c_rk = tm.tm_search(plan, r, seg, topk=64)
+    torch.cuda.synchronize()
+    ce, cr = c_ex.cpu().numpy(), c_rk.cpu().numpy()
+    ok = (ce[:, 2] == cr[:, 2]) & (ce[:, 3] == cr[:, 3])
+    say(f"  {ok.sum()}/{len(ok)} instances at the exhaustive optimum; candidates {len(cands)}")
+    assert ok.mean() >= 0.9
+    # never better than the optimum
+    assert ((cr[:, 2] > ce[:, 2]) | ((cr[:, 2] == ce[:, 2]) & (cr[:, 3] >= ce[:, 3]))).all()
