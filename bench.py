@@ -38,6 +38,13 @@ def parse():
     ap.add_argument("--extent", type=int, default=512, help="cube side of the launch domain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--search", action="store_true", help="also run the learned-ranker search leg")
+    ap.add_argument("--search-train", type=int, default=1_000_000, help="training candidates (exact costs)")
+    ap.add_argument("--search-eval", type=int, default=1_000_000, help="evaluation candidates")
+    ap.add_argument("--search-epochs", type=int, default=8)
+    ap.add_argument("--search-octaves", type=int, nargs=2, default=[5, 9])
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="one 256 MiB device-to-device copy before timing (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -53,6 +60,77 @@ def cpu_baseline(cands, st, extent):
     return {"value": pts / dt, "unit": "point-evals/s", "cores": 1, "kind": "oracle",
             "sample": f"1 of the 216 candidates (F=(4,4,8), identity chain) on the full {extent}^3 "
                       f"domain: {pts} point-evals in {dt:.2f} s, single thread"}
+
+
+def instances_with(tm, W, seed, target, octaves, min_cands=1024):
+    """Search instances (c3's domain and machine distribution, launch rank 3) whose
+    candidate lists (factorizations x 32 chains) have at least min_cands entries,
+    until `target` candidates are reached."""
+    inst, fls, total, first = [], [], 0, 0
+    while total < target:
+        for ext, n, g in W.random_instances(256, seed=seed, first=first, octaves=tuple(octaves)):
+            fs = tm.tm_enumerate_factorizations(n * g, 3)
+            if len(fs) * 32 >= min_cands:
+                inst.append((ext, n, g))
+                fls.append(fs)
+                total += len(fs) * 32
+                if total >= target:
+                    break
+        first += 256
+    return W.instance_batch(inst, fls)
+
+
+def search_leg(args, tm, W):
+    """Learned ranker: train on exact costs of seed-1 instances, then rank the
+    candidates of seed-2 instances (top-64 per instance re-evaluated exactly) and
+    compare with exhaustive exact evaluation of every candidate."""
+    import torch
+    st = W.c3_stencil(3)
+    t0 = time.perf_counter()
+    tc, _ = instances_with(tm, W, 1, args.search_train, args.search_octaves)
+    plan = tm.Plan(len(tc), 1)
+    plan.load(tc, st)
+    costs = torch.empty((len(tc), 4), dtype=torch.int64, device="cuda")
+    plan.run(costs)
+    feat = tm.tm_ranker_features(plan)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r = tm.Ranker(seed=1)
+    losses = r.train(feat, costs, epochs=args.search_epochs, batch=4096, lr=2e-3, seed=1)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    del feat, costs
+    plan.close()
+    ec, seg = instances_with(tm, W, 2, args.search_eval, args.search_octaves)
+    plan = tm.Plan(len(ec), 1)
+    plan.load(ec, st)
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    b_ex, c_ex = tm.tm_search(plan, None, seg)
+    torch.cuda.synchronize()
+    e1 = time.perf_counter()
+    tm.tm_search(plan, r, seg, topk=64)  # warm-up
+    torch.cuda.synchronize()
+    reps = 3
+    e2 = time.perf_counter()
+    for _ in range(reps):
+        b_rk, c_rk = tm.tm_search(plan, r, seg, topk=64)
+    torch.cuda.synchronize()
+    e3 = time.perf_counter()
+    ce, cr = c_ex.cpu().numpy(), c_rk.cpu().numpy()
+    ok = (ce[:, 2] == cr[:, 2]) & (ce[:, 3] == cr[:, 3])
+    n = len(ec)
+    ex_rate = n / (e1 - e0)
+    rk_rate = n / ((e3 - e2) / reps)
+    plan.close()
+    r.close()
+    return {"instances": int(len(seg) - 1), "candidates": int(n), "topk": 64,
+            "opt_rate": float(ok.mean()), "ranked_candidates_per_s": rk_rate,
+            "exhaustive_candidates_per_s": ex_rate, "speedup": rk_rate / ex_rate,
+            "train_candidates": int(len(tc)), "train_epochs": args.search_epochs,
+            "train_loss_first_last": [losses[0], losses[-1]] if losses else None,
+            "exact_costs_s": t1 - t0, "train_s": t2 - t1,
+            "extents": f"octaves {args.search_octaves[0]}..{args.search_octaves[1]} per dim (log-uniform)"}
 
 
 def main():
@@ -81,6 +159,12 @@ def main():
     out = torch.empty((n, 4), dtype=torch.int64, device="cuda")
     best = torch.empty(1, dtype=torch.int64, device="cuda")
     pmap = torch.empty(L ** 3, dtype=torch.int32, device="cuda")
+    if args.copy_probe:
+        a = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     tuned = (0, 0)
     if not args.no_autotune:
         tuned = plan.autotune(out)
@@ -155,9 +239,12 @@ def main():
         "selected": {"index": b, "factorization": list(fs[b // 6]), "chain": b % 6,
                      "bytes": int(costs[b][2]), "inter_bytes": int(costs[b][3])},
     }
+    plan.close()
+    del pmap
+    if args.search:
+        res["search"] = search_leg(args, tm, W)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cands, st, L)
-    plan.close()
     print(json.dumps(res))
 
 

@@ -113,8 +113,9 @@ def final_shape_and_blocks(c):
     return s, blocks
 
 
-def features(c, halo):
-    """The 64 ranker features of one candidate (float64)."""
+def features(c, halo, chain_table=None):
+    """The 64 ranker features of one candidate (float64); chain_table(c) gives the
+    processor of every final-space coordinate (needed for the node crossings)."""
     f = np.zeros(F)
     k = int(c["lrank"])
     f[k - 1] = 1
@@ -127,13 +128,12 @@ def features(c, halo):
             nf = int(op["nf"])
             F_ = [int(x) for x in op["f"][:4]]
             break
-    vb = vf = 0.0
+    vf = 0.0
     for d in range(k):
         l = float(c["extent"][d])
         f[4 + d] = math.log2(l) / 10
         f[15 + d] = math.log2(blocks[d]) / 9
         f[19 + d] = (math.log2(l) - math.log2(blocks[d])) / 10
-        vb += 2.0 * halo[d] * (blocks[d] - 1.0) / l
         if d < nf:
             vf += 2.0 * halo[d] * (F_[d] - 1.0) / l
         f[54 + d] = halo[d] / 4
@@ -143,7 +143,6 @@ def features(c, halo):
     f[10] = math.log2(n * g) / 9
     for m in range(min(nf, 4)):
         f[11 + m] = math.log2(F_[m]) / 9
-    f[23] = math.log2(1 + vb) / 4
     f[24] = math.log2(1 + vf) / 4
     for t, op in enumerate(ops):
         kd = int(op["kind"])
@@ -151,7 +150,8 @@ def features(c, halo):
             f[25 + kd - 1] += 0.25
         if t < 6:
             f[30 + t] = kd / 5
-            f[36 + t] = int(op["a"]) / 8
+            if t < 3:
+                f[39 + t] = int(op["a"]) / 8
             f[42 + t] = 0.0 if kd == DECOMPOSE else math.log2(1 + int(op["b"])) / 9
     f[48] = 1.0 if len(ops) and int(ops[0]["kind"]) == SWAP else 0.0
     for j in range(min(len(s), 4)):
@@ -159,4 +159,34 @@ def features(c, halo):
     f[53] = len(s) / 8
     f[58] = math.ceil(math.log2(g)) / 3 if g > 1 else 0.0
     f[59] = 1.0
+    # node / processor crossings: per final dim, the fractions of adjacent coordinate
+    # pairs whose owners are on different nodes / are different processors (from the
+    # oracle's own chain table); block-model estimates of ghost cells from them
+    cross_n = [0.0] * len(s)
+    cross_p = [0.0] * len(s)
+    if chain_table is not None and int(np.prod(s)) <= 16384:
+        proc = np.asarray(chain_table(c)).reshape(s)
+        node = proc // g
+        for j in range(len(s)):
+            if s[j] > 1:
+                a = np.arange(s[j] - 1)
+                cross_n[j] = float((np.take(node, a, axis=j) != np.take(node, a + 1, axis=j)).mean())
+                cross_p[j] = float((np.take(proc, a, axis=j) != np.take(proc, a + 1, axis=j)).mean())
+    cn, cp = [0.0] * 4, [0.0] * 4
+    for j in range(min(len(s), 8)):
+        d = int(c["proj_src"][j])
+        cn[d] = max(cn[d], cross_n[j])
+        cp[d] = max(cp[d], cross_p[j])
+    est_t = est_i = 0.0
+    pts = 1.0
+    for d in range(k):
+        face = 2.0 * halo[d] * (blocks[d] - 1.0) / float(c["extent"][d])
+        est_t += face * cp[d]
+        est_i += face * cn[d]
+        pts *= float(c["extent"][d])
+    f[23] = math.log2(1 + est_t * pts) / 32
+    f[60] = math.log2(1 + est_i * pts) / 32
+    for d in range(3):
+        f[61 + d] = cn[d]
+        f[36 + d] = cp[d]
     return f

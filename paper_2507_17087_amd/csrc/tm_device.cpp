@@ -38,7 +38,7 @@ static int layout_tables(DevCand& d, int H) {
     const int K = d.lrank;
     int64_t off = up4(d.vol);
     d.coord_off[K - 1] = (int32_t)off;
-    off += (d.extent[K - 1] + 255) & ~int64_t(255);  // zero-padded to whole 256-entry chunks
+    off += (d.extent[K - 1] + 511) & ~int64_t(511);  // zero-padded to whole 512-entry chunks
     for (int k = 0; k < K - 1; ++k) {
         d.coord_off[k] = (int32_t)std::min<int64_t>(off, INT32_MAX);
         off += d.extent[k];
@@ -401,7 +401,7 @@ static void plan_drop_graphs(tm_plan* p) {
 }
 
 static void search_free(SearchBufs& b) {
-    void* ptrs[] = {b.X, b.Y, b.score, b.scratch, b.seg, b.sel, b.sub, b.map, b.sub_seg, b.sub_hdr,
+    void* ptrs[] = {b.X, b.Y, b.score, b.scratch, b.cross, b.seg, b.sel, b.sub, b.map, b.sub_seg, b.sub_hdr,
                     b.sub_arena, b.sub_counter, b.sub_out, b.sub_best, b.all_out};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -731,15 +731,17 @@ int plan_features(const tm_plan* p, float* d_feat, hipStream_t s) {
         if (b.Y) (void)hipFree(b.Y);
         if (b.score) (void)hipFree(b.score);
         if (b.scratch) (void)hipFree(b.scratch);
-        b.Y = b.score = b.scratch = nullptr;
+        if (b.cross) (void)hipFree(b.cross);
+        b.Y = b.score = b.scratch = b.cross = nullptr;
         if (hipMalloc((void**)&b.X, (size_t)std::max<int64_t>(n, 1) * kFeat * 2) != hipSuccess ||
             hipMalloc((void**)&b.Y, (size_t)std::max<int64_t>(n, 1) * kOut * 4) != hipSuccess ||
             hipMalloc((void**)&b.score, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
-            hipMalloc((void**)&b.scratch, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess)
+            hipMalloc((void**)&b.scratch, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
+            hipMalloc((void**)&b.cross, (size_t)std::max<int64_t>(n, 1) * 2 * kMaxMrankCross * 4) != hipSuccess)
             return set_error(TM_ENOMEM, "feature buffers");
         b.cap_n = n;
     }
-    TM_HIP(launch_features(p->d_cands, n, p->d_hdr->halo, b.X, d_feat, s));
+    TM_HIP(launch_features(p->d_cands, n, p->d_hdr->halo, b.cross, b.X, d_feat, s));
     return TM_OK;
 }
 
@@ -769,13 +771,15 @@ int plan_search_prepare(tm_plan* p, const int64_t* seg, int64_t nseg, int32_t to
             if (b.Y) (void)hipFree(b.Y);
             if (b.score) (void)hipFree(b.score);
             if (b.scratch) (void)hipFree(b.scratch);
+            if (b.cross) (void)hipFree(b.cross);
             b.X = nullptr;
-            b.Y = b.score = b.scratch = nullptr;
+            b.Y = b.score = b.scratch = b.cross = nullptr;
             b.cap_n = 0;
             if (hipMalloc((void**)&b.X, (size_t)std::max<int64_t>(n, 1) * kFeat * 2) != hipSuccess ||
                 hipMalloc((void**)&b.Y, (size_t)std::max<int64_t>(n, 1) * kOut * 4) != hipSuccess ||
                 hipMalloc((void**)&b.score, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
-                hipMalloc((void**)&b.scratch, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess)
+                hipMalloc((void**)&b.scratch, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
+                hipMalloc((void**)&b.cross, (size_t)std::max<int64_t>(n, 1) * 2 * kMaxMrankCross * 4) != hipSuccess)
                 return set_error(TM_ENOMEM, "score buffers");
             b.cap_n = n;
         }

@@ -6,7 +6,7 @@
 
 #include <string>
 
-#include "../../include/taskmap.h"
+#include "taskmap.h"
 
 namespace tmk {
 
@@ -74,7 +74,7 @@ hipError_t launch_count(int K, int H, const DevHeader* hdr, const DevCand* cands
 hipError_t launch_finalize_select(const DevHeader* hdr, tm_stencil_cost* out, int64_t* best,
                                   hipStream_t s);
 hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* seg, int64_t nseg,
-                                  int64_t* best, hipStream_t s);
+                                  int64_t* best, hipStream_t s, const int64_t* key = nullptr);
 hipError_t launch_map(const DevCand* cands, int64_t n, const int32_t* arena, const int64_t* d_index,
                       int64_t index, int32_t* out, int grid, int lds_words, hipStream_t s);
 hipError_t launch_chain_table(const DevCand* cand, const int32_t* arena, int32_t* out, hipStream_t s);

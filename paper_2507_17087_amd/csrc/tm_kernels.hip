@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "tm_internal.h"
+#include "tm_chain.h"
 
 namespace tmk {
 
@@ -37,80 +38,6 @@ __device__ __forceinline__ int32_t uniform32(int32_t x) {
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Copy a DevCand into LDS with all threads of the block (it is read many times).
-__device__ __forceinline__ void stage_cand(DevCand* dst, const DevCand* src) {
-    const int32_t* s = reinterpret_cast<const int32_t*>(src);
-    int32_t* d = reinterpret_cast<int32_t*>(dst);
-    for (int i = threadIdx.x; i < (int)(sizeof(DevCand) / 4); i += blockDim.x) d[i] = s[i];
-}
-
-// Owner key of final-space coordinate v: decode v (C order), then undo the ops.
-__device__ int32_t owner_key(const DevCand& c, int32_t v) {
-    int32_t a[TM_MAX_MRANK], b[TM_MAX_MRANK];
-    for (int j = c.frank - 1; j >= 0; --j) {
-        const int32_t s = c.fshape[j];
-        a[j] = v % s;
-        v /= s;
-    }
-    for (int t = c.nops - 1; t >= 0; --t) {
-        const int r = c.rank[t];
-        const int32_t* s = c.shape[t];
-        const int pa = c.op_a[t], pb = c.op_b[t];
-        switch (c.op_kind[t]) {
-            case TM_SPLIT:
-                for (int u = 0; u < pa; ++u) b[u] = a[u];
-                b[pa] = a[pa] + a[pa + 1] * pb;
-                for (int u = pa + 1; u < r; ++u) b[u] = a[u + 1];
-                break;
-            case TM_MERGE:
-                for (int u = 0; u < r; ++u) {
-                    if (u < pa || (u > pa && u < pb)) b[u] = a[u];
-                    else if (u == pa) b[u] = a[pa] % s[pa];
-                    else if (u == pb) b[u] = a[pa] / s[pa];
-                    else b[u] = a[u - 1];
-                }
-                break;
-            case TM_SWAP:
-                for (int u = 0; u < r; ++u) b[u] = a[u];
-                b[pa] = a[pb];
-                b[pb] = a[pa];
-                break;
-            case TM_BALANCE_SPLIT: {
-                const int64_t si = s[pa];
-                const int64_t cc = (si + pb - 1) / pb;
-                const int64_t vv = (int64_t)a[pa] + (int64_t)a[pa + 1] * pb;
-                for (int u = 0; u < pa; ++u) b[u] = a[u];
-                b[pa] = (int32_t)((vv * si) / ((int64_t)pb * cc));
-                for (int u = pa + 1; u < r; ++u) b[u] = a[u + 1];
-                break;
-            }
-            default: {  // TM_DECOMPOSE
-                const int k = c.op_nf[t];
-                int32_t acc = 0;
-                for (int m = k - 1; m >= 0; --m) acc = acc * c.op_f[t][m] + a[pa + m];
-                for (int u = 0; u < pa; ++u) b[u] = a[u];
-                b[pa] = acc;
-                for (int u = pa + 1; u < r; ++u) b[u] = a[u + k - 1];
-                break;
-            }
-        }
-        for (int u = 0; u < r; ++u) a[u] = b[u];
-    }
-    return (a[0] << c.gbits) | a[1];
-}
-
-// Contribution of coordinate x of launch dim d to the linear final index.
-__device__ int32_t coord_value(const DevCand& c, int d, int64_t x) {
-    int32_t v = 0;
-    for (int j = 0; j < c.frank; ++j) {
-        if (c.proj_src[j] != d) continue;
-        const int64_t s = c.fshape[j];
-        const int64_t a = c.proj_mode[j] == TM_BLOCK ? (x * s) / c.extent[d] : x % s;
-        v += (int32_t)a * c.fstride[j];
-    }
     return v;
 }
 
@@ -154,8 +81,8 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
                 for (int i = cnt; i < hs; ++i) dl[x * hs + i] = 0;
                 ct[x] = val | (cnt << kCntShift);
             }
-            if (d == sc.lrank - 1)  // zero entries up to a multiple of 256 (scanned four per lane)
-                for (int64_t x = l + threadIdx.x; x < ((l + 255) & ~int64_t(255)); x += blockDim.x) ct[x] = 0;
+            if (d == sc.lrank - 1)  // zero entries up to a multiple of 512 (scanned eight per lane)
+                for (int64_t x = l + threadIdx.x; x < ((l + 511) & ~int64_t(511)); x += blockDim.x) ct[x] = 0;
         }
     }
 }
@@ -192,23 +119,28 @@ hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_
 // A work item is a block of consecutive rows (all launch dims but the last fixed)
 // of one candidate.  A workgroup takes items from a global atomic counter (the
 // next one is requested while the current one runs), stages the candidate's owner
-// table, coordinate tables and last-dim offset lists in LDS when the candidate
-// changes, and gives each wave whole rows.  Every cell is examined: a lane reads
-// the coordinate entries of four consecutive cells with one LDS load.
-//   - The outer coordinates of a row fix a base index and the row's list of
-//     distinct offsets to outer neighbours (usually empty: the row lies inside a
-//     block along every outer dim).
-//   - Rows with an empty list: a cell can have a foreign neighbour only along the
-//     last dim, i.e. when its entry's offset count is non-zero.  Groups of four
-//     cells holding such a cell are compacted into a per-wave LDS queue (ballot +
-//     prefix count) and evaluated 64 groups at a time with every lane busy.
-//   - Rows with a non-empty list: every cell is evaluated.
+// table, coordinate tables and (when they fit) the last dim's offset lists in LDS
+// when the candidate changes, and gives each wave a contiguous share of the rows,
+// stepping the outer coordinates without divisions.  Every cell is examined: a
+// lane reads the coordinate entries of eight consecutive cells with two LDS loads.
+//   - A row's outer coordinates fix its base index and the distinct non-zero
+//     offsets to its outer neighbours, computed from the coordinate tables when
+//     the row lies within a halo of a block boundary of an outer dim.
+//   - Rows without outer offsets: a cell can have a foreign neighbour only along
+//     the last dim, i.e. when its entry's offset count is non-zero.  Groups of
+//     eight cells holding such a cell are compacted into a per-wave LDS queue
+//     (ballot + prefix count) and evaluated 64 groups at a time with every lane busy.
+//   - Rows with outer offsets: every cell is evaluated; a cell whose entry equals
+//     its left neighbour's and has no last-dim offsets reuses its result (same
+//     index, same neighbours).
 // Evaluating a cell: its owner o = T[v], then the owners T[v + delta] over the row
-// list and the cell's own last-dim list; the distinct ones other than o are
+// offsets and the cell's last-dim offsets; the distinct ones other than o are
 // counted (and those on another node).  Lanes count in registers, waves reduce,
 // and one 64-bit atomic per wave and item adds to the candidate's totals.
 
 constexpr int kQueueCap = 128;
+constexpr int kCellsPerLane = 8;
+constexpr int kChunk = 64 * kCellsPerLane;
 
 __device__ __forceinline__ int32_t cval(int32_t e) { return e & kValMask; }
 __device__ __forceinline__ int32_t ccnt(int32_t e) { return (e >> kCntShift) & 0xf; }
@@ -220,28 +152,213 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // Distinct owners, other than o, among T[v + delta] for delta in rl[0..nr) then
-// xl[0..nx).  Offsets repeat nothing within one list; equal owners are merged.
-__device__ __forceinline__ void eval_cell(const int32_t* __restrict__ T, int32_t v, int32_t o,
-                                          const int32_t* rl, int nr, const int32_t* xl, int nx, int gbits,
-                                          int& cnt, int& icnt) {
+// xl[0..nx).  Offsets are distinct within each list; equal owners are merged.
+// The first two owners are handled in straight-line code (the usual case).
+template <typename XP>
+__device__ __forceinline__ void eval_cell(const int32_t* __restrict__ T, int32_t v, const int32_t* rl, int nr,
+                                          XP xl, int nx, int gbits, int& cnt, int& icnt) {
     const int n = nr + nx;
+    if (n == 0) return;
+    const int32_t o = T[v];
     const int32_t onode = o >> gbits;
-    for (int t = 0; t < n; ++t) {
+    const int32_t d0 = nr > 0 ? rl[0] : xl[0];
+    const int32_t o0 = T[v + d0];
+    const bool f0 = o0 != o;
+    cnt += f0;
+    icnt += (f0 && (o0 >> gbits) != onode) ? 1 : 0;
+    if (n == 1) return;
+    const int32_t d1 = nr > 1 ? rl[1] : xl[1 - nr];
+    const int32_t o1 = T[v + d1];
+    const bool f1 = o1 != o && o1 != o0;
+    cnt += f1;
+    icnt += (f1 && (o1 >> gbits) != onode) ? 1 : 0;
+    for (int t = 2; t < n; ++t) {
         const int32_t dt = t < nr ? rl[t] : xl[t - nr];
         const int32_t ot = T[v + dt];
-        if (ot == o) continue;
-        bool fresh = true;
-        for (int s = 0; s < t; ++s) {
+        bool fresh = ot != o && ot != o0 && ot != o1;
+        for (int s = 2; s < t && fresh; ++s) {
             const int32_t ds = s < nr ? rl[s] : xl[s - nr];
-            if (T[v + ds] == ot) {
-                fresh = false;
-                break;
-            }
+            fresh = T[v + ds] != ot;
         }
         if (fresh) {
             ++cnt;
             icnt += ((ot >> gbits) != onode) ? 1 : 0;
         }
+    }
+}
+
+// Evaluates the cells x0 .. x0+7 of a row (see above).  only_flagged: skip cells
+// without last-dim offsets (rows without outer offsets).
+template <typename XP>
+__device__ __forceinline__ void eval_group(const int32_t* __restrict__ T, XP DL, int HS,
+                                           const int32_t (&e8)[kCellsPerLane], int x0, int L, int32_t base,
+                                           const int32_t* rl, int nr, int gbits, bool only_flagged, int& cnt,
+                                           int& icnt) {
+    int32_t ep = -1;  // never a valid entry (bits 28..31 are zero)
+    int cp = 0, ip = 0;
+#pragma unroll
+    for (int j = 0; j < kCellsPerLane; ++j) {
+        const int x = x0 + j;
+        const int32_t e = e8[j];
+        const int nx = ccnt(e);
+        if (x >= L || (only_flagged && nx == 0)) continue;
+        if (e != ep || nx != 0) {
+            cp = 0;
+            ip = 0;
+            eval_cell(T, base + cval(e), rl, nr, DL + x * HS, nx, gbits, cp, ip);
+            ep = nx == 0 ? e : -1;
+        }
+        cnt += cp;
+        icnt += ip;
+    }
+}
+
+__device__ __forceinline__ void load8(const int32_t* p, int32_t (&e8)[kCellsPerLane]) {
+    const i32x4 a = *reinterpret_cast<const i32x4*>(p);
+    const i32x4 b = *reinterpret_cast<const i32x4*>(p + 4);
+    e8[0] = a.x;
+    e8[1] = a.y;
+    e8[2] = a.z;
+    e8[3] = a.w;
+    e8[4] = b.x;
+    e8[5] = b.y;
+    e8[6] = b.z;
+    e8[7] = b.w;
+}
+
+// Distinct non-zero offsets from coordinate q of outer dim d to its in-domain
+// neighbours within the halo, appended to rl[nr..) (uniform: every lane writes the
+// same values).  Offsets equal to the previous one in the same direction are
+// dropped (a block holds consecutive coordinates).
+template <int H>
+__device__ __forceinline__ int outer_offsets(const int32_t* __restrict__ C, int32_t q, int32_t ext, int h,
+                                             int32_t* rl, int nr) {
+    const int32_t ev = cval(C[q]);
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+        int32_t prev = 0;
+#pragma unroll
+        for (int s = 1; s <= H; ++s) {
+            const int32_t xx = dir ? q + s : q - s;
+            if (s <= h && xx >= 0 && xx < ext) {
+                const int32_t dv = cval(C[xx]) - ev;
+                if (dv != 0 && dv != prev) rl[nr++] = dv;
+                prev = dv;
+            }
+        }
+    }
+    return nr;
+}
+
+// The rows [ra, rb) of the staged candidate, for one wave.
+template <int K, int H, typename XP>
+__device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const int32_t* __restrict__ CL, XP DL,
+                                           const int32_t (&off)[K], const int32_t (&ext)[K], const int (&hal)[K],
+                                           int64_t ra, int64_t rb, int L, int gbits, int lane, int32_t* rl,
+                                           int32_t* qv, int32_t* qx, int& cnt, int& icnt) {
+    constexpr int HS = 2 * H;
+    constexpr int KO = K > 1 ? K - 1 : 1;
+    int qn = 0;  // wave-uniform queue length
+    int32_t q[KO];
+    {
+        uint32_t rr = (uint32_t)ra;
+#pragma unroll
+        for (int d = K - 2; d >= 0; --d) {
+            q[d] = (int32_t)(rr % (uint32_t)ext[d]);
+            rr /= (uint32_t)ext[d];
+        }
+    }
+    // prefix over dims 0..K-3: base index and offsets, refreshed on carries
+    int32_t base_o = 0;
+    int no = 0;
+    auto load_prefix = [&]() {
+        base_o = 0;
+        no = 0;
+#pragma unroll
+        for (int d = 0; d < K - 2; ++d) {
+            const int32_t e = uniform32(T[off[d] + q[d]]);
+            base_o += cval(e);
+            if (ccnt(e)) no = outer_offsets<H>(T + off[d], q[d], ext[d], hal[d], rl, no);
+        }
+    };
+    load_prefix();
+    for (int64_t r = ra; r < rb; ++r) {
+        int32_t base = base_o;
+        int nr = no;
+        if constexpr (K > 1) {
+            const int32_t e = uniform32(T[off[K - 2] + q[K - 2]]);
+            base += cval(e);
+            if (ccnt(e)) nr = outer_offsets<H>(T + off[K - 2], q[K - 2], ext[K - 2], hal[K - 2], rl, no);
+        }
+        if (nr == 0) {
+            // ---- sparse row: groups of eight cells with last-dim offsets go to the queue
+            for (int xb = 0; xb < L; xb += kChunk) {
+                const int x0 = xb + kCellsPerLane * lane;
+                int32_t e8[kCellsPerLane];
+                load8(CL + x0, e8);  // zero-padded past L
+                int32_t any = 0;
+#pragma unroll
+                for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
+                const bool hit = (uint32_t)any > (uint32_t)kValMask;
+                const uint64_t m = __ballot(hit);
+                if (m == 0ull) continue;
+                const int pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (hit) {
+                    qv[pos] = base;
+                    qx[pos] = x0;
+                }
+                qn += __popcll(m);
+                wave_sync_lds();
+                if (qn >= 64) {
+                    const int32_t bq = qv[lane], xq = qx[lane];
+                    int32_t g8[kCellsPerLane];
+                    load8(CL + xq, g8);
+                    eval_group(T, DL, HS, g8, xq, L, bq, rl, 0, gbits, true, cnt, icnt);
+                    wave_sync_lds();
+                    if (lane < qn - 64) {
+                        qv[lane] = qv[lane + 64];
+                        qx[lane] = qx[lane + 64];
+                    }
+                    qn -= 64;
+                    wave_sync_lds();
+                }
+            }
+        } else {
+            // ---- dense row: every cell sees the outer neighbours of the row
+            wave_sync_lds();
+            for (int xb = 0; xb < L; xb += kChunk) {
+                const int x0 = xb + kCellsPerLane * lane;
+                if (x0 >= L) continue;
+                int32_t e8[kCellsPerLane];
+                load8(CL + x0, e8);
+                eval_group(T, DL, HS, e8, x0, L, base, rl, nr, gbits, false, cnt, icnt);
+            }
+            wave_sync_lds();
+        }
+        // next row: step the outer coordinates
+        if constexpr (K > 1) {
+            if (r + 1 < rb && ++q[K - 2] == ext[K - 2]) {
+                q[K - 2] = 0;
+#pragma unroll
+                for (int d = K - 3; d >= 0; --d) {
+                    if (++q[d] < ext[d]) break;
+                    q[d] = 0;
+                }
+                load_prefix();
+                wave_sync_lds();
+            }
+        }
+    }
+    // drain the queue
+    if (qn > 0) {
+        if (lane < qn) {
+            const int32_t bq = qv[lane], xq = qx[lane];
+            int32_t g8[kCellsPerLane];
+            load8(CL + xq, g8);
+            eval_group(T, DL, HS, g8, xq, L, bq, rl, 0, gbits, true, cnt, icnt);
+        }
+        wave_sync_lds();
     }
 }
 
@@ -251,8 +368,6 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
                                                const int32_t* __restrict__ arena,
                                                unsigned long long* __restrict__ counter,
                                                tm_stencil_cost* __restrict__ out) {
-    constexpr int HS = 2 * H;  // offsets per coordinate
-    constexpr int KO = K > 1 ? K - 1 : 1;
     extern __shared__ int32_t lds[];
     __shared__ long long s_item;
     __shared__ int32_t s_qv[4][kQueueCap], s_qx[4][kQueueCap];
@@ -261,19 +376,18 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t total = uniform64(hdr->total_items);
     const int64_t n = uniform64(hdr->n);
+    int hal[K];
+#pragma unroll
+    for (int d = 0; d < K; ++d) hal[d] = uniform32(hdr->halo[d]);
 
     int64_t cur = -1;
-    int32_t L = 0, gbits = 0, rpi = 1;
+    int32_t L = 0, gbits = 0, rpi = 1, dl_lds = 0;
     int64_t rows = 0, ifirst = 0;
-    int32_t off[K], ext[K], dlo[K];
+    int32_t off[K], ext[K];
+    int32_t dlo = 0;
     const int32_t* garena = arena;
-    const int32_t* DL = arena;  // last dim's offset lists: LDS when staged, else global
 #pragma unroll
-    for (int d = 0; d < K; ++d) off[d] = ext[d] = dlo[d] = 0;
-
-    int32_t* qv = s_qv[wid];
-    int32_t* qx = s_qx[wid];
-    int32_t* rl = s_rl[wid];
+    for (int d = 0; d < K; ++d) off[d] = ext[d] = 0;
 
     unsigned long long next = 0;
     if (tid == 0) next = atomicAdd(counter, 1ull);
@@ -308,15 +422,12 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
             for (int d = 0; d < K; ++d) {
                 off[d] = uniform32(c->coord_off[d]);
                 ext[d] = uniform32((int32_t)c->extent[d]);
-                dlo[d] = uniform32(c->dl_off[d]);
             }
-            DL = uniform32(c->dl_lds) ? lds + dlo[K - 1] : src + dlo[K - 1];
+            dlo = uniform32(c->dl_off[K - 1]);
+            dl_lds = uniform32(c->dl_lds);
             cur = lo;
             __syncthreads();
         }
-        const int32_t* T = lds;
-        const int32_t* CL = lds + off[K - 1];
-
         // this wave's contiguous share of the item's rows
         const int64_t r0 = (item - ifirst) * rpi;
         const int64_t r1 = r0 + rpi < rows ? r0 + rpi : rows;
@@ -324,131 +435,14 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
         const int64_t ra = r0 + wid * nrw;
         const int64_t rb = ra + nrw < r1 ? ra + nrw : r1;
         int cnt = 0, icnt = 0;
-        int qn = 0;  // wave-uniform queue length
-
         if (ra < rb) {
-            // outer coordinates of the first row (one division per dim, then stepping)
-            int32_t q[KO];
-            {
-                uint32_t rr = (uint32_t)ra;
-#pragma unroll
-                for (int d = K - 2; d >= 0; --d) {
-                    q[d] = (int32_t)(rr % (uint32_t)ext[d]);
-                    rr /= (uint32_t)ext[d];
-                }
-            }
-            // prefix over dims 0..K-3: base index and offsets, refreshed on carries
-            int32_t base_o = 0, no = 0;
-            auto load_prefix = [&]() {
-                base_o = 0;
-                no = 0;
-#pragma unroll
-                for (int d = 0; d < K - 2; ++d) {
-                    const int32_t e = uniform32(T[off[d] + q[d]]);
-                    base_o += cval(e);
-                    const int nd = ccnt(e);
-                    if (nd) {
-                        if (lane < nd) rl[no + lane] = garena[dlo[d] + q[d] * HS + lane];
-                        no += nd;
-                    }
-                }
-            };
-            load_prefix();
-            for (int64_t r = ra; r < rb; ++r) {
-                int32_t base = base_o, nr = no;
-                if (K > 1) {
-                    const int32_t e = uniform32(T[off[K - 2] + q[K - 2]]);
-                    base += cval(e);
-                    const int nd = ccnt(e);
-                    if (nd) {
-                        if (lane < nd) rl[no + lane] = garena[dlo[K - 2] + q[K - 2] * HS + lane];
-                        nr += nd;
-                    }
-                }
-                if (nr == 0) {
-                    // ---- sparse row: groups of four cells with last-dim offsets go to the queue
-                    for (int xb = 0; xb < L; xb += 256) {
-                        const int x0 = xb + 4 * lane;
-                        const i32x4 e4 = *reinterpret_cast<const i32x4*>(CL + x0);  // zero-padded past L
-                        const bool hit = (uint32_t)(e4.x | e4.y | e4.z | e4.w) > (uint32_t)kValMask;
-                        const uint64_t m = __ballot(hit);
-                        if (m == 0ull) continue;
-                        const int pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                        if (hit) {
-                            qv[pos] = base;
-                            qx[pos] = x0;
-                        }
-                        qn += __popcll(m);
-                        wave_sync_lds();
-                        if (qn >= 64) {
-                            const int32_t bq = qv[lane], xq = qx[lane];
-                            const i32x4 g4 = *reinterpret_cast<const i32x4*>(CL + xq);
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                const int32_t e = j == 0 ? g4.x : (j == 1 ? g4.y : (j == 2 ? g4.z : g4.w));
-                                const int nx = ccnt(e);
-                                if (nx == 0) continue;
-                                const int32_t v = bq + cval(e);
-                                eval_cell(T, v, T[v], rl, 0, DL + (xq + j) * HS, nx, gbits, cnt, icnt);
-                            }
-                            wave_sync_lds();
-                            if (lane < qn - 64) {
-                                qv[lane] = qv[lane + 64];
-                                qx[lane] = qx[lane + 64];
-                            }
-                            qn -= 64;
-                            wave_sync_lds();
-                        }
-                    }
-                } else {
-                    // ---- dense row: every cell sees the outer neighbours of the row
-                    wave_sync_lds();
-                    for (int xb = 0; xb < L; xb += 256) {
-                        const int x0 = xb + 4 * lane;
-                        const i32x4 e4 = *reinterpret_cast<const i32x4*>(CL + x0);
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int x = x0 + j;
-                            if (x >= L) continue;
-                            const int32_t e = j == 0 ? e4.x : (j == 1 ? e4.y : (j == 2 ? e4.z : e4.w));
-                            const int32_t v = base + cval(e);
-                            eval_cell(T, v, T[v], rl, nr, DL + x * HS, ccnt(e), gbits, cnt, icnt);
-                        }
-                    }
-                    wave_sync_lds();
-                }
-                // next row: step the outer coordinates
-                if (K > 1) {
-                    if (++q[K - 2] == ext[K - 2]) {
-                        q[K - 2] = 0;
-#pragma unroll
-                        for (int d = K - 3; d >= 0; --d) {
-                            if (++q[d] < ext[d]) break;
-                            q[d] = 0;
-                        }
-                        load_prefix();
-                        wave_sync_lds();
-                    }
-                }
-            }
-        }
-        // drain the queue
-        if (qn > 0) {
-            if (lane < qn) {
-                const int32_t bq = qv[lane], xq = qx[lane];
-                const i32x4 g4 = *reinterpret_cast<const i32x4*>(CL + xq);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int32_t e = j == 0 ? g4.x : (j == 1 ? g4.y : (j == 2 ? g4.z : g4.w));
-                    const int nx = ccnt(e);
-                    if (nx == 0) continue;
-                    const int32_t v = bq + cval(e);
-                    eval_cell(T, v, T[v], rl, 0, DL + (xq + j) * HS, nx, gbits, cnt, icnt);
-                }
-            }
-            qn = 0;
-            wave_sync_lds();
+            const int32_t* CL = lds + off[K - 1];
+            if (dl_lds)
+                count_rows<K, H>(lds, CL, lds + dlo, off, ext, hal, ra, rb, L, gbits, lane, s_rl[wid], s_qv[wid],
+                                 s_qx[wid], cnt, icnt);
+            else
+                count_rows<K, H>(lds, CL, garena + dlo, off, ext, hal, ra, rb, L, gbits, lane, s_rl[wid],
+                                 s_qv[wid], s_qx[wid], cnt, icnt);
         }
         cnt = wave_sum(cnt);
         icnt = wave_sum(icnt);
@@ -543,20 +537,26 @@ hipError_t launch_finalize_select(const DevHeader* hdr, tm_stencil_cost* out, in
 }
 
 // One workgroup per segment.
+// Ties on (bytes, inter_bytes) go to the smallest tie key: key[i] when given (the
+// original candidate index of a gathered sub-batch), else i.  Writes the position.
 __global__ __launch_bounds__(256) void k_select_segments(const tm_stencil_cost* __restrict__ costs,
                                                          const int64_t* __restrict__ seg,
+                                                         const int64_t* __restrict__ key,
                                                          int64_t* __restrict__ best) {
-    __shared__ int64_t sb[256], si[256], sx[256];
+    __shared__ int64_t sb[256], si[256], sx[256], sp[256];
     const int64_t a = seg[blockIdx.x], e = seg[blockIdx.x + 1];
-    int64_t kb = INT64_MAX, ki = INT64_MAX, kx = INT64_MAX;
+    int64_t kb = INT64_MAX, ki = INT64_MAX, kx = INT64_MAX, kp = INT64_MAX;
     for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
         const int64_t b = costs[i].bytes, ib = costs[i].inter_bytes;
-        if (b < kb || (b == kb && (ib < ki || (ib == ki && i < kx)))) {
+        const int64_t x = key ? key[i] : i;
+        if (b < kb || (b == kb && (ib < ki || (ib == ki && x < kx)))) {
             kb = b;
             ki = ib;
-            kx = i;
+            kx = x;
+            kp = i;
         }
     }
+    sp[threadIdx.x] = kp;
     sb[threadIdx.x] = kb;
     si[threadIdx.x] = ki;
     sx[threadIdx.x] = kx;
@@ -570,17 +570,18 @@ __global__ __launch_bounds__(256) void k_select_segments(const tm_stencil_cost* 
                 sb[threadIdx.x] = sb[o];
                 si[threadIdx.x] = si[o];
                 sx[threadIdx.x] = sx[o];
+                sp[threadIdx.x] = sp[o];
             }
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) best[blockIdx.x] = e > a ? sx[0] - a : -1;
+    if (threadIdx.x == 0) best[blockIdx.x] = e > a ? sp[0] - a : -1;
 }
 
 hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* seg, int64_t nseg,
-                                  int64_t* best, hipStream_t s) {
+                                  int64_t* best, hipStream_t s, const int64_t* key) {
     if (nseg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_select_segments, dim3((unsigned)nseg), dim3(256), 0, s, costs, seg, best);
+    hipLaunchKernelGGL(k_select_segments, dim3((unsigned)nseg), dim3(256), 0, s, costs, seg, key, best);
     return hipGetLastError();
 }
 

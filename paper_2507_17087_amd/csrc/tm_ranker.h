@@ -71,8 +71,10 @@ struct RankerBuffers {
     float* part;                                   // fp32 [kSplits][kWidth * kWidth]
 };
 
-hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_halo, uint16_t* X, float* f32,
-                           hipStream_t s);
+constexpr int kMaxMrankCross = 8;  // node-crossing fractions kept per candidate
+
+hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_halo, float* cross, uint16_t* X,
+                           float* f32, hipStream_t s);
 hipError_t launch_mlp_forward(const uint16_t* X, int64_t n, const RankerWeights& W, float* Y, uint16_t* H1,
                               uint16_t* H2, uint16_t* H3, hipStream_t s);
 hipError_t launch_backward(const RankerBuffers& B, const RankerWeights& W, int64_t n, float s0, float s1,

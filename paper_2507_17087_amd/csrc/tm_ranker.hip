@@ -8,6 +8,7 @@
 // 8 * (l / 16); the result holds rows 4 * (l / 16) + r (r = 0..3) of column l % 16.
 #include <hip/hip_runtime.h>
 
+#include "tm_chain.h"
 #include "tm_internal.h"
 #include "tm_ranker.h"
 
@@ -35,10 +36,69 @@ __device__ __forceinline__ f32x4 mfma16(u16x8 a, u16x8 b, f32x4 c) {
 
 __device__ __forceinline__ float lg2(double x) { return (float)log2(x); }
 
+// Crossings of the chain: for every final-space dim j, the fractions of adjacent
+// coordinate pairs (a, a + e_j) whose owners sit on different nodes (first 8
+// floats) and are different processors (next 8).
+// One workgroup per candidate; node ids of all final coordinates staged in LDS
+// (volumes above kCrossMax give zeros).
+constexpr int kCrossMax = 16384;
+
+__global__ __launch_bounds__(256) void k_node_cross(const DevCand* __restrict__ cands, int64_t n,
+                                                    float* __restrict__ cross) {
+    __shared__ DevCand sc;
+    __shared__ int32_t node[kCrossMax];
+    __shared__ int32_t red[3][256];
+    for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
+        __syncthreads();
+        stage_cand(&sc, &cands[ci]);
+        __syncthreads();
+        const int32_t vol = sc.vol;
+        if (vol > kCrossMax) {
+            if (threadIdx.x < 2 * kMaxMrankCross) cross[ci * 2 * kMaxMrankCross + threadIdx.x] = 0.f;
+            continue;
+        }
+        for (int32_t v = threadIdx.x; v < vol; v += blockDim.x) node[v] = owner_key(sc, v);
+        __syncthreads();
+        const int gb = sc.gbits;
+        for (int j = 0; j < kMaxMrankCross; ++j) {
+            int pairs = 0, dn = 0, dp = 0;
+            if (j < sc.frank) {
+                const int32_t S = sc.fshape[j], st = sc.fstride[j];
+                for (int32_t v = threadIdx.x; v < vol; v += blockDim.x) {
+                    if ((v / st) % S < S - 1) {
+                        ++pairs;
+                        dp += node[v] != node[v + st];
+                        dn += (node[v] >> gb) != (node[v + st] >> gb);
+                    }
+                }
+            }
+            red[0][threadIdx.x] = pairs;
+            red[1][threadIdx.x] = dn;
+            red[2][threadIdx.x] = dp;
+            __syncthreads();
+            for (int w = 128; w > 0; w >>= 1) {
+                if ((int)threadIdx.x < w) {
+                    red[0][threadIdx.x] += red[0][threadIdx.x + w];
+                    red[1][threadIdx.x] += red[1][threadIdx.x + w];
+                    red[2][threadIdx.x] += red[2][threadIdx.x + w];
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                const float inv = red[0][0] ? 1.f / (float)red[0][0] : 0.f;
+                cross[ci * 2 * kMaxMrankCross + j] = (float)red[1][0] * inv;
+                cross[ci * 2 * kMaxMrankCross + kMaxMrankCross + j] = (float)red[2][0] * inv;
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // One thread per candidate; writes kFeat bf16 values (row of X) and, when
 // feat_f32 is given, the same values in fp32.
 __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ cands, int64_t n,
-                                                  const int32_t* __restrict__ halo, uint16_t* __restrict__ X,
+                                                  const int32_t* __restrict__ halo,
+                                                  const float* __restrict__ cross, uint16_t* __restrict__ X,
                                                   float* __restrict__ feat_f32) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -50,7 +110,7 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
     f[k - 1] = 1.f;
     double blocks[4] = {1, 1, 1, 1};
     for (int j = 0; j < c.frank; ++j) blocks[c.proj_src[j]] *= c.fshape[j];
-    double vol_b = 0, vol_f = 0;
+    double vol_f = 0;
     int32_t F[4] = {1, 1, 1, 1};
     int nf = 0;
     for (int t = 0; t < c.nops; ++t)
@@ -64,7 +124,6 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
         f[4 + d] = lg2(l) / 10.f;
         f[15 + d] = lg2(blocks[d]) / 9.f;
         f[19 + d] = (lg2(l) - lg2(blocks[d])) / 10.f;
-        vol_b += 2.0 * halo[d] * (blocks[d] - 1.0) / l;
         if (d < nf) vol_f += 2.0 * halo[d] * (F[d] - 1.0) / l;
         f[54 + d] = halo[d] / 4.f;
     }
@@ -72,14 +131,13 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
     f[9] = lg2((double)c.gpus) / 3.f;
     f[10] = lg2((double)c.nodes * c.gpus) / 9.f;
     for (int m = 0; m < nf && m < 4; ++m) f[11 + m] = lg2((double)F[m]) / 9.f;
-    f[23] = lg2(1.0 + vol_b) / 4.f;
     f[24] = lg2(1.0 + vol_f) / 4.f;
     for (int t = 0; t < c.nops; ++t) {
         const int kd = c.op_kind[t];
         if (kd >= 1 && kd <= 5) f[25 + kd - 1] += 0.25f;
         if (t < 6) {
             f[30 + t] = kd / 5.f;
-            f[36 + t] = c.op_a[t] / 8.f;
+            if (t < 3) f[39 + t] = c.op_a[t] / 8.f;
             f[42 + t] = kd == TM_DECOMPOSE ? 0.f : lg2(1.0 + (double)c.op_b[t]) / 9.f;
         }
     }
@@ -88,6 +146,28 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
     f[53] = c.frank / 8.f;
     f[58] = c.gbits / 3.f;
     f[59] = 1.f;
+    // node / processor crossings per launch dim (largest over the final dims it
+    // projects onto) and block-model estimates of the ghost cells, total and
+    // inter-node, in the log space of the targets
+    float cn[4] = {0.f, 0.f, 0.f, 0.f}, cp[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < c.frank && j < kMaxMrankCross; ++j) {
+        const int d = c.proj_src[j];
+        cn[d] = fmaxf(cn[d], cross[i * 2 * kMaxMrankCross + j]);
+        cp[d] = fmaxf(cp[d], cross[i * 2 * kMaxMrankCross + kMaxMrankCross + j]);
+    }
+    double est_t = 0, est_i = 0, pts = 1;
+    for (int d = 0; d < k; ++d) {
+        const double face = 2.0 * halo[d] * (blocks[d] - 1.0) / (double)c.extent[d];
+        est_t += face * cp[d];
+        est_i += face * cn[d];
+        pts *= (double)c.extent[d];
+    }
+    f[23] = lg2(1.0 + est_t * pts) / 32.f;
+    f[60] = lg2(1.0 + est_i * pts) / 32.f;
+    for (int d = 0; d < 3; ++d) {
+        f[61 + d] = cn[d];
+        f[36 + d] = cp[d];
+    }
     uint16_t* row = X + i * kFeat;
 #pragma unroll
     for (int t = 0; t < kFeat; ++t) {
@@ -576,10 +656,13 @@ __global__ void k_pick_costs(const int64_t* __restrict__ best, const int64_t* __
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_halo, uint16_t* X, float* f32,
-                           hipStream_t s) {
+hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_halo, float* cross, uint16_t* X,
+                           float* f32, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cands, n, d_halo, X, f32);
+    const int64_t g = n < 65536 ? n : 65536;
+    hipLaunchKernelGGL(k_node_cross, dim3((unsigned)g), dim3(256), 0, s, cands, n, cross);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cands, n, d_halo, cross, X,
+                       f32);
     return hipGetLastError();
 }
 

@@ -459,7 +459,7 @@ int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nse
     const int64_t n = plan_size(p);
     const int64_t nsel = nseg * topk;
     // scores of every candidate
-    hipError_t e = launch_features(plan_cands(p), n, plan_halo(p), sb->X, nullptr, s);
+    hipError_t e = launch_features(plan_cands(p), n, plan_halo(p), sb->cross, sb->X, nullptr, s);
     if (e == hipSuccess) e = launch_mlp_forward(sb->X, n, r->W, sb->Y, nullptr, nullptr, nullptr, s);
     if (e == hipSuccess) e = launch_combine(sb->Y, n, lambda, sb->score, s);
     // top-k per instance, then the survivors' exact costs
@@ -468,7 +468,7 @@ int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nse
         e = launch_gather(plan_cands(p), sb->sel, nsel, topk, plan_cells_per_item(p), sb->sub, sb->map, sb->sub_seg,
                           sb->sub_hdr, plan_hdr(p), s);
     if (e == hipSuccess) e = plan_eval_sub(p, sb, s);
-    if (e == hipSuccess) e = launch_select_segments(sb->sub_out, sb->sub_seg, nseg, sb->sub_best, s);
+    if (e == hipSuccess) e = launch_select_segments(sb->sub_out, sb->sub_seg, nseg, sb->sub_best, s, sb->map);
     if (e == hipSuccess)
         e = launch_map_best(sb->sub_best, sb->sub_seg, sb->map, sb->sub_out, nseg, sb->seg, d_best, d_best_cost, s);
     if (e != hipSuccess) return set_error(TM_EDEVICE, "ranked search: %s", hipGetErrorString(e));

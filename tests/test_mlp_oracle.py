@@ -78,9 +78,25 @@ def test_features_hand_worked():
     # after the swap the final shape is (2, 4): 2 blocks along dim 0, 4 along dim 1
     assert math.isclose(f[15], 1 / 9) and math.isclose(f[16], 2 / 9)
     assert math.isclose(f[19], (6 - 1) / 10) and math.isclose(f[20], (5 - 2) / 10)
-    vb = 2 * (2 - 1) / 64 + 2 * (4 - 1) / 32
     vf = 2 * (4 - 1) / 64 + 2 * (2 - 1) / 32
-    assert math.isclose(f[23], math.log2(1 + vb) / 4) and math.isclose(f[24], math.log2(1 + vf) / 4)
+    assert f[23] == 0 and math.isclose(f[24], math.log2(1 + vf) / 4)  # no chain table: no estimate
     assert math.isclose(f[25 + 1], 0.25) and math.isclose(f[25 + 4], 0.25) and math.isclose(f[25 + 2], 0.25)
     assert math.isclose(f[30], 2 / 5) and math.isclose(f[31], 1.0) and math.isclose(f[32], 3 / 5)
+    assert f[39] == 0 and f[40] == 0 and math.isclose(f[41], 0 / 8)
     assert f[48] == 0 and f[53] == 2 / 8 and math.isclose(f[58], 1 / 3) and f[59] == 1
+    assert f[60] == 0 and f[61] == 0  # no chain table given: no node crossings
+    # with the chain table: final space (2, 4) after the swap; decompose (4, 2) of
+    # merge(0,1) puts node = a mod 4 with a = F0-fastest index, so along the final
+    # dim of size 4 (the old first factor) every step changes node; along the other
+    # (size 2) a step adds 4 to a, which keeps a mod 4: no crossings
+    import oracle
+    g = mlp.features(c, (1, 1), oracle.chain_table)
+    assert g[61] == 0.0 and g[62] == 1.0
+    # every step along either final dim changes processor (a bijective chain)
+    assert g[36] == 1.0 and g[37] == 1.0
+    cells_t = (2 * (2 - 1) / 64 + 2 * (4 - 1) / 32) * 64 * 32   # = 448 ghost cells
+    cells_i = (2 * (4 - 1) / 32) * 64 * 32                      # = 384 of them inter-node
+    assert math.isclose(g[23], math.log2(1 + cells_t) / 32) and math.isclose(g[60], math.log2(1 + cells_i) / 32)
+    # and the block model is exact here: the oracle's ghost count agrees
+    gc, ic, _, _ = oracle.stencil_cost(c, W.stencil((1, 1), 8))
+    assert (gc, ic) == (448, 384)

@@ -250,7 +250,7 @@ def chain_menu(k):
     if k == 2:
         tails = [lambda f: [], lambda f: [swap(0, 1)],
                  lambda f: [merge(0, 1), split(0, f[1])],
-                 lambda f: [merge(0, 1), balance_split(0, max(1, f[0] - 1))],
+                 lambda f: [merge(0, 1), balance_split(0, np.maximum(1, f[0] - 1))],
                  lambda f: [merge(0, 1), balance_split(0, f[0] + 1)],
                  lambda f: [swap(0, 1), merge(0, 1), split(0, f[0])],
                  lambda f: [merge(0, 1), split(0, f[0] * f[1])],
@@ -264,7 +264,7 @@ def chain_menu(k):
                  lambda f: [merge(0, 2), split(0, f[2]), swap(1, 2)],
                  lambda f: [merge(0, 1), split(0, 1), swap(0, 2)],
                  lambda f: [swap(0, 2), swap(0, 1)],
-                 lambda f: [merge(0, 1), balance_split(0, max(1, f[0] * f[1] - 1))],
+                 lambda f: [merge(0, 1), balance_split(0, np.maximum(1, f[0] * f[1] - 1))],
                  lambda f: [merge(1, 2), split(1, f[2]), swap(0, 1)],
                  lambda f: [merge(0, 1), split(0, f[1]), swap(1, 2)]]
     for base in bases:
@@ -290,3 +290,49 @@ def random_instances(n, seed=2, first=0, octaves=(5, 9), nodes_max=64, gpus=(1, 
     cs = random_candidates(n, seed=seed, first=first, ranks=(3,), octaves=octaves,
                            nodes_max=nodes_max, gpus=gpus, max_ops=0)
     return [(tuple(int(x) for x in c["extent"][:3]), int(c["nodes"]), int(c["gpus"])) for c in cs]
+
+
+def _menu_templates(k):
+    """The chain menu as (kind, a, b, factor-index or None) templates: the argument b
+    of each op is either a constant or derived from F by the given function."""
+    return chain_menu(k)
+
+
+def instance_batch(instances, factorization_lists, menu=None):
+    """Candidates of many search instances at once (vectorised over factorizations):
+    returns (records, seg) with seg[s]..seg[s+1] the candidates of instance s, in the
+    order of instance_candidates()."""
+    out, seg = [], [0]
+    for (extent, nodes, gpus), fs in zip(instances, factorization_lists):
+        k = len(extent)
+        fa = np.asarray(fs, dtype=np.int64).reshape(-1, k)
+        menu_k = menu or chain_menu(k)
+        m = len(fa)
+        recs = np.zeros((m, len(menu_k)), dtype=CAND_DTYPE)
+        recs["lrank"] = k
+        recs["nodes"], recs["gpus"] = nodes, gpus
+        for d, l in enumerate(extent):
+            recs["extent"][:, :, d] = l
+        cols = tuple(fa[:, j] for j in range(k))
+        for mi, (base, tail) in enumerate(menu_k):
+            ops = base + [(DECOMPOSE, 0, 0, None)] + tail(cols)
+            r = recs[:, mi]
+            r["nops"] = len(ops)
+            rank = 2
+            for t, (kind, a, b, f) in enumerate(ops):
+                r["ops"][:, t]["kind"] = kind
+                r["ops"][:, t]["a"] = a
+                if kind == DECOMPOSE:
+                    r["ops"][:, t]["nf"] = k
+                    for j in range(k):
+                        r["ops"][:, t]["f"][:, j] = fa[:, j]
+                    rank += k - 1
+                else:
+                    r["ops"][:, t]["b"] = b
+                    rank += 1 if kind in (SPLIT, BALANCE_SPLIT) else (-1 if kind == MERGE else 0)
+            r["mrank"] = rank
+            for j in range(rank):
+                r["proj_src"][:, j] = j
+        out.append(recs.reshape(-1))
+        seg.append(seg[-1] + m * len(menu_k))
+    return np.concatenate(out), np.array(seg, np.int64)
