@@ -177,15 +177,71 @@ def features(c, halo, chain_table=None):
         d = int(c["proj_src"][j])
         cn[d] = max(cn[d], cross_n[j])
         cp[d] = max(cp[d], cross_p[j])
+    # block-model estimates of the ghost cells (total, inter-node).  When every launch
+    # dim is block-projected onto exactly one final dim: at each block boundary b
+    # along a launch dim the min(h, b) + min(h, l - b) cells within the halo, times
+    # the face area (product of the other dims' block widths), count where the
+    # owners (nodes) of the two adjacent blocks differ.  Otherwise: per launch dim,
+    # the (cell, distinct foreign final coordinate) pairs along it, times the other
+    # extents, times that dim's crossing fraction.
+    pts = float(np.prod([int(x) for x in c["extent"][:k]]))
     est_t = est_i = 0.0
-    pts = 1.0
-    for d in range(k):
-        face = 2.0 * halo[d] * (blocks[d] - 1.0) / float(c["extent"][d])
-        est_t += face * cp[d]
-        est_i += face * cn[d]
-        pts *= float(c["extent"][d])
-    f[23] = math.log2(1 + est_t * pts) / 32
-    f[60] = math.log2(1 + est_i * pts) / 32
+    proj = [(int(c["proj_src"][j]), int(c["proj_mode"][j])) for j in range(len(s))]
+    simple = len(s) == k and sorted(p for p, _ in proj) == list(range(k)) and all(m == 0 for _, m in proj)
+    have = chain_table is not None and int(np.prod(s)) <= 16384
+    if have and simple:
+        def width(a, S, l):
+            return -(-(a + 1) * l // S) - (-(-a * l // S))
+        for j in range(k):
+            d = proj[j][0]
+            l, S, h = int(c["extent"][d]), s[j], int(halo[d])
+            if h == 0 or S == 1:
+                continue
+            # face area of every coordinate of the other final dims
+            face = np.ones([s[jj] for jj in range(k) if jj != j])
+            for ax, jj in enumerate([jj for jj in range(k) if jj != j]):
+                ld = int(c["extent"][proj[jj][0]])
+                wv = np.array([width(a, s[jj], ld) for a in range(s[jj])], dtype=np.float64)
+                shp = [1] * face.ndim
+                shp[ax] = s[jj]
+                face = face * wv.reshape(shp)
+            for aR in range(1, S):
+                b = -(-aR * l // S)
+                if b >= l or width(aR, S, l) == 0:
+                    continue
+                aL = (b - 1) * S // l
+                pr, pl = np.take(proc, aR, axis=j), np.take(proc, aL, axis=j)
+                w = min(h, b) + min(h, l - b)
+                est_t += w * float(face[pr != pl].sum())
+                est_i += w * float(face[pr // g != pl // g].sum())
+    elif have:
+        stride = [1] * len(s)
+        for j in range(len(s) - 2, -1, -1):
+            stride[j] = stride[j + 1] * s[j + 1]
+        for d in range(k):
+            l = int(c["extent"][d])
+            h = int(halo[d])
+            if h == 0 or l > 65536:
+                continue
+            x = np.arange(l, dtype=np.int64)
+            val = np.zeros(l, dtype=np.int64)
+            for j in range(len(s)):
+                if proj[j][0] == d:
+                    a = (x * s[j]) // l if proj[j][1] == 0 else x % s[j]
+                    val += a * stride[j]
+            nb = 0
+            for xi in range(l):
+                seen = set()
+                for sft in range(1, h + 1):
+                    for xx in (xi - sft, xi + sft):
+                        if 0 <= xx < l and val[xx] != val[xi]:
+                            seen.add(int(val[xx] - val[xi]))
+                nb += len(seen)
+            cells = nb * (pts / l)
+            est_t += cells * cp[d]
+            est_i += cells * cn[d]
+    f[23] = math.log2(1 + est_t) / 32
+    f[60] = math.log2(1 + est_i) / 32
     for d in range(3):
         f[61 + d] = cn[d]
         f[36 + d] = cp[d]

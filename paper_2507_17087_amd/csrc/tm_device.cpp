@@ -30,10 +30,10 @@ static int64_t rows_per_item_for(const DevCand& d, int64_t cells_per_item) {
 static int64_t up4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
 // Arena layout of one candidate: owner table T, the last dim's coordinate table
-// (16-byte aligned, read four entries at a time), the other coordinate tables --
-// the prefix staged in LDS -- then the last dim's offset lists (also staged when
-// they fit the LDS budget, else read from global memory), then the other dims'
-// offset lists (read from global memory once per row).  H = 0: no offset lists.
+// (16-byte aligned, zero-padded to whole 512-entry chunks), the other coordinate
+// tables -- the prefix staged in LDS -- then the last dim's offset lists (also
+// staged when they fit the LDS budget, else read from global memory).  H = 0: no
+// offset lists.
 static int layout_tables(DevCand& d, int H) {
     const int K = d.lrank;
     int64_t off = up4(d.vol);
@@ -54,10 +54,7 @@ static int layout_tables(DevCand& d, int H) {
         // the last dim's offset lists join the LDS prefix when they fit
         d.dl_lds = off + 4 <= kMaxLdsWords ? 1 : 0;
         staged = d.dl_lds ? off + 4 : tables;
-        for (int k = 0; k < K - 1; ++k) {
-            d.dl_off[k] = (int32_t)std::min<int64_t>(off, INT32_MAX);
-            off += 2 * H * d.extent[k];
-        }
+        for (int k = 0; k < K - 1; ++k) d.dl_off[k] = 0;  // outer dims: offsets come from the tables
     } else {
         for (int k = 0; k < K; ++k) d.dl_off[k] = 0;
         d.dl_lds = 0;
@@ -737,7 +734,7 @@ int plan_features(const tm_plan* p, float* d_feat, hipStream_t s) {
             hipMalloc((void**)&b.Y, (size_t)std::max<int64_t>(n, 1) * kOut * 4) != hipSuccess ||
             hipMalloc((void**)&b.score, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
             hipMalloc((void**)&b.scratch, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
-            hipMalloc((void**)&b.cross, (size_t)std::max<int64_t>(n, 1) * 2 * kMaxMrankCross * 4) != hipSuccess)
+            hipMalloc((void**)&b.cross, (size_t)std::max<int64_t>(n, 1) * (2 * kMaxMrankCross + 4) * 4) != hipSuccess)
             return set_error(TM_ENOMEM, "feature buffers");
         b.cap_n = n;
     }
@@ -779,7 +776,7 @@ int plan_search_prepare(tm_plan* p, const int64_t* seg, int64_t nseg, int32_t to
                 hipMalloc((void**)&b.Y, (size_t)std::max<int64_t>(n, 1) * kOut * 4) != hipSuccess ||
                 hipMalloc((void**)&b.score, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
                 hipMalloc((void**)&b.scratch, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
-                hipMalloc((void**)&b.cross, (size_t)std::max<int64_t>(n, 1) * 2 * kMaxMrankCross * 4) != hipSuccess)
+                hipMalloc((void**)&b.cross, (size_t)std::max<int64_t>(n, 1) * (2 * kMaxMrankCross + 4) * 4) != hipSuccess)
                 return set_error(TM_ENOMEM, "score buffers");
             b.cap_n = n;
         }

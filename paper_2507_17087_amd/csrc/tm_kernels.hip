@@ -44,9 +44,9 @@ __device__ __forceinline__ int wave_sum(int v) {
 // ------------------------------------------------------------------ table build
 
 // One workgroup per candidate (grid-stride over candidates).  With halos (use_halo),
-// each coordinate x of launch dim d also gets the list of distinct non-zero offsets
-// C_d[x +- s] - C_d[x] (1 <= s <= h_d, in-domain neighbours), and its count in the
-// coordinate entry.
+// each coordinate x of launch dim d gets the number of distinct non-zero offsets
+// C_d[x +- s] - C_d[x] (1 <= s <= h_d, in-domain neighbours) in its entry, and for
+// the last launch dim the list of those offsets.
 __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restrict__ hdr,
                                                       const DevCand* __restrict__ cands,
                                                       int32_t* __restrict__ arena, int use_halo) {
@@ -63,9 +63,11 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
             const int64_t l = sc.extent[d];
             const int h = use_halo ? hdr->halo[d] : 0;
             int32_t* ct = base + sc.coord_off[d];
+            const bool last = d == sc.lrank - 1;
             int32_t* dl = base + sc.dl_off[d];
             for (int64_t x = threadIdx.x; x < l; x += blockDim.x) {
                 const int32_t val = coord_value(sc, d, x);
+                int32_t found[2 * kMaxHalo];
                 int cnt = 0;
                 for (int s = 1; s <= h; ++s) {
                     for (int dir = 0; dir < 2; ++dir) {
@@ -74,11 +76,12 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
                         const int32_t dv = coord_value(sc, d, xx) - val;
                         if (dv == 0) continue;
                         bool seen = false;
-                        for (int i = 0; i < cnt; ++i) seen = seen || (dl[x * hs + i] == dv);
-                        if (!seen) dl[x * hs + cnt++] = dv;
+                        for (int i = 0; i < cnt; ++i) seen = seen || (found[i] == dv);
+                        if (!seen) found[cnt++] = dv;
                     }
                 }
-                for (int i = cnt; i < hs; ++i) dl[x * hs + i] = 0;
+                if (last)  // only the last dim's lists are stored (outer dims use the tables)
+                    for (int i = 0; i < hs; ++i) dl[x * hs + i] = i < cnt ? found[i] : 0;
                 ct[x] = val | (cnt << kCntShift);
             }
             if (d == sc.lrank - 1)  // zero entries up to a multiple of 512 (scanned eight per lane)

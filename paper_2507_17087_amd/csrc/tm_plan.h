@@ -25,7 +25,7 @@ struct SearchBufs {
     int64_t cap_n = 0, cap_sel = 0, cap_seg = 0, cap_words = 0, cap_all = 0;
     uint16_t* X = nullptr;          // [n][kFeat] bf16 features
     float *Y = nullptr, *score = nullptr, *scratch = nullptr;
-    float* cross = nullptr;         // [n][16] node / processor crossing fractions (ranker features)
+    float* cross = nullptr;         // [n][16] crossing fractions, then [n][4] neighbour counts (features)
     int64_t* seg = nullptr;         // [nseg+1] instance segments
     int64_t* sel = nullptr;         // [nseg*k] chosen candidate indices
     DevCand* sub = nullptr;         // [nseg*k] survivors

@@ -36,30 +36,46 @@ __device__ __forceinline__ f32x4 mfma16(u16x8 a, u16x8 b, f32x4 c) {
 
 __device__ __forceinline__ float lg2(double x) { return (float)log2(x); }
 
-// Crossings of the chain: for every final-space dim j, the fractions of adjacent
-// coordinate pairs (a, a + e_j) whose owners sit on different nodes (first 8
-// floats) and are different processors (next 8).
-// One workgroup per candidate; node ids of all final coordinates staged in LDS
+// Per-candidate chain statistics for the ranker features:
+//   cross[0..8)   per final dim j: fraction of adjacent coordinate pairs (a, a+e_j)
+//                 whose owners sit on different nodes;
+//   cross[8..16)  the same for different processors;
+//   est[0..2)     block-model estimate of the ghost cells and of the inter-node
+//                 ones.  When every launch dim is projected (block) onto exactly one
+//                 final dim, each cell boundary b along a launch dim is seen by the
+//                 min(h, b) + min(h, l - b) cells within the halo of it, times the
+//                 area of the face (product of the block widths of the other dims),
+//                 counted where the owners (or nodes) on the two sides differ --
+//                 exact for bijective chains whose blocks are at least h wide.
+//                 Otherwise: per launch dim, the (cell, distinct foreign coordinate)
+//                 pairs along it times the other extents times the crossing fraction.
+// One workgroup per candidate; owners of all final coordinates staged in LDS
 // (volumes above kCrossMax give zeros).
 constexpr int kCrossMax = 16384;
 
-__global__ __launch_bounds__(256) void k_node_cross(const DevCand* __restrict__ cands, int64_t n,
-                                                    float* __restrict__ cross) {
+__device__ __forceinline__ int64_t block_first(int64_t a, int64_t S, int64_t l) { return (a * l + S - 1) / S; }
+
+__global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__ cands, int64_t n,
+                                                     const int32_t* __restrict__ halo, float* __restrict__ cross,
+                                                     double* __restrict__ est) {
     __shared__ DevCand sc;
-    __shared__ int32_t node[kCrossMax];
+    __shared__ int32_t key[kCrossMax];
     __shared__ int32_t red[3][256];
+    __shared__ double dred[2][256];
     for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
         __syncthreads();
         stage_cand(&sc, &cands[ci]);
         __syncthreads();
         const int32_t vol = sc.vol;
+        const int K = sc.lrank, gb = sc.gbits;
         if (vol > kCrossMax) {
             if (threadIdx.x < 2 * kMaxMrankCross) cross[ci * 2 * kMaxMrankCross + threadIdx.x] = 0.f;
+            if (threadIdx.x < 2) est[ci * 2 + threadIdx.x] = 0.0;
             continue;
         }
-        for (int32_t v = threadIdx.x; v < vol; v += blockDim.x) node[v] = owner_key(sc, v);
+        for (int32_t v = threadIdx.x; v < vol; v += blockDim.x) key[v] = owner_key(sc, v);
         __syncthreads();
-        const int gb = sc.gbits;
+        // crossing fractions per final dim
         for (int j = 0; j < kMaxMrankCross; ++j) {
             int pairs = 0, dn = 0, dp = 0;
             if (j < sc.frank) {
@@ -67,8 +83,8 @@ __global__ __launch_bounds__(256) void k_node_cross(const DevCand* __restrict__ 
                 for (int32_t v = threadIdx.x; v < vol; v += blockDim.x) {
                     if ((v / st) % S < S - 1) {
                         ++pairs;
-                        dp += node[v] != node[v + st];
-                        dn += (node[v] >> gb) != (node[v + st] >> gb);
+                        dp += key[v] != key[v + st];
+                        dn += (key[v] >> gb) != (key[v + st] >> gb);
                     }
                 }
             }
@@ -91,6 +107,96 @@ __global__ __launch_bounds__(256) void k_node_cross(const DevCand* __restrict__ 
             }
             __syncthreads();
         }
+        // is every launch dim projected (block) onto exactly one final dim?
+        int fdim[4] = {-1, -1, -1, -1};
+        bool simple = sc.frank == K;
+        for (int j = 0; j < sc.frank && simple; ++j) {
+            const int d = sc.proj_src[j];
+            if (fdim[d] >= 0 || sc.proj_mode[j] != TM_BLOCK) simple = false;
+            else fdim[d] = j;
+        }
+        double tot = 0, inter = 0;
+        if (simple) {
+            for (int d = 0; d < K; ++d) {
+                const int j = fdim[d];
+                const int64_t l = sc.extent[d], S = sc.fshape[j];
+                const int h = halo[d];
+                const int32_t st = sc.fstride[j];
+                if (h == 0 || S == 1) continue;
+                // boundaries along d: the first cell b of every non-empty block a >= 1,
+                // against the block holding cell b - 1
+                const int32_t others = vol / (int32_t)S;
+                for (int64_t t = threadIdx.x; t < (S - 1) * others; t += blockDim.x) {
+                    const int32_t aR = (int32_t)(1 + t / others);
+                    int32_t u = (int32_t)(t % others);
+                    const int64_t b = block_first(aR, S, l);
+                    if (b >= l || b >= block_first(aR + 1, S, l)) continue;  // empty block
+                    const int32_t aL = (int32_t)((b - 1) * S / l);
+                    // decode the other coordinates from u (C order over dims != j)
+                    int32_t vR = aR * st, vL = aL * st;
+                    double face = 1;
+                    for (int jj = sc.frank - 1; jj >= 0; --jj) {
+                        if (jj == j) continue;
+                        const int32_t Sj = sc.fshape[jj];
+                        const int32_t aj = u % Sj;
+                        u /= Sj;
+                        vR += aj * sc.fstride[jj];
+                        vL += aj * sc.fstride[jj];
+                        const int64_t lj = sc.extent[sc.proj_src[jj]];
+                        face *= (double)(block_first(aj + 1, Sj, lj) - block_first(aj, Sj, lj));
+                    }
+                    const double w = (double)((h < b ? h : b) + (h < l - b ? h : l - b));
+                    if (key[vL] != key[vR]) tot += w * face;
+                    if ((key[vL] >> gb) != (key[vR] >> gb)) inter += w * face;
+                }
+                __syncthreads();
+            }
+        } else {
+            for (int d = 0; d < K; ++d) {
+                const int64_t l = sc.extent[d];
+                const int h = halo[d];
+                double part = 0;
+                if (h > 0 && l <= 65536) {
+                    for (int64_t x = threadIdx.x; x < l; x += blockDim.x) {
+                        const int32_t val = coord_value(sc, d, x);
+                        int32_t found[2 * kMaxHalo];
+                        int cnt = 0;
+                        for (int sft = 1; sft <= h && sft <= kMaxHalo; ++sft)
+                            for (int dir = 0; dir < 2; ++dir) {
+                                const int64_t xx = dir ? x + sft : x - sft;
+                                if (xx < 0 || xx >= l) continue;
+                                const int32_t dv = coord_value(sc, d, xx) - val;
+                                bool seen = dv == 0;
+                                for (int i = 0; i < cnt; ++i) seen = seen || found[i] == dv;
+                                if (!seen) found[cnt++] = dv;
+                            }
+                        part += cnt;
+                    }
+                }
+                float cn = 0.f, cp = 0.f;
+                for (int j = 0; j < sc.frank && j < kMaxMrankCross; ++j)
+                    if (sc.proj_src[j] == d) {
+                        cn = fmaxf(cn, cross[ci * 2 * kMaxMrankCross + j]);
+                        cp = fmaxf(cp, cross[ci * 2 * kMaxMrankCross + kMaxMrankCross + j]);
+                    }
+                double pts = 1;
+                for (int dd = 0; dd < K; ++dd)
+                    if (dd != d) pts *= (double)sc.extent[dd];
+                tot += part * pts * cp;
+                inter += part * pts * cn;
+            }
+        }
+        dred[0][threadIdx.x] = tot;
+        dred[1][threadIdx.x] = inter;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                dred[0][threadIdx.x] += dred[0][threadIdx.x + w];
+                dred[1][threadIdx.x] += dred[1][threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x < 2) est[ci * 2 + threadIdx.x] = dred[threadIdx.x][0];
     }
 }
 
@@ -98,8 +204,8 @@ __global__ __launch_bounds__(256) void k_node_cross(const DevCand* __restrict__ 
 // feat_f32 is given, the same values in fp32.
 __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ cands, int64_t n,
                                                   const int32_t* __restrict__ halo,
-                                                  const float* __restrict__ cross, uint16_t* __restrict__ X,
-                                                  float* __restrict__ feat_f32) {
+                                                  const float* __restrict__ cross, const double* __restrict__ est,
+                                                  uint16_t* __restrict__ X, float* __restrict__ feat_f32) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const DevCand& c = cands[i];
@@ -155,15 +261,8 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
         cn[d] = fmaxf(cn[d], cross[i * 2 * kMaxMrankCross + j]);
         cp[d] = fmaxf(cp[d], cross[i * 2 * kMaxMrankCross + kMaxMrankCross + j]);
     }
-    double est_t = 0, est_i = 0, pts = 1;
-    for (int d = 0; d < k; ++d) {
-        const double face = 2.0 * halo[d] * (blocks[d] - 1.0) / (double)c.extent[d];
-        est_t += face * cp[d];
-        est_i += face * cn[d];
-        pts *= (double)c.extent[d];
-    }
-    f[23] = lg2(1.0 + est_t * pts) / 32.f;
-    f[60] = lg2(1.0 + est_i * pts) / 32.f;
+    f[23] = lg2(1.0 + est[i * 2]) / 32.f;
+    f[60] = lg2(1.0 + est[i * 2 + 1]) / 32.f;
     for (int d = 0; d < 3; ++d) {
         f[61 + d] = cn[d];
         f[36 + d] = cp[d];
@@ -660,9 +759,10 @@ hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_hal
                            float* f32, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t g = n < 65536 ? n : 65536;
-    hipLaunchKernelGGL(k_node_cross, dim3((unsigned)g), dim3(256), 0, s, cands, n, cross);
-    hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cands, n, d_halo, cross, X,
-                       f32);
+    double* est = reinterpret_cast<double*>(cross + n * 2 * kMaxMrankCross);  // 64n bytes in: 8-byte aligned
+    hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(256), 0, s, cands, n, d_halo, cross, est);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cands, n, d_halo, cross, est,
+                       X, f32);
     return hipGetLastError();
 }
 
