@@ -29,6 +29,24 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 32-bit VALU lane-ops/s: 256 CUs x 64 lan
 OPS_PER_POINT = 2                     # table read + boundary test: the least any point costs
 PEAK_HBM = 8.0e12                     # bytes/s
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a
+# plain copy's readings: reads x2.000, writes x1.000), valid only for the kernel
+# sources they were taken on (hash of the files below); see
+# profiles/k_count_k_map_c2_512cube_hbm_traffic.txt.
+KERNEL_SOURCES = ["paper_2507_17087_amd/csrc/tm_kernels.hip", "paper_2507_17087_amd/csrc/tm_chain.h",
+                  "paper_2507_17087_amd/csrc/tm_internal.h"]
+TRAFFIC_SOURCE_HASH = "cb67c951323296a2"
+TRAFFIC_BYTES = {"k_count<3,2>": 42.71e6, "k_map": 537.84e6}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC_BYTES.get(kernel) if h.hexdigest()[:16] == TRAFFIC_SOURCE_HASH else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -38,6 +56,8 @@ def parse():
     ap.add_argument("--extent", type=int, default=512, help="cube side of the launch domain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--launch", type=int, nargs=2, metavar=("CELLS_PER_ITEM", "WG_PER_CU"),
+                    help="fixed counting launch configuration instead of autotuning (e.g. for profiling)")
     ap.add_argument("--search", action="store_true", help="also run the learned-ranker search leg")
     ap.add_argument("--search-train", type=int, default=1_000_000, help="training candidates (exact costs)")
     ap.add_argument("--search-eval", type=int, default=1_000_000, help="evaluation candidates")
@@ -119,13 +139,22 @@ def search_leg(args, tm, W):
     e3 = time.perf_counter()
     ce, cr = c_ex.cpu().numpy(), c_rk.cpu().numpy()
     ok = (ce[:, 2] == cr[:, 2]) & (ce[:, 3] == cr[:, 3])
+    # ablation: the same search with an all-zero network ranks by the block-model
+    # estimates alone
+    r0 = tm.Ranker(seed=1)
+    r0.set_params(torch.zeros(tm.tm_ranker_param_count(), dtype=torch.float32, device="cuda"))
+    _, c_0 = tm.tm_search(plan, r0, seg, topk=64)
+    c0 = c_0.cpu().numpy()
+    ok0 = (ce[:, 2] == c0[:, 2]) & (ce[:, 3] == c0[:, 3])
+    r0.close()
     n = len(ec)
     ex_rate = n / (e1 - e0)
     rk_rate = n / ((e3 - e2) / reps)
     plan.close()
     r.close()
     return {"instances": int(len(seg) - 1), "candidates": int(n), "topk": 64,
-            "opt_rate": float(ok.mean()), "ranked_candidates_per_s": rk_rate,
+            "opt_rate": float(ok.mean()), "estimate_only_opt_rate": float(ok0.mean()),
+            "ranked_candidates_per_s": rk_rate,
             "exhaustive_candidates_per_s": ex_rate, "speedup": rk_rate / ex_rate,
             "train_candidates": int(len(tc)), "train_epochs": args.search_epochs,
             "train_loss_first_last": [losses[0], losses[-1]] if losses else None,
@@ -166,7 +195,10 @@ def main():
         torch.cuda.synchronize()
         del a, b
     tuned = (0, 0)
-    if not args.no_autotune:
+    if args.launch:
+        tuned = tuple(args.launch)
+        plan.set_launch(*tuned)
+    elif not args.no_autotune:
         tuned = plan.autotune(out)
     _, items, _ = plan.info()
 
@@ -227,11 +259,11 @@ def main():
                    "machine": [16, 8], "work_items": items,
                    "cells_per_item": tuned[0], "wg_per_cu": tuned[1]},
         "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": None,
+                     "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": measured_traffic("k_count<3,2>"),
                      "kernel": "k_count<3,2>", "ops_per_point": OPS_PER_POINT,
                      "kernel_ms": count},
         "roofline_map": {"bound": "hbm", "achieved": map_bw / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                         "frac": map_bw / PEAK_HBM, "traffic": None, "kernel": "k_map",
+                         "frac": map_bw / PEAK_HBM, "traffic": measured_traffic("k_map"), "kernel": "k_map",
                          "bytes_per_point": 4, "kernel_ms": mapk},
         "stages_ms": {"tables": prep, "count": count, "select": sel, "map": mapk},
         "count_point_evals_per_s": points / (count * 1e-3),

@@ -222,6 +222,11 @@ int tm_plan_materialize(tm_plan* p, const int64_t* d_index, int64_t host_index, 
  * writes the chosen cells_per_item and workgroups per CU (host pointers, nullable). */
 int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cells_per_item,
                      int32_t* wg_per_cu, void* stream);
+/* Sets the launch configuration of the loaded batch without timing anything: work
+ * items of cells_per_item cells (0 = default) and at most wg_per_cu counting
+ * workgroups per CU (0 = as many as occupancy allows) -- e.g. a configuration found
+ * by tm_plan_autotune earlier.  TM_EINVAL on negative values. */
+int tm_plan_set_launch(tm_plan* p, int64_t cells_per_item, int32_t wg_per_cu, void* stream);
 /* Counts of the loaded batch: candidates, work items, total points (host, nullable). */
 int tm_plan_info(const tm_plan* p, int64_t* n, int64_t* items, int64_t* points);
 int tm_plan_destroy(tm_plan* p);
@@ -232,8 +237,9 @@ int tm_plan_destroy(tm_plan* p);
  * transformation chains).  Model: 64 features -> 3 hidden layers of width 256
  * (ReLU) -> 2 outputs, BF16 weights and activations with FP32 accumulation on the
  * matrix cores, FP32 master weights trained with Adam on the mean squared error
- * against standardised log2(1 + bytes) and log2(1 + inter-node bytes) of exact
- * costs.  Parameters are one flat fp32 vector of tm_ranker_param_count() values:
+ * against standardised residuals: log2(1 + bytes) and log2(1 + inter-node bytes)
+ * of exact costs, each minus the block-model estimate the features carry
+ * (32 * feature 23 and 32 * feature 60, in fp32).  Parameters are one flat fp32 vector of tm_ranker_param_count() values:
  * W1[64][256], b1[256], W2[256][256], b2, W3[256][256], b3, W4[256][2], b4[2]
  * (row-major, inputs along rows). */
 typedef struct tm_ranker tm_ranker;
@@ -272,7 +278,8 @@ int tm_ranker_load(const char* path, tm_ranker** out);
  * int64[nseg]) receives the index (relative to the instance) of the candidate
  * minimising (bytes, inter_bytes, index) and d_best_cost (device, nullable) its
  * cost.  r == NULL: every candidate is evaluated exactly.  Otherwise the ranker
- * scores every candidate (y0 + lambda * y1), the topk lowest per instance are
+ * scores every candidate by predicted log2(1 + bytes) + lambda * predicted
+ * log2(1 + inter-node bytes) (estimate + residual head), the topk lowest per instance are
  * evaluated exactly on the GPU, and the best of those is returned.  Everything
  * after the segment upload runs on the device, on `stream`. */
 int tm_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t topk, float lambda,

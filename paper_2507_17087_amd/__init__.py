@@ -64,6 +64,7 @@ def lib():
             "tm_plan_run_stage": [P, I32, P, P, P],
             "tm_plan_materialize": [P, P, I64, P, I64, P],
             "tm_plan_autotune": [P, P, P, P, P],
+            "tm_plan_set_launch": [P, I64, I32, P],
             "tm_plan_info": [P, P, P, P],
             "tm_plan_destroy": [P],
         }
@@ -283,6 +284,9 @@ class Plan:
         _check(lib().tm_plan_autotune(self._p, _dev_ptr(out, torch.int64, 4 * self.n), ctypes.byref(c),
                                       ctypes.byref(w), _stream()))
         return c.value, w.value
+
+    def set_launch(self, cells_per_item=0, wg_per_cu=0):
+        _check(lib().tm_plan_set_launch(self._p, int(cells_per_item), int(wg_per_cu), _stream()))
 
     def info(self):
         n, it, pts = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

@@ -702,6 +702,18 @@ extern "C" int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cel
     return rc;
 }
 
+extern "C" int tm_plan_set_launch(tm_plan* p, int64_t cells_per_item, int32_t wg_per_cu, void* stream) {
+    if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
+    if (cells_per_item < 0 || wg_per_cu < 0)
+        return set_error(TM_EINVAL, "cells_per_item %lld, wg_per_cu %d", (long long)cells_per_item, wg_per_cu);
+    p->cells_per_item = cells_per_item;
+    p->wg_per_cu = wg_per_cu;
+    if (p->cp.hdr.n == 0) return TM_OK;
+    layout_items(p->cp, cells_per_item > 0 ? cells_per_item : kDefaultCellsPerItem);
+    plan_drop_graphs(p);
+    return plan_upload(p, (hipStream_t)stream);
+}
+
 // ------------------------------------------------------------------ search support
 
 namespace tmk {

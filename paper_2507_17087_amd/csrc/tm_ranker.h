@@ -72,6 +72,17 @@ struct RankerBuffers {
 };
 
 constexpr int kMaxMrankCross = 8;  // node-crossing fractions kept per candidate
+// The block-model estimates (ghost cells, inter-node ghost cells) enter the features
+// as log2(1 + est) / kBaseScale at kBaseFeat[h]; the network learns the residual of
+// log2(1 + exact bytes) over kBaseScale * feature, so the estimate keeps its fp32
+// precision instead of passing through bf16.
+constexpr int kBaseFeat[kOut] = {23, 60};
+constexpr float kBaseScale = 32.f;
+// Per-candidate chain statistics: 2 * kMaxMrankCross floats, then 2 doubles (estimates).
+constexpr int64_t kCrossFloats = 2 * kMaxMrankCross;
+inline double* chain_estimates(float* cross, int64_t n) {
+    return reinterpret_cast<double*>(cross + n * kCrossFloats);  // 64n bytes in: 8-byte aligned
+}
 
 hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_halo, float* cross, uint16_t* X,
                            float* f32, hipStream_t s);
@@ -84,7 +95,8 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t cou
 hipError_t launch_publish(const float* p, int64_t count, const RankerWeights& W, hipStream_t s);
 hipError_t launch_topk(const float* score, const int64_t* seg, int64_t nseg, int k, float* scratch, int64_t* sel,
                        hipStream_t s);
-hipError_t launch_combine(const float* Y, int64_t n, float lambda, float* s, hipStream_t st);
+hipError_t launch_combine(const float* Y, const double* est, int64_t n, const float* mu, const float* sigma,
+                          float lambda, float* s, hipStream_t st);
 hipError_t launch_gather(const DevCand* cands, const int64_t* sel, int64_t nsel, int k, int64_t cells_per_item,
                          DevCand* sub, int64_t* map, int64_t* seg_out, DevHeader* hdr, const DevHeader* proto,
                          hipStream_t s);

@@ -261,8 +261,8 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
         cn[d] = fmaxf(cn[d], cross[i * 2 * kMaxMrankCross + j]);
         cp[d] = fmaxf(cp[d], cross[i * 2 * kMaxMrankCross + kMaxMrankCross + j]);
     }
-    f[23] = lg2(1.0 + est[i * 2]) / 32.f;
-    f[60] = lg2(1.0 + est[i * 2 + 1]) / 32.f;
+    f[kBaseFeat[0]] = lg2(1.0 + est[i * 2]) / kBaseScale;
+    f[kBaseFeat[1]] = lg2(1.0 + est[i * 2 + 1]) / kBaseScale;
     for (int d = 0; d < 3; ++d) {
         f[61 + d] = cn[d];
         f[36 + d] = cp[d];
@@ -640,10 +640,16 @@ __global__ __launch_bounds__(256) void k_topk(const float* __restrict__ score, c
     }
 }
 
-// Ranking score from the two heads: s = y0 + lambda * y1.
-__global__ void k_combine(const float* __restrict__ Y, int64_t n, float lambda, float* __restrict__ s) {
+// Ranking score: predicted log2(1 + bytes) + lambda * predicted log2(1 + inter-node
+// bytes), each = estimate base (the same fp32 value training used) + un-standardised
+// residual head.
+__global__ void k_combine(const float* __restrict__ Y, const double* __restrict__ est, int64_t n, float mu0,
+                          float s0, float mu1, float s1, float lambda, float* __restrict__ s) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) s[i] = Y[i * kOut] + lambda * Y[i * kOut + 1];
+    if (i >= n) return;
+    const float b0 = kBaseScale * (lg2(1.0 + est[i * 2]) / kBaseScale);
+    const float b1 = kBaseScale * (lg2(1.0 + est[i * 2 + 1]) / kBaseScale);
+    s[i] = (b0 + mu0 + s0 * Y[i * kOut]) + lambda * (b1 + mu1 + s1 * Y[i * kOut + 1]);
 }
 
 // ------------------------------------------------------------------ survivors
@@ -759,7 +765,7 @@ hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_hal
                            float* f32, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t g = n < 65536 ? n : 65536;
-    double* est = reinterpret_cast<double*>(cross + n * 2 * kMaxMrankCross);  // 64n bytes in: 8-byte aligned
+    double* est = chain_estimates(cross, n);
     hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(256), 0, s, cands, n, d_halo, cross, est);
     hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cands, n, d_halo, cross, est,
                        X, f32);
@@ -830,9 +836,11 @@ hipError_t launch_topk(const float* score, const int64_t* seg, int64_t nseg, int
     return hipGetLastError();
 }
 
-hipError_t launch_combine(const float* Y, int64_t n, float lambda, float* s, hipStream_t st) {
+hipError_t launch_combine(const float* Y, const double* est, int64_t n, const float* mu, const float* sigma,
+                          float lambda, float* s, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Y, n, lambda, s);
+    hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Y, est, n, mu[0], sigma[0],
+                       mu[1], sigma[1], lambda, s);
     return hipGetLastError();
 }
 

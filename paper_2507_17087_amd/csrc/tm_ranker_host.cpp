@@ -119,21 +119,29 @@ __global__ void k_pack_batch(const float* __restrict__ feat, const float* __rest
 }
 
 // Standardised targets from exact costs: t_h = (log2(1 + x_h) - mu_h) / sigma_h.
-__global__ void k_targets(const tm_stencil_cost* __restrict__ cost, int64_t n, float m0, float s0, float m1,
-                          float s1, float* __restrict__ T) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    T[i * kOut] = (float)((log2(1.0 + (double)cost[i].bytes) - m0) / s0);
-    T[i * kOut + 1] = (float)((log2(1.0 + (double)cost[i].inter_bytes) - m1) / s1);
+// Residual targets: log2(1 + exact bytes) minus the estimate base carried by the
+// features (kBaseScale * feature kBaseFeat[h]).
+__device__ __forceinline__ double residual(const tm_stencil_cost& c, const float* feat, int64_t i, int h) {
+    const double x = log2(1.0 + (double)(h == 0 ? c.bytes : c.inter_bytes));
+    return x - (double)(kBaseScale * feat[i * kFeat + kBaseFeat[h]]);
 }
 
-// Per-block sums of log2(1 + x) and its square for both heads (fp64 partials).
-__global__ __launch_bounds__(256) void k_target_moments(const tm_stencil_cost* __restrict__ cost, int64_t n,
+__global__ void k_targets(const tm_stencil_cost* __restrict__ cost, const float* __restrict__ feat, int64_t n,
+                          float m0, float s0, float m1, float s1, float* __restrict__ T) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T[i * kOut] = (float)((residual(cost[i], feat, i, 0) - m0) / s0);
+    T[i * kOut + 1] = (float)((residual(cost[i], feat, i, 1) - m1) / s1);
+}
+
+// Per-block sums of the residual targets and their squares for both heads (fp64 partials).
+__global__ __launch_bounds__(256) void k_target_moments(const tm_stencil_cost* __restrict__ cost,
+                                                        const float* __restrict__ feat, int64_t n,
                                                         double* __restrict__ part) {
     __shared__ double s[4][256];
     double a0 = 0, a1 = 0, q0 = 0, q1 = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double x0 = log2(1.0 + (double)cost[i].bytes), x1 = log2(1.0 + (double)cost[i].inter_bytes);
+        const double x0 = residual(cost[i], feat, i, 0), x1 = residual(cost[i], feat, i, 1);
         a0 += x0;
         a1 += x1;
         q0 += x0 * x0;
@@ -302,7 +310,7 @@ int tm_ranker_train(tm_ranker* r, const float* d_feat, const tm_stencil_cost* d_
     float* d_T = nullptr;
     int64_t* d_perm = nullptr;
     TM_HIP(hipMalloc((void**)&d_part, nb * 4 * sizeof(double)));
-    hipLaunchKernelGGL(k_target_moments, dim3(nb), dim3(256), 0, s, d_cost, n, d_part);
+    hipLaunchKernelGGL(k_target_moments, dim3(nb), dim3(256), 0, s, d_cost, d_feat, n, d_part);
     std::vector<double> part(nb * 4);
     TM_HIP(hipMemcpyAsync(part.data(), d_part, part.size() * 8, hipMemcpyDeviceToHost, s));
     TM_HIP(hipStreamSynchronize(s));
@@ -319,7 +327,7 @@ int tm_ranker_train(tm_ranker* r, const float* d_feat, const tm_stencil_cost* d_
         hipMalloc((void**)&d_perm, (size_t)n * 8) != hipSuccess)
         rc = set_error(TM_ENOMEM, "training buffers");
     if (rc == TM_OK) {
-        hipLaunchKernelGGL(k_targets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_cost, n, r->mu[0],
+        hipLaunchKernelGGL(k_targets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_cost, d_feat, n, r->mu[0],
                            r->sigma[0], r->mu[1], r->sigma[1], d_T);
         rc = ranker_buffers(r, batch);
     }
@@ -461,7 +469,7 @@ int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nse
     // scores of every candidate
     hipError_t e = launch_features(plan_cands(p), n, plan_halo(p), sb->cross, sb->X, nullptr, s);
     if (e == hipSuccess) e = launch_mlp_forward(sb->X, n, r->W, sb->Y, nullptr, nullptr, nullptr, s);
-    if (e == hipSuccess) e = launch_combine(sb->Y, n, lambda, sb->score, s);
+    if (e == hipSuccess) e = launch_combine(sb->Y, chain_estimates(sb->cross, n), n, r->mu, r->sigma, lambda, sb->score, s);
     // top-k per instance, then the survivors' exact costs
     if (e == hipSuccess) e = launch_topk(sb->score, sb->seg, nseg, topk, sb->scratch, sb->sel, s);
     if (e == hipSuccess)

@@ -301,6 +301,14 @@ def test_plan_autotune_keeps_results(tm):
     torch.cuda.synchronize()
     assert (out.cpu().numpy() == a).all()
     assert (a == oracle.stencil_cost_batch(cands, st)).all()
+    # fixed launch configurations give the same counts
+    for cpi, wg in ((1 << 12, 1), (1 << 15, 0), (0, 2)):
+        say("  set_launch", cpi, wg)
+        plan.set_launch(cpi, wg)
+        out.fill_(-1)
+        plan.run(out)
+        torch.cuda.synchronize()
+        assert (out.cpu().numpy() == a).all()
     plan.close()
 
 

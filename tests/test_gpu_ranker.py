@@ -115,7 +115,15 @@ def test_one_adam_step(tm):
     r.train(feat, costs, epochs=1, batch=len(cands), lr=1e-3, seed=1)
     mu0, s0, mu1, s1 = r.scaling()
     c = costs.cpu().numpy().astype(np.float64)
-    T = np.stack([(np.log2(1 + c[:, 2]) - mu0) / s0, (np.log2(1 + c[:, 3]) - mu1) / s1], 1).astype(np.float32)
+    fb = feat.cpu().numpy()
+    # residual targets over the block-model estimate features (fp32 base, as trained)
+    b0 = (np.float32(32) * fb[:, 23]).astype(np.float64)
+    b1 = (np.float32(32) * fb[:, 60]).astype(np.float64)
+    T = np.stack([(np.log2(1 + c[:, 2]) - b0 - mu0) / s0, (np.log2(1 + c[:, 3]) - b1 - mu1) / s1],
+                 1).astype(np.float32)
+    # the scaling is the mean / standard deviation of those residuals
+    assert abs(np.mean(np.log2(1 + c[:, 2]) - b0) - mu0) < 1e-4
+    assert abs(np.std(np.log2(1 + c[:, 3]) - b1) - s1) < 1e-3 * max(1.0, s1)
     g = twin.grad(feat, torch.from_numpy(T).cuda()).cpu().numpy().astype(np.float64)
     exp, _, _ = mlp.adam_step(p0, g, np.zeros_like(p0), np.zeros_like(p0), 1, 1e-3)
     got = r.get_params().cpu().numpy().astype(np.float64)
