@@ -130,9 +130,10 @@ hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_
 //     offsets to its outer neighbours, computed from the coordinate tables when
 //     the row lies within a halo of a block boundary of an outer dim.
 //   - Rows without outer offsets: a cell can have a foreign neighbour only along
-//     the last dim, i.e. when its entry's offset count is non-zero.  Groups of
-//     eight cells holding such a cell are compacted into a per-wave LDS queue
-//     (ballot + prefix count) and evaluated 64 groups at a time with every lane busy.
+//     the last dim, i.e. when its entry's offset count is non-zero.  Such cells
+//     are compacted into a per-wave LDS queue (prefix count from ballots) and
+//     evaluated 64 at a time, one per lane; a chunk holding more than 64 of them
+//     is evaluated in place.
 //   - Rows with outer offsets: every cell is evaluated; a cell whose entry equals
 //     its left neighbour's and has no last-dim offsets reuses its result (same
 //     index, same neighbours).
@@ -216,6 +217,20 @@ __device__ __forceinline__ void eval_group(const int32_t* __restrict__ T, XP DL,
     }
 }
 
+// One queued cell (row base index bq, last-dim coordinate xq) of a row without
+// outer offsets: only its last-dim neighbours can be foreign.
+template <typename XP>
+__device__ __forceinline__ void eval_queued(const int32_t* __restrict__ T, const int32_t* __restrict__ CL, XP DL,
+                                            int HS, int32_t bq, int32_t xq, int gbits, int& cnt, int& icnt) {
+    const int32_t e = CL[xq];
+    eval_cell(T, bq + cval(e), nullptr, 0, DL + xq * HS, ccnt(e), gbits, cnt, icnt);
+}
+
+// Number of set bits of m in the lanes below this one.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ __forceinline__ void load8(const int32_t* p, int32_t (&e8)[kCellsPerLane]) {
     const i32x4 a = *reinterpret_cast<const i32x4*>(p);
     const i32x4 b = *reinterpret_cast<const i32x4*>(p + 4);
@@ -294,7 +309,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
             if (ccnt(e)) nr = outer_offsets<H>(T + off[K - 2], q[K - 2], ext[K - 2], hal[K - 2], rl, no);
         }
         if (nr == 0) {
-            // ---- sparse row: groups of eight cells with last-dim offsets go to the queue
+            // ---- sparse row: cells with last-dim offsets go to the queue one by one
             for (int xb = 0; xb < L; xb += kChunk) {
                 const int x0 = xb + kCellsPerLane * lane;
                 int32_t e8[kCellsPerLane];
@@ -303,21 +318,36 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
 #pragma unroll
                 for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
                 const bool hit = (uint32_t)any > (uint32_t)kValMask;
-                const uint64_t m = __ballot(hit);
-                if (m == 0ull) continue;
-                const int pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                if (hit) {
-                    qv[pos] = base;
-                    qx[pos] = x0;
+                if (__ballot(hit) == 0ull) continue;
+                uint32_t fl = 0;
+#pragma unroll
+                for (int j = 0; j < kCellsPerLane; ++j) fl |= ((uint32_t)e8[j] > (uint32_t)kValMask ? 1u : 0u) << j;
+                // exclusive prefix of the per-lane counts (0..8) over the wave, from the
+                // ballots of their four bit planes
+                const int c = __popc(fl);
+                int pre = 0, tot = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint64_t m = __ballot((c >> b) & 1);
+                    pre += lanes_below(m) << b;
+                    tot += __popcll(m) << b;
                 }
-                qn += __popcll(m);
+                if (tot > 64) {  // a crowded chunk: evaluate it in place
+                    eval_group(T, DL, HS, e8, x0, L, base, rl, 0, gbits, true, cnt, icnt);
+                    continue;
+                }
+                int pos = qn + pre;
+                while (fl) {
+                    const int j = __builtin_ctz(fl);
+                    fl &= fl - 1;
+                    qv[pos] = base;
+                    qx[pos] = x0 + j;
+                    ++pos;
+                }
+                qn += tot;
                 wave_sync_lds();
                 if (qn >= 64) {
-                    const int32_t bq = qv[lane], xq = qx[lane];
-                    int32_t g8[kCellsPerLane];
-                    load8(CL + xq, g8);
-                    eval_group(T, DL, HS, g8, xq, L, bq, rl, 0, gbits, true, cnt, icnt);
+                    eval_queued(T, CL, DL, HS, qv[lane], qx[lane], gbits, cnt, icnt);
                     wave_sync_lds();
                     if (lane < qn - 64) {
                         qv[lane] = qv[lane + 64];
@@ -355,12 +385,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     }
     // drain the queue
     if (qn > 0) {
-        if (lane < qn) {
-            const int32_t bq = qv[lane], xq = qx[lane];
-            int32_t g8[kCellsPerLane];
-            load8(CL + xq, g8);
-            eval_group(T, DL, HS, g8, xq, L, bq, rl, 0, gbits, true, cnt, icnt);
-        }
+        if (lane < qn) eval_queued(T, CL, DL, HS, qv[lane], qx[lane], gbits, cnt, icnt);
         wave_sync_lds();
     }
 }
@@ -376,7 +401,8 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
     __shared__ int32_t s_qv[4][kQueueCap], s_qx[4][kQueueCap];
     __shared__ int32_t s_rl[4][32];
 
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps the row loops scalar
     const int64_t total = uniform64(hdr->total_items);
     const int64_t n = uniform64(hdr->n);
     int hal[K];

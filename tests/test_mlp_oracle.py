@@ -100,3 +100,37 @@ def test_features_hand_worked():
     # and the block model is exact here: the oracle's ghost count agrees
     gc, ic, _, _ = oracle.stencil_cost(c, W.stencil((1, 1), 8))
     assert (gc, ic) == (448, 384)
+
+
+def test_block_estimate_exact_for_bijective_block_chains():
+    """For a bijective block mapping (every processor owns one block), the ghost cells
+    along a launch dim are, per cell, the blocks whose first or last cell lies within
+    the halo; summed per block boundary that is min(h, b) + min(h, l - b) cells times
+    the face area -- so the estimate equals the exact distinct-pair volume of the C
+    oracle (Sec. 4.1's definition) for any block width, halos wider than blocks included.
+    Inter-node cells are exact when no block is narrower than the halo."""
+    import oracle
+    rng = np.random.default_rng(5)
+    checked = 0
+    for _ in range(40):
+        k = int(rng.integers(2, 4))
+        ext = tuple(int(x) for x in rng.integers(3, 40, size=k))
+        halo = tuple(int(x) for x in rng.integers(1, 5, size=k))
+        n, g = int(rng.integers(1, 5)), int(rng.choice([1, 2, 4]))
+        P = n * g
+        fs = oracle.enumerate_factorizations(P, k)
+        f = fs[int(rng.integers(0, len(fs)))]
+        if any(f[d] > ext[d] for d in range(k)):
+            continue  # empty blocks: not bijective
+        base = [merge(0, 1)] if rng.integers(0, 2) else [swap(0, 1), merge(0, 1)]
+        c = W.candidate(ext, n, g, base + [decompose(0, f)])
+        cost = oracle.stencil_cost(c, W.stencil(halo, 8))
+        feat = mlp.features(c, halo, oracle.chain_table)
+        est_t = 2.0 ** (feat[23] * 32) - 1
+        est_i = 2.0 ** (feat[60] * 32) - 1
+        assert math.isclose(est_t * 8, cost[2], rel_tol=1e-9, abs_tol=1e-6), (ext, halo, n, g, f)
+        widths_ok = all(ext[d] // f[d] >= halo[d] for d in range(k))
+        if widths_ok:
+            assert math.isclose(est_i * 8, cost[3], rel_tol=1e-9, abs_tol=1e-6), (ext, halo, n, g, f)
+        checked += 1
+    assert checked >= 20
