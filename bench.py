@@ -35,8 +35,8 @@ PEAK_HBM = 8.0e12                     # bytes/s
 # profiles/k_count_k_map_c2_512cube_hbm_traffic.txt.
 KERNEL_SOURCES = ["paper_2507_17087_amd/csrc/tm_kernels.hip", "paper_2507_17087_amd/csrc/tm_chain.h",
                   "paper_2507_17087_amd/csrc/tm_internal.h"]
-TRAFFIC_SOURCE_HASH = "cb67c951323296a2"
-TRAFFIC_BYTES = {"k_count<3,2>": 42.71e6, "k_map": 537.84e6}
+TRAFFIC_SOURCE_HASH = "292317a31c97a3bd"
+TRAFFIC_BYTES = {"k_count<3,2>": 42.61e6, "k_map": 537.91e6}
 
 
 def measured_traffic(kernel):
@@ -97,7 +97,8 @@ def instances_with(tm, W, seed, target, octaves, min_cands=1024):
                 if total >= target:
                     break
         first += 256
-    return W.instance_batch(inst, fls)
+    cands, seg = W.instance_batch(inst, fls)
+    return cands, seg, inst
 
 
 def search_leg(args, tm, W):
@@ -107,7 +108,7 @@ def search_leg(args, tm, W):
     import torch
     st = W.c3_stencil(3)
     t0 = time.perf_counter()
-    tc, _ = instances_with(tm, W, 1, args.search_train, args.search_octaves)
+    tc, _, _ = instances_with(tm, W, 1, args.search_train, args.search_octaves)
     plan = tm.Plan(len(tc), 1)
     plan.load(tc, st)
     costs = torch.empty((len(tc), 4), dtype=torch.int64, device="cuda")
@@ -121,7 +122,7 @@ def search_leg(args, tm, W):
     t2 = time.perf_counter()
     del feat, costs
     plan.close()
-    ec, seg = instances_with(tm, W, 2, args.search_eval, args.search_octaves)
+    ec, seg, einst = instances_with(tm, W, 2, args.search_eval, args.search_octaves)
     plan = tm.Plan(len(ec), 1)
     plan.load(ec, st)
     torch.cuda.synchronize()
@@ -147,6 +148,18 @@ def search_leg(args, tm, W):
     c0 = c_0.cpu().numpy()
     ok0 = (ce[:, 2] == c0[:, 2]) & (ce[:, 3] == c0[:, 3])
     r0.close()
+    # the paper's choice without search: decompose's argmin factorization (Sec. 4.3)
+    # under the better of the two machine orders, evaluated exactly
+    base = []
+    for ext, nn, g in einst:
+        f = tm.tm_decompose_argmin(nn * g, ext, (1, 1, 1))
+        base.append(W.candidate(ext, nn, g, [W.merge(0, 1), W.decompose(0, f)]))
+        base.append(W.candidate(ext, nn, g, [W.swap(0, 1), W.merge(0, 1), W.decompose(0, f)]))
+    cb = tm.tm_eval_stencil_batch(W.batch(base), st).cpu().numpy()
+    ev, od = cb[0::2], cb[1::2]
+    first_le = (ev[:, 2] < od[:, 2]) | ((ev[:, 2] == od[:, 2]) & (ev[:, 3] <= od[:, 3]))
+    cd = np.where(first_le[:, None], ev, od)
+    better = (cr[:, 2] < cd[:, 2]) | ((cr[:, 2] == cd[:, 2]) & (cr[:, 3] < cd[:, 3]))
     n = len(ec)
     ex_rate = n / (e1 - e0)
     rk_rate = n / ((e3 - e2) / reps)
@@ -154,6 +167,9 @@ def search_leg(args, tm, W):
     r.close()
     return {"instances": int(len(seg) - 1), "candidates": int(n), "topk": 64,
             "opt_rate": float(ok.mean()), "estimate_only_opt_rate": float(ok0.mean()),
+            "vs_decompose": {"better_instances": float(better.mean()),
+                             "bytes_reduction": float(1 - cr[:, 2].sum() / cd[:, 2].sum()),
+                             "inter_bytes_reduction": float(1 - cr[:, 3].sum() / max(1, cd[:, 3].sum()))},
             "ranked_candidates_per_s": rk_rate,
             "exhaustive_candidates_per_s": ex_rate, "speedup": rk_rate / ex_rate,
             "train_candidates": int(len(tc)), "train_epochs": args.search_epochs,
