@@ -396,7 +396,7 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
                                                const int32_t* __restrict__ arena,
                                                unsigned long long* __restrict__ counter,
                                                tm_stencil_cost* __restrict__ out) {
-    extern __shared__ int32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) int32_t lds[];  // 16-byte aligned: ds_read_b128 of staged tables
     __shared__ long long s_item;
     __shared__ int32_t s_qv[4][kQueueCap], s_qx[4][kQueueCap];
     __shared__ int32_t s_rl[4][32];
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, 
                                              const int32_t* __restrict__ arena,
                                              const int64_t* __restrict__ d_index, int64_t index,
                                              int32_t* __restrict__ out) {
-    extern __shared__ int32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) int32_t lds[];  // 16-byte aligned: ds_read_b128 of staged tables
     __shared__ DevCand sc;
     const int64_t ci = d_index ? uniform64(*d_index) : index;
     if (ci < 0 || ci >= n) return;  // no candidate selected (empty batch)
@@ -713,7 +713,7 @@ __global__ __launch_bounds__(256) void k_matmul(const DevCand* __restrict__ cand
                                                 const int64_t* __restrict__ proc_off,
                                                 unsigned long long* __restrict__ per_proc,
                                                 const int64_t* __restrict__ block_first, int64_t total_blocks) {
-    extern __shared__ int32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) int32_t lds[];  // 16-byte aligned: ds_read_b128 of staged tables
     __shared__ DevCand sc;
     const int lane = threadIdx.x & 63;
     int64_t cur = -1;
