@@ -142,7 +142,7 @@ hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_
 // counted (and those on another node).  Lanes count in registers, waves reduce,
 // and one 64-bit atomic per wave and item adds to the candidate's totals.
 
-constexpr int kQueueCap = 128;
+constexpr int kQueueCap = 192;  // drained 128 at a time (two cells per lane); a push adds <= 64
 constexpr int kCellsPerLane = 8;
 constexpr int kChunk = 64 * kCellsPerLane;
 
@@ -218,17 +218,57 @@ __device__ __forceinline__ void eval_group(const int32_t* __restrict__ T, XP DL,
 }
 
 // One queued cell (row base index bq, last-dim coordinate xq) of a row without
-// outer offsets: only its last-dim neighbours can be foreign.
+// outer offsets: only its last-dim neighbours can be foreign.  The first two
+// offsets are loaded without branches (a cell's list always has HS >= 2 slots;
+// unused offsets are replaced by 0, which reads the cell's own owner), so the
+// owner lookups of the usual one- and two-offset cells issue together.
 template <typename XP>
 __device__ __forceinline__ void eval_queued(const int32_t* __restrict__ T, const int32_t* __restrict__ CL, XP DL,
                                             int HS, int32_t bq, int32_t xq, int gbits, int& cnt, int& icnt) {
     const int32_t e = CL[xq];
-    eval_cell(T, bq + cval(e), nullptr, 0, DL + xq * HS, ccnt(e), gbits, cnt, icnt);
+    const int32_t d0 = DL[xq * HS], d1 = DL[xq * HS + 1];
+    const int32_t v = bq + cval(e);
+    const int nx = ccnt(e);
+    const int32_t o = T[v];
+    const int32_t o0 = T[v + (nx > 0 ? d0 : 0)];
+    const int32_t o1 = T[v + (nx > 1 ? d1 : 0)];
+    const int32_t onode = o >> gbits;
+    const bool f0 = o0 != o;
+    const bool f1 = o1 != o && o1 != o0;
+    cnt += (int)f0 + (int)f1;
+    icnt += (f0 && (o0 >> gbits) != onode ? 1 : 0) + (f1 && (o1 >> gbits) != onode ? 1 : 0);
+    for (int t = 2; t < nx; ++t) {
+        const int32_t ot = T[v + DL[xq * HS + t]];
+        bool fresh = ot != o && ot != o0 && ot != o1;
+        for (int s2 = 2; s2 < t && fresh; ++s2) fresh = T[v + DL[xq * HS + s2]] != ot;
+        if (fresh) {
+            ++cnt;
+            icnt += ((ot >> gbits) != onode) ? 1 : 0;
+        }
+    }
 }
 
 // Number of set bits of m in the lanes below this one.
 __device__ __forceinline__ int lanes_below(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Flags of a lane's eight cells (bit j: cell j has last-dim offsets), the number of
+// flagged cells in the lanes below (prefix over the wave, from the ballots of the
+// four bit planes of the per-lane counts 0..8) and the wave's total.
+__device__ __forceinline__ void chunk_flags(const int32_t (&e8)[kCellsPerLane], uint32_t& fl, int& pre, int& tot) {
+    fl = 0;
+#pragma unroll
+    for (int j = 0; j < kCellsPerLane; ++j) fl |= ((uint32_t)e8[j] > (uint32_t)kValMask ? 1u : 0u) << j;
+    const int c = __popc(fl);
+    pre = 0;
+    tot = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint64_t m = __ballot((c >> b) & 1);
+        pre += lanes_below(m) << b;
+        tot += __popcll(m) << b;
+    }
 }
 
 __device__ __forceinline__ void load8(const int32_t* p, int32_t (&e8)[kCellsPerLane]) {
@@ -277,6 +317,17 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     constexpr int HS = 2 * H;
     constexpr int KO = K > 1 ? K - 1 : 1;
     int qn = 0;  // wave-uniform queue length
+    // Rows that fit one chunk: in rows without outer offsets the flags of a lane's
+    // cells depend on the last coordinate only, so their compaction (per-lane
+    // flags, prefix over the wave, total) is computed once here.
+    const bool one_chunk = L <= kChunk;
+    uint32_t hfl = 0;
+    int hpre = 0, htot = 0;
+    if (one_chunk) {
+        int32_t e8[kCellsPerLane];
+        load8(CL + kCellsPerLane * lane, e8);
+        chunk_flags(e8, hfl, hpre, htot);
+    }
     int32_t q[KO];
     {
         uint32_t rr = (uint32_t)ra;
@@ -319,19 +370,9 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
                 const bool hit = (uint32_t)any > (uint32_t)kValMask;
                 if (__ballot(hit) == 0ull) continue;
-                uint32_t fl = 0;
-#pragma unroll
-                for (int j = 0; j < kCellsPerLane; ++j) fl |= ((uint32_t)e8[j] > (uint32_t)kValMask ? 1u : 0u) << j;
-                // exclusive prefix of the per-lane counts (0..8) over the wave, from the
-                // ballots of their four bit planes
-                const int c = __popc(fl);
-                int pre = 0, tot = 0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const uint64_t m = __ballot((c >> b) & 1);
-                    pre += lanes_below(m) << b;
-                    tot += __popcll(m) << b;
-                }
+                uint32_t fl = hfl;
+                int pre = hpre, tot = htot;
+                if (!one_chunk) chunk_flags(e8, fl, pre, tot);
                 if (tot > 64) {  // a crowded chunk: evaluate it in place
                     eval_group(T, DL, HS, e8, x0, L, base, rl, 0, gbits, true, cnt, icnt);
                     continue;
@@ -346,14 +387,15 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 }
                 qn += tot;
                 wave_sync_lds();
-                if (qn >= 64) {
+                if (qn >= 128) {
                     eval_queued(T, CL, DL, HS, qv[lane], qx[lane], gbits, cnt, icnt);
+                    eval_queued(T, CL, DL, HS, qv[lane + 64], qx[lane + 64], gbits, cnt, icnt);
                     wave_sync_lds();
-                    if (lane < qn - 64) {
-                        qv[lane] = qv[lane + 64];
-                        qx[lane] = qx[lane + 64];
+                    if (lane < qn - 128) {
+                        qv[lane] = qv[lane + 128];
+                        qx[lane] = qx[lane + 128];
                     }
-                    qn -= 64;
+                    qn -= 128;
                     wave_sync_lds();
                 }
             }
@@ -386,6 +428,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // drain the queue
     if (qn > 0) {
         if (lane < qn) eval_queued(T, CL, DL, HS, qv[lane], qx[lane], gbits, cnt, icnt);
+        if (lane + 64 < qn) eval_queued(T, CL, DL, HS, qv[lane + 64], qx[lane + 64], gbits, cnt, icnt);
         wave_sync_lds();
     }
 }
