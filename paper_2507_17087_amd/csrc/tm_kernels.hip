@@ -328,6 +328,48 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
         load8(CL + kCellsPerLane * lane, e8);
         chunk_flags(e8, hfl, hpre, htot);
     }
+    // Row queue (single-chunk rows with 1..64 flagged cells): a row without outer
+    // offsets queues only its base index; a drain of rq_rows rows evaluates
+    // rq_rows * htot <= 128 cells, cell idx being flagged cell idx % htot of
+    // queued row idx / htot.  qx[0..128) holds that map as (x << 8) | row,
+    // built once here from the flagged positions (staged in qx[128..192)).
+    const bool rowq = one_chunk && htot > 0 && htot <= 64;
+    const int rq_rows = rowq ? 128 / htot : 0;
+    const int rq_cells = rq_rows * htot;
+    int nrow = 0;
+    if (rowq) {
+        uint32_t f = hfl;
+        int pos = 128 + hpre;
+        while (f) {
+            const int j = __builtin_ctz(f);
+            f &= f - 1;
+            qx[pos++] = kCellsPerLane * lane + j;
+        }
+        wave_sync_lds();
+        int32_t m0 = 0, m1 = 0;
+        if (lane < rq_cells) {
+            const int r = lane / htot;
+            m0 = (qx[128 + lane - r * htot] << 8) | r;
+        }
+        if (lane + 64 < rq_cells) {
+            const int r = (lane + 64) / htot;
+            m1 = (qx[128 + lane + 64 - r * htot] << 8) | r;
+        }
+        wave_sync_lds();
+        if (lane < rq_cells) qx[lane] = m0;
+        if (lane + 64 < rq_cells) qx[lane + 64] = m1;
+        wave_sync_lds();
+    }
+    auto drain_rows = [&](int ncell) {
+        if (lane < ncell) {
+            const int32_t m = qx[lane];
+            eval_queued(T, CL, DL, HS, qv[m & 0xff], m >> 8, gbits, cnt, icnt);
+        }
+        if (lane + 64 < ncell) {
+            const int32_t m = qx[lane + 64];
+            eval_queued(T, CL, DL, HS, qv[m & 0xff], m >> 8, gbits, cnt, icnt);
+        }
+    };
     int32_t q[KO];
     {
         uint32_t rr = (uint32_t)ra;
@@ -359,7 +401,25 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
             base += cval(e);
             if (ccnt(e)) nr = outer_offsets<H>(T + off[K - 2], q[K - 2], ext[K - 2], hal[K - 2], rl, no);
         }
-        if (nr == 0) {
+        if (nr == 0 && rowq) {
+            // ---- sparse single-chunk row: every cell is read and tested; the row's
+            // flagged cells are the precomputed ones, so only its base is queued
+            int32_t e8[kCellsPerLane];
+            load8(CL + kCellsPerLane * lane, e8);
+            int32_t any = 0;
+#pragma unroll
+            for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
+            if (__ballot((uint32_t)any > (uint32_t)kValMask) != 0ull) {
+                if (lane == 0) qv[nrow] = base;
+                ++nrow;
+                if (nrow == rq_rows) {
+                    wave_sync_lds();
+                    drain_rows(rq_cells);
+                    wave_sync_lds();
+                    nrow = 0;
+                }
+            }
+        } else if (nr == 0) {
             // ---- sparse row: cells with last-dim offsets go to the queue one by one
             for (int xb = 0; xb < L; xb += kChunk) {
                 const int x0 = xb + kCellsPerLane * lane;
@@ -425,7 +485,12 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
             }
         }
     }
-    // drain the queue
+    // drain the queues
+    if (nrow > 0) {
+        wave_sync_lds();
+        drain_rows(nrow * htot);
+        wave_sync_lds();
+    }
     if (qn > 0) {
         if (lane < qn) eval_queued(T, CL, DL, HS, qv[lane], qx[lane], gbits, cnt, icnt);
         if (lane + 64 < qn) eval_queued(T, CL, DL, HS, qv[lane + 64], qx[lane + 64], gbits, cnt, icnt);
@@ -433,8 +498,10 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     }
 }
 
+// Six waves per SIMD for H >= 2 (fits 80 VGPRs without spilling); the H = 1
+// instantiations need more registers and keep the compiler's choice.
 template <int K, int H>
-__global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 4 : 6))) void k_count(const DevHeader* __restrict__ hdr,
                                                const DevCand* __restrict__ cands,
                                                const int32_t* __restrict__ arena,
                                                unsigned long long* __restrict__ counter,
