@@ -393,11 +393,23 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
         }
     };
     load_prefix();
+    // entries of dim K-2 for 64 rows at a time, one per lane (row rbat + lane), so a
+    // row takes its entry with a lane read instead of an LDS round trip
+    int64_t rbat = ra;
+    int32_t eb = 0;
+    auto load_batch = [&]() {
+        if constexpr (K > 1) eb = T[off[K - 2] + (int32_t)((uint32_t)(q[K - 2] + lane) % (uint32_t)ext[K - 2])];
+    };
+    load_batch();
     for (int64_t r = ra; r < rb; ++r) {
         int32_t base = base_o;
         int nr = no;
         if constexpr (K > 1) {
-            const int32_t e = uniform32(T[off[K - 2] + q[K - 2]]);
+            if (r - rbat == 64) {
+                rbat = r;
+                load_batch();
+            }
+            const int32_t e = __builtin_amdgcn_readlane(eb, (int)(r - rbat));
             base += cval(e);
             if (ccnt(e)) nr = outer_offsets<H>(T + off[K - 2], q[K - 2], ext[K - 2], hal[K - 2], rl, no);
         }
