@@ -40,6 +40,9 @@ def build(verbose=False):
         elif verbose and lines:
             sys.stderr.write("\n".join(lines) + "\n")
     if failed:
+        # no stale library may outlive a failed build of its sources
+        if os.path.exists(SO):
+            os.remove(SO)
         raise RuntimeError("hipcc failed")
     tmp = SO + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs +

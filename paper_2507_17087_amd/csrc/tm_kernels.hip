@@ -217,6 +217,51 @@ __device__ __forceinline__ void eval_group(const int32_t* __restrict__ T, XP DL,
     }
 }
 
+// Distinct owners, other than T[v], among T[v + rl[t]] for t < nr (nr >= 1).
+__device__ __forceinline__ void eval_row_offsets(const int32_t* __restrict__ T, int32_t v, const int32_t* rl, int nr,
+                                                 int gbits, int& cnt, int& icnt) {
+    const int32_t o = T[v];
+    const int32_t onode = o >> gbits;
+    const int32_t o0 = T[v + rl[0]];
+    const int32_t o1 = T[v + (nr > 1 ? rl[1] : 0)];
+    const bool f0 = o0 != o;
+    const bool f1 = o1 != o && o1 != o0;
+    cnt += (int)f0 + (int)f1;
+    icnt += (f0 && (o0 >> gbits) != onode ? 1 : 0) + (f1 && (o1 >> gbits) != onode ? 1 : 0);
+    for (int t = 2; t < nr; ++t) {
+        const int32_t ot = T[v + rl[t]];
+        bool fresh = ot != o && ot != o0 && ot != o1;
+        for (int s2 = 2; s2 < t && fresh; ++s2) fresh = T[v + rl[s2]] != ot;
+        if (fresh) {
+            ++cnt;
+            icnt += ((ot >> gbits) != onode) ? 1 : 0;
+        }
+    }
+}
+
+// The cells x0 .. x0+7 of a row with outer offsets rl[0..nr) that have no last-dim
+// offsets (the others are evaluated separately); a cell whose entry equals the
+// previous evaluated one reuses its result (same index, same neighbours).
+__device__ __forceinline__ void eval_interior(const int32_t* __restrict__ T, const int32_t (&e8)[kCellsPerLane],
+                                              int x0, int L, int32_t base, const int32_t* rl, int nr, int gbits,
+                                              int& cnt, int& icnt) {
+    int32_t ep = -1;
+    int cp = 0, ip = 0;
+#pragma unroll
+    for (int j = 0; j < kCellsPerLane; ++j) {
+        const int32_t e = e8[j];
+        if (x0 + j >= L || ccnt(e) != 0) continue;
+        if (e != ep) {
+            cp = 0;
+            ip = 0;
+            eval_row_offsets(T, base + cval(e), rl, nr, gbits, cp, ip);
+            ep = e;
+        }
+        cnt += cp;
+        icnt += ip;
+    }
+}
+
 // One queued cell (row base index bq, last-dim coordinate xq) of a row without
 // outer offsets: only its last-dim neighbours can be foreign.  The first two
 // offsets are loaded without branches (a cell's list always has HS >= 2 slots;
@@ -471,6 +516,18 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                     wave_sync_lds();
                 }
             }
+        } else if (rowq) {
+            // ---- dense single-chunk row: cells without last-dim offsets in the lanes
+            // (memoised on equal entries), the flagged cells one per lane from the map
+            int32_t e8[kCellsPerLane];
+            load8(CL + kCellsPerLane * lane, e8);
+            eval_interior(T, e8, kCellsPerLane * lane, L, base, rl, nr, gbits, cnt, icnt);
+            if (lane < htot) {
+                const int32_t x = qx[lane] >> 8;
+                const int32_t e = CL[x];
+                eval_cell(T, base + cval(e), rl, nr, DL + x * HS, ccnt(e), gbits, cnt, icnt);
+            }
+            wave_sync_lds();
         } else {
             // ---- dense row: every cell sees the outer neighbours of the row
             wave_sync_lds();
