@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--extent", type=int, default=512, help="cube side of the launch domain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host threads for the oracle baseline (one candidate each)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", type=int, nargs=2, metavar=("CELLS_PER_ITEM", "WG_PER_CU"),
                     help="fixed counting launch configuration instead of autotuning (e.g. for profiling)")
@@ -68,18 +70,23 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(cands, st, extent):
-    """The oracle (plain C, one thread) on one full-size candidate of the workload."""
+def cpu_baseline(cands, st, extent, threads):
+    """The oracle (plain C, single-threaded per call) on `threads` full-size candidates
+    of the workload, one per host thread (ctypes releases the GIL during each call):
+    the same evaluator, run side by side on the machine's cores."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
-    from workloads import c2_candidates
-    c = c2_candidates([(4, 4, 8)], extent=(extent,) * 3)[0]
+    picks = [(i * 37) % len(cands) for i in range(threads)]
     t0 = time.perf_counter()
-    oracle.stencil_cost(c, st)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda i: oracle.stencil_cost(cands[i], st), picks))
     dt = time.perf_counter() - t0
-    pts = extent ** 3
-    return {"value": pts / dt, "unit": "point-evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 of the 216 candidates (F=(4,4,8), identity chain) on the full {extent}^3 "
-                      f"domain: {pts} point-evals in {dt:.2f} s, single thread"}
+    pts = threads * extent ** 3
+    return {"value": pts / dt, "unit": "point-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{threads} of the {len(cands)} candidates (indices {picks[0]}, {picks[1] if threads > 1 else ''}"
+                      f"... step 37 mod {len(cands)}) on the full {extent}^3 domain, one oracle call per "
+                      f"host thread: {pts} point-evals in {dt:.2f} s"}
 
 
 def instances_with(tm, W, seed, target, octaves, min_cands=1024):
@@ -292,7 +299,7 @@ def main():
     if args.search:
         res["search"] = search_leg(args, tm, W)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(cands, st, L)
+        res["cpu_baseline"] = cpu_baseline(cands, st, L, args.cpu_threads)
     print(json.dumps(res))
 
 
