@@ -30,36 +30,37 @@ static int64_t rows_per_item_for(const DevCand& d, int64_t cells_per_item) {
 static int64_t up4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
 // Arena layout of one candidate: owner table T, the last dim's coordinate table
-// (16-byte aligned, zero-padded to whole 512-entry chunks), the other coordinate
-// tables -- the prefix staged in LDS -- then the last dim's offset lists (also
-// staged when they fit the LDS budget, else read from global memory).  H = 0: no
+// (16-byte aligned, zero-padded to whole 512-entry chunks), the last dim's offset
+// lists (H > 0), then the other dims' coordinate tables.  The counting and map
+// kernels stage the longest prefix that fits the LDS budget -- T always, then the
+// last dim's table, then its offset lists -- and read the rest (the outer tables,
+// used once per row, and whatever did not fit) from global memory.  H = 0: no
 // offset lists.
 static int layout_tables(DevCand& d, int H) {
     const int K = d.lrank;
     int64_t off = up4(d.vol);
-    d.coord_off[K - 1] = (int32_t)off;
+    const int64_t t_end = off + 4;
+    d.coord_off[K - 1] = (int32_t)std::min<int64_t>(off, INT32_MAX);
     off += (d.extent[K - 1] + 511) & ~int64_t(511);  // zero-padded to whole 512-entry chunks
+    const int64_t c_end = off + 4;                   // slack for the last four-entry read of a ragged row
+    d.hstride = 2 * H;
+    for (int k = 0; k < K; ++k) d.dl_off[k] = 0;     // outer dims: offsets come from the tables
+    int64_t d_end = c_end;
+    if (H > 0) {
+        off = up4(off);
+        d.dl_off[K - 1] = (int32_t)std::min<int64_t>(off, INT32_MAX);
+        off += 2 * H * d.extent[K - 1];
+        off = up4(off);
+        d_end = off + 4;
+    }
+    off = std::max(off, d_end);
     for (int k = 0; k < K - 1; ++k) {
         d.coord_off[k] = (int32_t)std::min<int64_t>(off, INT32_MAX);
         off += d.extent[k];
     }
-    d.hstride = 2 * H;
-    int64_t staged;
-    if (H > 0) {
-        off = up4(off);
-        const int64_t tables = off + 4;  // slack for the last four-entry read of a ragged row
-        d.dl_off[K - 1] = (int32_t)std::min<int64_t>(off, INT32_MAX);
-        off += 2 * H * d.extent[K - 1];
-        off = up4(off);
-        // the last dim's offset lists join the LDS prefix when they fit
-        d.dl_lds = off + 4 <= kMaxLdsWords ? 1 : 0;
-        staged = d.dl_lds ? off + 4 : tables;
-        for (int k = 0; k < K - 1; ++k) d.dl_off[k] = 0;  // outer dims: offsets come from the tables
-    } else {
-        for (int k = 0; k < K; ++k) d.dl_off[k] = 0;
-        d.dl_lds = 0;
-        staged = up4(off) + 4;
-    }
+    d.cl_lds = c_end <= kMaxLdsWords ? 1 : 0;
+    d.dl_lds = H > 0 && d_end <= kMaxLdsWords ? 1 : 0;
+    const int64_t staged = d.dl_lds ? d_end : (d.cl_lds ? c_end : t_end);
     const int64_t words = std::max(off, staged);
     if (words > INT32_MAX) return TM_EOVERFLOW;
     d.lds_words = (int32_t)staged;
@@ -304,6 +305,10 @@ extern "C" int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_m
     if (rc != TM_OK) return rc;
     if (n == 0) return TM_OK;
     if (!d_out) return set_error(TM_EINVAL, "null output");
+    // the matmul kernel reads every coordinate table per task point: all of them in LDS
+    if (cp.max_all_words > kMaxLdsWords)
+        return set_error(TM_ENOTSUP, "matmul tables of %d words exceed the LDS budget of %d", cp.max_all_words,
+                         kMaxLdsWords);
     std::vector<int64_t> proc_off((size_t)n + 1), block_first((size_t)n + 1);
     int64_t procs = 0, blocks = 0;
     int pmax = 0;
@@ -349,7 +354,7 @@ extern "C" int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_m
         if (rc == TM_OK && e == hipSuccess) e = hipMemsetAsync(d_pp, 0, (size_t)std::max<int64_t>(procs, 1) * 24, s);
         if (rc == TM_OK && e == hipSuccess) e = launch_build_tables(db.hdr, db.cands, n, db.arena, 0, s);
         if (rc == TM_OK && e == hipSuccess)
-            e = launch_matmul(db.cands, n, db.arena, cp.max_words, pmax, d_off, d_pp, blocks, d_bf, s);
+            e = launch_matmul(db.cands, n, db.arena, cp.max_all_words, pmax, d_off, d_pp, blocks, d_bf, s);
         if (rc == TM_OK && e == hipSuccess)
             e = launch_matmul_finalize(db.cands, n, d_off, d_pp, mm->tile_bytes, d_out, d_per_proc, s);
         if (rc == TM_OK && e != hipSuccess) rc = set_error(TM_EDEVICE, "matmul launch: %s", hipGetErrorString(e));

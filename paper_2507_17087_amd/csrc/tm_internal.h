@@ -25,7 +25,7 @@ struct DevCand {
     int32_t coord_off[TM_MAX_LRANK];    // table offsets of the per-dim coordinate tables
     int32_t dl_off[TM_MAX_LRANK];       // table offsets of the per-dim neighbour-offset lists
     int32_t lds_words, hstride;         // leading words staged in LDS; list stride (2*H)
-    int32_t dl_lds, pad1;               // last dim's offset lists are in the staged prefix
+    int32_t dl_lds, cl_lds;             // last dim's offset lists / coordinate table are in the staged prefix
     int32_t fshape[TM_MAX_MRANK], fstride[TM_MAX_MRANK];
     int8_t proj_src[TM_MAX_MRANK], proj_mode[TM_MAX_MRANK];
     int32_t rank[TM_MAX_OPS];                    // rank before op t

@@ -122,8 +122,9 @@ hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_
 // A work item is a block of consecutive rows (all launch dims but the last fixed)
 // of one candidate.  A workgroup takes items from a global atomic counter (the
 // next one is requested while the current one runs), stages the candidate's owner
-// table, coordinate tables and (when they fit) the last dim's offset lists in LDS
-// when the candidate changes, and gives each wave a contiguous share of the rows,
+// table and, when they fit, the last dim's coordinate table and offset lists in LDS
+// when the candidate changes (the outer dims' tables are read from global memory,
+// once per row), and gives each wave a contiguous share of the rows,
 // stepping the outer coordinates without divisions.  Every cell is examined: a
 // lane reads the coordinate entries of eight consecutive cells with two LDS loads.
 //   - A row's outer coordinates fix its base index and the distinct non-zero
@@ -355,7 +356,8 @@ __device__ __forceinline__ int outer_offsets(const int32_t* __restrict__ C, int3
 
 // The rows [ra, rb) of the staged candidate, for one wave.
 template <int K, int H, typename XP>
-__device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const int32_t* __restrict__ CL, XP DL,
+__device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const int32_t* __restrict__ G,
+                                           const int32_t* __restrict__ CL, XP DL,
                                            const int32_t (&off)[K], const int32_t (&ext)[K], const int (&hal)[K],
                                            int64_t ra, int64_t rb, int L, int gbits, int lane, int32_t* rl,
                                            int32_t* qv, int32_t* qx, int& cnt, int& icnt) {
@@ -432,9 +434,9 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
         no = 0;
 #pragma unroll
         for (int d = 0; d < K - 2; ++d) {
-            const int32_t e = uniform32(T[off[d] + q[d]]);
+            const int32_t e = uniform32(G[off[d] + q[d]]);
             base_o += cval(e);
-            if (ccnt(e)) no = outer_offsets<H>(T + off[d], q[d], ext[d], hal[d], rl, no);
+            if (ccnt(e)) no = outer_offsets<H>(G + off[d], q[d], ext[d], hal[d], rl, no);
         }
     };
     load_prefix();
@@ -443,7 +445,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     int64_t rbat = ra;
     int32_t eb = 0;
     auto load_batch = [&]() {
-        if constexpr (K > 1) eb = T[off[K - 2] + (int32_t)((uint32_t)(q[K - 2] + lane) % (uint32_t)ext[K - 2])];
+        if constexpr (K > 1) eb = G[off[K - 2] + (int32_t)((uint32_t)(q[K - 2] + lane) % (uint32_t)ext[K - 2])];
     };
     load_batch();
     for (int64_t r = ra; r < rb; ++r) {
@@ -456,7 +458,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
             }
             const int32_t e = __builtin_amdgcn_readlane(eb, (int)(r - rbat));
             base += cval(e);
-            if (ccnt(e)) nr = outer_offsets<H>(T + off[K - 2], q[K - 2], ext[K - 2], hal[K - 2], rl, no);
+            if (ccnt(e)) nr = outer_offsets<H>(G + off[K - 2], q[K - 2], ext[K - 2], hal[K - 2], rl, no);
         }
         if (nr == 0 && rowq) {
             // ---- sparse single-chunk row: every cell is read and tested; the row's
@@ -590,7 +592,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 5 
     for (int d = 0; d < K; ++d) hal[d] = uniform32(hdr->halo[d]);
 
     int64_t cur = -1;
-    int32_t L = 0, gbits = 0, rpi = 1, dl_lds = 0;
+    int32_t L = 0, gbits = 0, rpi = 1, dl_lds = 0, cl_lds = 0;
     int64_t rows = 0, ifirst = 0;
     int32_t off[K], ext[K];
     int32_t dlo = 0;
@@ -634,6 +636,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 5 
             }
             dlo = uniform32(c->dl_off[K - 1]);
             dl_lds = uniform32(c->dl_lds);
+            cl_lds = uniform32(c->cl_lds);
             cur = lo;
             __syncthreads();
         }
@@ -645,13 +648,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 5 
         const int64_t rb = ra + nrw < r1 ? ra + nrw : r1;
         int cnt = 0, icnt = 0;
         if (ra < rb) {
-            const int32_t* CL = lds + off[K - 1];
-            if (dl_lds)
-                count_rows<K, H>(lds, CL, lds + dlo, off, ext, hal, ra, rb, L, gbits, lane, s_rl[wid], s_qv[wid],
-                                 s_qx[wid], cnt, icnt);
-            else
-                count_rows<K, H>(lds, CL, garena + dlo, off, ext, hal, ra, rb, L, gbits, lane, s_rl[wid],
-                                 s_qv[wid], s_qx[wid], cnt, icnt);
+            if (dl_lds)  // last dim's table and offset lists in LDS
+                count_rows<K, H>(lds, garena, lds + off[K - 1], lds + dlo, off, ext, hal, ra, rb, L, gbits, lane,
+                                 s_rl[wid], s_qv[wid], s_qx[wid], cnt, icnt);
+            else if (cl_lds)  // table in LDS, offset lists in global memory
+                count_rows<K, H>(lds, garena, lds + off[K - 1], garena + dlo, off, ext, hal, ra, rb, L, gbits, lane,
+                                 s_rl[wid], s_qv[wid], s_qx[wid], cnt, icnt);
+            else  // long rows: both in global memory
+                count_rows<K, H>(lds, garena, garena + off[K - 1], garena + dlo, off, ext, hal, ra, rb, L, gbits,
+                                 lane, s_rl[wid], s_qv[wid], s_qx[wid], cnt, icnt);
         }
         cnt = wave_sum(cnt);
         icnt = wave_sum(icnt);
@@ -798,8 +803,9 @@ hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* s
 //
 // Rows of the launch domain are spread over the workgroups; each wave writes whole
 // rows.  A lane produces four consecutive points (one 16-byte non-temporal store)
-// when the row start is 16-byte aligned, else single points.  The candidate's
-// tables sit in LDS.
+// when the row start is 16-byte aligned, else single points.  The owner table and
+// (when it fits) the last dim's coordinate table sit in LDS; the outer dims'
+// tables are read once per row from global memory.
 
 __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, int64_t n,
                                              const int32_t* __restrict__ arena,
@@ -821,7 +827,8 @@ __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, 
     const int64_t rows = sc.rows;
     const int32_t gb = sc.gbits, g = sc.gpus, gmask = (1 << sc.gbits) - 1;
     const int32_t* T = lds;
-    const int32_t* CL = lds + sc.coord_off[K - 1];
+    const int32_t* G = arena + sc.arena_off;  // outer tables (and a last-dim table that did not fit)
+    const int32_t* CL = sc.cl_lds ? lds + sc.coord_off[K - 1] : G + sc.coord_off[K - 1];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t nw = (int64_t)gridDim.x * 4;
     const bool vec = (L & 3) == 0 && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
@@ -830,7 +837,7 @@ __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, 
         int32_t base = 0;
         for (int d = K - 2; d >= 0; --d) {
             const uint32_t e = (uint32_t)sc.extent[d];
-            base += lds[sc.coord_off[d] + (int32_t)(rr % e)] & kValMask;
+            base += G[sc.coord_off[d] + (int32_t)(rr % e)] & kValMask;
             rr /= e;
         }
         int32_t* row = out + r * (int64_t)L;
@@ -909,7 +916,7 @@ __global__ __launch_bounds__(256) void k_matmul(const DevCand* __restrict__ cand
             stage_cand(&sc, &cands[lo]);
             __syncthreads();
             const int32_t* src = arena + sc.arena_off;
-            for (int i = threadIdx.x; i < sc.lds_words; i += blockDim.x) lds[i] = src[i];
+            for (int i = threadIdx.x; i < sc.words; i += blockDim.x) lds[i] = src[i];  // every table
             __syncthreads();
             cur = lo;
         }

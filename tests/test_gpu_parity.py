@@ -101,6 +101,34 @@ def test_rank4_and_ragged(tm):
     assert (gpu_costs(tm, long_rows, st) == oracle.stencil_cost_batch(long_rows, st)).all()
 
 
+def test_long_rows_and_tall_outer_dims(tm):
+    """Last dims too long for the LDS budget (coordinate table and offset lists read
+    from global memory), outer dims with long tables (always global), block and
+    cyclic projections, ragged blocks; costs and maps against the oracle."""
+    say("long rows and tall outer dims")
+    cands = W.batch([
+        W.candidate((100_003,), 7, 4, [merge(0, 1)]),
+        W.candidate((65_536,), 3, 2, [merge(0, 1)], proj=[(0, W.CYCLIC)]),
+        W.candidate((3, 50_001), 5, 4, [merge(0, 1), decompose(0, (4, 5))]),
+        W.candidate((2, 40_000), 6, 2, [merge(0, 1), decompose(0, (3, 4))], proj=[(0, W.BLOCK), (1, W.CYCLIC)]),
+        W.candidate((2, 36_000), 4, 2, [merge(0, 1), decompose(0, (1, 8))]),
+    ])
+    for k, idx, sub in by_rank(cands):
+        for h in ((1,) * k, (4,) * k, (2, 3)[:k] if k == 2 else (3,)):
+            st = W.stencil(h, 8)
+            say(f"  rank {k} halo {h}")
+            assert (gpu_costs(tm, sub, st) == oracle.stencil_cost_batch(sub, st)).all()
+    tall = W.batch([W.candidate((40_000, 5), 4, 4, [merge(0, 1), decompose(0, (8, 2))]),
+                    W.candidate((20_011, 3, 7), 2, 4, [merge(0, 1), decompose(0, (4, 1, 2))],
+                                proj=[(0, W.CYCLIC), (1, W.BLOCK), (2, W.BLOCK)])])
+    for k, idx, sub in by_rank(tall):
+        st = W.stencil((2,) * k, 8)
+        say(f"  tall rank {k}")
+        assert (gpu_costs(tm, sub, st) == oracle.stencil_cost_batch(sub, st)).all()
+    for c in list(cands) + list(tall):
+        assert (tm.tm_proc_map(c).cpu().numpy() == oracle.proc_map(c)).all()
+
+
 def test_empty_batch_and_invalid_input(tm):
     import torch
     say("empty and invalid")
