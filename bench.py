@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--launch", type=int, nargs=2, metavar=("CELLS_PER_ITEM", "WG_PER_CU"),
                     help="fixed counting launch configuration instead of autotuning (e.g. for profiling)")
     ap.add_argument("--search", action="store_true", help="also run the learned-ranker search leg")
+    ap.add_argument("--study", action="store_true", help="also run the decompose-vs-Alg.-A1 volume study")
     ap.add_argument("--search-train", type=int, default=1_000_000, help="training candidates (exact costs)")
     ap.add_argument("--search-eval", type=int, default=1_000_000, help="evaluation candidates")
     ap.add_argument("--search-epochs", type=int, default=8)
@@ -185,6 +186,60 @@ def search_leg(args, tm, W):
             "extents": f"octaves {args.search_octaves[0]}..{args.search_octaves[1]} per dim (log-uniform)"}
 
 
+def study_leg(tm, W):
+    """Sec. 6.3's decompose-vs-Alg.-A1 comparison as exact communication volumes:
+    180 2-D stencil configurations x {decompose's F, Alg. A1's F} x {node-major,
+    GPU-major machine order}, halo 1, 8-B cells, all evaluated in one plan."""
+    import torch
+    cf = W.study_configs(long_last=True) + W.study_configs(long_last=False)
+    fd = [tm.tm_decompose_argmin(g, ext, (1, 1)) for a, s, g, ext, n, gp in cf]
+    fg = [tm.tm_greedy_grid(g, 2) for a, s, g, ext, n, gp in cf]
+    cands = W.study_candidates(cf, fd, fg)
+    st = W.stencil((1, 1), 8)
+    plan = tm.Plan(len(cands), 1)
+    plan.load(cands, st)
+    out = torch.empty((len(cands), 4), dtype=torch.int64, device="cuda")
+    plan.run(out)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.run(out)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    _, _, pts = plan.info()
+    plan.close()
+    c = out.cpu().numpy().reshape(len(cf), 2, 2, 4)  # config, (decompose, A1), (node-major, GPU-major)
+
+    def gm(x):
+        return float(np.exp(np.mean(np.log(x))))
+
+    def ratios(col, order):
+        g, d = c[:, 1, order, col].astype(np.float64), c[:, 0, order, col].astype(np.float64)
+        ok = d > 0
+        return np.where(ok, g / np.where(ok, d, 1), 1.0)
+
+    res = {"configs": len(cf), "candidates": int(len(cands)), "point_evals": int(pts),
+           "gpu_ms": min(ts), "point_evals_per_s": pts / (min(ts) * 1e-3),
+           "differs": int(sum(1 for a, b in zip(fd, fg) if tuple(a) != tuple(b)))}
+    half = len(cf) // 2
+    for orient, rows in (("long_dim_last", slice(0, half)), ("long_dim_first", slice(half, len(cf)))):
+        sub_cf = cf[rows]
+        res[orient] = {}
+        for name, col, order in (("bytes", 2, 0), ("inter_bytes_node_major", 3, 0),
+                                 ("inter_bytes_gpu_major", 3, 1)):
+            r = ratios(col, order)[rows]
+            by = {}
+            for key, idx in (("aspect", 0), ("size_per_node", 1), ("gpus", 2)):
+                vals = sorted(set(x[idx] for x in sub_cf))
+                by[key] = {str(v): gm(r[[i for i, x in enumerate(sub_cf) if x[idx] == v]]) - 1 for v in vals}
+            res[orient][name] = {"A1_over_decompose_geomean_minus_1": gm(r) - 1, "max": float(r.max() - 1),
+                                 "min": float(r.min() - 1), **by}
+    return res
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -298,6 +353,8 @@ def main():
     del pmap
     if args.search:
         res["search"] = search_leg(args, tm, W)
+    if args.study:
+        res["study"] = study_leg(tm, W)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cands, st, L, args.cpu_threads)
     print(json.dumps(res))

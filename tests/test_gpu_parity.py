@@ -352,3 +352,41 @@ def test_select_segments(tm):
     for s in range(len(seg) - 1):
         a, b = seg[s], seg[s + 1]
         assert got[s] == (oracle.select_best(costs[a:b]) if b > a else -1)
+
+
+# ---------------------------------------------------------------- decompose vs Alg. A1 study
+
+def test_study_full_size(tm):
+    """Sec. 6.3's 180 2-D configurations at full size (up to 20,000 x 640,000 points):
+    every candidate is a bijective block chain with blocks wider than the halo, so its
+    total volume has the closed form sum_m 2 h (f_m - 1) prod_{j != m} l_j (both
+    directions, Sec. 4.1's counting); single-node machines send nothing between nodes;
+    the smallest configurations are checked against the oracle exactly."""
+    import torch
+    say("study: 2 x 180 configurations x 4 candidates at full size")
+    cf = W.study_configs(long_last=True) + W.study_configs(long_last=False)
+    fd = [oracle.decompose_argmin(g, ext, (1, 1)) for a, s_, g, ext, n, gp in cf]
+    fg = [oracle.greedy_grid(g, 2) for a, s_, g, ext, n, gp in cf]
+    cands = W.study_candidates(cf, fd, fg)
+    st = W.stencil((1, 1), 8)
+    plan = tm.Plan(len(cands), 1)
+    plan.load(cands, st)
+    out = torch.empty((len(cands), 4), dtype=torch.int64, device="cuda")
+    plan.run(out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    plan.close()
+    for i, (a, s_, g, (l0, l1), n, gp) in enumerate(cf):
+        for j, f in enumerate((fd[i], fg[i])):
+            assert f[0] <= l0 and f[1] <= l1
+            cells = 2 * (f[0] - 1) * l1 + 2 * (f[1] - 1) * l0
+            for o in range(2):
+                row = got[4 * i + 2 * j + o]
+                assert row[0] == cells and row[2] == 8 * cells, (cf[i], f, o)
+                assert 0 <= row[1] <= row[0]
+                if n == 1:
+                    assert row[1] == 0
+    small = [i for i, x in enumerate(cf) if x[3][0] * x[3][1] <= 2_100_000]
+    assert len(small) >= 24
+    idx = [4 * i + t for i in small for t in range(4)]
+    assert (got[idx] == oracle.stencil_cost_batch(cands[idx], st)).all()

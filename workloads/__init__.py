@@ -336,3 +336,47 @@ def instance_batch(instances, factorization_lists, menu=None):
         out.append(recs.reshape(-1))
         seg.append(seg[-1] + m * len(menu_k))
     return np.concatenate(out), np.array(seg, np.int64)
+
+
+# ---------------------------------------------------------------- decompose vs Alg. A1 study
+# Sec. 6.3 varies 2-D stencils over six aspect ratios 1:1 .. 1:32, five task-space sizes
+# per node (1e6 .. 4e8 points) and 4 .. 128 GPUs in powers of two (4 per node, the
+# paper's machines): 180 configurations.  Here each configuration's domain is
+# (l0, l1) with l1 / l0 = the aspect ratio and l0 * l1 = size per node * nodes
+# (rounded to integers), and two factorizations of the GPUs are compared: decompose's
+# argmin of the surface-area objective and Alg. A1's even grid (its factors, sorted
+# descending, assigned to dims 0, 1 in that order).
+
+STUDY_ASPECTS = (1, 2, 4, 8, 16, 32)
+STUDY_SIZES = (10**6, 10**7, 10**8, 2 * 10**8, 4 * 10**8)
+STUDY_GPUS = (4, 8, 16, 32, 64, 128)
+STUDY_GPUS_PER_NODE = 4
+
+
+def study_configs(aspects=STUDY_ASPECTS, sizes=STUDY_SIZES, gpus=STUDY_GPUS, long_last=True):
+    """[(aspect, size per node, GPUs, (l0, l1), nodes, GPUs per node)]; long_last: the
+    longer dim is dim 1 (else dim 0) -- the paper does not say which, and Alg. A1's
+    descending factors make the two orientations differ."""
+    out = []
+    for a in aspects:
+        for s in sizes:
+            for g in gpus:
+                nodes = g // STUDY_GPUS_PER_NODE
+                total = s * nodes
+                short = max(1, int(round((total / a) ** 0.5)))
+                long_ = max(1, int(round(total / short)))
+                ext = (short, long_) if long_last else (long_, short)
+                out.append((a, s, g, ext, nodes, STUDY_GPUS_PER_NODE))
+    return out
+
+
+def study_candidates(configs, f_decompose, f_greedy):
+    """Four candidates per configuration, in this order: decompose's F and Alg. A1's F,
+    each under the node-major machine order (swap(0,1) before the merge: consecutive
+    processors share a node) and the GPU-major one (the merge alone)."""
+    recs = []
+    for (a, s, g, ext, n, gp), fd, fg in zip(configs, f_decompose, f_greedy):
+        for f in (fd, fg):
+            recs.append(candidate(ext, n, gp, [swap(0, 1), merge(0, 1), decompose(0, f)]))
+            recs.append(candidate(ext, n, gp, [merge(0, 1), decompose(0, f)]))
+    return batch(recs)
