@@ -195,6 +195,26 @@ int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_matmul* mm,
 int tm_select_best(const tm_stencil_cost* d_costs, const int64_t* seg, int64_t nseg,
                    int64_t* d_best, void* stream);
 
+/* ---------------------------------------------------------------- front end
+ * Translates the IndexTaskMap mapper of `task` in a mapping-language program (the
+ * syntax figure of Sec. 7; Fig. 1 and App. A.1 give examples) into one candidate
+ * for the launch domain extent[0..lrank) on Machine(GPU) = (nodes, gpus_per_node).
+ * Supported inside the mapper: `def f(Task t)` with t.ipoint / t.ispace, or
+ * `def f(Tuple point, Tuple space)`; assignments; integer and element-wise tuple
+ * arithmetic (+ - * / // %), tuple literals, indexing, slicing and * unpacking;
+ * Machine(GPU) and its methods split / merge / swap / balance_split /
+ * decompose(i, domain) (factors from decompose's argmin over `domain`, weighted by
+ * `halo` when the domain has the launch rank; halo may be NULL = all 1), .size, and
+ * m[i] as the size of dim i inside arithmetic; `return m[...]` whose coordinates are
+ * ip[d]*s/ispace[d] (BLOCK) or ip[d]%s (CYCLIC) with s the size of that processor
+ * dim, or 0 for a dim of size 1.  Module-level assignments (e.g. m = Machine(GPU))
+ * are visible in functions; other statements (Task, Region, Layout, collection
+ * and backpressure directives) are ignored.  `IndexTaskMap * f` applies to every
+ * task without its own mapper.  Host only, synchronous.  TM_EINVAL with the line
+ * and column of the first unsupported construct in tm_last_error(). */
+int tm_parse_index_task_map(const char* source, const char* task, int32_t lrank, const int64_t* extent,
+                            int32_t nodes, int32_t gpus_per_node, const int32_t* halo, tm_candidate* out);
+
 /* ---------------------------------------------------------------- batch plans
  * A plan owns device memory for up to max_cands candidates and max_words table
  * words.  tm_plan_load validates a batch on the host and uploads its descriptors

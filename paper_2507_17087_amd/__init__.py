@@ -64,6 +64,7 @@ def lib():
             "tm_plan_run_stage": [P, I32, P, P, P],
             "tm_plan_materialize": [P, P, I64, P, I64, P],
             "tm_plan_autotune": [P, P, P, P, P],
+            "tm_parse_index_task_map": [ctypes.c_char_p, ctypes.c_char_p, I32, P, I32, I32, P, P],
             "tm_plan_set_launch": [P, I64, I32, P],
             "tm_plan_info": [P, P, P, P],
             "tm_plan_destroy": [P],
@@ -156,6 +157,18 @@ def tm_workload_greedy(P, extent):
 
 
 # ---------------------------------------------------------------- device calls
+
+def tm_parse_index_task_map(source, task, extent, nodes, gpus, halo=None):
+    """One candidate record (TM_CANDIDATE_DTYPE) from the IndexTaskMap mapper of
+    `task` in a mapping-language program."""
+    k = len(extent)
+    ext = np.array(list(extent) + [1] * (4 - k), np.int64)
+    h = None if halo is None else np.array(list(halo) + [0] * (4 - k), np.int32)
+    out = np.zeros((), dtype=TM_CANDIDATE_DTYPE)
+    _check(lib().tm_parse_index_task_map(source.encode(), task.encode(), k, ext.ctypes.data, nodes, gpus,
+                                         None if h is None else h.ctypes.data, out.ctypes.data))
+    return out
+
 
 def tm_chain_table(c, out=None):
     import torch

@@ -390,3 +390,22 @@ def test_study_full_size(tm):
     assert len(small) >= 24
     idx = [4 * i + t for i in small for t in range(4)]
     assert (got[idx] == oracle.stencil_cost_batch(cands[idx], st)).all()
+
+
+# ---------------------------------------------------------------- front end
+
+def test_translated_mappers(tm):
+    """Mappers written in the mapping language, translated by the front end, then
+    evaluated on the GPU: costs and maps against the oracle."""
+    from test_frontend_cpu import HIER, ROWS, TILES
+    say("translated mappers")
+    cases = []
+    for src, task in ((TILES, "stencil_step"), (HIER, "cannon_tiles"), (ROWS, "any")):
+        for ext, n, g in (((64, 64), 4, 4), ((96, 40), 6, 8), ((130, 67), 5, 2)):
+            cases.append(tm.tm_parse_index_task_map(src, task, ext, n, g))
+    cands = W.batch(cases)
+    for h in ((1, 1), (2, 3)):
+        st = W.stencil(h, 8)
+        assert (gpu_costs(tm, cands, st) == oracle.stencil_cost_batch(cands, st)).all()
+    for c in cands:
+        assert (tm.tm_proc_map(c).cpu().numpy() == oracle.proc_map(c)).all()
