@@ -177,10 +177,19 @@ int tm_proc_map(const tm_candidate* c, int32_t* d_map, int64_t len, void* stream
 
 /* Stencil cost of n candidates (host array) sharing one stencil (host); results to
  * d_out (device, tm_stencil_cost[n]).  All candidates must have launch rank
- * st->lrank.  TM_ENOTSUP if a halo exceeds 4 or a candidate's tables exceed the
- * per-workgroup LDS budget (32768 words of final-space volume + extents). */
+ * st->lrank.  TM_ENOTSUP if a halo exceeds 4 or a candidate's owner table (its
+ * final-space volume) exceeds the per-workgroup LDS budget of 32768 words; the
+ * coordinate tables have no such limit (long ones are read from global memory). */
 int tm_eval_stencil_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
                           tm_stencil_cost* d_out, void* stream);
+
+/* Node-level exchange volume (two-level mappings, where a node receives each remote
+ * cell once however many of its GPUs read it; App. A.1's hierarchical mappers):
+ * for every cell, the distinct nodes other than its owner's node that own one of
+ * its star neighbours.  Same arguments, limits and output layout as
+ * tm_eval_stencil_batch, with ghost_cells = inter_cells = that count. */
+int tm_eval_stencil_node_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
+                               tm_stencil_cost* d_out, void* stream);
 
 /* Matmul tile fetches of n rank-3 candidates: d_per_proc (device, int64[sum P_c][3],
  * candidates back to back, may be NULL) and d_out (device, tm_matmul_cost[n]).

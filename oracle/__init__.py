@@ -38,6 +38,7 @@ def lib():
         for name, args in [("or_validate", [P, P, P]), ("or_point_owner", [P, P, P, P]),
                            ("or_proc_map", [P, P, I64]), ("or_chain_table", [P, P, I64, P]),
                            ("or_stencil_cost", [P, P, P]), ("or_stencil_cost_batch", [P, I64, P, P]),
+                           ("or_stencil_node_cost_batch", [P, I64, P, P]),
                            ("or_matmul_cost", [P, I64, P, P]),
                            ("or_enum_factorizations", [I64, I32, P, I64, P]),
                            ("or_decompose_argmin", [I64, I32, P, P, P]),
@@ -126,6 +127,16 @@ def stencil_cost_batch(cands, st):
     out = np.zeros((len(a), 4), np.int64)
     _chk(lib().or_stencil_cost_batch(a.ctypes.data, len(a), s.ctypes.data, out.ctypes.data),
          "stencil_cost_batch")
+    return out
+
+
+def stencil_node_cost_batch(cands, st):
+    """Node-level exchange volume per candidate: rows (cells, cells, bytes, bytes)."""
+    a = _rec(cands)
+    s = np.ascontiguousarray(st)
+    out = np.zeros((len(a), 4), np.int64)
+    _chk(lib().or_stencil_node_cost_batch(a.ctypes.data, len(a), s.ctypes.data, out.ctypes.data),
+         "stencil_node_cost_batch")
     return out
 
 

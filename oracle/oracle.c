@@ -399,6 +399,84 @@ int or_stencil_cost(const or_cand* c, const or_stencil* st, int64_t* out4) {
     return OR_OK;
 }
 
+/* Node-level exchange volume (the per-node de-duplicated inter-node count used
+ * with two-level mappings, where a node receives each remote cell once however many
+ * of its GPUs read it): for every cell, the distinct nodes, other than the node
+ * owning the cell, that own one of its star neighbours (halo[m] cells along each
+ * axis, non-periodic).  out4 = {cells, cells, bytes, bytes}: every such transfer
+ * crosses nodes. */
+int or_stencil_node_cost(const or_cand* c, const or_stencil* st, int64_t* out4) {
+    or_shapes sh;
+    int rc = compute_shapes(c, &sh);
+    if (rc != OR_OK) return rc;
+    if (st->lrank != c->lrank || st->elem_bytes < 0) return OR_EINVAL;
+    int nh = 0;
+    for (int d = 0; d < c->lrank; d++) {
+        if (st->halo[d] < 0 || st->halo[d] > OR_MAX_HALO) return OR_EINVAL;
+        nh += 2 * st->halo[d];
+    }
+    int64_t np = n_points(c);
+    int32_t* own = NULL;
+    if (np <= OR_MATERIALISE_LIMIT) {
+        own = (int32_t*)malloc((size_t)np * sizeof(int32_t));
+        if (!own) return OR_ENOMEM;
+        rc = or_proc_map(c, own, np);
+        if (rc != OR_OK) { free(own); return rc; }
+    }
+    int32_t* seen = (int32_t*)malloc((size_t)(nh > 0 ? nh : 1) * sizeof(int32_t));
+    if (!seen) { free(own); return OR_ENOMEM; }
+    int64_t cells = 0;
+    int64_t ip[OR_MAX_LRANK], jp[OR_MAX_LRANK];
+    int g = c->gpus;
+    for (int64_t f = 0; f < np; f++) {
+        unflatten(c, f, ip);
+        int32_t node_q;
+        if (own) node_q = own[f] / g;
+        else { int32_t nd, gp; owner_of_point(c, &sh, ip, &nd, &gp); node_q = nd; }
+        int ns = 0;
+        for (int m = 0; m < c->lrank; m++) {
+            for (int s = 1; s <= st->halo[m]; s++) {
+                for (int dir = -1; dir <= 1; dir += 2) {
+                    int64_t x = ip[m] + dir * (int64_t)s;
+                    if (x < 0 || x >= c->extent[m]) continue;
+                    for (int d = 0; d < c->lrank; d++) jp[d] = ip[d];
+                    jp[m] = x;
+                    int32_t node_p;
+                    if (own) {
+                        int64_t jf = 0;
+                        for (int d = 0; d < c->lrank; d++) jf = jf * c->extent[d] + jp[d];
+                        node_p = own[jf] / g;
+                    } else {
+                        int32_t nd, gp;
+                        owner_of_point(c, &sh, jp, &nd, &gp);
+                        node_p = nd;
+                    }
+                    if (node_p == node_q) continue;
+                    int dup = 0;
+                    for (int u = 0; u < ns; u++) if (seen[u] == node_p) dup = 1;
+                    if (!dup) seen[ns++] = node_p;
+                }
+            }
+        }
+        cells += ns;
+    }
+    free(seen);
+    free(own);
+    out4[0] = cells;
+    out4[1] = cells;
+    out4[2] = cells * st->elem_bytes;
+    out4[3] = cells * st->elem_bytes;
+    return OR_OK;
+}
+
+int or_stencil_node_cost_batch(const or_cand* c, int64_t n, const or_stencil* st, int64_t* out4n) {
+    for (int64_t i = 0; i < n; i++) {
+        int rc = or_stencil_node_cost(&c[i], st, out4n + 4 * i);
+        if (rc != OR_OK) return rc;
+    }
+    return OR_OK;
+}
+
 /* Stencil cost of a batch, one candidate after the other. */
 int or_stencil_cost_batch(const or_cand* c, int64_t n, const or_stencil* st, int64_t* out4n) {
     for (int64_t i = 0; i < n; i++) {

@@ -56,6 +56,7 @@ def lib():
             "tm_chain_table": [P, P, I64, P, P],
             "tm_proc_map": [P, P, I64, P],
             "tm_eval_stencil_batch": [P, I64, P, P, P],
+            "tm_eval_stencil_node_batch": [P, I64, P, P, P],
             "tm_eval_matmul_batch": [P, I64, P, P, P, P],
             "tm_select_best": [P, P, I64, P, P],
             "tm_plan_create": [I64, I64, P],
@@ -225,6 +226,19 @@ def tm_eval_stencil_batch(c, st, out=None):
         out = torch.empty((n, 4), dtype=torch.int64, device="cuda")
     _check(lib().tm_eval_stencil_batch(a.ctypes.data, n, s.ctypes.data, _dev_ptr(out, torch.int64, 4 * n),
                                        _stream()))
+    return out
+
+
+def tm_eval_stencil_node_batch(c, st, out=None):
+    """int64 [n,4] device tensor: node-level exchange cells (twice), bytes (twice)."""
+    import torch
+    a = _cands(c)
+    s = _st(st)
+    n = len(a)
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.int64, device="cuda")
+    _check(lib().tm_eval_stencil_node_batch(a.ctypes.data, n, s.ctypes.data, _dev_ptr(out, torch.int64, 4 * n),
+                                            _stream()))
     return out
 
 

@@ -272,13 +272,13 @@ extern "C" int tm_proc_map(const tm_candidate* c, int32_t* d_map, int64_t len, v
     return rc;
 }
 
-extern "C" int tm_eval_stencil_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
-                                     tm_stencil_cost* d_out, void* stream) {
-    hipStream_t s = (hipStream_t)stream;
+static int eval_stencil(const tm_candidate* c, int64_t n, const tm_stencil* st, tm_stencil_cost* d_out,
+                        hipStream_t s, bool node_level) {
     if (!st) return set_error(TM_EINVAL, "null stencil");
     Compiled cp;
     int rc = compile_batch(c, n, st, 0, true, cp);
     if (rc != TM_OK) return rc;
+    cp.hdr.node_level = node_level ? 1 : 0;
     if (n == 0) return TM_OK;
     if (!d_out) return set_error(TM_EINVAL, "null output");
     DeviceBatch db;
@@ -294,6 +294,16 @@ extern "C" int tm_eval_stencil_batch(const tm_candidate* c, int64_t n, const tm_
     }
     free_batch(db, s);
     return rc;
+}
+
+extern "C" int tm_eval_stencil_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
+                                     tm_stencil_cost* d_out, void* stream) {
+    return eval_stencil(c, n, st, d_out, (hipStream_t)stream, false);
+}
+
+extern "C" int tm_eval_stencil_node_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
+                                          tm_stencil_cost* d_out, void* stream) {
+    return eval_stencil(c, n, st, d_out, (hipStream_t)stream, true);
 }
 
 extern "C" int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_matmul* mm, int64_t* d_per_proc,

@@ -41,6 +41,8 @@ struct DevHeader {
     int32_t halo[TM_MAX_LRANK];
     int32_t elem_bytes, lrank;
     int32_t max_words, H;  // largest staged table; max halo (0: no neighbour lists)
+    int32_t node_level;    // owner tables hold nodes only (node-level exchange volume)
+    int32_t pad0;
 };
 
 // Host-side result of validation.

@@ -57,7 +57,10 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
         stage_cand(&sc, &cands[ci]);
         __syncthreads();
         int32_t* base = arena + sc.arena_off;
-        for (int32_t v = threadIdx.x; v < sc.vol; v += blockDim.x) base[v] = owner_key(sc, v);
+        // node-level tables keep the node of each owner (GPU bits cleared): the
+        // counting kernel then counts distinct other nodes per cell
+        const int32_t keep = hdr->node_level ? ~((1 << sc.gbits) - 1) : -1;
+        for (int32_t v = threadIdx.x; v < sc.vol; v += blockDim.x) base[v] = owner_key(sc, v) & keep;
         const int hs = sc.hstride;
         for (int d = 0; d < sc.lrank; ++d) {
             const int64_t l = sc.extent[d];

@@ -407,3 +407,66 @@ def test_validation_extent_and_machine():
     assert oracle.validate(c)[0] == -1
     c = W.candidate((4, 4), 0, 4, [])
     assert oracle.validate(c)[0] == -1
+
+
+# ---------------------------------------------------------------- node-level exchange volume
+
+def _node_level_brute(c, halo):
+    """Independent formulation on the materialised map (numpy): per cell, the set of
+    other nodes among its star neighbours' owners."""
+    ext = tuple(int(x) for x in c["extent"][: int(c["lrank"])])
+    node = (oracle.proc_map(c).reshape(ext) // int(c["gpus"])).astype(np.int64)
+    k = len(ext)
+    sets = [set() for _ in range(node.size)]
+    flat_node = node.ravel()
+    idx = np.arange(node.size).reshape(ext)
+    for m in range(k):
+        for s in range(1, halo[m] + 1):
+            for sgn in (1, -1):
+                src = [slice(None)] * k
+                dst = [slice(None)] * k
+                if sgn > 0:
+                    src[m], dst[m] = slice(0, ext[m] - s), slice(s, None)
+                else:
+                    src[m], dst[m] = slice(s, None), slice(0, ext[m] - s)
+                a = idx[tuple(src)].ravel()
+                b = idx[tuple(dst)].ravel()
+                for i, j in zip(a, b):
+                    if flat_node[j] != flat_node[i]:
+                        sets[i].add(int(flat_node[j]))
+    return sum(len(x) for x in sets)
+
+
+def test_node_level_matches_brute_force():
+    rng = np.random.default_rng(11)
+    cands = W.random_candidates(30, seed=23, ranks=(2,), octaves=(2, 4), nodes_max=6, gpus=(1, 2, 4), max_ops=3,
+                                cyclic_pct=25)
+    for c in cands:
+        halo = tuple(int(x) for x in rng.integers(0, 3, size=2))
+        got = oracle.stencil_node_cost_batch(W.batch([c]), W.stencil(halo, 8))[0]
+        exp = _node_level_brute(c, halo)
+        assert got[0] == exp and got[1] == exp and got[2] == 8 * exp
+
+
+def test_node_level_closed_form_and_invariants():
+    """Hierarchical blocks at least h wide: the node-level volume is the surface-area
+    count of the node grid alone, sum_m 2 h (Fn_m - 1) prod_{j != m} l_j (Sec. 4.1's
+    counting on the nodes); the GPU-cyclic variant has the same node partition and so
+    the same value; de-duplicating per node never exceeds the per-processor
+    inter-node count, and equals it with one GPU per node."""
+    ext, n, g, h = (24, 36), 6, 4, (2, 1)
+    fn_all = oracle.enumerate_factorizations(n, 2)
+    fg_all = oracle.enumerate_factorizations(g, 2)
+    cands = W.two_level_candidates(ext, n, g, fn_all, fg_all)
+    st = W.stencil(h, 8)
+    node = oracle.stencil_node_cost_batch(cands, st)
+    proc = oracle.stencil_cost_batch(cands, st)
+    i = 0
+    for fn in fn_all:
+        for fg in fg_all:
+            closed = sum(2 * h[m] * (fn[m] - 1) * (ext[1 - m]) for m in range(2))
+            assert node[i][0] == closed and node[i + 1][0] == closed, (fn, fg)
+            i += 2
+    assert (node[:, 0] <= proc[:, 1]).all()
+    one = W.two_level_candidates(ext, 6, 1, fn_all, [(1, 1)])
+    assert (oracle.stencil_node_cost_batch(one, st)[:, 0] == oracle.stencil_cost_batch(one, st)[:, 1]).all()

@@ -380,3 +380,26 @@ def study_candidates(configs, f_decompose, f_greedy):
             recs.append(candidate(ext, n, gp, [swap(0, 1), merge(0, 1), decompose(0, f)]))
             recs.append(candidate(ext, n, gp, [merge(0, 1), decompose(0, f)]))
     return batch(recs)
+
+
+# ---------------------------------------------------------------- two-level decompositions
+# App. A.1's hierarchical mappers: nodes tiled over the domain, then each node's GPUs
+# over the node's tile.  Two variants per (node grid Fn, GPU grid Fg):
+#   hierarchical block: swap(0,1), decompose the GPU dim by Fg, decompose the node
+#     dim by Fn, then merge each GPU factor (fastest) with its node factor, so final
+#     dim d has Fn_d * Fg_d coordinates gpu_d + Fg_d * node_d, projected BLOCK: every
+#     node holds a contiguous block, cut into contiguous GPU sub-blocks;
+#   node-block / GPU-cyclic: decompose the node dim by Fn and the GPU dim by Fg, node
+#     dims BLOCK and GPU dims CYCLIC over the launch dims (the Cannon mapper's form).
+
+def two_level_candidates(extent, nodes, gpus, node_grids, gpu_grids):
+    """For every (Fn, Fg) pair: [hierarchical block, node-block / GPU-cyclic]."""
+    k = len(extent)
+    recs = []
+    for fn in node_grids:
+        for fg in gpu_grids:
+            ops = [swap(0, 1), decompose(0, fg), decompose(k, fn)] + [merge(d, k) for d in range(k)]
+            recs.append(candidate(extent, nodes, gpus, ops))
+            proj = [(d, BLOCK) for d in range(k)] + [(d, CYCLIC) for d in range(k)]
+            recs.append(candidate(extent, nodes, gpus, [decompose(0, fn), decompose(k, fg)], proj))
+    return batch(recs)
