@@ -62,6 +62,7 @@ def parse():
                     help="fixed counting launch configuration instead of autotuning (e.g. for profiling)")
     ap.add_argument("--search", action="store_true", help="also run the learned-ranker search leg")
     ap.add_argument("--study", action="store_true", help="also run the decompose-vs-Alg.-A1 volume study")
+    ap.add_argument("--two-level", action="store_true", help="also run the two-level decomposition leg")
     ap.add_argument("--search-train", type=int, default=1_000_000, help="training candidates (exact costs)")
     ap.add_argument("--search-eval", type=int, default=1_000_000, help="evaluation candidates")
     ap.add_argument("--search-epochs", type=int, default=8)
@@ -240,6 +241,36 @@ def study_leg(tm, W):
     return res
 
 
+def two_level_leg(tm, W):
+    """Two-level decompositions (App. A.1's hierarchical mappers) of the benchmark
+    domain: every node grid of the 16 nodes x every GPU grid of the 8 GPUs per node,
+    hierarchical block and node-block / GPU-cyclic (300 candidates), against the
+    benchmark's flat candidates; per-processor costs and the node-level exchange
+    volume (a node receives each remote cell once)."""
+    import torch
+    L = 512
+    fam = W.two_level_candidates((L, L, L), 16, 8, tm.tm_enumerate_factorizations(16, 3),
+                                 tm.tm_enumerate_factorizations(8, 3))
+    flat = W.c2_candidates(tm.tm_enumerate_factorizations(128, 3), extent=(L, L, L))
+    st = W.c2_stencil()
+    res = {"candidates": int(len(fam)), "flat_candidates": int(len(flat))}
+    for name, cands in (("two_level", fam), ("flat", flat)):
+        tm.tm_eval_stencil_batch(cands, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        proc = tm.tm_eval_stencil_batch(cands, st).cpu().numpy()
+        t1 = time.perf_counter()
+        node = tm.tm_eval_stencil_node_batch(cands, st).cpu().numpy()
+        t2 = time.perf_counter()
+        pts = len(cands) * L ** 3
+        bi = int(np.lexsort((np.arange(len(cands)), proc[:, 3], proc[:, 2]))[0])
+        res[name] = {"best_bytes": int(proc[bi, 2]), "best_inter_bytes": int(proc[bi, 3]),
+                     "min_inter_bytes": int(proc[:, 3].min()), "min_node_level_bytes": int(node[:, 2].min()),
+                     "node_level_bytes_of_best": int(node[bi, 2]),
+                     "point_evals_per_s_host_inclusive": [pts / (t1 - t0), pts / (t2 - t1)]}
+    return res
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -355,6 +386,8 @@ def main():
         res["search"] = search_leg(args, tm, W)
     if args.study:
         res["study"] = study_leg(tm, W)
+    if args.two_level:
+        res["two_level"] = two_level_leg(tm, W)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cands, st, L, args.cpu_threads)
     print(json.dumps(res))

@@ -409,3 +409,46 @@ def test_translated_mappers(tm):
         assert (gpu_costs(tm, cands, st) == oracle.stencil_cost_batch(cands, st)).all()
     for c in cands:
         assert (tm.tm_proc_map(c).cpu().numpy() == oracle.proc_map(c)).all()
+
+
+# ---------------------------------------------------------------- node-level volume, two-level families
+
+def node_costs(tm, cands, st):
+    import torch
+    out = tm.tm_eval_stencil_node_batch(cands, st)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_node_level_parity(tm):
+    say("node-level volume: random chains and two-level families")
+    cs = W.random_candidates(600, seed=29, ranks=(2, 3), octaves=(1, 4), nodes_max=16, max_ops=4, cyclic_pct=25)
+    for k, idx, sub in by_rank(cs):
+        st = W.stencil((2,) * k, 8)
+        assert (node_costs(tm, sub, st) == oracle.stencil_node_cost_batch(sub, st)).all()
+    fam = W.two_level_candidates((32, 48, 40), 16, 8, oracle.enumerate_factorizations(16, 3),
+                                 oracle.enumerate_factorizations(8, 3))
+    st = W.c2_stencil()
+    assert (node_costs(tm, fam, st) == oracle.stencil_node_cost_batch(fam, st)).all()
+    assert (gpu_costs(tm, fam, st) == oracle.stencil_cost_batch(fam, st)).all()
+
+
+def test_two_level_full_size(tm):
+    """512^3 on 16 x 8, halo 2: all 15 x 10 node x GPU grids, both variants: the
+    node-level volume of every candidate equals the node grid's surface-area count
+    (blocks are at least 32 wide), and it never exceeds the per-processor
+    inter-node volume."""
+    say("two-level families at 512^3")
+    fn_all = oracle.enumerate_factorizations(16, 3)
+    fg_all = oracle.enumerate_factorizations(8, 3)
+    fam = W.two_level_candidates((512, 512, 512), 16, 8, fn_all, fg_all)
+    st = W.c2_stencil()
+    node = node_costs(tm, fam, st)
+    proc = gpu_costs(tm, fam, st)
+    i = 0
+    for fn in fn_all:
+        for fg in fg_all:
+            closed = sum(2 * 2 * (fn[m] - 1) * 512 * 512 for m in range(3))
+            assert node[i][0] == closed and node[i + 1][0] == closed, (fn, fg)
+            i += 2
+    assert (node[:, 0] <= proc[:, 1]).all()
