@@ -835,14 +835,24 @@ __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int64_t nw = (int64_t)gridDim.x * 4;
     const bool vec = (L & 3) == 0 && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
-    for (int64_t r = (int64_t)blockIdx.x * 4 + wid; r < rows; r += nw) {
-        uint32_t rr = (uint32_t)r;
-        int32_t base = 0;
-        for (int d = K - 2; d >= 0; --d) {
-            const uint32_t e = (uint32_t)sc.extent[d];
-            base += G[sc.coord_off[d] + (int32_t)(rr % e)] & kValMask;
-            rr /= e;
+    // a wave's rows are r0 + t * nw; lane i works out the base index of row
+    // r0 + i * nw for 64 rows at a time, and row t takes it with a lane read
+    const int64_t r0 = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(wid);
+    int32_t bl = 0;
+    for (int64_t t = 0, r = r0; r < rows; ++t, r += nw) {
+        if ((t & 63) == 0) {
+            const int64_t ri = r + (int64_t)lane * nw;
+            bl = 0;
+            if (ri < rows) {
+                uint32_t rr = (uint32_t)ri;
+                for (int d = K - 2; d >= 0; --d) {
+                    const uint32_t e = (uint32_t)sc.extent[d];
+                    bl += G[sc.coord_off[d] + (int32_t)(rr % e)] & kValMask;
+                    rr /= e;
+                }
+            }
         }
+        const int32_t base = __builtin_amdgcn_readlane(bl, (int)(t & 63));
         int32_t* row = out + r * (int64_t)L;
         if (vec) {
             for (int x = lane * 4; x < L; x += 256) {
