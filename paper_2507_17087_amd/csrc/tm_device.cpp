@@ -127,6 +127,7 @@ static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
         cp.max_all_words = std::max(cp.max_all_words, d.words);
         cp.points += d.npoints;
         cp.max_points = std::max(cp.max_points, d.npoints);
+        cp.max_vol = std::max(cp.max_vol, d.vol);
     }
     cp.arena_words = words;
     cp.hdr.max_words = cp.max_words;
@@ -735,6 +736,7 @@ namespace tmk {
 
 int64_t plan_size(const tm_plan* p) { return p->cp.hdr.n; }
 const DevCand* plan_cands(const tm_plan* p) { return p->d_cands; }
+int32_t plan_max_vol(const tm_plan* p) { return p->cp.max_vol; }
 const int32_t* plan_halo(const tm_plan* p) { return p->d_hdr->halo; }
 const DevHeader* plan_hdr(const tm_plan* p) { return p->d_hdr; }
 int64_t plan_cells_per_item(const tm_plan* p) {
@@ -765,7 +767,7 @@ int plan_features(const tm_plan* p, float* d_feat, hipStream_t s) {
             return set_error(TM_ENOMEM, "feature buffers");
         b.cap_n = n;
     }
-    TM_HIP(launch_features(p->d_cands, n, p->d_hdr->halo, b.cross, b.X, d_feat, s));
+    TM_HIP(launch_features(p->d_cands, n, plan_max_vol(p), p->d_hdr->halo, b.cross, b.X, d_feat, s));
     return TM_OK;
 }
 

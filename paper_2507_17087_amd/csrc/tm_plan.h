@@ -17,6 +17,7 @@ struct Compiled {
     int64_t arena_words = 0, items = 0, points = 0, max_points = 0;
     int32_t max_words = 0;      // largest LDS-staged prefix
     int32_t max_all_words = 0;  // largest whole table block of one candidate
+    int32_t max_vol = 0;        // largest final-space volume
     int K = 0, H = 1;
 };
 
@@ -25,7 +26,7 @@ struct SearchBufs {
     int64_t cap_n = 0, cap_sel = 0, cap_seg = 0, cap_words = 0, cap_all = 0;
     uint16_t* X = nullptr;          // [n][kFeat] bf16 features
     float *Y = nullptr, *score = nullptr, *scratch = nullptr;
-    float* cross = nullptr;         // [n][16] crossing fractions, then [n][4] neighbour counts (features)
+    float* cross = nullptr;         // [n][16] crossing fractions, then [n][2] fp64 block-model estimates
     int64_t* seg = nullptr;         // [nseg+1] instance segments
     int64_t* sel = nullptr;         // [nseg*k] chosen candidate indices
     DevCand* sub = nullptr;         // [nseg*k] survivors
@@ -73,6 +74,7 @@ namespace tmk {
 
 int64_t plan_size(const tm_plan* p);
 const DevCand* plan_cands(const tm_plan* p);
+int32_t plan_max_vol(const tm_plan* p);
 const int32_t* plan_halo(const tm_plan* p);
 const DevHeader* plan_hdr(const tm_plan* p);
 int64_t plan_cells_per_item(const tm_plan* p);

@@ -84,7 +84,8 @@ inline double* chain_estimates(float* cross, int64_t n) {
     return reinterpret_cast<double*>(cross + n * kCrossFloats);  // 64n bytes in: 8-byte aligned
 }
 
-hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_halo, float* cross, uint16_t* X,
+hipError_t launch_features(const DevCand* cands, int64_t n, int32_t max_vol, const int32_t* d_halo, float* cross,
+                           uint16_t* X,
                            float* f32, hipStream_t s);
 hipError_t launch_mlp_forward(const uint16_t* X, int64_t n, const RankerWeights& W, float* Y, uint16_t* H1,
                               uint16_t* H2, uint16_t* H3, hipStream_t s);

@@ -49,8 +49,8 @@ __device__ __forceinline__ float lg2(double x) { return (float)log2(x); }
 //                 exact for bijective chains whose blocks are at least h wide.
 //                 Otherwise: per launch dim, the (cell, distinct foreign coordinate)
 //                 pairs along it times the other extents times the crossing fraction.
-// One workgroup per candidate; owners of all final coordinates staged in LDS
-// (volumes above kCrossMax give zeros).
+// One workgroup per candidate; owners of all final coordinates staged in LDS, sized
+// for the batch's largest volume (volumes above kCrossMax give zeros).
 constexpr int kCrossMax = 16384;
 
 __device__ __forceinline__ int64_t block_first(int64_t a, int64_t S, int64_t l) { return (a * l + S - 1) / S; }
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
                                                      const int32_t* __restrict__ halo, float* __restrict__ cross,
                                                      double* __restrict__ est) {
     __shared__ DevCand sc;
-    __shared__ int32_t key[kCrossMax];
+    extern __shared__ int32_t key[];  // the batch's largest final-space volume (at most kCrossMax)
     __shared__ int32_t red[3][256];
     __shared__ double dred[2][256];
     for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
@@ -761,12 +761,13 @@ __global__ void k_pick_costs(const int64_t* __restrict__ best, const int64_t* __
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_halo, float* cross, uint16_t* X,
-                           float* f32, hipStream_t s) {
+hipError_t launch_features(const DevCand* cands, int64_t n, int32_t max_vol, const int32_t* d_halo, float* cross,
+                           uint16_t* X, float* f32, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t g = n < 65536 ? n : 65536;
     double* est = chain_estimates(cross, n);
-    hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(256), 0, s, cands, n, d_halo, cross, est);
+    const size_t key_bytes = (size_t)std::max(1, std::min(max_vol, kCrossMax)) * 4;
+    hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(256), key_bytes, s, cands, n, d_halo, cross, est);
     hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cands, n, d_halo, cross, est,
                        X, f32);
     return hipGetLastError();

@@ -467,7 +467,7 @@ int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nse
     const int64_t n = plan_size(p);
     const int64_t nsel = nseg * topk;
     // scores of every candidate
-    hipError_t e = launch_features(plan_cands(p), n, plan_halo(p), sb->cross, sb->X, nullptr, s);
+    hipError_t e = launch_features(plan_cands(p), n, plan_max_vol(p), plan_halo(p), sb->cross, sb->X, nullptr, s);
     if (e == hipSuccess) e = launch_mlp_forward(sb->X, n, r->W, sb->Y, nullptr, nullptr, nullptr, s);
     if (e == hipSuccess) e = launch_combine(sb->Y, chain_estimates(sb->cross, n), n, r->mu, r->sigma, lambda, sb->score, s);
     // top-k per instance, then the survivors' exact costs
