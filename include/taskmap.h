@@ -155,6 +155,15 @@ int tm_enumerate_factorizations(int64_t P, int32_t k, int32_t* out, int64_t cap,
 int tm_decompose_argmin(int64_t P, int32_t k, const int64_t* extent, const int32_t* halo,
                         int32_t* out_f);
 
+/* decompose with transposes (App. A.3): the same search, objective
+ * sum_m halo[m] F[m] prod_{j != m} extent[j] + sum_{n in T} (1 - 1/F[n]) prod_m extent[m],
+ * T = the dims whose bit is set in transpose_mask (an all-to-all along dim n moves
+ * all but 1/F[n] of every partition's data); compared exactly, ties to the
+ * lexicographically smallest F.  halo[m] <= 255 here (TM_EINVAL beyond), at most
+ * 2^40 points (host). */
+int tm_decompose_argmin_transpose(int64_t P, int32_t k, const int64_t* extent, const int32_t* halo,
+                                  int32_t transpose_mask, int32_t* out_f);
+
 /* Alg. A1 (App. A.2): primes of P ascending, each multiplied into the smallest
  * current factor (lowest index on ties), result sorted descending (host). */
 int tm_greedy_grid(int64_t P, int32_t k, int32_t* out_f);

@@ -190,3 +190,28 @@ def select_best(costs):
     b = ctypes.c_int64()
     _chk(lib().or_select_best(a.ctypes.data, len(a), ctypes.byref(b)), "select_best")
     return b.value
+
+
+def decompose_argmin_transpose(P, extent, halo, transpose):
+    """decompose's argmin with all-to-all transposes (App. A.3), in exact rationals:
+    V = sum_n h_n f_n prod_{m != n} l_m + sum_{n in T} (1 - 1/f_n) prod_m l_m over the
+    ordered factorizations of P; the first minimum in lexicographic order."""
+    from fractions import Fraction
+    k = len(extent)
+    total = 1
+    for l in extent:
+        total *= int(l)
+    best, arg = None, None
+    for f in enumerate_factorizations(P, k):
+        v = Fraction(0)
+        for n in range(k):
+            area = 1
+            for m in range(k):
+                if m != n:
+                    area *= int(extent[m])
+            v += int(halo[n]) * int(f[n]) * area
+        for n in transpose:
+            v += (1 - Fraction(1, int(f[n]))) * total
+        if best is None or v < best:
+            best, arg = v, tuple(int(x) for x in f)
+    return arg

@@ -51,6 +51,7 @@ def lib():
             "tm_validate": [P, P, P],
             "tm_enumerate_factorizations": [I64, I32, P, I64, P],
             "tm_decompose_argmin": [I64, I32, P, P, P],
+            "tm_decompose_argmin_transpose": [I64, I32, P, P, I32, P],
             "tm_greedy_grid": [I64, I32, P],
             "tm_workload_greedy": [I64, I32, P, P],
             "tm_chain_table": [P, P, I64, P, P],
@@ -140,6 +141,17 @@ def tm_decompose_argmin(P, extent, halo=None):
     h = np.array(list(halo if halo is not None else [1] * k) + [0] * (4 - k), np.int32)
     out = np.zeros(4, np.int32)
     _check(lib().tm_decompose_argmin(P, k, ext.ctypes.data, h.ctypes.data, out.ctypes.data))
+    return tuple(int(x) for x in out[:k])
+
+
+def tm_decompose_argmin_transpose(P, extent, halo=None, transpose=()):
+    """decompose's argmin with all-to-all transposes along the dims in `transpose`."""
+    k = len(extent)
+    ext = np.array(list(extent) + [1] * (4 - k), np.int64)
+    h = np.array(list(halo if halo is not None else [1] * k) + [0] * (4 - k), np.int32)
+    mask = sum(1 << int(d) for d in set(transpose))
+    out = np.zeros(4, np.int32)
+    _check(lib().tm_decompose_argmin_transpose(P, k, ext.ctypes.data, h.ctypes.data, mask, out.ctypes.data))
     return tuple(int(x) for x in out[:k])
 
 

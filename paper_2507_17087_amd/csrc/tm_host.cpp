@@ -318,6 +318,49 @@ int tm_decompose_argmin(int64_t P, int32_t k, const int64_t* extent, const int32
     return TM_OK;
 }
 
+int tm_decompose_argmin_transpose(int64_t P, int32_t k, const int64_t* extent, const int32_t* halo,
+                                  int32_t transpose_mask, int32_t* out_f) {
+    int rc = check_pk(P, k);
+    if (rc != TM_OK) return rc;
+    if (!extent || !halo || !out_f) return set_error(TM_EINVAL, "null argument");
+    if (transpose_mask < 0 || transpose_mask >= (1 << k)) return set_error(TM_EINVAL, "transpose mask %d", transpose_mask);
+    for (int m = 0; m < k; ++m) {
+        if (extent[m] < 1 || extent[m] > TM_MAX_EXTENT) return set_error(TM_EINVAL, "extent[%d]", m);
+        if (halo[m] < 0 || halo[m] > 255) return set_error(TM_EINVAL, "halo[%d] (at most 255 here)", m);
+    }
+    __int128 vol = 1;
+    for (int m = 0; m < k; ++m) vol *= extent[m];
+    if (vol > ((__int128)1 << 40)) return set_error(TM_EOVERFLOW, "more than 2^40 points");
+    std::vector<std::array<int32_t, 4>> all;
+    all_factorizations(P, k, all);
+    // objective = A + vol * sum_{n in T} (f_n - 1) / f_n with A = sum_m h_m f_m
+    // prod_{j != m} l_j (< 2^74); as the fraction (A * D + vol * N) / D with
+    // D = prod_{n in T} f_n <= P <= 2^24 and N = sum_{n in T} (f_n - 1) D / f_n, two
+    // candidates compare by cross-multiplying: every product stays below 2^123
+    __int128 best_num = 0, best_den = 1;
+    int64_t bi = -1;
+    for (size_t i = 0; i < all.size(); ++i) {
+        __int128 a = 0, d = 1, nsum = 0;
+        for (int m = 0; m < k; ++m) {
+            __int128 term = (__int128)halo[m] * all[i][m];
+            for (int j = 0; j < k; ++j)
+                if (j != m) term *= extent[j];
+            a += term;
+            if ((transpose_mask >> m) & 1) d *= all[i][m];
+        }
+        for (int m = 0; m < k; ++m)
+            if ((transpose_mask >> m) & 1) nsum += (__int128)(all[i][m] - 1) * (d / all[i][m]);
+        const __int128 num = a * d + vol * nsum;
+        if (bi < 0 || num * best_den < best_num * d) {
+            best_num = num;
+            best_den = d;
+            bi = (int64_t)i;
+        }
+    }
+    for (int m = 0; m < k; ++m) out_f[m] = all[bi][m];
+    return TM_OK;
+}
+
 int tm_greedy_grid(int64_t P, int32_t k, int32_t* out_f) {
     int rc = check_pk(P, k);
     if (rc != TM_OK) return rc;

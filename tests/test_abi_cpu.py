@@ -100,3 +100,19 @@ def test_error_codes_and_messages():
     cnt = ctypes.c_int64()
     rc = tm.lib().tm_enumerate_factorizations(128, 3, None, 0, ctypes.byref(cnt))
     assert rc == tm.TM_ECAPACITY and cnt.value == 36
+
+
+def test_decompose_transpose_matches_oracle():
+    """Host logic: the library's exact integer comparison against the oracle's
+    rational arithmetic, random domains, halos and transpose sets."""
+    import oracle
+    rng = np.random.default_rng(8)
+    for _ in range(60):
+        k = int(rng.integers(1, 5))
+        P = int(rng.choice([4, 8, 12, 30, 64, 96, 128, 360]))
+        ext = tuple(int(x) for x in rng.integers(2, 900, size=k))  # at most 2^40 points
+        h = tuple(int(x) for x in rng.integers(0, 5, size=k))
+        T = [d for d in range(k) if rng.random() < 0.4]
+        assert tm.tm_decompose_argmin_transpose(P, ext, h, T) == oracle.decompose_argmin_transpose(P, ext, h, T)
+    with pytest.raises(tm.TaskmapError):
+        tm.tm_decompose_argmin_transpose(8, (64, 64), (256, 1), [0])

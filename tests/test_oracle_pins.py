@@ -470,3 +470,30 @@ def test_node_level_closed_form_and_invariants():
     assert (node[:, 0] <= proc[:, 1]).all()
     one = W.two_level_candidates(ext, 6, 1, fn_all, [(1, 1)])
     assert (oracle.stencil_node_cost_batch(one, st)[:, 0] == oracle.stencil_cost_batch(one, st)[:, 1]).all()
+
+
+# ---------------------------------------------------------------- decompose with transposes (App. A.3)
+
+def test_transpose_objective_hand_worked():
+    """P = 8 on 64 x 64, halo 1, an all-to-all transpose along dim 0.  By hand from
+    App. A.3's formula (area term + (1 - 1/f_0) * 4096):
+      (1,8): 1*64 + 8*64 = 576,   + 0      = 576
+      (2,4): 2*64 + 4*64 = 384,   + 2048   = 2432
+      (4,2): 384,                 + 3072   = 3456
+      (8,1): 576,                 + 3584   = 4160
+    so the transposed dim stays whole: (1, 8); along dim 1 instead: (8, 1)."""
+    assert oracle.decompose_argmin_transpose(8, (64, 64), (1, 1), [0]) == (1, 8)
+    assert oracle.decompose_argmin_transpose(8, (64, 64), (1, 1), [1]) == (8, 1)
+    # no transposes: plain decompose (ties to the lexicographically smallest)
+    assert oracle.decompose_argmin_transpose(8, (64, 64), (1, 1), []) == (2, 4)
+    assert oracle.decompose_argmin_transpose(8, (64, 64), (1, 1), []) == oracle.decompose_argmin(8, (64, 64), (1, 1))
+
+
+def test_transpose_objective_without_transposes_is_decompose():
+    rng = np.random.default_rng(4)
+    for _ in range(40):
+        k = int(rng.integers(1, 4))
+        P = int(rng.choice([6, 8, 12, 16, 24, 36, 60]))
+        ext = tuple(int(x) for x in rng.integers(4, 300, size=k))
+        h = tuple(int(x) for x in rng.integers(0, 4, size=k))
+        assert oracle.decompose_argmin_transpose(P, ext, h, []) == oracle.decompose_argmin(P, ext, h)
