@@ -202,7 +202,9 @@ int tm_eval_stencil_node_batch(const tm_candidate* c, int64_t n, const tm_stenci
 
 /* Matmul tile fetches of n rank-3 candidates: d_per_proc (device, int64[sum P_c][3],
  * candidates back to back, may be NULL) and d_out (device, tm_matmul_cost[n]).
- * TM_ENOTSUP if a candidate has more than 1024 processors. */
+ * TM_ENOTSUP if a candidate has more than 1024 processors or its owner and
+ * coordinate tables together exceed the LDS budget of 32768 words (the kernel reads
+ * all three coordinate tables per task point). */
 int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_matmul* mm,
                          int64_t* d_per_proc, tm_matmul_cost* d_out, void* stream);
 
