@@ -127,8 +127,8 @@ hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_
 // next one is requested while the current one runs), stages the candidate's owner
 // table and, when they fit, the last dim's coordinate table and offset lists in LDS
 // when the candidate changes (the outer dims' tables are read from global memory,
-// once per row), and gives each wave a contiguous share of the rows,
-// stepping the outer coordinates without divisions.  Every cell is examined: a
+// once per row), and gives each wave every fourth row of the item, stepping the
+// outer coordinates without divisions.  Every cell is examined: a
 // lane reads the coordinate entries of eight consecutive cells with two LDS loads.
 //   - A row's outer coordinates fix its base index and the distinct non-zero
 //     offsets to its outer neighbours, computed from the coordinate tables when
@@ -362,7 +362,7 @@ template <int K, int H, typename XP>
 __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const int32_t* __restrict__ G,
                                            const int32_t* __restrict__ CL, XP DL,
                                            const int32_t (&off)[K], const int32_t (&ext)[K], const int (&hal)[K],
-                                           int64_t ra, int64_t rb, int L, int gbits, int lane, int32_t* rl,
+                                           int64_t ra, int64_t rb, int rs, int L, int gbits, int lane, int32_t* rl,
                                            int32_t* qv, int32_t* qx, int& cnt, int& icnt) {
     constexpr int HS = 2 * H;
     constexpr int KO = K > 1 ? K - 1 : 1;
@@ -443,23 +443,25 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
         }
     };
     load_prefix();
-    // entries of dim K-2 for 64 rows at a time, one per lane (row rbat + lane), so a
-    // row takes its entry with a lane read instead of an LDS round trip
-    int64_t rbat = ra;
+    // entries of dim K-2 for this wave's next 64 rows, one per lane (lane i: the row
+    // i steps of rs ahead), so a row takes its entry with a lane read instead of a
+    // memory round trip
+    int tb = 0;
     int32_t eb = 0;
     auto load_batch = [&]() {
-        if constexpr (K > 1) eb = G[off[K - 2] + (int32_t)((uint32_t)(q[K - 2] + lane) % (uint32_t)ext[K - 2])];
+        if constexpr (K > 1)
+            eb = G[off[K - 2] + (int32_t)((uint32_t)(q[K - 2] + lane * rs) % (uint32_t)ext[K - 2])];
     };
     load_batch();
-    for (int64_t r = ra; r < rb; ++r) {
+    for (int64_t r = ra; r < rb; r += rs) {
         int32_t base = base_o;
         int nr = no;
         if constexpr (K > 1) {
-            if (r - rbat == 64) {
-                rbat = r;
+            if (tb == 64) {
+                tb = 0;
                 load_batch();
             }
-            const int32_t e = __builtin_amdgcn_readlane(eb, (int)(r - rbat));
+            const int32_t e = __builtin_amdgcn_readlane(eb, tb++);
             base += cval(e);
             if (ccnt(e)) nr = outer_offsets<H>(G + off[K - 2], q[K - 2], ext[K - 2], hal[K - 2], rl, no);
         }
@@ -545,17 +547,28 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
             }
             wave_sync_lds();
         }
-        // next row: step the outer coordinates
+        // next row of this wave: step the outer coordinates by rs
         if constexpr (K > 1) {
-            if (r + 1 < rb && ++q[K - 2] == ext[K - 2]) {
-                q[K - 2] = 0;
+            if (r + rs < rb) {
+                q[K - 2] += rs;
+                if (q[K - 2] >= ext[K - 2]) {
+                    int32_t c = 0;
+                    while (q[K - 2] >= ext[K - 2]) {
+                        q[K - 2] -= ext[K - 2];
+                        ++c;
+                    }
 #pragma unroll
-                for (int d = K - 3; d >= 0; --d) {
-                    if (++q[d] < ext[d]) break;
-                    q[d] = 0;
+                    for (int d = K - 3; d >= 0; --d) {
+                        q[d] += c;
+                        c = 0;
+                        while (q[d] >= ext[d]) {
+                            q[d] -= ext[d];
+                            ++c;
+                        }
+                    }
+                    load_prefix();
+                    wave_sync_lds();
                 }
-                load_prefix();
-                wave_sync_lds();
             }
         }
     }
@@ -643,22 +656,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 5 
             cur = lo;
             __syncthreads();
         }
-        // this wave's contiguous share of the item's rows
+        // this wave's rows of the item: every fourth, so rows near block boundaries
+        // (dense ones cluster there) spread evenly over the waves
         const int64_t r0 = (item - ifirst) * rpi;
-        const int64_t r1 = r0 + rpi < rows ? r0 + rpi : rows;
-        const int64_t nrw = (r1 - r0 + 3) >> 2;
-        const int64_t ra = r0 + wid * nrw;
-        const int64_t rb = ra + nrw < r1 ? ra + nrw : r1;
+        const int64_t rb = r0 + rpi < rows ? r0 + rpi : rows;
+        const int64_t ra = r0 + wid;
         int cnt = 0, icnt = 0;
         if (ra < rb) {
             if (dl_lds)  // last dim's table and offset lists in LDS
-                count_rows<K, H>(lds, garena, lds + off[K - 1], lds + dlo, off, ext, hal, ra, rb, L, gbits, lane,
+                count_rows<K, H>(lds, garena, lds + off[K - 1], lds + dlo, off, ext, hal, ra, rb, 4, L, gbits, lane,
                                  s_rl[wid], s_qv[wid], s_qx[wid], cnt, icnt);
             else if (cl_lds)  // table in LDS, offset lists in global memory
-                count_rows<K, H>(lds, garena, lds + off[K - 1], garena + dlo, off, ext, hal, ra, rb, L, gbits, lane,
+                count_rows<K, H>(lds, garena, lds + off[K - 1], garena + dlo, off, ext, hal, ra, rb, 4, L, gbits, lane,
                                  s_rl[wid], s_qv[wid], s_qx[wid], cnt, icnt);
             else  // long rows: both in global memory
-                count_rows<K, H>(lds, garena, garena + off[K - 1], garena + dlo, off, ext, hal, ra, rb, L, gbits,
+                count_rows<K, H>(lds, garena, garena + off[K - 1], garena + dlo, off, ext, hal, ra, rb, 4, L, gbits,
                                  lane, s_rl[wid], s_qv[wid], s_qx[wid], cnt, icnt);
         }
         cnt = wave_sum(cnt);
