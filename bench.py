@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--search", action="store_true", help="also run the learned-ranker search leg")
     ap.add_argument("--study", action="store_true", help="also run the decompose-vs-Alg.-A1 volume study")
     ap.add_argument("--two-level", action="store_true", help="also run the two-level decomposition leg")
+    ap.add_argument("--c3", action="store_true", help="also run the 4,096-candidate random batch")
+    ap.add_argument("--c4", action="store_true", help="also run the matmul batch")
     ap.add_argument("--search-train", type=int, default=1_000_000, help="training candidates (exact costs)")
     ap.add_argument("--search-eval", type=int, default=1_000_000, help="evaluation candidates")
     ap.add_argument("--search-epochs", type=int, default=8)
@@ -271,6 +273,64 @@ def two_level_leg(tm, W):
     return res
 
 
+def c3_leg(tm, W, reps=5):
+    """The batched workload: 4,096 random candidates (seed 17087; ranks 2 and 3,
+    extents log-uniform 32..1023, 1..64 nodes x {1,2,4,8} GPUs, 0-4 random
+    transformations), halo 1, one plan per launch rank, autotuned, timed as graph
+    replays of the whole evaluation (tables, counting, selection)."""
+    import torch
+    cs = W.c3_candidates(4096)
+    res = {"candidates": int(len(cs))}
+    total_pts, total_ms = 0, 0.0
+    for k in (2, 3):
+        sub = cs[cs["lrank"] == k]
+        st = W.c3_stencil(k)
+        plan = tm.Plan(len(sub), 1)
+        plan.load(sub, st)
+        out = torch.empty((len(sub), 4), dtype=torch.int64, device="cuda")
+        plan.run(out)
+        cpi, wg = plan.autotune(out)
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.run(out)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        _, _, pts = plan.info()
+        plan.close()
+        ms = float(np.median(ts))
+        res[f"rank{k}"] = {"candidates": int(len(sub)), "points": int(pts), "ms": ms,
+                           "point_evals_per_s": pts / (ms * 1e-3), "cells_per_item": cpi, "wg_per_cu": wg}
+        total_pts += pts
+        total_ms += ms
+    res["point_evals_per_s"] = total_pts / (total_ms * 1e-3)
+    return res
+
+
+def c4_leg(tm, W, reps=5):
+    """The matmul workload: 256^3 task points on 16 nodes x 4 GPUs, every
+    3-factorization of 64 (with and without swap(0,1)) plus the hierarchical Cannon
+    mapper: 57 candidates, 8 MiB tiles; one call per evaluation (host-inclusive:
+    validation, upload, tables, counting)."""
+    import torch
+    fs = tm.tm_enumerate_factorizations(64, 3)
+    mc = W.c4_candidates(fs)
+    tm.tm_eval_matmul_batch(mc, W.C4_TILE_BYTES)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        tm.tm_eval_matmul_batch(mc, W.C4_TILE_BYTES)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
+    pts = len(mc) * 256 ** 3
+    return {"candidates": int(len(mc)), "task_points": int(pts), "ms_host_inclusive": dt * 1e3,
+            "point_evals_per_s": pts / dt}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -388,6 +448,10 @@ def main():
         res["study"] = study_leg(tm, W)
     if args.two_level:
         res["two_level"] = two_level_leg(tm, W)
+    if args.c3:
+        res["c3"] = c3_leg(tm, W)
+    if args.c4:
+        res["c4"] = c4_leg(tm, W)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cands, st, L, args.cpu_threads)
     print(json.dumps(res))
