@@ -608,7 +608,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 5 
     for (int d = 0; d < K; ++d) hal[d] = uniform32(hdr->halo[d]);
 
     int64_t cur = -1;
-    int32_t L = 0, gbits = 0, rpi = 1, dl_lds = 0, cl_lds = 0;
+    int32_t L = 0, gbits = 0, rpi = 1, dl_lds = 0;
     int64_t rows = 0, ifirst = 0;
     int32_t off[K], ext[K];
     int32_t dlo = 0;
@@ -652,7 +652,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 5 
             }
             dlo = uniform32(c->dl_off[K - 1]);
             dl_lds = uniform32(c->dl_lds);
-            cl_lds = uniform32(c->cl_lds);
             cur = lo;
             __syncthreads();
         }
@@ -666,10 +665,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 5 
             if (dl_lds)  // last dim's table and offset lists in LDS
                 count_rows<K, H>(lds, garena, lds + off[K - 1], lds + dlo, off, ext, hal, ra, rb, 4, L, gbits, lane,
                                  s_rl[wid], s_qv[wid], s_qx[wid], cnt, icnt);
-            else if (cl_lds)  // table in LDS, offset lists in global memory
-                count_rows<K, H>(lds, garena, lds + off[K - 1], garena + dlo, off, ext, hal, ra, rb, 4, L, gbits, lane,
-                                 s_rl[wid], s_qv[wid], s_qx[wid], cnt, icnt);
-            else  // long rows: both in global memory
+            else  // long rows: both read from global memory (one code path keeps the kernel small)
                 count_rows<K, H>(lds, garena, garena + off[K - 1], garena + dlo, off, ext, hal, ra, rb, 4, L, gbits,
                                  lane, s_rl[wid], s_qv[wid], s_qx[wid], cnt, icnt);
         }
