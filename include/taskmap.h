@@ -320,10 +320,13 @@ int tm_ranker_load(const char* path, tm_ranker** out);
  * cost.  r == NULL: every candidate is evaluated exactly.  Otherwise the ranker
  * scores every candidate by predicted log2(1 + bytes) + lambda * predicted
  * log2(1 + inter-node bytes) (estimate + residual head), the topk lowest per instance are
- * evaluated exactly on the GPU, and the best of those is returned.  Everything
- * after the segment upload runs on the device, on `stream`. */
+ * evaluated exactly on the GPU, and the best of those is returned.  margin > 0 keeps
+ * of those only the candidates scoring at most `margin` above the instance's best
+ * score (log2 units: 0.05 = predicted costs within ~3.5 %), so fewer are evaluated;
+ * margin = 0 keeps all topk; negative: TM_EINVAL.  Everything after the segment
+ * upload runs on the device, on `stream`. */
 int tm_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t topk, float lambda,
-              int64_t* d_best, tm_stencil_cost* d_best_cost, void* stream);
+              float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, void* stream);
 
 #ifdef __cplusplus
 }

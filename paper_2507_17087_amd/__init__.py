@@ -421,14 +421,15 @@ class Ranker:
             pass
 
 
-def tm_search(plan, ranker, seg, topk=64, lam=0.05):
+def tm_search(plan, ranker, seg, topk=64, lam=0.05, margin=0.0):
     """Per instance [seg[s], seg[s+1]) of the batch loaded in `plan`: (best index
-    relative to the instance, its cost) as device tensors.  ranker None = exhaustive."""
+    relative to the instance, its cost) as device tensors.  ranker None = exhaustive;
+    margin > 0 re-evaluates only the top-k scoring within `margin` of the best."""
     import torch
     sg = np.ascontiguousarray(seg, dtype=np.int64)
     nseg = len(sg) - 1
     best = torch.empty(max(nseg, 1), dtype=torch.int64, device="cuda")
     cost = torch.empty((max(nseg, 1), 4), dtype=torch.int64, device="cuda")
     _check(lib().tm_search(plan._p, ranker._r if ranker is not None else None, sg.ctypes.data, nseg, topk, lam,
-                           _dev_ptr(best, torch.int64), _dev_ptr(cost, torch.int64), _stream()))
+                           margin, _dev_ptr(best, torch.int64), _dev_ptr(cost, torch.int64), _stream()))
     return best[:nseg], cost[:nseg]

@@ -17,7 +17,7 @@ SIGNATURES = {
     "tm_ranker_train": [P, P, P, I64, I32, I32, F32, U64, P, P],
     "tm_ranker_save": [P, ctypes.c_char_p],
     "tm_ranker_load": [ctypes.c_char_p, P],
-    "tm_search": [P, P, P, I64, I32, F32, P, P, P],
+    "tm_search": [P, P, P, I64, I32, F32, F32, P, P, P],
 }
 
 

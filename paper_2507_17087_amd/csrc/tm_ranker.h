@@ -94,8 +94,8 @@ hipError_t launch_backward(const RankerBuffers& B, const RankerWeights& W, int64
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2,
                        float eps, int64_t t, const RankerWeights& W, hipStream_t s);
 hipError_t launch_publish(const float* p, int64_t count, const RankerWeights& W, hipStream_t s);
-hipError_t launch_topk(const float* score, const int64_t* seg, int64_t nseg, int k, float* scratch, int64_t* sel,
-                       hipStream_t s);
+hipError_t launch_topk(const float* score, const int64_t* seg, int64_t nseg, int k, float margin, float* scratch,
+                       int64_t* sel, hipStream_t s);
 hipError_t launch_combine(const float* Y, const double* est, int64_t n, const float* mu, const float* sigma,
                           float lambda, float* s, hipStream_t st);
 hipError_t launch_gather(const DevCand* cands, const int64_t* sel, int64_t nsel, int k, int64_t cells_per_item,

@@ -595,13 +595,15 @@ __global__ __launch_bounds__(256) void k_publish(const float* __restrict__ p, in
 // indices, ascending by (score, index); -1 past the end of a shorter segment.
 
 __global__ __launch_bounds__(256) void k_topk(const float* __restrict__ score, const int64_t* __restrict__ seg,
-                                              int k, float* __restrict__ scratch, int64_t* __restrict__ sel) {
+                                              int k, float margin, float* __restrict__ scratch,
+                                              int64_t* __restrict__ sel) {
     __shared__ float sv[256];
     __shared__ int64_t si[256];
     const int64_t a = seg[blockIdx.x], e = seg[blockIdx.x + 1];
     for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) scratch[i] = score[i];
     __syncthreads();
     const float taken = __builtin_nanf("");  // never wins a comparison
+    float best = 0.f;
     for (int round = 0; round < k; ++round) {
         float bv = INFINITY;
         int64_t bi = INT64_MAX;
@@ -627,8 +629,12 @@ __global__ __launch_bounds__(256) void k_topk(const float* __restrict__ score, c
             __syncthreads();
         }
         const int64_t win = si[0];
+        const float wv = sv[0];
         __syncthreads();
-        if (win == INT64_MAX) {  // segment exhausted
+        if (round == 0) best = wv;
+        // segment exhausted, or (margin > 0) the next pick scores more than `margin`
+        // above the segment's best: the remaining slots stay empty
+        if (win == INT64_MAX || (margin > 0.f && round > 0 && wv > best + margin)) {
             for (int rr = round + threadIdx.x; rr < k; rr += blockDim.x) sel[blockIdx.x * (int64_t)k + rr] = -1;
             break;
         }
@@ -830,10 +836,10 @@ hipError_t launch_publish(const float* p, int64_t count, const RankerWeights& W,
     return hipGetLastError();
 }
 
-hipError_t launch_topk(const float* score, const int64_t* seg, int64_t nseg, int k, float* scratch, int64_t* sel,
-                       hipStream_t s) {
+hipError_t launch_topk(const float* score, const int64_t* seg, int64_t nseg, int k, float margin, float* scratch,
+                       int64_t* sel, hipStream_t s) {
     if (nseg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_topk, dim3((unsigned)nseg), dim3(256), 0, s, score, seg, k, scratch, sel);
+    hipLaunchKernelGGL(k_topk, dim3((unsigned)nseg), dim3(256), 0, s, score, seg, k, margin, scratch, sel);
     return hipGetLastError();
 }
 

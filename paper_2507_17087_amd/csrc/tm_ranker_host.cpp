@@ -443,7 +443,7 @@ int tm_ranker_load(const char* path, tm_ranker** out) {
 namespace tmk {
 
 int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t topk, float lambda,
-                       int64_t* d_best, tm_stencil_cost* d_best_cost, hipStream_t s);
+                       float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, hipStream_t s);
 
 }  // namespace tmk
 
@@ -452,15 +452,16 @@ extern "C" int tm_ranker_features(const tm_plan* p, float* d_feat, void* stream)
 }
 
 extern "C" int tm_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t topk, float lambda,
-                         int64_t* d_best, tm_stencil_cost* d_best_cost, void* stream) {
+                         float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, void* stream) {
     if (!r) return tmk::plan_exhaustive_search(p, seg, nseg, d_best, d_best_cost, (hipStream_t)stream);
-    return tmk::plan_ranked_search(p, r, seg, nseg, topk, lambda, d_best, d_best_cost, (hipStream_t)stream);
+    if (!(margin >= 0.f)) return tmk::set_error(TM_EINVAL, "margin must be >= 0");
+    return tmk::plan_ranked_search(p, r, seg, nseg, topk, lambda, margin, d_best, d_best_cost, (hipStream_t)stream);
 }
 
 namespace tmk {
 
 int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t topk, float lambda,
-                       int64_t* d_best, tm_stencil_cost* d_best_cost, hipStream_t s) {
+                       float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, hipStream_t s) {
     SearchBufs* sb = nullptr;
     int rc = plan_search_prepare(p, seg, nseg, topk, true, &sb, s);
     if (rc != TM_OK) return rc;
@@ -471,7 +472,7 @@ int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nse
     if (e == hipSuccess) e = launch_mlp_forward(sb->X, n, r->W, sb->Y, nullptr, nullptr, nullptr, s);
     if (e == hipSuccess) e = launch_combine(sb->Y, chain_estimates(sb->cross, n), n, r->mu, r->sigma, lambda, sb->score, s);
     // top-k per instance, then the survivors' exact costs
-    if (e == hipSuccess) e = launch_topk(sb->score, sb->seg, nseg, topk, sb->scratch, sb->sel, s);
+    if (e == hipSuccess) e = launch_topk(sb->score, sb->seg, nseg, topk, margin, sb->scratch, sb->sel, s);
     if (e == hipSuccess)
         e = launch_gather(plan_cands(p), sb->sel, nsel, topk, plan_cells_per_item(p), sb->sub, sb->map, sb->sub_seg,
                           sb->sub_hdr, plan_hdr(p), s);

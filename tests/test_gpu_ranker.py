@@ -280,3 +280,25 @@ def test_network_gain(tm, trained, held_out):
     assert worse.mean() <= 1 - rate_tr + 1e-9
     assert better.sum() > 0
     ru.close()
+
+
+def test_search_margin(tm, trained, held_out):
+    """A score margin keeps, of the top-k, only candidates predicted within `margin`
+    (log2 units) of the instance's best: a huge margin is plain top-k, 0.05 keeps
+    the quality bar with fewer exact evaluations, and nothing beats the optimum."""
+    import torch
+    say("search with a score margin")
+    r, _ = trained
+    inst, cands, seg, plan, ce = held_out
+    _, c_k = tm.tm_search(plan, r, seg, topk=64)
+    _, c_m = tm.tm_search(plan, r, seg, topk=64, margin=1e9)
+    assert (c_k.cpu() == c_m.cpu()).all()
+    _, c_5 = tm.tm_search(plan, r, seg, topk=64, margin=0.05)
+    torch.cuda.synchronize()
+    c5 = c_5.cpu().numpy()
+    rate = _at_opt(ce, c5).mean()
+    say(f"  margin 0.05: {rate:.3f} of instances at the optimum")
+    assert rate >= 0.98
+    assert _lex_le(ce, c5).all()
+    with pytest.raises(tm.TaskmapError):
+        tm.tm_search(plan, r, seg, topk=64, margin=-1.0)
