@@ -68,6 +68,7 @@ def parse():
     ap.add_argument("--search-train", type=int, default=1_000_000, help="training candidates (exact costs)")
     ap.add_argument("--search-eval", type=int, default=1_000_000, help="evaluation candidates")
     ap.add_argument("--search-epochs", type=int, default=8)
+    ap.add_argument("--search-eval-seed", type=int, default=2, help="seed of the evaluation instances")
     ap.add_argument("--search-octaves", type=int, nargs=2, default=[5, 9])
     ap.add_argument("--copy-probe", action="store_true",
                     help="one 256 MiB device-to-device copy before timing (reference for HBM counters)")
@@ -133,7 +134,7 @@ def search_leg(args, tm, W):
     t2 = time.perf_counter()
     del feat, costs
     plan.close()
-    ec, seg, einst = instances_with(tm, W, 2, args.search_eval, args.search_octaves)
+    ec, seg, einst = instances_with(tm, W, args.search_eval_seed, args.search_eval, args.search_octaves)
     plan = tm.Plan(len(ec), 1)
     plan.load(ec, st)
     torch.cuda.synchronize()
