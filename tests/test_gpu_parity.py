@@ -452,3 +452,37 @@ def test_two_level_full_size(tm):
             assert node[i][0] == closed and node[i + 1][0] == closed, (fn, fg)
             i += 2
     assert (node[:, 0] <= proc[:, 1]).all()
+
+
+# ---------------------------------------------------------------- limits
+
+def test_limits(tm):
+    """Edges of the documented limits: a chain of the maximum 8 transformations, a
+    final space of 32,760 processors (the largest owner table the LDS budget holds
+    for these kernels) and one past it (TM_ENOTSUP, nothing launched), and a
+    candidate of 2^32 points whose counts need 64 bits (closed form)."""
+    import torch
+    say("limits")
+    eight = W.candidate((40, 36), 6, 4, [merge(0, 1), split(0, 4), swap(0, 1), merge(0, 1), split(0, 8),
+                                         balance_split(1, 2), merge(1, 2), swap(0, 1)])
+    assert tm.tm_validate(eight)[0] == 0
+    big = W.candidate((300, 280), 4095, 8, [merge(0, 1), decompose(0, (182, 180))])
+    cands = W.batch([eight])
+    st = W.stencil((2, 3), 8)
+    assert (gpu_costs(tm, cands, st) == oracle.stencil_cost_batch(cands, st)).all()
+    assert (gpu_costs(tm, W.batch([big]), st) == oracle.stencil_cost_batch(W.batch([big]), st)).all()
+    assert (tm.tm_proc_map(big).cpu().numpy() == oracle.proc_map(big)).all()
+    too_big = W.candidate((300, 300), 4097, 8, [merge(0, 1), decompose(0, (241, 136))])
+    out = torch.full((1, 4), -5, dtype=torch.int64, device="cuda")
+    with pytest.raises(tm.TaskmapError) as e:
+        tm.tm_eval_stencil_batch(W.batch([too_big]), st, out)
+    assert e.value.code == tm.TM_ENOTSUP
+    torch.cuda.synchronize()
+    assert (out.cpu() == -5).all()
+    # 2048 x 2048 x 1024 = 2^32 points, bijective blocks: V = sum_m 2 h (f_m - 1) prod_{j != m} l_j
+    huge = W.candidate((2048, 2048, 1024), 16, 8, [merge(0, 1), decompose(0, (4, 8, 4))])
+    st3 = W.stencil((2, 2, 2), 8)
+    got = gpu_costs(tm, W.batch([huge]), st3)[0]
+    ext, f = (2048, 2048, 1024), (4, 8, 4)
+    cells = sum(2 * 2 * (f[m] - 1) * (ext[0] * ext[1] * ext[2] // ext[m]) for m in range(3))
+    assert got[0] == cells and got[2] == 8 * cells and 0 < got[1] < got[0]
