@@ -350,7 +350,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build evaluates mappings on a single MI355X "
+        print("bench.py runs on one GPU only: the library evaluates mappings on a single MI355X "
               "(multi-GPU sharding is described in the design notes, not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch

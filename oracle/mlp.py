@@ -8,8 +8,8 @@ the benchmark's CPU leg use it.
 Parameter vector layout (flat): W1[64][256], b1[256], W2[256][256], b2[256],
 W3[256][256], b3[256], W4[256][2], b4[2]; rows index inputs.
 
-The ranker is not described by the paper (it is this build's learned pruning of
-decompose's search space); its feature encoding below is a definition, so the
+The ranker is not described by the paper (it is a learned pruning of decompose's
+search space added by this library); its feature encoding below is a definition, so the
 feature function is checked only against values worked out by hand in the tests
 ("parity unpinned" beyond those).
 """
