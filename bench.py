@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--search-eval", type=int, default=1_000_000, help="evaluation candidates")
     ap.add_argument("--search-epochs", type=int, default=8)
     ap.add_argument("--search-eval-seed", type=int, default=2, help="seed of the evaluation instances")
+    ap.add_argument("--search-train-source", choices=("c3", "menu"), default="c3",
+                    help="training candidates: the random-chain generator (c3 recipe, rank 3, seed 1) or "
+                         "chain-menu instances (seed 1)")
     ap.add_argument("--search-octaves", type=int, nargs=2, default=[5, 9])
     ap.add_argument("--copy-probe", action="store_true",
                     help="one 256 MiB device-to-device copy before timing (reference for HBM counters)")
@@ -114,13 +117,17 @@ def instances_with(tm, W, seed, target, octaves, min_cands=1024):
 
 
 def search_leg(args, tm, W):
-    """Learned ranker: train on exact costs of seed-1 instances, then rank the
-    candidates of seed-2 instances (top-64 per instance re-evaluated exactly) and
-    compare with exhaustive exact evaluation of every candidate."""
+    """Learned ranker: train on exact costs of 1M candidates (by default from the
+    random-chain generator, seed 1), then rank the candidates of seed-2 chain-menu
+    instances (top-64 per instance re-evaluated exactly) and compare with exhaustive
+    exact evaluation of every candidate."""
     import torch
     st = W.c3_stencil(3)
     t0 = time.perf_counter()
-    tc, _, _ = instances_with(tm, W, 1, args.search_train, args.search_octaves)
+    if args.search_train_source == "c3":
+        tc = W.random_candidates(args.search_train, seed=1, ranks=(3,), octaves=tuple(args.search_octaves))
+    else:
+        tc, _, _ = instances_with(tm, W, 1, args.search_train, args.search_octaves)
     plan = tm.Plan(len(tc), 1)
     plan.load(tc, st)
     costs = torch.empty((len(tc), 4), dtype=torch.int64, device="cuda")
@@ -198,7 +205,8 @@ def search_leg(args, tm, W):
                              "inter_bytes_reduction": float(1 - cr[:, 3].sum() / max(1, cd[:, 3].sum()))},
             "ranked_candidates_per_s": rk_rate,
             "exhaustive_candidates_per_s": ex_rate, "speedup": rk_rate / ex_rate,
-            "train_candidates": int(len(tc)), "train_epochs": args.search_epochs,
+            "train_candidates": int(len(tc)), "train_source": args.search_train_source,
+            "train_epochs": args.search_epochs,
             "train_loss_first_last": [losses[0], losses[-1]] if losses else None,
             "exact_costs_s": t1 - t0, "train_s": t2 - t1,
             "extents": f"octaves {args.search_octaves[0]}..{args.search_octaves[1]} per dim (log-uniform)"}
