@@ -10,6 +10,13 @@ cheapest by (bytes, inter-node bytes, index), and materialises the selected
 candidate's int32 processor map (512 MiB).  Inputs (candidate descriptors) are
 resident on the device before timing starts.
 
+The metric's second part -- candidates ranked per second by the learned ranker vs
+exhaustive exact evaluation, at the exhaustive optimum -- is the "search" object of
+the same line (trained on 1M exact costs from the random-chain generator, evaluated
+on ~1M candidates of 457 search instances; --no-search skips it).  Optional legs:
+--study (decompose vs Alg. A1 volumes), --two-level (hierarchical decompositions),
+--c3 (4,096-candidate random batch), --c4 (matmul batch).
+
 Prints one JSON line (see the keys below).  Only one GPU is supported.
 """
 import argparse
@@ -60,7 +67,9 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--launch", type=int, nargs=2, metavar=("CELLS_PER_ITEM", "WG_PER_CU"),
                     help="fixed counting launch configuration instead of autotuning (e.g. for profiling)")
-    ap.add_argument("--search", action="store_true", help="also run the learned-ranker search leg")
+    ap.add_argument("--search", dest="search", action="store_true", default=True,
+                    help="run the learned-ranker search leg (the default: the metric's second part)")
+    ap.add_argument("--no-search", dest="search", action="store_false", help="skip the search leg")
     ap.add_argument("--study", action="store_true", help="also run the decompose-vs-Alg.-A1 volume study")
     ap.add_argument("--two-level", action="store_true", help="also run the two-level decomposition leg")
     ap.add_argument("--c3", action="store_true", help="also run the 4,096-candidate random batch")
