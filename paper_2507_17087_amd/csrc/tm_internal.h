@@ -58,6 +58,9 @@ struct Shapes {
 // offsets is stored separately, 2*H words per coordinate, zero-padded.
 constexpr int32_t kValMask = 0x00ffffff;
 constexpr int kCntShift = 24;
+// Bit 28 of a last-dim entry with offsets: cell x - 1 has the same contribution and
+// the same offset list, so (in the same row) the same foreign owners.
+constexpr int kSameShift = 28;
 constexpr int32_t kMaxLdsWords = 32768;
 constexpr int kMaxHalo = 4;
 

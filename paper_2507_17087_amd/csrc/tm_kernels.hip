@@ -89,6 +89,18 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
             }
             if (d == sc.lrank - 1)  // zero entries up to a multiple of 512 (scanned eight per lane)
                 for (int64_t x = l + threadIdx.x; x < ((l + 511) & ~int64_t(511)); x += blockDim.x) ct[x] = 0;
+            if (last && hs > 0) {
+                // mark cells whose contribution and offset list equal their left
+                // neighbour's (bits 28..31 of the entries are otherwise zero)
+                __syncthreads();
+                for (int64_t x = 1 + threadIdx.x; x < l; x += blockDim.x) {
+                    const int32_t e = ct[x] & 0x0fffffff, ep = ct[x - 1] & 0x0fffffff;
+                    if (((e >> kCntShift) & 0xf) == 0 || e != ep) continue;
+                    bool same = true;
+                    for (int i = 0; i < hs; ++i) same = same && dl[x * hs + i] == dl[(x - 1) * hs + i];
+                    if (same) ct[x] = e | (1 << kSameShift);
+                }
+            }
         }
     }
 }
@@ -197,12 +209,12 @@ __device__ __forceinline__ void eval_cell(const int32_t* __restrict__ T, int32_t
 
 // Evaluates the cells x0 .. x0+7 of a row (see above).  only_flagged: skip cells
 // without last-dim offsets (rows without outer offsets).
-template <typename XP>
+template <bool SAME, typename XP>
 __device__ __forceinline__ void eval_group(const int32_t* __restrict__ T, XP DL, int HS,
                                            const int32_t (&e8)[kCellsPerLane], int x0, int L, int32_t base,
                                            const int32_t* rl, int nr, int gbits, bool only_flagged, int& cnt,
                                            int& icnt) {
-    int32_t ep = -1;  // never a valid entry (bits 28..31 are zero)
+    int32_t ep = -1;  // never a valid entry (bits 29..31 are zero)
     int cp = 0, ip = 0;
 #pragma unroll
     for (int j = 0; j < kCellsPerLane; ++j) {
@@ -210,7 +222,10 @@ __device__ __forceinline__ void eval_group(const int32_t* __restrict__ T, XP DL,
         const int32_t e = e8[j];
         const int nx = ccnt(e);
         if (x >= L || (only_flagged && nx == 0)) continue;
-        if (e != ep || nx != 0) {
+        // a flagged cell equal to its left neighbour (evaluated just before, in this
+        // lane) has its result (SAME: halos of 2 and more, where such runs occur)
+        const bool same = SAME && j > 0 && ((e >> kSameShift) & 1);
+        if (!same && (e != ep || nx != 0)) {
             cp = 0;
             ip = 0;
             eval_cell(T, base + cval(e), rl, nr, DL + x * HS, nx, gbits, cp, ip);
@@ -498,7 +513,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 int pre = hpre, tot = htot;
                 if (!one_chunk) chunk_flags(e8, fl, pre, tot);
                 if (tot > 64) {  // a crowded chunk: evaluate it in place
-                    eval_group(T, DL, HS, e8, x0, L, base, rl, 0, gbits, true, cnt, icnt);
+                    eval_group<(H > 1)>(T, DL, HS, e8, x0, L, base, rl, 0, gbits, true, cnt, icnt);
                     continue;
                 }
                 int pos = qn + pre;
@@ -543,7 +558,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 if (x0 >= L) continue;
                 int32_t e8[kCellsPerLane];
                 load8(CL + x0, e8);
-                eval_group(T, DL, HS, e8, x0, L, base, rl, nr, gbits, false, cnt, icnt);
+                eval_group<(H > 1)>(T, DL, HS, e8, x0, L, base, rl, nr, gbits, false, cnt, icnt);
             }
             wave_sync_lds();
         }
