@@ -386,53 +386,73 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // cells depend on the last coordinate only, so their compaction (per-lane
     // flags, prefix over the wave, total) is computed once here.
     const bool one_chunk = L <= kChunk;
-    uint32_t hfl = 0;
-    int hpre = 0, htot = 0;
+    uint32_t hfl = 0, rfl = 0;
+    int hpre = 0, htot = 0, rpre = 0, rtot = 0;
     if (one_chunk) {
         int32_t e8[kCellsPerLane];
         load8(CL + kCellsPerLane * lane, e8);
         chunk_flags(e8, hfl, hpre, htot);
+        // runs: a flagged cell equal to its left neighbour (same contribution and
+        // offsets) has that neighbour's result in every row; only run starts are kept
+#pragma unroll
+        for (int j = 0; j < kCellsPerLane; ++j)
+            rfl |= (((hfl >> j) & 1u) && !((e8[j] >> kSameShift) & 1) ? 1u : 0u) << j;
+        const int c = __popc(rfl);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint64_t m = __ballot((c >> b) & 1);
+            rpre += lanes_below(m) << b;
+            rtot += __popcll(m) << b;
+        }
     }
-    // Row queue (single-chunk rows with 1..64 flagged cells): a row without outer
-    // offsets queues only its base index; a drain of rq_rows rows evaluates
-    // rq_rows * htot <= 128 cells, cell idx being flagged cell idx % htot of
-    // queued row idx / htot.  qx[0..128) holds that map as (x << 8) | row,
-    // built once here from the flagged positions (staged in qx[128..192)).
-    const bool rowq = one_chunk && htot > 0 && htot <= 64;
-    const int rq_rows = rowq ? 128 / htot : 0;
-    const int rq_cells = rq_rows * htot;
+    // Row queue (single-chunk rows with 1..64 runs of flagged cells): a row without
+    // outer offsets queues only its base index; a drain of rq_rows rows evaluates
+    // rq_rows * rtot <= 128 run starts, entry idx being run idx % rtot of queued row
+    // idx / rtot, each counted times its run length.  qx[0..128) holds that map as
+    // (run length << 18) | (x << 8) | row, built once here (staged in qx[128..192)).
+    const bool rowq = one_chunk && rtot > 0 && rtot <= 64;
+    const int rq_rows = rowq ? 128 / rtot : 0;
+    const int rq_cells = rq_rows * rtot;
     int nrow = 0;
     if (rowq) {
-        uint32_t f = hfl;
-        int pos = 128 + hpre;
+        uint32_t f = rfl;
+        int pos = 128 + rpre;
         while (f) {
             const int j = __builtin_ctz(f);
             f &= f - 1;
-            qx[pos++] = kCellsPerLane * lane + j;
+            const int32_t x = kCellsPerLane * lane + j;
+            int32_t run = 1;
+            while (x + run < L && ((CL[x + run] >> kSameShift) & 1)) ++run;
+            qx[pos++] = x | (run << 10);
         }
         wave_sync_lds();
         int32_t m0 = 0, m1 = 0;
         if (lane < rq_cells) {
-            const int r = lane / htot;
-            m0 = (qx[128 + lane - r * htot] << 8) | r;
+            const int r = lane / rtot;
+            m0 = (qx[128 + lane - r * rtot] << 8) | r;
         }
         if (lane + 64 < rq_cells) {
-            const int r = (lane + 64) / htot;
-            m1 = (qx[128 + lane + 64 - r * htot] << 8) | r;
+            const int r = (lane + 64) / rtot;
+            m1 = (qx[128 + lane + 64 - r * rtot] << 8) | r;
         }
         wave_sync_lds();
         if (lane < rq_cells) qx[lane] = m0;
         if (lane + 64 < rq_cells) qx[lane + 64] = m1;
         wave_sync_lds();
     }
+    auto run_x = [](int32_t m) { return (m >> 8) & 0x3ff; };
+    auto run_len = [](int32_t m) { return (m >> 18) & 0x3ff; };
     auto drain_rows = [&](int ncell) {
-        if (lane < ncell) {
-            const int32_t m = qx[lane];
-            eval_queued(T, CL, DL, HS, qv[m & 0xff], m >> 8, gbits, cnt, icnt);
-        }
-        if (lane + 64 < ncell) {
-            const int32_t m = qx[lane + 64];
-            eval_queued(T, CL, DL, HS, qv[m & 0xff], m >> 8, gbits, cnt, icnt);
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int idx = lane + 64 * half;
+            if (idx < ncell) {
+                const int32_t m = qx[idx];
+                int c = 0, ic = 0;
+                eval_queued(T, CL, DL, HS, qv[m & 0xff], run_x(m), gbits, c, ic);
+                cnt += run_len(m) * c;
+                icnt += run_len(m) * ic;
+            }
         }
     };
     int32_t q[KO];
@@ -540,14 +560,19 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
             }
         } else if (rowq) {
             // ---- dense single-chunk row: cells without last-dim offsets in the lanes
-            // (memoised on equal entries), the flagged cells one per lane from the map
+            // (memoised on equal entries), the runs of flagged cells one per lane from
+            // the map
             int32_t e8[kCellsPerLane];
             load8(CL + kCellsPerLane * lane, e8);
             eval_interior(T, e8, kCellsPerLane * lane, L, base, rl, nr, gbits, cnt, icnt);
-            if (lane < htot) {
-                const int32_t x = qx[lane] >> 8;
+            if (lane < rtot) {
+                const int32_t m = qx[lane];
+                const int32_t x = run_x(m);
                 const int32_t e = CL[x];
-                eval_cell(T, base + cval(e), rl, nr, DL + x * HS, ccnt(e), gbits, cnt, icnt);
+                int c = 0, ic = 0;
+                eval_cell(T, base + cval(e), rl, nr, DL + x * HS, ccnt(e), gbits, c, ic);
+                cnt += run_len(m) * c;
+                icnt += run_len(m) * ic;
             }
             wave_sync_lds();
         } else {
@@ -590,7 +615,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // drain the queues
     if (nrow > 0) {
         wave_sync_lds();
-        drain_rows(nrow * htot);
+        drain_rows(nrow * rtot);
         wave_sync_lds();
     }
     if (qn > 0) {
