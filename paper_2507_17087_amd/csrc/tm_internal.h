@@ -61,6 +61,10 @@ constexpr int kCntShift = 24;
 // Bit 28 of a last-dim entry with offsets: cell x - 1 has the same contribution and
 // the same offset list, so (in the same row) the same foreign owners.
 constexpr int kSameShift = 28;
+// Bit 29: cells x - 1 and x each have a single offset, pointing at the other's
+// coordinate (the two sides of one block boundary compare the same pair of owners),
+// so in a row without outer offsets both count the same foreign owners.
+constexpr int kMirrorShift = 29;
 constexpr int32_t kMaxLdsWords = 32768;
 constexpr int kMaxHalo = 4;
 

@@ -90,15 +90,23 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
             if (d == sc.lrank - 1)  // zero entries up to a multiple of 512 (scanned eight per lane)
                 for (int64_t x = l + threadIdx.x; x < ((l + 511) & ~int64_t(511)); x += blockDim.x) ct[x] = 0;
             if (last && hs > 0) {
-                // mark cells whose contribution and offset list equal their left
-                // neighbour's (bits 28..31 of the entries are otherwise zero)
+                // mark cells whose counts equal their left neighbour's (bits 28..31 of
+                // the entries are otherwise zero): same contribution and offset list
+                // (bit 28, every row), or single offsets pointing at each other (bit
+                // 29, rows without outer offsets)
                 __syncthreads();
                 for (int64_t x = 1 + threadIdx.x; x < l; x += blockDim.x) {
                     const int32_t e = ct[x] & 0x0fffffff, ep = ct[x - 1] & 0x0fffffff;
-                    if (((e >> kCntShift) & 0xf) == 0 || e != ep) continue;
-                    bool same = true;
-                    for (int i = 0; i < hs; ++i) same = same && dl[x * hs + i] == dl[(x - 1) * hs + i];
-                    if (same) ct[x] = e | (1 << kSameShift);
+                    const int n = (e >> kCntShift) & 0xf, np = (ep >> kCntShift) & 0xf;
+                    if (n == 0) continue;
+                    bool same = e == ep;
+                    for (int i = 0; i < hs && same; ++i) same = dl[x * hs + i] == dl[(x - 1) * hs + i];
+                    bool mirror = false;
+                    if (!same && n == 1 && np == 1) {
+                        const int32_t dv = dl[(x - 1) * hs];
+                        mirror = dv == (e & kValMask) - (ep & kValMask) && dl[x * hs] == -dv;
+                    }
+                    if (same || mirror) ct[x] = e | (1 << (same ? kSameShift : kMirrorShift));
                 }
             }
         }
@@ -158,7 +166,8 @@ hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_
 // counted (and those on another node).  Lanes count in registers, waves reduce,
 // and one 64-bit atomic per wave and item adds to the candidate's totals.
 
-constexpr int kQueueCap = 192;  // drained 128 at a time (two cells per lane); a push adds <= 64
+constexpr int kQueueCap = 256;  // drained 128 at a time (two per lane); a push adds <= 64; the row
+                                 // queue's run list is staged in [128, 256)
 constexpr int kCellsPerLane = 8;
 constexpr int kChunk = 64 * kCellsPerLane;
 
@@ -209,7 +218,7 @@ __device__ __forceinline__ void eval_cell(const int32_t* __restrict__ T, int32_t
 
 // Evaluates the cells x0 .. x0+7 of a row (see above).  only_flagged: skip cells
 // without last-dim offsets (rows without outer offsets).
-template <bool SAME, typename XP>
+template <int32_t SAME, typename XP>
 __device__ __forceinline__ void eval_group(const int32_t* __restrict__ T, XP DL, int HS,
                                            const int32_t (&e8)[kCellsPerLane], int x0, int L, int32_t base,
                                            const int32_t* rl, int nr, int gbits, bool only_flagged, int& cnt,
@@ -222,9 +231,9 @@ __device__ __forceinline__ void eval_group(const int32_t* __restrict__ T, XP DL,
         const int32_t e = e8[j];
         const int nx = ccnt(e);
         if (x >= L || (only_flagged && nx == 0)) continue;
-        // a flagged cell equal to its left neighbour (evaluated just before, in this
-        // lane) has its result (SAME: halos of 2 and more, where such runs occur)
-        const bool same = SAME && j > 0 && ((e >> kSameShift) & 1);
+        // a flagged cell whose entry carries one of the SAME bits has the result of
+        // its left neighbour (evaluated just before, in this lane)
+        const bool same = SAME != 0 && j > 0 && (e & SAME) != 0;
         if (!same && (e != ep || nx != 0)) {
             cp = 0;
             ip = 0;
@@ -386,45 +395,53 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // cells depend on the last coordinate only, so their compaction (per-lane
     // flags, prefix over the wave, total) is computed once here.
     const bool one_chunk = L <= kChunk;
-    uint32_t hfl = 0, rfl = 0;
-    int hpre = 0, htot = 0, rpre = 0, rtot = 0;
+    uint32_t hfl = 0, rfl = 0, dfl = 0;
+    int hpre = 0, htot = 0, rpre = 0, rtot = 0, dpre = 0, dtot = 0;
     if (one_chunk) {
         int32_t e8[kCellsPerLane];
         load8(CL + kCellsPerLane * lane, e8);
         chunk_flags(e8, hfl, hpre, htot);
-        // runs: a flagged cell equal to its left neighbour (same contribution and
-        // offsets) has that neighbour's result in every row; only run starts are kept
+        // runs: a flagged cell whose counts equal its left neighbour's has that
+        // neighbour's result; only run starts are kept -- rfl for rows without outer
+        // offsets (either bit), dfl for rows with them (equal entries only)
 #pragma unroll
-        for (int j = 0; j < kCellsPerLane; ++j)
-            rfl |= (((hfl >> j) & 1u) && !((e8[j] >> kSameShift) & 1) ? 1u : 0u) << j;
-        const int c = __popc(rfl);
+        for (int j = 0; j < kCellsPerLane; ++j) {
+            const bool f = (hfl >> j) & 1u;
+            rfl |= (f && !((e8[j] >> kSameShift) & 3) ? 1u : 0u) << j;
+            dfl |= (f && !((e8[j] >> kSameShift) & 1) ? 1u : 0u) << j;
+        }
+        const int c = __popc(rfl), cd = __popc(dfl);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const uint64_t m = __ballot((c >> b) & 1);
+            const uint64_t m = __ballot((c >> b) & 1), md = __ballot((cd >> b) & 1);
             rpre += lanes_below(m) << b;
             rtot += __popcll(m) << b;
+            dpre += lanes_below(md) << b;
+            dtot += __popcll(md) << b;
         }
     }
-    // Row queue (single-chunk rows with 1..64 runs of flagged cells): a row without
+    // Row queue (single-chunk rows with 1..128 runs of flagged cells): a row without
     // outer offsets queues only its base index; a drain of rq_rows rows evaluates
     // rq_rows * rtot <= 128 run starts, entry idx being run idx % rtot of queued row
     // idx / rtot, each counted times its run length.  qx[0..128) holds that map as
-    // (run length << 18) | (x << 8) | row, built once here (staged in qx[128..192)).
-    const bool rowq = one_chunk && rtot > 0 && rtot <= 64;
+    // (run length << 18) | (x << 8) | row, built once here (staged in qx[128..256));
+    // qx[128..128 + dtot) then holds the runs of rows with outer offsets.
+    const bool rowq = one_chunk && dtot > 0 && dtot <= 128;  // rtot <= dtot
     const int rq_rows = rowq ? 128 / rtot : 0;
     const int rq_cells = rq_rows * rtot;
     int nrow = 0;
     if (rowq) {
-        uint32_t f = rfl;
-        int pos = 128 + rpre;
-        while (f) {
-            const int j = __builtin_ctz(f);
-            f &= f - 1;
-            const int32_t x = kCellsPerLane * lane + j;
-            int32_t run = 1;
-            while (x + run < L && ((CL[x + run] >> kSameShift) & 1)) ++run;
-            qx[pos++] = x | (run << 10);
-        }
+        auto stage_runs = [&](uint32_t f, int pos, int32_t bits) {
+            while (f) {
+                const int j = __builtin_ctz(f);
+                f &= f - 1;
+                const int32_t x = kCellsPerLane * lane + j;
+                int32_t run = 1;
+                while (x + run < L && (CL[x + run] & bits) != 0) ++run;
+                qx[pos++] = x | (run << 10);
+            }
+        };
+        stage_runs(rfl, 128 + rpre, 3 << kSameShift);
         wave_sync_lds();
         int32_t m0 = 0, m1 = 0;
         if (lane < rq_cells) {
@@ -438,6 +455,10 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
         wave_sync_lds();
         if (lane < rq_cells) qx[lane] = m0;
         if (lane + 64 < rq_cells) qx[lane + 64] = m1;
+        stage_runs(dfl, 128 + dpre, 1 << kSameShift);
+        wave_sync_lds();
+        if (lane < dtot) qx[128 + lane] <<= 8;
+        if (lane + 64 < dtot) qx[192 + lane] <<= 8;
         wave_sync_lds();
     }
     auto run_x = [](int32_t m) { return (m >> 8) & 0x3ff; };
@@ -533,7 +554,8 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 int pre = hpre, tot = htot;
                 if (!one_chunk) chunk_flags(e8, fl, pre, tot);
                 if (tot > 64) {  // a crowded chunk: evaluate it in place
-                    eval_group<(H > 1)>(T, DL, HS, e8, x0, L, base, rl, 0, gbits, true, cnt, icnt);
+                    eval_group<(H > 1 ? 3 << kSameShift : 0)>(T, DL, HS, e8, x0, L, base, rl, 0, gbits, true,
+                                                               cnt, icnt);
                     continue;
                 }
                 int pos = qn + pre;
@@ -565,14 +587,18 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
             int32_t e8[kCellsPerLane];
             load8(CL + kCellsPerLane * lane, e8);
             eval_interior(T, e8, kCellsPerLane * lane, L, base, rl, nr, gbits, cnt, icnt);
-            if (lane < rtot) {
-                const int32_t m = qx[lane];
-                const int32_t x = run_x(m);
-                const int32_t e = CL[x];
-                int c = 0, ic = 0;
-                eval_cell(T, base + cval(e), rl, nr, DL + x * HS, ccnt(e), gbits, c, ic);
-                cnt += run_len(m) * c;
-                icnt += run_len(m) * ic;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const int k = lane + 64 * half;
+                if (k < dtot) {
+                    const int32_t m = qx[128 + k];
+                    const int32_t x = run_x(m);
+                    const int32_t e = CL[x];
+                    int c = 0, ic = 0;
+                    eval_cell(T, base + cval(e), rl, nr, DL + x * HS, ccnt(e), gbits, c, ic);
+                    cnt += run_len(m) * c;
+                    icnt += run_len(m) * ic;
+                }
             }
             wave_sync_lds();
         } else {
@@ -583,7 +609,8 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 if (x0 >= L) continue;
                 int32_t e8[kCellsPerLane];
                 load8(CL + x0, e8);
-                eval_group<(H > 1)>(T, DL, HS, e8, x0, L, base, rl, nr, gbits, false, cnt, icnt);
+                eval_group<(H > 1 ? 1 << kSameShift : 0)>(T, DL, HS, e8, x0, L, base, rl, nr, gbits, false,
+                                                           cnt, icnt);
             }
             wave_sync_lds();
         }
