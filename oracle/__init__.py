@@ -40,6 +40,7 @@ def lib():
                            ("or_stencil_cost", [P, P, P]), ("or_stencil_cost_batch", [P, I64, P, P]),
                            ("or_stencil_node_cost_batch", [P, I64, P, P]),
                            ("or_matmul_cost", [P, I64, P, P]),
+                           ("or_redistribution_cost_batch", [P, P, I64, I64, P]),
                            ("or_enum_factorizations", [I64, I32, P, I64, P]),
                            ("or_decompose_argmin", [I64, I32, P, P, P]),
                            ("or_greedy_grid", [I64, I32, P]),
@@ -138,6 +139,60 @@ def stencil_node_cost_batch(cands, st):
     _chk(lib().or_stencil_node_cost_batch(a.ctypes.data, len(a), s.ctypes.data, out.ctypes.data),
          "stencil_node_cost_batch")
     return out
+
+
+def redistribution_cost_batch(src, dst, elem_bytes=8):
+    """Per pair (src[i], dst[i]): (moved cells, inter-node moved cells, bytes, inter bytes)."""
+    a, b = _rec(src), _rec(dst)
+    assert len(a) == len(b)
+    out = np.zeros((len(a), 4), np.int64)
+    _chk(lib().or_redistribution_cost_batch(a.ctypes.data, b.ctypes.data, len(a), elem_bytes, out.ctypes.data),
+         "redistribution_cost_batch")
+    return out
+
+
+def transpose_target(c, n, t):
+    """The pencil-transposed image of mapping c for an all-to-all transpose along
+    launch dim n (App. A.3), reading: the processors that share every final coordinate
+    except the one taken from dim n (a pencil of d_n processors along n) split their
+    joint data along launch dim t instead, d_n ways inside each block of t.  The final
+    dim j_n projected from n is merged into the final dim j_t projected from t as its
+    fast part (merge inverse b_p = a mod s_p, b_q = floor(a / s_p)), launch dim n is no
+    longer projected, and the merged dim is a block projection of t.  Requires exactly
+    one final dim projected from each of n and t, both block-projected, and room for
+    two more operations."""
+    r = np.array(_rec(c), copy=True).reshape(())
+    mrank = int(r["mrank"])
+    src = [int(x) for x in r["proj_src"][:mrank]]
+    mode = [int(x) for x in r["proj_mode"][:mrank]]
+    if n == t or src.count(n) != 1 or src.count(t) != 1:
+        raise ValueError("need exactly one final dim projected from each of n and t")
+    jn, jt = src.index(n), src.index(t)
+    if mode[jn] != 0 or mode[jt] != 0:
+        raise ValueError("both dims must be block-projected")
+    ops = []
+    if jn > jt:  # bring the dim of n in front of the dim of t
+        ops.append((3, jt, jn))
+        src[jn], src[jt] = src[jt], src[jn]
+        mode[jn], mode[jt] = mode[jt], mode[jn]
+        jn, jt = jt, jn
+    ops.append((2, jn, jt))  # merge(p = jn, q = jt): the dim of n is the fast part
+    nops = int(r["nops"])
+    if nops + len(ops) > 8:
+        raise ValueError("no room for the transpose operations")
+    for i, (kind, a, b) in enumerate(ops):
+        op = r["ops"][nops + i]
+        op["kind"], op["a"], op["b"], op["nf"] = kind, a, b, 0
+        op["f"][:] = 0
+    r["nops"] = nops + len(ops)
+    src[jn], mode[jn] = t, 0
+    del src[jt], mode[jt]
+    r["mrank"] = mrank - 1
+    r["proj_src"][:] = 0
+    r["proj_mode"][:] = 0
+    r["proj_src"][: mrank - 1] = src
+    r["proj_mode"][: mrank - 1] = mode
+    return r
 
 
 def matmul_cost(c, tile_bytes):

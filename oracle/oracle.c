@@ -17,6 +17,8 @@
  *     own a star neighbour and differ from the cell's owner (Sec. 4.1 example,
  *     Fig. 9 volume, App. A.3 halo widths);
  *   - matmul tile fetches: distinct A[i,k], B[k,j], C[i,j] tiles per processor;
+ *   - redistribution volume between two mappings (App. A.3 transposes): cells
+ *     whose owner, or owner's node, differs;
  *   - decompose's search: enumeration of ordered factorizations by prime exponents
  *     (Sec. 4.3), the objective of Sec. 4.2 / App. A.3 compared exactly, the
  *     greedy grid of Alg. A1 (App. A.2), the workload greedy of Sec. 4.3.
@@ -481,6 +483,50 @@ int or_stencil_node_cost_batch(const or_cand* c, int64_t n, const or_stencil* st
 int or_stencil_cost_batch(const or_cand* c, int64_t n, const or_stencil* st, int64_t* out4n) {
     for (int64_t i = 0; i < n; i++) {
         int rc = or_stencil_cost(&c[i], st, out4n + 4 * i);
+        if (rc != OR_OK) return rc;
+    }
+    return OR_OK;
+}
+
+/* ---------------------------------------------------------------------------
+ * Redistribution volume between two mappings a and b of the same launch domain on
+ * the same machine: every cell's data moves from its owner under a to its owner
+ * under b.  A transpose by all-to-all exchanges along one dimension (App. A.3) is
+ * such a redistribution, from a mapping to its pencil-transposed image (built by
+ * the caller).  moved = cells whose two owners differ; inter = cells whose two
+ * owners sit on different nodes.  out4 = {moved, inter, moved * elem_bytes,
+ * inter * elem_bytes}.
+ * --------------------------------------------------------------------------- */
+int or_redistribution_cost(const or_cand* a, const or_cand* b, int64_t elem_bytes, int64_t* out4) {
+    or_shapes sa, sb;
+    int rc = compute_shapes(a, &sa);
+    if (rc != OR_OK) return rc;
+    rc = compute_shapes(b, &sb);
+    if (rc != OR_OK) return rc;
+    if (elem_bytes < 0 || a->lrank != b->lrank || a->nodes != b->nodes || a->gpus != b->gpus) return OR_EINVAL;
+    for (int d = 0; d < a->lrank; d++)
+        if (a->extent[d] != b->extent[d]) return OR_EINVAL;
+    int64_t np = n_points(a), moved = 0, inter = 0;
+    int64_t ip[OR_MAX_LRANK];
+    for (int64_t f = 0; f < np; f++) {
+        int32_t na, ga, nb, gb;
+        unflatten(a, f, ip);
+        owner_of_point(a, &sa, ip, &na, &ga);
+        owner_of_point(b, &sb, ip, &nb, &gb);
+        if (na != nb || ga != gb) moved++;
+        if (na != nb) inter++;
+    }
+    out4[0] = moved;
+    out4[1] = inter;
+    out4[2] = moved * elem_bytes;
+    out4[3] = inter * elem_bytes;
+    return OR_OK;
+}
+
+int or_redistribution_cost_batch(const or_cand* a, const or_cand* b, int64_t n, int64_t elem_bytes,
+                                 int64_t* out4n) {
+    for (int64_t i = 0; i < n; i++) {
+        int rc = or_redistribution_cost(&a[i], &b[i], elem_bytes, out4n + 4 * i);
         if (rc != OR_OK) return rc;
     }
     return OR_OK;

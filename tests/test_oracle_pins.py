@@ -497,3 +497,136 @@ def test_transpose_objective_without_transposes_is_decompose():
         ext = tuple(int(x) for x in rng.integers(4, 300, size=k))
         h = tuple(int(x) for x in rng.integers(0, 4, size=k))
         assert oracle.decompose_argmin_transpose(P, ext, h, []) == oracle.decompose_argmin(P, ext, h)
+
+
+# ---------------------------------------------------------------- transposes as redistributions (App. A.3)
+
+def _grid(extent, F, n, g, tail=()):
+    return W.candidate(extent, n, g, [merge(0, 1), decompose(0, F)] + list(tail))
+
+
+def _moved(a, b, elem_bytes=1):
+    return tuple(int(x) for x in oracle.redistribution_cost_batch(W.batch([a]), W.batch([b]), elem_bytes)[0])
+
+
+def test_transpose_redistribution_hand_worked():
+    """4 x 4 on two processors, row blocks (F = (2, 1)); the transpose along dim 0 into
+    dim 1 gives column blocks.  Cells whose row block differs from their column block
+    move: rows 0-1 x cols 2-3 and rows 2-3 x cols 0-1 = 8 = (1 - 1/2) * 16.  On 3 x 3
+    the blocks are uneven (rows {0,1},{2}; cols {0,1},{2}): 2 + 2 = 4 cells, where the
+    divisible-case formula would give 4.5."""
+    a = _grid((4, 4), (2, 1), 1, 2)
+    b = oracle.transpose_target(a, 0, 1)
+    assert oracle.validate(b)[1] == (2,)
+    assert _moved(a, b) == (8, 0, 8, 0)               # one node: nothing crosses nodes
+    a2 = _grid((4, 4), (2, 1), 2, 1)
+    assert _moved(a2, oracle.transpose_target(a2, 0, 1), 8) == (8, 8, 64, 64)  # one GPU per node
+    a3 = _grid((3, 3), (2, 1), 1, 2)
+    assert _moved(a3, oracle.transpose_target(a3, 0, 1)) == (4, 0, 4, 0)
+    pa = oracle.proc_map(a3)
+    pb = oracle.proc_map(oracle.transpose_target(a3, 0, 1))
+    assert pa.tolist() == [[0, 0, 0], [0, 0, 0], [1, 1, 1]]
+    assert pb.tolist() == [[0, 0, 1], [0, 0, 1], [0, 0, 1]]
+
+
+def test_transpose_target_is_the_pencil_split():
+    """Divisible 2-D and 3-D grids: the transposed image gives the processor of block
+    (i_0, .., i_{k-1}) the i_n-th of f_n equal slices of dim t inside its own block of
+    t, dim n whole -- written out here from the block geometry, not from the chain."""
+    rng = np.random.default_rng(11)
+    for _ in range(30):
+        k = int(rng.integers(2, 4))
+        F = [int(x) for x in rng.choice([1, 2, 3, 4], size=k)]
+        w = [int(x) for x in rng.integers(1, 4, size=k)]
+        n, t = (int(x) for x in rng.choice(k, size=2, replace=False))
+        w[t] *= F[n]                                   # slices of t divide evenly
+        ext = tuple(F[d] * w[d] for d in range(k))
+        P = int(np.prod(F))
+        g = int(rng.choice([g for g in (1, 2, 3, 4) if P % g == 0]))
+        a = _grid(ext, F, P // g, g)
+        pa = oracle.proc_map(a)
+        pb = oracle.proc_map(oracle.transpose_target(a, n, t))
+        sl = w[t] // F[n]
+        for ip in itertools.product(*[range(e) for e in ext]):
+            blk = [ip[d] // w[d] for d in range(k)]
+            blk[n] = (ip[t] % w[t]) // sl             # the slice of t picks the pencil member
+            corner = tuple(blk[d] * w[d] for d in range(k))
+            assert pb[ip] == pa[corner]
+
+
+def test_transpose_volume_closed_form():
+    """App. A.3: with f_n | l_n for every n, a transpose along n moves
+    (1 - 1/f_n) * prod(w) * P = (f_n - 1) / f_n * prod(l) cells, whatever dim t
+    absorbs the split (t's blocks divisible by f_n); inter-node cells are zero on one
+    node and all of them with one GPU per node."""
+    rng = np.random.default_rng(12)
+    for _ in range(40):
+        k = int(rng.integers(2, 4))
+        F = [int(x) for x in rng.choice([1, 2, 3, 4, 6], size=k)]
+        w = [int(x) for x in rng.integers(1, 4, size=k)]
+        n, t = (int(x) for x in rng.choice(k, size=2, replace=False))
+        w[t] *= F[n]
+        ext = tuple(F[d] * w[d] for d in range(k))
+        P = int(np.prod(F))
+        total = int(np.prod(ext))
+        for nodes, g in ((1, P), (P, 1)):
+            a = _grid(ext, F, nodes, g)
+            moved, inter, _, _ = _moved(a, oracle.transpose_target(a, n, t))
+            assert moved * F[n] == (F[n] - 1) * total
+            assert inter == (0 if nodes == 1 else moved)
+
+
+def test_redistribution_invariants():
+    rng = np.random.default_rng(13)
+    for _ in range(20):
+        F = [int(x) for x in rng.choice([1, 2, 3, 4], size=2)]
+        ext = tuple(int(x) for x in rng.integers(3, 14, size=2))
+        P = F[0] * F[1]
+        g = int(rng.choice([g for g in (1, 2, 3, 4, 6) if P % g == 0]))
+        a = _grid(ext, F, P // g, g)
+        assert _moved(a, a) == (0, 0, 0, 0)
+        # the same mapping written with a swap of the final dims moves nothing
+        a_sw = W.candidate(ext, P // g, g, [merge(0, 1), decompose(0, F), swap(0, 1)],
+                           proj=[(1, W.BLOCK), (0, W.BLOCK)])
+        assert _moved(a, a_sw) == (0, 0, 0, 0)
+        b = oracle.transpose_target(a, 0, 1)
+        pa, pb = oracle.proc_map(a).ravel(), oracle.proc_map(b).ravel()
+        m = _moved(a, b)
+        assert m == _moved(b, a)
+        assert m[0] == int((pa != pb).sum())
+        assert m[1] == int((pa // g != pb // g).sum())
+
+
+def test_transpose_argmin_matches_exact_volumes():
+    """Without halos, decompose's objective with transposes (App. A.3) is the exact
+    moved-cell count on divisible grids, so its argmin is the argmin of the exact
+    counts (first in lexicographic order)."""
+    for ext, P, T in (((12, 12), 6, [0]), ((12, 24), 6, [1]), ((8, 8, 8), 8, [0, 2]), ((6, 12, 4), 4, [2])):
+        k = len(ext)
+        best, arg = None, None
+        for F in oracle.enumerate_factorizations(P, k):
+            if any(ext[d] % F[d] for d in range(k)):
+                continue
+            a = _grid(ext, F, 1, P)
+            tot = 0
+            for n in T:
+                tdim = (n + 1) % k
+                if (ext[tdim] // F[tdim]) % F[n]:
+                    break
+                tot += _moved(a, oracle.transpose_target(a, n, tdim))[0]
+            else:
+                if best is None or tot < best:
+                    best, arg = tot, tuple(F)
+        assert arg == oracle.decompose_argmin_transpose(P, ext, (0,) * k, T)
+
+
+def test_transpose_target_errors():
+    a = _grid((8, 8), (2, 2), 1, 4)
+    with pytest.raises(ValueError):
+        oracle.transpose_target(a, 0, 0)
+    cyc = W.candidate((8, 8), 1, 4, [merge(0, 1), decompose(0, (2, 2))], proj=[(0, W.CYCLIC), (1, W.BLOCK)])
+    with pytest.raises(ValueError):
+        oracle.transpose_target(cyc, 0, 1)
+    bad = W.candidate((8, 8), 1, 4, [merge(0, 1), decompose(0, (2, 2))], proj=[(0, W.BLOCK), (0, W.BLOCK)])
+    with pytest.raises(ValueError):
+        oracle.transpose_target(bad, 0, 1)
