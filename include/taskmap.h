@@ -18,6 +18,8 @@
  *     App. A.3 anisotropic halos);
  *   - matmul tile fetches: distinct A[i,k], B[k,j], C[i,j] tiles per processor for a
  *     task space (i,j,k) (the matmul mappers of Sec. 6 and App. A.1);
+ *   - redistribution volume between two mappings, e.g. the all-to-all transposes of
+ *     App. A.3 (cells whose owner, or owner's node, changes);
  *   - decompose's search (Sec. 4.3): every ordered factorization, the exact argmin
  *     of the objective, the greedy grid of Alg. A1, and a learned ranker that
  *     prunes candidate lists before exact evaluation.
@@ -120,6 +122,12 @@ typedef struct {
     int64_t ghost_cells, inter_cells, bytes, inter_bytes;
 } tm_stencil_cost;
 
+/* moved_cells = cells whose owner differs between two mappings; inter_cells = the
+ * part whose owner's node differs; bytes = cells * elem_bytes. */
+typedef struct {
+    int64_t moved_cells, inter_cells, bytes, inter_bytes;
+} tm_redist_cost;
+
 /* Matmul task space (i,j,k) = extent[0..2]; each task touches A[i,k], B[k,j], C[i,j]. */
 typedef struct {
     int64_t tile_bytes;
@@ -164,6 +172,20 @@ int tm_decompose_argmin(int64_t P, int32_t k, const int64_t* extent, const int32
 int tm_decompose_argmin_transpose(int64_t P, int32_t k, const int64_t* extent, const int32_t* halo,
                                   int32_t transpose_mask, int32_t* out_f);
 
+/* The pencil-transposed image of mapping c for an all-to-all transpose along launch
+ * dim `dim` (App. A.3: each partition keeps 1/d of its data and sends the rest to the
+ * other d - 1 processors of its pencil along `dim`).  Reading: the d processors that
+ * share every final coordinate except the one projected from `dim` split their joint
+ * data along launch dim `into` instead, d ways inside each block of `into`, with
+ * `dim` whole.  Built as c's chain followed by swap (when needed) and merge of the
+ * final dim projected from `dim` (the fast part) into the final dim projected from
+ * `into`, which is then projected by blocks from `into`; `dim` is no longer
+ * projected.  Requires dim != into, exactly one final dim projected from each, both
+ * TM_BLOCK, and room for the one or two added ops (TM_EINVAL otherwise).  The
+ * transpose's traffic is tm_eval_redistribution_batch(c, *out); with divisible
+ * blocks it is (1 - 1/d) * (points) cells, App. A.3's closed form (host). */
+int tm_transpose_target(const tm_candidate* c, int32_t dim, int32_t into, tm_candidate* out);
+
 /* Alg. A1 (App. A.2): primes of P ascending, each multiplied into the smallest
  * current factor (lowest index on ties), result sorted descending (host). */
 int tm_greedy_grid(int64_t P, int32_t k, int32_t* out_f);
@@ -199,6 +221,18 @@ int tm_eval_stencil_batch(const tm_candidate* c, int64_t n, const tm_stencil* st
  * tm_eval_stencil_batch, with ghost_cells = inter_cells = that count. */
 int tm_eval_stencil_node_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
                                tm_stencil_cost* d_out, void* stream);
+
+/* Redistribution volume of n pairs (src[i], dst[i]) of mappings of the same launch
+ * domain on the same Machine(GPU) (host arrays): the cells whose owner under src
+ * differs from their owner under dst -- the data a change of mapping moves, e.g. a
+ * transpose by all-to-all exchanges (App. A.3; dst from tm_transpose_target) -- and
+ * the part whose owner's node changes.  d_out (device, tm_redist_cost[n]).  TM_EINVAL
+ * if a pair differs in launch rank, extents or machine (validation messages number
+ * src[i] as candidate i and dst[i] as candidate n + i); TM_ENOTSUP if a pair's owner
+ * tables and last-dim coordinate tables together exceed the LDS budget of 32768
+ * words (a last-dim table that does not fit on its own is read from global memory). */
+int tm_eval_redistribution_batch(const tm_candidate* src, const tm_candidate* dst, int64_t n, int64_t elem_bytes,
+                                 tm_redist_cost* d_out, void* stream);
 
 /* Matmul tile fetches of n rank-3 candidates: d_per_proc (device, int64[sum P_c][3],
  * candidates back to back, may be NULL) and d_out (device, tm_matmul_cost[n]).

@@ -58,6 +58,8 @@ def lib():
             "tm_proc_map": [P, P, I64, P],
             "tm_eval_stencil_batch": [P, I64, P, P, P],
             "tm_eval_stencil_node_batch": [P, I64, P, P, P],
+            "tm_eval_redistribution_batch": [P, P, I64, I64, P, P],
+            "tm_transpose_target": [P, I32, I32, P],
             "tm_eval_matmul_batch": [P, I64, P, P, P, P],
             "tm_select_best": [P, P, I64, P, P],
             "tm_plan_create": [I64, I64, P],
@@ -153,6 +155,17 @@ def tm_decompose_argmin_transpose(P, extent, halo=None, transpose=()):
     out = np.zeros(4, np.int32)
     _check(lib().tm_decompose_argmin_transpose(P, k, ext.ctypes.data, h.ctypes.data, mask, out.ctypes.data))
     return tuple(int(x) for x in out[:k])
+
+
+def tm_transpose_target(c, dim, into):
+    """The pencil-transposed image of candidate c for an all-to-all transpose along
+    launch dim `dim`, split along launch dim `into` (one TM_CANDIDATE_DTYPE record)."""
+    a = _cands(c)
+    if len(a) != 1:
+        raise TaskmapError(TM_EINVAL, "one candidate expected")
+    out = np.zeros((), dtype=TM_CANDIDATE_DTYPE)
+    _check(lib().tm_transpose_target(a.ctypes.data, int(dim), int(into), out.ctypes.data))
+    return out
 
 
 def tm_greedy_grid(P, k):
@@ -251,6 +264,21 @@ def tm_eval_stencil_node_batch(c, st, out=None):
         out = torch.empty((n, 4), dtype=torch.int64, device="cuda")
     _check(lib().tm_eval_stencil_node_batch(a.ctypes.data, n, s.ctypes.data, _dev_ptr(out, torch.int64, 4 * n),
                                             _stream()))
+    return out
+
+
+def tm_eval_redistribution_batch(src, dst, elem_bytes=8, out=None):
+    """int64 [n,4] device tensor per pair (src[i], dst[i]): moved cells, inter-node
+    moved cells, bytes, inter-node bytes."""
+    import torch
+    a, b = _cands(src), _cands(dst)
+    if len(a) != len(b):
+        raise TaskmapError(TM_EINVAL, "src and dst differ in length")
+    n = len(a)
+    if out is None:
+        out = torch.empty((n, 4), dtype=torch.int64, device="cuda")
+    _check(lib().tm_eval_redistribution_batch(a.ctypes.data, b.ctypes.data, n, int(elem_bytes),
+                                              _dev_ptr(out, torch.int64, 4 * n), _stream()))
     return out
 
 

@@ -61,7 +61,7 @@ static int layout_tables(DevCand& d, int H) {
     d.cl_lds = c_end <= kMaxLdsWords ? 1 : 0;
     d.dl_lds = H > 0 && d_end <= kMaxLdsWords ? 1 : 0;
     const int64_t staged = d.dl_lds ? d_end : (d.cl_lds ? c_end : t_end);
-    const int64_t words = std::max(off, staged);
+    const int64_t words = up4(std::max(off, staged));  // the next candidate's tables start 16-byte aligned
     if (words > INT32_MAX) return TM_EOVERFLOW;
     d.lds_words = (int32_t)staged;
     d.words = (int32_t)words;
@@ -305,6 +305,56 @@ extern "C" int tm_eval_stencil_batch(const tm_candidate* c, int64_t n, const tm_
 extern "C" int tm_eval_stencil_node_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
                                           tm_stencil_cost* d_out, void* stream) {
     return eval_stencil(c, n, st, d_out, (hipStream_t)stream, true);
+}
+
+extern "C" int tm_eval_redistribution_batch(const tm_candidate* src, const tm_candidate* dst, int64_t n,
+                                            int64_t elem_bytes, tm_redist_cost* d_out, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (n < 0) return set_error(TM_EINVAL, "n = %lld", (long long)n);
+    if (elem_bytes < 0) return set_error(TM_EINVAL, "elem_bytes %lld", (long long)elem_bytes);
+    if (n > 0 && (!src || !dst)) return set_error(TM_EINVAL, "null candidate array");
+    for (int64_t i = 0; i < n; ++i) {
+        const tm_candidate &a = src[i], &b = dst[i];
+        bool same = a.lrank == b.lrank && a.nodes == b.nodes && a.gpus_per_node == b.gpus_per_node;
+        for (int d = 0; same && d < a.lrank && d < TM_MAX_LRANK; ++d) same = a.extent[d] == b.extent[d];
+        if (!same) return set_error(TM_EINVAL, "pair %lld: different launch domains or machines", (long long)i);
+    }
+    std::vector<tm_candidate> both((size_t)(2 * n));
+    if (n > 0) {
+        std::memcpy(both.data(), src, (size_t)n * sizeof(tm_candidate));
+        std::memcpy(both.data() + n, dst, (size_t)n * sizeof(tm_candidate));
+    }
+    Compiled cp;
+    int rc = compile_batch(both.data(), 2 * n, nullptr, 0, true, cp);
+    if (rc != TM_OK) return rc;
+    if (n == 0) return TM_OK;
+    if (!d_out) return set_error(TM_EINVAL, "null output");
+    // work items over the pairs (the first mapping's rows); both tables in LDS
+    int64_t items = 0;
+    int32_t lds_words = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        DevCand& a = cp.cands[(size_t)i];
+        const DevCand& b = cp.cands[(size_t)(n + i)];
+        const int64_t w = up4(a.lds_words) + b.lds_words;
+        if (w > kMaxLdsWords)
+            return set_error(TM_ENOTSUP, "pair %lld: %lld table words exceed the LDS budget of %d", (long long)i,
+                             (long long)w, kMaxLdsWords);
+        lds_words = std::max<int32_t>(lds_words, (int32_t)w);
+        const int64_t rpi = rows_per_item_for(a, kDefaultCellsPerItem);
+        a.rows_per_item = (int32_t)rpi;
+        a.item_first = items;
+        items += (a.rows + rpi - 1) / rpi;
+    }
+    DeviceBatch db;
+    rc = upload_batch(cp, db, s);
+    if (rc == TM_OK) {
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)num_cus() * 8));
+        hipError_t e = launch_build_tables(db.hdr, db.cands, 2 * n, db.arena, 0, s);
+        if (e == hipSuccess) e = launch_redist(db.cands, n, db.arena, items, elem_bytes, d_out, grid, lds_words, s);
+        if (e != hipSuccess) rc = set_error(TM_EDEVICE, "redistribution launch: %s", hipGetErrorString(e));
+    }
+    free_batch(db, s);
+    return rc;
 }
 
 extern "C" int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_matmul* mm, int64_t* d_per_proc,

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "tm_internal.h"
@@ -315,6 +316,60 @@ int tm_decompose_argmin(int64_t P, int32_t k, const int64_t* extent, const int32
         }
     }
     for (int m = 0; m < k; ++m) out_f[m] = all[bi][m];
+    return TM_OK;
+}
+
+int tm_transpose_target(const tm_candidate* c, int32_t dim, int32_t into, tm_candidate* out) {
+    if (!c || !out) return set_error(TM_EINVAL, "null argument");
+    int32_t shape[TM_MAX_MRANK], rank = 0;
+    int rc = tm_validate(c, shape, &rank);
+    if (rc != TM_OK) return rc;
+    if (dim < 0 || dim >= c->lrank || into < 0 || into >= c->lrank || dim == into)
+        return set_error(TM_EINVAL, "transpose dims %d into %d", dim, into);
+    int jn = -1, jt = -1, cn = 0, ct = 0;
+    for (int j = 0; j < c->mrank; ++j) {
+        if (c->proj_src[j] == dim) { jn = j; ++cn; }
+        if (c->proj_src[j] == into) { jt = j; ++ct; }
+    }
+    if (cn != 1 || ct != 1) return set_error(TM_EINVAL, "each transpose dim must be projected onto one final dim");
+    if (c->proj_mode[jn] != TM_BLOCK || c->proj_mode[jt] != TM_BLOCK)
+        return set_error(TM_EINVAL, "transpose dims must be block-projected");
+    tm_candidate r = *c;
+    int8_t src[TM_MAX_MRANK], mode[TM_MAX_MRANK];
+    for (int j = 0; j < c->mrank; ++j) {
+        src[j] = c->proj_src[j];
+        mode[j] = c->proj_mode[j];
+    }
+    const int add = jn > jt ? 2 : 1;
+    if (r.nops + add > TM_MAX_OPS) return set_error(TM_EINVAL, "no room for %d more ops", add);
+    auto push = [&](int32_t kind, int32_t a, int32_t b) {
+        tm_op& op = r.ops[r.nops++];
+        std::memset(&op, 0, sizeof(op));
+        op.kind = kind;
+        op.a = a;
+        op.b = b;
+    };
+    if (jn > jt) {  // the final dim of `dim` goes first: merge's lower index is its fast part
+        push(TM_SWAP, jt, jn);
+        std::swap(src[jn], src[jt]);
+        std::swap(mode[jn], mode[jt]);
+        std::swap(jn, jt);
+    }
+    push(TM_MERGE, jn, jt);
+    src[jn] = (int8_t)into;
+    mode[jn] = TM_BLOCK;
+    for (int j = jt; j + 1 < c->mrank; ++j) {
+        src[j] = src[j + 1];
+        mode[j] = mode[j + 1];
+    }
+    r.mrank = c->mrank - 1;
+    for (int j = 0; j < TM_MAX_MRANK; ++j) {
+        r.proj_src[j] = j < r.mrank ? src[j] : 0;
+        r.proj_mode[j] = j < r.mrank ? mode[j] : 0;
+    }
+    rc = tm_validate(&r, shape, &rank);
+    if (rc != TM_OK) return rc;
+    *out = r;
     return TM_OK;
 }
 

@@ -87,6 +87,8 @@ hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* s
 hipError_t launch_map(const DevCand* cands, int64_t n, const int32_t* arena, const int64_t* d_index,
                       int64_t index, int32_t* out, int grid, int lds_words, hipStream_t s);
 hipError_t launch_chain_table(const DevCand* cand, const int32_t* arena, int32_t* out, hipStream_t s);
+hipError_t launch_redist(const DevCand* cands, int64_t npair, const int32_t* arena, int64_t items,
+                         int64_t elem_bytes, tm_redist_cost* out, int grid, int lds_words, hipStream_t s);
 hipError_t launch_matmul(const DevCand* cands, int64_t n, const int32_t* arena, int words_max,
                          int pmax, const int64_t* proc_off, unsigned long long* per_proc,
                          int64_t total_blocks, const int64_t* block_first, hipStream_t s);

@@ -971,6 +971,137 @@ hipError_t launch_chain_table(const DevCand* cand, const int32_t* arena, int32_t
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ redistribution
+//
+// Pairs (a, b) of mappings of one launch domain: candidates [0, npair) of the batch
+// are the a's, [npair, 2 npair) the b's, and a's item_first / rows_per_item give the
+// pair's work items (blocks of rows).  A workgroup stages both owner tables and
+// last-dim coordinate tables of its item's pair in LDS when the pair changes; each
+// wave takes every fourth row of the item, works out the row's base index under
+// both mappings from the outer tables, and compares the two owner keys of four
+// consecutive cells per lane (a cell whose two entries equal the previous cell's has
+// its result).  Counts go to the pair's totals with one atomic per wave and item.
+
+__global__ void k_redist_zero(tm_redist_cost* __restrict__ out, int64_t npair) {
+    int64_t* o = reinterpret_cast<int64_t*>(out);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 4 * npair; i += (int64_t)gridDim.x * blockDim.x)
+        o[i] = 0;
+}
+
+__global__ void k_redist_bytes(tm_redist_cost* __restrict__ out, int64_t npair, int64_t elem_bytes) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npair; i += (int64_t)gridDim.x * blockDim.x) {
+        out[i].bytes = out[i].moved_cells * elem_bytes;
+        out[i].inter_bytes = out[i].inter_cells * elem_bytes;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_redist(const DevCand* __restrict__ cands, int64_t npair,
+                                                const int32_t* __restrict__ arena, int64_t total_items,
+                                                tm_redist_cost* __restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) int32_t lds[];  // 16-byte aligned: ds_read_b128 of the tables
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int64_t cur = -1, rows = 0, ifirst = 0;
+    int32_t K = 1, L = 0, gbits = 0, rpi = 1, wa = 0;
+    int32_t offa[TM_MAX_LRANK] = {0, 0, 0, 0}, offb[TM_MAX_LRANK] = {0, 0, 0, 0}, ext[TM_MAX_LRANK] = {1, 1, 1, 1};
+    const int32_t *GA = arena, *GB = arena, *CA = lds, *CB = lds;
+    for (int64_t item = blockIdx.x; item < total_items; item += gridDim.x) {
+        int64_t lo = 0, hi = npair - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (cands[mid].item_first <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        lo = uniform64(lo);
+        if (lo != cur) {
+            __syncthreads();  // no wave still reads the previous pair's tables
+            const DevCand* a = &cands[lo];
+            const DevCand* b = &cands[npair + lo];
+            const int32_t na = uniform32(a->lds_words), nb = uniform32(b->lds_words);
+            wa = (na + 3) & ~3;
+            GA = arena + uniform64(a->arena_off);
+            GB = arena + uniform64(b->arena_off);
+            for (int i = tid; i < na; i += 256) lds[i] = GA[i];
+            for (int i = tid; i < nb; i += 256) lds[wa + i] = GB[i];
+            K = uniform32(a->lrank);
+            L = uniform32(a->L);
+            gbits = uniform32(a->gbits);
+            rpi = uniform32(a->rows_per_item);
+            rows = uniform64(a->rows);
+            ifirst = uniform64(a->item_first);
+            for (int d = 0; d < TM_MAX_LRANK; ++d) {
+                offa[d] = uniform32(a->coord_off[d]);
+                offb[d] = uniform32(b->coord_off[d]);
+                ext[d] = d < K ? uniform32((int32_t)a->extent[d]) : 1;
+            }
+            CA = uniform32(a->cl_lds) ? lds + offa[K - 1] : GA + offa[K - 1];
+            CB = uniform32(b->cl_lds) ? lds + wa + offb[K - 1] : GB + offb[K - 1];
+            cur = lo;
+            __syncthreads();
+        }
+        const int32_t* TA = lds;
+        const int32_t* TB = lds + wa;
+        const int64_t r0 = (item - ifirst) * rpi;
+        const int64_t rb = r0 + rpi < rows ? r0 + rpi : rows;
+        uint32_t moved = 0, inter = 0;
+        for (int64_t r = r0 + wid; r < rb; r += 4) {
+            int32_t ba = 0, bb = 0;
+            uint32_t rr = (uint32_t)r;  // rows < 2^31 (checked on the host)
+            for (int d = K - 2; d >= 0; --d) {
+                const uint32_t e = (uint32_t)ext[d];
+                const int32_t q = (int32_t)(rr % e);
+                rr /= e;
+                ba += GA[offa[d] + q] & kValMask;
+                bb += GB[offb[d] + q] & kValMask;
+            }
+            int32_t pa = -1, pb = -1;
+            uint32_t pm = 0, pi = 0;
+            for (int x = 4 * lane; x < L; x += 256) {
+                // tables are zero-padded to whole 512-entry chunks: x + 3 is in bounds
+                const i32x4 ea = *reinterpret_cast<const i32x4*>(CA + x);
+                const i32x4 eb = *reinterpret_cast<const i32x4*>(CB + x);
+                const int32_t va[4] = {ea.x, ea.y, ea.z, ea.w}, vb[4] = {eb.x, eb.y, eb.z, eb.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (x + j >= L) break;
+                    if (va[j] != pa || vb[j] != pb) {
+                        const int32_t ka = TA[ba + (va[j] & kValMask)];
+                        const int32_t kb = TB[bb + (vb[j] & kValMask)];
+                        pm = ka != kb ? 1u : 0u;
+                        pi = (ka >> gbits) != (kb >> gbits) ? 1u : 0u;
+                        pa = va[j];
+                        pb = vb[j];
+                    }
+                    moved += pm;
+                    inter += pi;
+                }
+            }
+        }
+        unsigned long long m64 = moved, i64 = inter;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            m64 += __shfl_xor(m64, o, 64);
+            i64 += __shfl_xor(i64, o, 64);
+        }
+        if (lane == 0 && (m64 | i64)) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].moved_cells), m64);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].inter_cells), i64);
+        }
+    }
+}
+
+hipError_t launch_redist(const DevCand* cands, int64_t npair, const int32_t* arena, int64_t items,
+                         int64_t elem_bytes, tm_redist_cost* out, int grid, int lds_words, hipStream_t s) {
+    const int64_t zb = (4 * npair + 255) / 256;
+    const int zg = zb < 1 ? 1 : (zb > 1024 ? 1024 : (int)zb);
+    hipLaunchKernelGGL(k_redist_zero, dim3(zg), dim3(256), 0, s, out, npair);
+    if (items > 0)
+        hipLaunchKernelGGL(k_redist, dim3(grid), dim3(256), (size_t)lds_words * 4, s, cands, npair, arena, items,
+                           out);
+    hipLaunchKernelGGL(k_redist_bytes, dim3(zg), dim3(256), 0, s, out, npair, elem_bytes);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ matmul tiles
 //
 // Work block = (candidate, matrix m in {A,B,C}, 16 x 256 consecutive tiles).  A thread

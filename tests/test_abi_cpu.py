@@ -116,3 +116,45 @@ def test_decompose_transpose_matches_oracle():
         assert tm.tm_decompose_argmin_transpose(P, ext, h, T) == oracle.decompose_argmin_transpose(P, ext, h, T)
     with pytest.raises(tm.TaskmapError):
         tm.tm_decompose_argmin_transpose(8, (64, 64), (256, 1), [0])
+
+
+def test_transpose_target_matches_oracle():
+    """Host logic: the library's pencil-transposed image of a mapping equals the
+    oracle's, record for record (ops, projections, rank), over random decompose
+    chains with extra ops, and the same cases are rejected."""
+    rng = np.random.default_rng(21)
+    fields = ("lrank", "nodes", "gpus", "nops", "extent", "mrank", "proj_src", "proj_mode")
+    checked = 0
+    for _ in range(200):
+        k = int(rng.integers(2, 5))
+        P = int(rng.choice([2, 4, 6, 8, 12, 16]))
+        g = int(rng.choice([g for g in (1, 2, 4) if P % g == 0]))
+        F = oracle.enumerate_factorizations(P, k)[int(rng.integers(0, len(oracle.enumerate_factorizations(P, k))))]
+        ext = tuple(int(x) for x in rng.integers(1, 40, size=k))
+        tail = [] if rng.random() < 0.5 else [swap(0, 1)]
+        proj = [(int(d), W.BLOCK if rng.random() < 0.8 else W.CYCLIC) for d in rng.permutation(k)]
+        c = W.candidate(ext, P // g, g, [merge(0, 1), decompose(0, F)] + tail, proj)
+        n, t = (int(x) for x in rng.choice(k, size=2, replace=False))
+        try:
+            want = oracle.transpose_target(c, n, t)
+        except ValueError:
+            with pytest.raises(tm.TaskmapError):
+                tm.tm_transpose_target(c, n, t)
+            continue
+        got = tm.tm_transpose_target(c, n, t)
+        for f in fields:
+            assert np.array_equal(np.asarray(got[f]), np.asarray(want[f])), f
+        for i in range(int(want["nops"])):
+            for f in ("kind", "a", "b", "nf", "f"):
+                assert np.array_equal(np.asarray(got["ops"][i][f]), np.asarray(want["ops"][i][f])), (i, f)
+        checked += 1
+    assert checked > 60
+    c = W.candidate((8, 8), 1, 4, [merge(0, 1), decompose(0, (2, 2))])
+    for n, t in ((0, 0), (0, 2), (-1, 0)):
+        with pytest.raises(tm.TaskmapError):
+            tm.tm_transpose_target(c, n, t)
+    full = W.candidate((8, 8), 1, 4, [merge(0, 1), decompose(0, (2, 2))] + [swap(0, 1)] * 6)
+    with pytest.raises(tm.TaskmapError):
+        tm.tm_transpose_target(full, 0, 1)          # no room for merge
+    assert int(tm.tm_transpose_target(W.candidate((8, 8), 1, 4, [merge(0, 1), decompose(0, (2, 2))] + [swap(0, 1)] * 5),
+                                      0, 1)["nops"]) == 8
