@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--no-search", dest="search", action="store_false", help="skip the search leg")
     ap.add_argument("--study", action="store_true", help="also run the decompose-vs-Alg.-A1 volume study")
     ap.add_argument("--two-level", action="store_true", help="also run the two-level decomposition leg")
+    ap.add_argument("--transpose", action="store_true", help="also run the all-to-all transpose leg")
     ap.add_argument("--c3", action="store_true", help="also run the 4,096-candidate random batch")
     ap.add_argument("--c4", action="store_true", help="also run the matmul batch")
     ap.add_argument("--search-train", type=int, default=1_000_000, help="training candidates (exact costs)")
@@ -305,6 +306,51 @@ def two_level_leg(tm, W):
     return res
 
 
+def transpose_leg(tm, W, reps=3):
+    """Transposes by all-to-all exchanges (App. A.3) on the benchmark domain: for
+    every decompose candidate of 128 processors, the exact halo-2 ghost transfers and
+    the exact cells moved by a transpose along each dim in T (to the pencil-transposed
+    image split along the next dim), for T = {0} and T = {0, 1}.  Reports decompose's
+    plain pick, the transpose-aware objective's pick and the exact optimum of
+    ghost + moved transfers, and the redistribution kernel's throughput."""
+    import torch
+    L = 512
+    ext = (L, L, L)
+    facs = tm.tm_enumerate_factorizations(128, 3)
+    cands = W.batch([W.candidate(ext, 16, 8, [W.merge(0, 1), W.decompose(0, f)]) for f in facs])
+    st = W.c2_stencil()
+    ghost = tm.tm_eval_stencil_batch(cands, st).cpu().numpy()
+    src, dst = [], []
+    for c in cands:
+        for n in range(3):
+            src.append(c)
+            dst.append(tm.tm_transpose_target(c, n, (n + 1) % 3))
+    src, dst = W.batch(src), W.batch(dst)
+    tm.tm_eval_redistribution_batch(src, dst, 8)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        moved = tm.tm_eval_redistribution_batch(src, dst, 8)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    moved = moved.cpu().numpy().reshape(len(facs), 3, 4)
+    pts = len(src) * L ** 3
+    res = {"pairs": int(len(src)), "points": int(pts), "ms_host_inclusive": 1e3 * float(np.median(ts)),
+           "point_evals_per_s_host_inclusive": pts / float(np.median(ts))}
+    plain = facs.index(tm.tm_decompose_argmin(128, ext, (2, 2, 2)))
+    for T in ((0,), (0, 1)):
+        tot = ghost[:, 2] + sum(moved[:, n, 2] for n in T)
+        inter = ghost[:, 3] + sum(moved[:, n, 3] for n in T)
+        aware = facs.index(tm.tm_decompose_argmin_transpose(128, ext, (2, 2, 2), T))
+        best = int(np.lexsort((np.arange(len(facs)), inter, tot))[0])
+        res["T=" + "".join(str(n) for n in T)] = {
+            "decompose": {"F": list(facs[plain]), "bytes": int(tot[plain]), "inter_bytes": int(inter[plain])},
+            "transpose_aware": {"F": list(facs[aware]), "bytes": int(tot[aware]), "inter_bytes": int(inter[aware])},
+            "exact_best": {"F": list(facs[best]), "bytes": int(tot[best]), "inter_bytes": int(inter[best])}}
+    return res
+
+
 def c3_leg(tm, W, reps=5):
     """The batched workload: 4,096 random candidates (seed 17087; ranks 2 and 3,
     extents log-uniform 32..1023, 1..64 nodes x {1,2,4,8} GPUs, 0-4 random
@@ -480,6 +526,8 @@ def main():
         res["study"] = study_leg(tm, W)
     if args.two_level:
         res["two_level"] = two_level_leg(tm, W)
+    if args.transpose:
+        res["transpose"] = transpose_leg(tm, W)
     if args.c3:
         res["c3"] = c3_leg(tm, W)
     if args.c4:

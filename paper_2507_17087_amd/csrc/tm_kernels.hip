@@ -425,8 +425,10 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // rq_rows * rtot <= 128 run starts, entry idx being run idx % rtot of queued row
     // idx / rtot, each counted times its run length.  qx[0..128) holds that map as
     // (run length << 18) | (x << 8) | row, built once here (staged in qx[128..256));
-    // qx[128..128 + dtot) then holds the runs of rows with outer offsets.
-    const bool rowq = one_chunk && dtot > 0 && dtot <= 128;  // rtot <= dtot
+    // qx[128..128 + dtot) then holds the runs of rows with outer offsets (rowd: when
+    // there are at most 128 of them; else such rows take the general dense path).
+    const bool rowq = one_chunk && rtot > 0 && rtot <= 128;
+    const bool rowd = rowq && dtot <= 128;  // rtot <= dtot
     const int rq_rows = rowq ? 128 / rtot : 0;
     const int rq_cells = rq_rows * rtot;
     int nrow = 0;
@@ -455,10 +457,12 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
         wave_sync_lds();
         if (lane < rq_cells) qx[lane] = m0;
         if (lane + 64 < rq_cells) qx[lane + 64] = m1;
-        stage_runs(dfl, 128 + dpre, 1 << kSameShift);
-        wave_sync_lds();
-        if (lane < dtot) qx[128 + lane] <<= 8;
-        if (lane + 64 < dtot) qx[192 + lane] <<= 8;
+        if (rowd) {
+            stage_runs(dfl, 128 + dpre, 1 << kSameShift);
+            wave_sync_lds();
+            if (lane < dtot) qx[128 + lane] <<= 8;
+            if (lane + 64 < dtot) qx[192 + lane] <<= 8;
+        }
         wave_sync_lds();
     }
     auto run_x = [](int32_t m) { return (m >> 8) & 0x3ff; };
@@ -580,7 +584,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                     wave_sync_lds();
                 }
             }
-        } else if (rowq) {
+        } else if (rowd) {
             // ---- dense single-chunk row: cells without last-dim offsets in the lanes
             // (memoised on equal entries), the runs of flagged cells one per lane from
             // the map
