@@ -158,9 +158,11 @@ hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_
 //     are compacted into a per-wave LDS queue (prefix count from ballots) and
 //     evaluated 64 at a time, one per lane; a chunk holding more than 64 of them
 //     is evaluated in place.
-//   - Rows with outer offsets: every cell is evaluated; a cell whose entry equals
-//     its left neighbour's and has no last-dim offsets reuses its result (same
-//     index, same neighbours).
+//   - Rows with outer offsets: every cell counts.  Cells with equal results share
+//     one evaluation: a stretch of equal entries without last-dim offsets (same
+//     index, same neighbours), or of flagged cells marked equal to their left
+//     neighbour.  For rows of one chunk these runs are listed once per row range,
+//     and a row evaluates each run once, one per lane, times its length.
 // Evaluating a cell: its owner o = T[v], then the owners T[v + delta] over the row
 // offsets and the cell's last-dim offsets; the distinct ones other than o are
 // counted (and those on another node).  Lanes count in registers, waves reduce,
@@ -264,29 +266,6 @@ __device__ __forceinline__ void eval_row_offsets(const int32_t* __restrict__ T, 
             ++cnt;
             icnt += ((ot >> gbits) != onode) ? 1 : 0;
         }
-    }
-}
-
-// The cells x0 .. x0+7 of a row with outer offsets rl[0..nr) that have no last-dim
-// offsets (the others are evaluated separately); a cell whose entry equals the
-// previous evaluated one reuses its result (same index, same neighbours).
-__device__ __forceinline__ void eval_interior(const int32_t* __restrict__ T, const int32_t (&e8)[kCellsPerLane],
-                                              int x0, int L, int32_t base, const int32_t* rl, int nr, int gbits,
-                                              int& cnt, int& icnt) {
-    int32_t ep = -1;
-    int cp = 0, ip = 0;
-#pragma unroll
-    for (int j = 0; j < kCellsPerLane; ++j) {
-        const int32_t e = e8[j];
-        if (x0 + j >= L || ccnt(e) != 0) continue;
-        if (e != ep) {
-            cp = 0;
-            ip = 0;
-            eval_row_offsets(T, base + cval(e), rl, nr, gbits, cp, ip);
-            ep = e;
-        }
-        cnt += cp;
-        icnt += ip;
     }
 }
 
@@ -395,8 +374,8 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // cells depend on the last coordinate only, so their compaction (per-lane
     // flags, prefix over the wave, total) is computed once here.
     const bool one_chunk = L <= kChunk;
-    uint32_t hfl = 0, rfl = 0, dfl = 0;
-    int hpre = 0, htot = 0, rpre = 0, rtot = 0, dpre = 0, dtot = 0;
+    uint32_t hfl = 0, rfl = 0, dfl = 0, ifl = 0;
+    int hpre = 0, htot = 0, rpre = 0, rtot = 0, dpre = 0, dtot = 0, ipre = 0, itot = 0;
     if (one_chunk) {
         int32_t e8[kCellsPerLane];
         load8(CL + kCellsPerLane * lane, e8);
@@ -409,6 +388,18 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
             const bool f = (hfl >> j) & 1u;
             rfl |= (f && !((e8[j] >> kSameShift) & 3) ? 1u : 0u) << j;
             dfl |= (f && !((e8[j] >> kSameShift) & 1) ? 1u : 0u) << j;
+            // interior runs: cells without last-dim offsets, a run per maximal stretch
+            // of equal entries (same index, same neighbours in every row)
+            const int32_t x = kCellsPerLane * lane + j;
+            const int32_t el = j > 0 ? e8[j - 1] : (lane > 0 ? CL[x - 1] : -1);
+            ifl |= (x < L && !f && e8[j] != el ? 1u : 0u) << j;
+        }
+        const int ci = __popc(ifl);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint64_t mi = __ballot((ci >> b) & 1);
+            ipre += lanes_below(mi) << b;
+            itot += __popcll(mi) << b;
         }
         const int c = __popc(rfl), cd = __popc(dfl);
 #pragma unroll
@@ -425,10 +416,11 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // rq_rows * rtot <= 128 run starts, entry idx being run idx % rtot of queued row
     // idx / rtot, each counted times its run length.  qx[0..128) holds that map as
     // (run length << 18) | (x << 8) | row, built once here (staged in qx[128..256));
-    // qx[128..128 + dtot) then holds the runs of rows with outer offsets (rowd: when
-    // there are at most 128 of them; else such rows take the general dense path).
+    // qx[128..128 + dtot) then holds the flagged runs of rows with outer offsets and
+    // qv[128..128 + itot) their interior runs (rowd: when there are at most 128 of
+    // each; else such rows take the general dense path).
     const bool rowq = one_chunk && rtot > 0 && rtot <= 128;
-    const bool rowd = rowq && dtot <= 128;  // rtot <= dtot
+    const bool rowd = rowq && dtot <= 128 && itot <= 128;  // rtot <= dtot
     const int rq_rows = rowq ? 128 / rtot : 0;
     const int rq_cells = rq_rows * rtot;
     int nrow = 0;
@@ -443,6 +435,19 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 qx[pos++] = x | (run << 10);
             }
         };
+        if (dtot <= 128 && itot <= 128) {  // interior runs to qv[128..128 + itot): (len << 18) | (x << 8)
+            uint32_t f = ifl;
+            int pos = 128 + ipre;
+            while (f) {
+                const int j = __builtin_ctz(f);
+                f &= f - 1;
+                const int32_t x = kCellsPerLane * lane + j;
+                const int32_t e = CL[x];
+                int32_t run = 1;
+                while (x + run < L && CL[x + run] == e) ++run;
+                qv[pos++] = (x << 8) | (run << 18);
+            }
+        }
         stage_runs(rfl, 128 + rpre, 3 << kSameShift);
         wave_sync_lds();
         int32_t m0 = 0, m1 = 0;
@@ -585,23 +590,39 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 }
             }
         } else if (rowd) {
-            // ---- dense single-chunk row: cells without last-dim offsets in the lanes
-            // (memoised on equal entries), the runs of flagged cells one per lane from
-            // the map
+            // ---- dense single-chunk row: every cell read and tested (the row's
+            // flagged cells gate their runs); interior runs, then flagged runs, one
+            // per lane from the maps
             int32_t e8[kCellsPerLane];
             load8(CL + kCellsPerLane * lane, e8);
-            eval_interior(T, e8, kCellsPerLane * lane, L, base, rl, nr, gbits, cnt, icnt);
+            int32_t any = 0;
+#pragma unroll
+            for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
+            const bool has_flagged = __ballot((uint32_t)any > (uint32_t)kValMask) != 0ull;
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
                 const int k = lane + 64 * half;
-                if (k < dtot) {
-                    const int32_t m = qx[128 + k];
-                    const int32_t x = run_x(m);
-                    const int32_t e = CL[x];
+                if (k < itot) {
+                    const int32_t m = qv[128 + k];
                     int c = 0, ic = 0;
-                    eval_cell(T, base + cval(e), rl, nr, DL + x * HS, ccnt(e), gbits, c, ic);
+                    eval_row_offsets(T, base + cval(CL[run_x(m)]), rl, nr, gbits, c, ic);
                     cnt += run_len(m) * c;
                     icnt += run_len(m) * ic;
+                }
+            }
+            if (has_flagged) {
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    const int k = lane + 64 * half;
+                    if (k < dtot) {
+                        const int32_t m = qx[128 + k];
+                        const int32_t x = run_x(m);
+                        const int32_t e = CL[x];
+                        int c = 0, ic = 0;
+                        eval_cell(T, base + cval(e), rl, nr, DL + x * HS, ccnt(e), gbits, c, ic);
+                        cnt += run_len(m) * c;
+                        icnt += run_len(m) * ic;
+                    }
                 }
             }
             wave_sync_lds();
