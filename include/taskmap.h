@@ -208,9 +208,10 @@ int tm_proc_map(const tm_candidate* c, int32_t* d_map, int64_t len, void* stream
 
 /* Stencil cost of n candidates (host array) sharing one stencil (host); results to
  * d_out (device, tm_stencil_cost[n]).  All candidates must have launch rank
- * st->lrank.  TM_ENOTSUP if a halo exceeds 4 or a candidate's owner table (its
- * final-space volume) exceeds the per-workgroup LDS budget of 32768 words; the
- * coordinate tables have no such limit (long ones are read from global memory). */
+ * st->lrank.  TM_ENOTSUP if a halo exceeds 4, a candidate's owner table (its
+ * final-space volume) exceeds the per-workgroup LDS budget of 32768 words, or it
+ * has more than 2^30 rows (points / last extent); the coordinate tables have no
+ * size limit (long ones are read from global memory). */
 int tm_eval_stencil_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
                           tm_stencil_cost* d_out, void* stream);
 

@@ -120,7 +120,9 @@ static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
         if (need_lds && d.lds_words > kMaxLdsWords)
             return set_error(TM_ENOTSUP, "candidate %lld: %d table words exceed the LDS budget of %d", (long long)i,
                              d.lds_words, kMaxLdsWords);
-        if (d.rows > INT32_MAX) return set_error(TM_ENOTSUP, "candidate %lld: more than 2^31 rows", (long long)i);
+        // row indices are 32-bit in the kernels, with room to step past the last row
+        if (d.rows > (int64_t(1) << 30))
+            return set_error(TM_ENOTSUP, "candidate %lld: more than 2^30 rows", (long long)i);
         d.arena_off = words;
         words += d.words;
         cp.max_words = std::max(cp.max_words, d.lds_words);

@@ -365,8 +365,8 @@ template <int K, int H, typename XP>
 __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const int32_t* __restrict__ G,
                                            const int32_t* __restrict__ CL, XP DL,
                                            const int32_t (&off)[K], const int32_t (&ext)[K], const int (&hal)[K],
-                                           int64_t ra, int64_t rb, int rs, int L, int gbits, int lane, int32_t* rl,
-                                           int32_t* qv, int32_t* qx, int& cnt, int& icnt) {
+                                           int32_t ra, int32_t rb, int rs, int L, int gbits, int lane, int32_t* rl,
+                                           int32_t* qv, int32_t* qx, int32_t* ob, int& cnt, int& icnt) {
     constexpr int HS = 2 * H;
     constexpr int KO = K > 1 ? K - 1 : 1;
     int qn = 0;  // wave-uniform queue length
@@ -510,15 +510,47 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     load_prefix();
     // entries of dim K-2 for this wave's next 64 rows, one per lane (lane i: the row
     // i steps of rs ahead), so a row takes its entry with a lane read instead of a
-    // memory round trip
+    // memory round trip.  A lane also works out its row's offsets along dim K-2 (the
+    // rule of outer_offsets, neighbour entries loaded together): the first two go to
+    // ob[2i], ob[2i+1], their number to bits 28..31 of the entry (15: more than two,
+    // left to outer_offsets).
     int tb = 0;
     int32_t eb = 0;
     auto load_batch = [&]() {
-        if constexpr (K > 1)
-            eb = G[off[K - 2] + (int32_t)((uint32_t)(q[K - 2] + lane * rs) % (uint32_t)ext[K - 2])];
+        if constexpr (K > 1) {
+            const int32_t* C = G + off[K - 2];
+            const int32_t qi = (int32_t)((uint32_t)(q[K - 2] + lane * rs) % (uint32_t)ext[K - 2]);
+            eb = C[qi];
+            if (ccnt(eb)) {
+                const int32_t ev = cval(eb);
+                int c = 0;
+                int32_t o0 = 0, o1 = 0;
+#pragma unroll
+                for (int dir = 0; dir < 2; ++dir) {
+                    int32_t prev = 0;
+#pragma unroll
+                    for (int s = 1; s <= H; ++s) {
+                        const int32_t xx = dir ? qi + s : qi - s;
+                        if (s <= hal[K - 2] && xx >= 0 && xx < ext[K - 2]) {
+                            const int32_t dv = cval(C[xx]) - ev;
+                            if (dv != 0 && dv != prev) {
+                                if (c == 0) o0 = dv;
+                                if (c == 1) o1 = dv;
+                                ++c;
+                            }
+                            prev = dv;
+                        }
+                    }
+                }
+                ob[2 * lane] = o0;
+                ob[2 * lane + 1] = o1;
+                eb |= (c > 2 ? 15 : c) << 28;
+            }
+            wave_sync_lds();
+        }
     };
     load_batch();
-    for (int64_t r = ra; r < rb; r += rs) {
+    for (int32_t r = ra; r < rb; r += rs) {
         int32_t base = base_o;
         int nr = no;
         if constexpr (K > 1) {
@@ -526,9 +558,19 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 tb = 0;
                 load_batch();
             }
-            const int32_t e = __builtin_amdgcn_readlane(eb, tb++);
+            const int32_t e = __builtin_amdgcn_readlane(eb, tb);
             base += cval(e);
-            if (ccnt(e)) nr = outer_offsets<H>(G + off[K - 2], q[K - 2], ext[K - 2], hal[K - 2], rl, no);
+            if (ccnt(e)) {
+                const int c = (int)((uint32_t)e >> 28);
+                if (c <= 2) {
+                    rl[no] = ob[2 * tb];
+                    rl[no + 1] = ob[2 * tb + 1];
+                    nr = no + c;
+                } else {
+                    nr = outer_offsets<H>(G + off[K - 2], q[K - 2], ext[K - 2], hal[K - 2], rl, no);
+                }
+            }
+            ++tb;
         }
         if (nr == 0 && rowq) {
             // ---- sparse single-chunk row: every cell is read and tested; the row's
@@ -690,6 +732,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 5 
     __shared__ long long s_item;
     __shared__ int32_t s_qv[4][kQueueCap], s_qx[4][kQueueCap];
     __shared__ int32_t s_rl[4][32];
+    __shared__ int32_t s_ob[4][128];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps the row loops scalar
@@ -749,17 +792,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 5 
         }
         // this wave's rows of the item: every fourth, so rows near block boundaries
         // (dense ones cluster there) spread evenly over the waves
-        const int64_t r0 = (item - ifirst) * rpi;
-        const int64_t rb = r0 + rpi < rows ? r0 + rpi : rows;
-        const int64_t ra = r0 + wid;
+        // rows of a candidate fit 31 bits (checked on the host)
+        const int32_t r0 = (int32_t)(item - ifirst) * rpi;
+        const int32_t rb = (int64_t)r0 + rpi < rows ? r0 + rpi : (int32_t)rows;
+        const int32_t ra = r0 + wid;
         int cnt = 0, icnt = 0;
         if (ra < rb) {
             if (dl_lds)  // last dim's table and offset lists in LDS
                 count_rows<K, H>(lds, garena, lds + off[K - 1], lds + dlo, off, ext, hal, ra, rb, 4, L, gbits, lane,
-                                 s_rl[wid], s_qv[wid], s_qx[wid], cnt, icnt);
+                                 s_rl[wid], s_qv[wid], s_qx[wid], s_ob[wid], cnt, icnt);
             else  // long rows: both read from global memory (one code path keeps the kernel small)
                 count_rows<K, H>(lds, garena, garena + off[K - 1], garena + dlo, off, ext, hal, ra, rb, 4, L, gbits,
-                                 lane, s_rl[wid], s_qv[wid], s_qx[wid], cnt, icnt);
+                                 lane, s_rl[wid], s_qv[wid], s_qx[wid], s_ob[wid], cnt, icnt);
         }
         cnt = wave_sum(cnt);
         icnt = wave_sum(icnt);

@@ -158,3 +158,16 @@ def test_transpose_target_matches_oracle():
         tm.tm_transpose_target(full, 0, 1)          # no room for merge
     assert int(tm.tm_transpose_target(W.candidate((8, 8), 1, 4, [merge(0, 1), decompose(0, (2, 2))] + [swap(0, 1)] * 5),
                                       0, 1)["nops"]) == 8
+
+
+def test_row_limit_rejected_before_any_launch():
+    """More than 2^30 rows (points / last extent) is TM_ENOTSUP from host-side
+    validation, before any device memory is touched (a null output is never reached)."""
+    st = W.stencil((1, 1), 8)
+    rows_ok = W.candidate((1 << 30, 1), 1, 2, [merge(0, 1), decompose(0, (2, 1))])
+    rows_bad = W.candidate(((1 << 30) + 1, 1), 1, 2, [merge(0, 1), decompose(0, (2, 1))])
+    L = tm.lib()
+    rc = L.tm_eval_stencil_batch(W.batch([rows_bad]).ctypes.data, 1, st.ctypes.data, None, None)
+    assert rc == tm.TM_ENOTSUP and b"2^30 rows" in L.tm_last_error()
+    rc = L.tm_eval_stencil_batch(W.batch([rows_ok]).ctypes.data, 1, st.ctypes.data, None, None)
+    assert rc == tm.TM_EINVAL  # passes validation, then stops at the null output
