@@ -514,7 +514,6 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // rule of outer_offsets, neighbour entries loaded together): the first two go to
     // ob[2i], ob[2i+1], their number to bits 28..31 of the entry (15: more than two,
     // left to outer_offsets).
-    int tb = 0;
     int32_t eb = 0;
     auto load_batch = [&]() {
         if constexpr (K > 1) {
@@ -549,15 +548,74 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
             wave_sync_lds();
         }
     };
-    load_batch();
-    for (int32_t r = ra; r < rb; r += rs) {
+    // the wave's rows ra, ra + rs, ... below rb, in batches of up to 64
+    const int nrows = (rb - ra + rs - 1) / rs;
+    // sparse single-chunk row: every cell is read and tested; the row's flagged cells
+    // are the precomputed ones, so only its base is queued
+    auto sparse_row = [&](int32_t base) {
+        int32_t e8[kCellsPerLane];
+        load8(CL + kCellsPerLane * lane, e8);
+        int32_t any = 0;
+#pragma unroll
+        for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
+        if (__ballot((uint32_t)any > (uint32_t)kValMask) != 0ull) {
+            qv[nrow] = base;  // every lane writes the same value
+            ++nrow;
+            if (nrow == rq_rows) {
+                wave_sync_lds();
+                drain_rows(rq_cells);
+                wave_sync_lds();
+                nrow = 0;
+            }
+        }
+    };
+    // next row of this wave (row index i of nrows): step the outer coordinates by rs,
+    // carried into the outer dims only while rows remain, so they never leave the domain
+    auto step_row = [&](int i) {
+        if constexpr (K > 1) {
+            q[K - 2] += rs;
+            if (__builtin_expect(q[K - 2] >= ext[K - 2], 0) && i + 1 < nrows) {
+                int32_t c = 0;
+                while (q[K - 2] >= ext[K - 2]) {
+                    q[K - 2] -= ext[K - 2];
+                    ++c;
+                }
+#pragma unroll
+                for (int d = K - 3; d >= 0; --d) {
+                    q[d] += c;
+                    c = 0;
+                    while (q[d] >= ext[d]) {
+                        q[d] -= ext[d];
+                        ++c;
+                    }
+                }
+                load_prefix();
+                wave_sync_lds();
+            }
+        }
+    };
+    for (int done = 0; done < nrows; done += 64) {
+      load_batch();
+      const int nb = nrows - done < 64 ? nrows - done : 64;
+      for (int tb = 0; tb < nb; ++tb) {
+        if constexpr (K > 1) {
+            // consecutive rows without outer offsets (the common case) in a tight loop;
+            // the first row with offsets falls through to the general code below
+            if (rowq && no == 0) {
+                while (tb < nb) {
+                    const int32_t e = __builtin_amdgcn_readlane(eb, tb);
+                    if (ccnt(e)) break;
+                    sparse_row(base_o + cval(e));
+                    step_row(done + tb);
+                    ++tb;
+                    if (no != 0) break;  // a carry reached an outer block boundary
+                }
+                if (tb == nb) break;
+            }
+        }
         int32_t base = base_o;
         int nr = no;
         if constexpr (K > 1) {
-            if (tb == 64) {
-                tb = 0;
-                load_batch();
-            }
             const int32_t e = __builtin_amdgcn_readlane(eb, tb);
             base += cval(e);
             if (ccnt(e)) {
@@ -570,27 +628,11 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                     nr = outer_offsets<H>(G + off[K - 2], q[K - 2], ext[K - 2], hal[K - 2], rl, no);
                 }
             }
-            ++tb;
         }
-        if (nr == 0 && rowq) {
-            // ---- sparse single-chunk row: every cell is read and tested; the row's
-            // flagged cells are the precomputed ones, so only its base is queued
-            int32_t e8[kCellsPerLane];
-            load8(CL + kCellsPerLane * lane, e8);
-            int32_t any = 0;
-#pragma unroll
-            for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
-            if (__ballot((uint32_t)any > (uint32_t)kValMask) != 0ull) {
-                if (lane == 0) qv[nrow] = base;
-                ++nrow;
-                if (nrow == rq_rows) {
-                    wave_sync_lds();
-                    drain_rows(rq_cells);
-                    wave_sync_lds();
-                    nrow = 0;
-                }
-            }
-        } else if (nr == 0) {
+        if (nr == 0) {
+          if (rowq) {
+            sparse_row(base);
+          } else {
             // ---- sparse row: cells with last-dim offsets go to the queue one by one
             for (int xb = 0; xb < L; xb += kChunk) {
                 const int x0 = xb + kCellsPerLane * lane;
@@ -631,6 +673,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                     wave_sync_lds();
                 }
             }
+          }
         } else if (rowd) {
             // ---- dense single-chunk row: every cell read and tested (the row's
             // flagged cells gate their runs); interior runs, then flagged runs, one
@@ -681,30 +724,8 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
             }
             wave_sync_lds();
         }
-        // next row of this wave: step the outer coordinates by rs
-        if constexpr (K > 1) {
-            if (r + rs < rb) {
-                q[K - 2] += rs;
-                if (q[K - 2] >= ext[K - 2]) {
-                    int32_t c = 0;
-                    while (q[K - 2] >= ext[K - 2]) {
-                        q[K - 2] -= ext[K - 2];
-                        ++c;
-                    }
-#pragma unroll
-                    for (int d = K - 3; d >= 0; --d) {
-                        q[d] += c;
-                        c = 0;
-                        while (q[d] >= ext[d]) {
-                            q[d] -= ext[d];
-                            ++c;
-                        }
-                    }
-                    load_prefix();
-                    wave_sync_lds();
-                }
-            }
-        }
+        step_row(done + tb);
+      }
     }
     // drain the queues
     if (nrow > 0) {
