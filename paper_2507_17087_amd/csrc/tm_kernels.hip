@@ -412,7 +412,8 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
         }
     }
     // Row queue (single-chunk rows with 1..128 runs of flagged cells): a row without
-    // outer offsets queues only its base index; a drain of rq_rows rows evaluates
+    // outer offsets queues only its base index (lane i of qrow holds that of queued
+    // row i, fetched in the drain with a lane permute); a drain of rq_rows rows evaluates
     // rq_rows * rtot <= 128 run starts, entry idx being run idx % rtot of queued row
     // idx / rtot, each counted times its run length.  qx[0..128) holds that map as
     // (run length << 18) | (x << 8) | row, built once here (staged in qx[128..256));
@@ -421,7 +422,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // each; else such rows take the general dense path).
     const bool rowq = one_chunk && rtot > 0 && rtot <= 128;
     const bool rowd = rowq && dtot <= 128 && itot <= 128;  // rtot <= dtot
-    const int rq_rows = rowq ? 128 / rtot : 0;
+    const int rq_rows = rowq ? (rtot == 1 ? 64 : 128 / rtot) : 0;  // at most 64: one row base per lane
     const int rq_cells = rq_rows * rtot;
     int nrow = 0;
     if (rowq) {
@@ -472,14 +473,18 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     }
     auto run_x = [](int32_t m) { return (m >> 8) & 0x3ff; };
     auto run_len = [](int32_t m) { return (m >> 18) & 0x3ff; };
+    // queued row bases: lane i holds that of queued row i
+    int32_t qrow = 0;
     auto drain_rows = [&](int ncell) {
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             const int idx = lane + 64 * half;
+            const int32_t m = qx[idx];
+            // every lane takes part in the permute (entries past ncell are not used)
+            const int32_t bq = __builtin_amdgcn_ds_bpermute((m & 63) << 2, qrow);
             if (idx < ncell) {
-                const int32_t m = qx[idx];
                 int c = 0, ic = 0;
-                eval_queued(T, CL, DL, HS, qv[m & 0xff], run_x(m), gbits, c, ic);
+                eval_queued(T, CL, DL, HS, bq, run_x(m), gbits, c, ic);
                 cnt += run_len(m) * c;
                 icnt += run_len(m) * ic;
             }
@@ -559,7 +564,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
 #pragma unroll
         for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
         if (__ballot((uint32_t)any > (uint32_t)kValMask) != 0ull) {
-            qv[nrow] = base;  // every lane writes the same value
+            qrow = lane == nrow ? base : qrow;
             ++nrow;
             if (nrow == rq_rows) {
                 wave_sync_lds();
@@ -606,9 +611,13 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                     const int32_t e = __builtin_amdgcn_readlane(eb, tb);
                     if (ccnt(e)) break;
                     sparse_row(base_o + cval(e));
-                    step_row(done + tb);
                     ++tb;
-                    if (no != 0) break;  // a carry reached an outer block boundary
+                    q[K - 2] += rs;
+                    if (q[K - 2] >= ext[K - 2]) {  // a carry: the general code takes the next row
+                        q[K - 2] -= rs;
+                        step_row(done + tb - 1);
+                        break;
+                    }
                 }
                 if (tb == nb) break;
             }
