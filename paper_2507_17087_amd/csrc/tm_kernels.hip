@@ -557,13 +557,39 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     const int nrows = (rb - ra + rs - 1) / rs;
     // sparse single-chunk row: every cell is read and tested; the row's flagged cells
     // are the precomputed ones, so only its base is queued
+    // Rows with several runs (crowd: 8 or more) are evaluated at once, one run per
+    // lane, and a row with the same base index as the previous one of this wave (the
+    // same outer blocks) has the same result: each lane adds its share again.  Rows
+    // with fewer runs go to the row queue, which fills the lanes from several rows.
+    const bool crowd = rtot >= 8;
+    int32_t mbase = -1, mc = 0, mic = 0;
     auto sparse_row = [&](int32_t base) {
         int32_t e8[kCellsPerLane];
         load8(CL + kCellsPerLane * lane, e8);
         int32_t any = 0;
 #pragma unroll
         for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
-        if (__ballot((uint32_t)any > (uint32_t)kValMask) != 0ull) {
+        if (__ballot((uint32_t)any > (uint32_t)kValMask) == 0ull) return;
+        if (crowd) {
+            if (base != mbase) {
+                mc = 0;
+                mic = 0;
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    const int k = lane + 64 * half;
+                    if (k < rtot) {
+                        const int32_t m = qx[k];  // run k of map row 0
+                        int c = 0, ic = 0;
+                        eval_queued(T, CL, DL, HS, base, run_x(m), gbits, c, ic);
+                        mc += run_len(m) * c;
+                        mic += run_len(m) * ic;
+                    }
+                }
+                mbase = base;
+            }
+            cnt += mc;
+            icnt += mic;
+        } else {
             qrow = lane == nrow ? base : qrow;
             ++nrow;
             if (nrow == rq_rows) {
