@@ -421,11 +421,11 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // qv[128..128 + itot) their interior runs (rowd: when there are at most 128 of
     // each; else such rows take the general dense path).
     const bool rowq = one_chunk && rtot > 0 && rtot <= 128;
-    const bool rowd = rowq && dtot <= 128 && itot <= 128;  // rtot <= dtot
+    const bool rowd = one_chunk && dtot <= 128 && itot <= 128;
     const int rq_rows = rowq ? (rtot == 1 ? 64 : 128 / rtot) : 0;  // at most 64: one row base per lane
     const int rq_cells = rq_rows * rtot;
     int nrow = 0;
-    if (rowq) {
+    if (rowq || rowd) {
         auto stage_runs = [&](uint32_t f, int pos, int32_t bits) {
             while (f) {
                 const int j = __builtin_ctz(f);
@@ -436,7 +436,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 qx[pos++] = x | (run << 10);
             }
         };
-        if (dtot <= 128 && itot <= 128) {  // interior runs to qv[128..128 + itot): (len << 18) | (x << 8)
+        if (rowd) {  // interior runs to qv[128..128 + itot): (len << 18) | (x << 8)
             uint32_t f = ifl;
             int pos = 128 + ipre;
             while (f) {
@@ -449,20 +449,22 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 qv[pos++] = (x << 8) | (run << 18);
             }
         }
-        stage_runs(rfl, 128 + rpre, 3 << kSameShift);
-        wave_sync_lds();
-        int32_t m0 = 0, m1 = 0;
-        if (lane < rq_cells) {
-            const int r = lane / rtot;
-            m0 = (qx[128 + lane - r * rtot] << 8) | r;
+        if (rowq) {
+            stage_runs(rfl, 128 + rpre, 3 << kSameShift);
+            wave_sync_lds();
+            int32_t m0 = 0, m1 = 0;
+            if (lane < rq_cells) {
+                const int r = lane / rtot;
+                m0 = (qx[128 + lane - r * rtot] << 8) | r;
+            }
+            if (lane + 64 < rq_cells) {
+                const int r = (lane + 64) / rtot;
+                m1 = (qx[128 + lane + 64 - r * rtot] << 8) | r;
+            }
+            wave_sync_lds();
+            if (lane < rq_cells) qx[lane] = m0;
+            if (lane + 64 < rq_cells) qx[lane + 64] = m1;
         }
-        if (lane + 64 < rq_cells) {
-            const int r = (lane + 64) / rtot;
-            m1 = (qx[128 + lane + 64 - r * rtot] << 8) | r;
-        }
-        wave_sync_lds();
-        if (lane < rq_cells) qx[lane] = m0;
-        if (lane + 64 < rq_cells) qx[lane + 64] = m1;
         if (rowd) {
             stage_runs(dfl, 128 + dpre, 1 << kSameShift);
             wave_sync_lds();
@@ -502,9 +504,16 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // prefix over dims 0..K-3: base index and offsets, refreshed on carries
     int32_t base_o = 0;
     int no = 0;
+    // the last row with outer offsets from dims 0..K-3 only: its dim K-2 entry, and
+    // each lane's share of its counts (rows with the same entry under the same
+    // prefix have the same index and neighbours)
+    int32_t dkey = -1;
+    bool dflag = false;
+    int dmc = 0, dmic = 0;
     auto load_prefix = [&]() {
         base_o = 0;
         no = 0;
+        dkey = -1;
 #pragma unroll
         for (int d = 0; d < K - 2; ++d) {
             const int32_t e = uniform32(G[off[d] + q[d]]);
@@ -650,8 +659,10 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
         }
         int32_t base = base_o;
         int nr = no;
+        int32_t erow = -1;  // dim K-2 entry of a row whose offsets come from the prefix only
         if constexpr (K > 1) {
             const int32_t e = __builtin_amdgcn_readlane(eb, tb);
+            if (ccnt(e) == 0) erow = e;
             base += cval(e);
             if (ccnt(e)) {
                 const int c = (int)((uint32_t)e >> 28);
@@ -709,53 +720,69 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
                 }
             }
           }
-        } else if (rowd) {
-            // ---- dense single-chunk row: every cell read and tested (the row's
-            // flagged cells gate their runs); interior runs, then flagged runs, one
-            // per lane from the maps
+        } else {
+            // ---- rows with outer offsets: every cell counts.  Every cell is read and
+            // tested (whether the row holds flagged cells, which gates their runs and is
+            // part of the memo's check); a row repeating the remembered entry under the
+            // same prefix adds the remembered shares.
             int32_t e8[kCellsPerLane];
             load8(CL + kCellsPerLane * lane, e8);
             int32_t any = 0;
 #pragma unroll
             for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
             const bool has_flagged = __ballot((uint32_t)any > (uint32_t)kValMask) != 0ull;
+            if (erow >= 0 && erow == dkey && has_flagged == dflag) {
+                cnt += dmc;
+                icnt += dmic;
+            } else {
+                int rc = 0, ric = 0;
+                if (rowd) {
+                    // single chunk: interior runs, then flagged runs, one per lane from the maps
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                const int k = lane + 64 * half;
-                if (k < itot) {
-                    const int32_t m = qv[128 + k];
-                    int c = 0, ic = 0;
-                    eval_row_offsets(T, base + cval(CL[run_x(m)]), rl, nr, gbits, c, ic);
-                    cnt += run_len(m) * c;
-                    icnt += run_len(m) * ic;
-                }
-            }
-            if (has_flagged) {
+                    for (int half = 0; half < 2; ++half) {
+                        const int k = lane + 64 * half;
+                        if (k < itot) {
+                            const int32_t m = qv[128 + k];
+                            int c = 0, ic = 0;
+                            eval_row_offsets(T, base + cval(CL[run_x(m)]), rl, nr, gbits, c, ic);
+                            rc += run_len(m) * c;
+                            ric += run_len(m) * ic;
+                        }
+                    }
+                    if (has_flagged) {
 #pragma unroll
-                for (int half = 0; half < 2; ++half) {
-                    const int k = lane + 64 * half;
-                    if (k < dtot) {
-                        const int32_t m = qx[128 + k];
-                        const int32_t x = run_x(m);
-                        const int32_t e = CL[x];
-                        int c = 0, ic = 0;
-                        eval_cell(T, base + cval(e), rl, nr, DL + x * HS, ccnt(e), gbits, c, ic);
-                        cnt += run_len(m) * c;
-                        icnt += run_len(m) * ic;
+                        for (int half = 0; half < 2; ++half) {
+                            const int k = lane + 64 * half;
+                            if (k < dtot) {
+                                const int32_t m = qx[128 + k];
+                                const int32_t x = run_x(m);
+                                const int32_t e = CL[x];
+                                int c = 0, ic = 0;
+                                eval_cell(T, base + cval(e), rl, nr, DL + x * HS, ccnt(e), gbits, c, ic);
+                                rc += run_len(m) * c;
+                                ric += run_len(m) * ic;
+                            }
+                        }
+                    }
+                } else {
+                    // every chunk, eight cells per lane (memoised on equal entries)
+                    for (int xb = 0; xb < L; xb += kChunk) {
+                        const int x0 = xb + kCellsPerLane * lane;
+                        if (x0 >= L) continue;
+                        int32_t f8[kCellsPerLane];
+                        load8(CL + x0, f8);
+                        eval_group<(H > 1 ? 1 << kSameShift : 0)>(T, DL, HS, f8, x0, L, base, rl, nr, gbits, false,
+                                                                   rc, ric);
                     }
                 }
-            }
-            wave_sync_lds();
-        } else {
-            // ---- dense row: every cell sees the outer neighbours of the row
-            wave_sync_lds();
-            for (int xb = 0; xb < L; xb += kChunk) {
-                const int x0 = xb + kCellsPerLane * lane;
-                if (x0 >= L) continue;
-                int32_t e8[kCellsPerLane];
-                load8(CL + x0, e8);
-                eval_group<(H > 1 ? 1 << kSameShift : 0)>(T, DL, HS, e8, x0, L, base, rl, nr, gbits, false,
-                                                           cnt, icnt);
+                cnt += rc;
+                icnt += ric;
+                if (erow >= 0) {
+                    dkey = erow;
+                    dflag = has_flagged;
+                    dmc = rc;
+                    dmic = ric;
+                }
             }
             wave_sync_lds();
         }
