@@ -421,6 +421,7 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     // qv[128..128 + itot) their interior runs (rowd: when there are at most 128 of
     // each; else such rows take the general dense path).
     const bool rowq = one_chunk && rtot > 0 && rtot <= 128;
+    const bool fastq = one_chunk && rtot <= 128;  // rows without outer offsets in the tight loop (rowq, or no runs)
     const bool rowd = one_chunk && dtot <= 128 && itot <= 128;
     const int rq_rows = rowq ? (rtot == 1 ? 64 : 128 / rtot) : 0;  // at most 64: one row base per lane
     const int rq_cells = rq_rows * rtot;
@@ -639,9 +640,10 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
       const int nb = nrows - done < 64 ? nrows - done : 64;
       for (int tb = 0; tb < nb; ++tb) {
         if constexpr (K > 1) {
-            // consecutive rows without outer offsets (the common case) in a tight loop;
-            // the first row with offsets falls through to the general code below
-            if (rowq && no == 0) {
+            // consecutive rows without outer offsets (the common case) in a tight loop
+            // (with no runs, a row only has its cells read and tested); the first row
+            // with offsets falls through to the general code below
+            if (fastq && no == 0) {
                 while (tb < nb) {
                     const int32_t e = __builtin_amdgcn_readlane(eb, tb);
                     if (ccnt(e)) break;
