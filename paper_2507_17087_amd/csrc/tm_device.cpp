@@ -337,7 +337,7 @@ extern "C" int tm_eval_redistribution_batch(const tm_candidate* src, const tm_ca
     for (int64_t i = 0; i < n; ++i) {
         DevCand& a = cp.cands[(size_t)i];
         const DevCand& b = cp.cands[(size_t)(n + i)];
-        const int64_t w = up4(a.lds_words) + b.lds_words;
+        const int64_t w = up4(a.lds_words) + up4(b.lds_words) + kRedistRuns;
         if (w > kMaxLdsWords)
             return set_error(TM_ENOTSUP, "pair %lld: %lld table words exceed the LDS budget of %d", (long long)i,
                              (long long)w, kMaxLdsWords);

@@ -66,6 +66,10 @@ constexpr int kSameShift = 28;
 // so in a row without outer offsets both count the same foreign owners.
 constexpr int kMirrorShift = 29;
 constexpr int32_t kMaxLdsWords = 32768;
+// Redistribution: LDS words for the joint runs of a pair's last dim (rows of at most
+// kRedistMaxL cells), staged after the pair's two tables.
+constexpr int32_t kRedistRuns = 512;
+constexpr int32_t kRedistMaxL = 4096;
 constexpr int kMaxHalo = 4;
 
 int set_error(int code, const char* fmt, ...);

@@ -1130,11 +1130,17 @@ hipError_t launch_chain_table(const DevCand* cand, const int32_t* arena, int32_t
 // Pairs (a, b) of mappings of one launch domain: candidates [0, npair) of the batch
 // are the a's, [npair, 2 npair) the b's, and a's item_first / rows_per_item give the
 // pair's work items (blocks of rows).  A workgroup stages both owner tables and
-// last-dim coordinate tables of its item's pair in LDS when the pair changes; each
-// wave takes every fourth row of the item, works out the row's base index under
-// both mappings from the outer tables, and compares the two owner keys of four
-// consecutive cells per lane (a cell whose two entries equal the previous cell's has
-// its result).  Counts go to the pair's totals with one atomic per wave and item.
+// last-dim coordinate tables of its item's pair in LDS when the pair changes, and the
+// pair's joint runs along the last dim: maximal stretches of cells whose entries in
+// both tables equal their left neighbour's (same owners in every row).  Each wave
+// takes every fourth row of the item and works out the row's base index under both
+// mappings from the outer tables.  Every cell's two entries are read (a row whose
+// entries are all zero has one owner pair), then the runs are evaluated one per lane,
+// times their length; a row with the same two base indices as the previous one of the
+// wave (the same outer blocks in both) reuses each lane's share.  Rows longer than
+// kRedistMaxL cells, or with more than kRedistRuns runs, compare the two owner keys
+// of four consecutive cells per lane instead.  Counts go to the pair's totals with
+// one atomic per wave and item.
 
 __global__ void k_redist_zero(tm_redist_cost* __restrict__ out, int64_t npair) {
     int64_t* o = reinterpret_cast<int64_t*>(out);
@@ -1153,13 +1159,18 @@ __global__ __launch_bounds__(256) void k_redist(const DevCand* __restrict__ cand
                                                 const int32_t* __restrict__ arena, int64_t total_items,
                                                 tm_redist_cost* __restrict__ out) {
     extern __shared__ __attribute__((aligned(16))) int32_t lds[];  // 16-byte aligned: ds_read_b128 of the tables
+    __shared__ int32_t s_scan[4];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     int64_t cur = -1, rows = 0, ifirst = 0;
-    int32_t K = 1, L = 0, gbits = 0, rpi = 1, wa = 0;
+    int32_t K = 1, L = 0, gbits = 0, rpi = 1, wa = 0, wb = 0, nrun = 0;
     int32_t offa[TM_MAX_LRANK] = {0, 0, 0, 0}, offb[TM_MAX_LRANK] = {0, 0, 0, 0}, ext[TM_MAX_LRANK] = {1, 1, 1, 1};
     const int32_t *GA = arena, *GB = arena, *CA = lds, *CB = lds;
-    for (int64_t item = blockIdx.x; item < total_items; item += gridDim.x) {
+    // a contiguous range of items per workgroup: consecutive items share a pair, so
+    // its tables and runs are staged once per range rather than once per item
+    const int64_t per = (total_items + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * per, i1 = i0 + per < total_items ? i0 + per : total_items;
+    for (int64_t item = i0; item < i1; ++item) {
         int64_t lo = 0, hi = npair - 1;
         while (lo < hi) {
             const int64_t mid = (lo + hi + 1) >> 1;
@@ -1173,6 +1184,7 @@ __global__ __launch_bounds__(256) void k_redist(const DevCand* __restrict__ cand
             const DevCand* b = &cands[npair + lo];
             const int32_t na = uniform32(a->lds_words), nb = uniform32(b->lds_words);
             wa = (na + 3) & ~3;
+            wb = (nb + 3) & ~3;
             GA = arena + uniform64(a->arena_off);
             GB = arena + uniform64(b->arena_off);
             for (int i = tid; i < na; i += 256) lds[i] = GA[i];
@@ -1192,21 +1204,109 @@ __global__ __launch_bounds__(256) void k_redist(const DevCand* __restrict__ cand
             CB = uniform32(b->cl_lds) ? lds + wa + offb[K - 1] : GB + offb[K - 1];
             cur = lo;
             __syncthreads();
+            // joint runs of the last dim: each thread counts the run starts of its
+            // stretch of cells, a scan places them, then each writes (length << 16) | x
+            int32_t* runs = lds + wa + wb;
+            nrun = 0;
+            if (L <= kRedistMaxL) {
+                const int seg = (L + 255) / 256;
+                const int x0 = tid * seg, x1 = x0 + seg < L ? x0 + seg : L;
+                int c = 0;
+                for (int x = x0; x < x1; ++x) c += (x == 0 || CA[x] != CA[x - 1] || CB[x] != CB[x - 1]) ? 1 : 0;
+                // exclusive scan over the workgroup: within each wave by shuffles, then
+                // the four wave totals
+                int v = c;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_up(v, o, 64);
+                    if (lane >= o) v += t;
+                }
+                if (lane == 63) s_scan[wid] = v;
+                __syncthreads();
+                int wbase = 0;
+                for (int w = 0; w < wid; ++w) wbase += s_scan[w];
+                const int total = s_scan[0] + s_scan[1] + s_scan[2] + s_scan[3];
+                __syncthreads();
+                if (total <= kRedistRuns) {
+                    int pos = wbase + v - c;
+                    for (int x = x0; x < x1; ++x) {
+                        if (x == 0 || CA[x] != CA[x - 1] || CB[x] != CB[x - 1]) {
+                            int y = x + 1;
+                            while (y < L && CA[y] == CA[x] && CB[y] == CB[x]) ++y;
+                            runs[pos++] = x | ((y - x) << 16);
+                        }
+                    }
+                    nrun = total;
+                }
+                __syncthreads();
+            }
+            nrun = uniform32(nrun);
         }
         const int32_t* TA = lds;
         const int32_t* TB = lds + wa;
+        const int32_t* runs = lds + wa + wb;
         const int64_t r0 = (item - ifirst) * rpi;
         const int64_t rb = r0 + rpi < rows ? r0 + rpi : rows;
         uint32_t moved = 0, inter = 0;
+        int32_t mba = -1, mbb = -1;
+        uint32_t mm = 0, mi = 0;
+        // base indices of the wave's next 64 rows, one row per lane (loads in parallel)
+        int32_t bab = 0, bbb = 0;
+        int t = 64;
         for (int64_t r = r0 + wid; r < rb; r += 4) {
-            int32_t ba = 0, bb = 0;
-            uint32_t rr = (uint32_t)r;  // rows < 2^31 (checked on the host)
-            for (int d = K - 2; d >= 0; --d) {
-                const uint32_t e = (uint32_t)ext[d];
-                const int32_t q = (int32_t)(rr % e);
-                rr /= e;
-                ba += GA[offa[d] + q] & kValMask;
-                bb += GB[offb[d] + q] & kValMask;
+            if (t == 64) {
+                t = 0;
+                const int64_t ri = r + 4 * (int64_t)lane;
+                bab = 0;
+                bbb = 0;
+                if (ri < rb) {
+                    uint32_t rr = (uint32_t)ri;  // rows <= 2^30 (checked on the host)
+                    for (int d = K - 2; d >= 0; --d) {
+                        const uint32_t e = (uint32_t)ext[d];
+                        const int32_t q = (int32_t)(rr % e);
+                        rr /= e;
+                        bab += GA[offa[d] + q] & kValMask;
+                        bbb += GB[offb[d] + q] & kValMask;
+                    }
+                }
+            }
+            const int32_t ba = __builtin_amdgcn_readlane(bab, t);
+            const int32_t bb = __builtin_amdgcn_readlane(bbb, t);
+            ++t;
+            if (nrun > 0) {
+                // every cell's two entries read; all zero: one owner pair for the row
+                int32_t any = 0;
+                for (int x = 4 * lane; x < L; x += 256) {
+                    const i32x4 ea = *reinterpret_cast<const i32x4*>(CA + x);
+                    const i32x4 eb = *reinterpret_cast<const i32x4*>(CB + x);
+                    any |= ea.x | ea.y | ea.z | ea.w | eb.x | eb.y | eb.z | eb.w;  // zero past L
+                }
+                if (__ballot(any != 0) == 0ull) {
+                    const int32_t ka = TA[ba], kb = TB[bb];
+                    if (lane == 0) {
+                        moved += ka != kb ? (uint32_t)L : 0u;
+                        inter += (ka >> gbits) != (kb >> gbits) ? (uint32_t)L : 0u;
+                    }
+                    continue;
+                }
+                if (ba != mba || bb != mbb) {
+                    mm = 0;
+                    mi = 0;
+                    for (int k = lane; k < nrun; k += 64) {
+                        const int32_t run = runs[k];
+                        const int32_t x = run & 0xffff;
+                        const uint32_t len = (uint32_t)run >> 16;
+                        const int32_t ka = TA[ba + (CA[x] & kValMask)];
+                        const int32_t kb = TB[bb + (CB[x] & kValMask)];
+                        mm += ka != kb ? len : 0u;
+                        mi += (ka >> gbits) != (kb >> gbits) ? len : 0u;
+                    }
+                    mba = ba;
+                    mbb = bb;
+                }
+                moved += mm;
+                inter += mi;
+                continue;
             }
             int32_t pa = -1, pb = -1;
             uint32_t pm = 0, pi = 0;
