@@ -146,23 +146,33 @@ hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_
 // of one candidate.  A workgroup takes items from a global atomic counter (the
 // next one is requested while the current one runs), stages the candidate's owner
 // table and, when they fit, the last dim's coordinate table and offset lists in LDS
-// when the candidate changes (the outer dims' tables are read from global memory,
-// once per row), and gives each wave every fourth row of the item, stepping the
-// outer coordinates without divisions.  Every cell is examined: a
-// lane reads the coordinate entries of eight consecutive cells with two LDS loads.
+// when the candidate changes (the outer dims' tables are read from global memory),
+// and gives each wave every fourth row of the item, in batches of 64 rows whose
+// fast outer entries and offsets one lane each works out at once, stepping the
+// outer coordinates without divisions.  Every cell of every row is read and
+// tested: a lane reads the coordinate entries of eight consecutive cells with two
+// LDS loads, and the test (does the row hold cells with last-dim offsets) gates
+// what follows.
 //   - A row's outer coordinates fix its base index and the distinct non-zero
 //     offsets to its outer neighbours, computed from the coordinate tables when
 //     the row lies within a halo of a block boundary of an outer dim.
 //   - Rows without outer offsets: a cell can have a foreign neighbour only along
-//     the last dim, i.e. when its entry's offset count is non-zero.  Such cells
-//     are compacted into a per-wave LDS queue (prefix count from ballots) and
-//     evaluated 64 at a time, one per lane; a chunk holding more than 64 of them
-//     is evaluated in place.
+//     the last dim, i.e. when its entry's offset count is non-zero.  In rows of
+//     one chunk such cells form runs with equal results (listed once per row
+//     range); consecutive such rows run in a tight loop.  With 8 or more runs a row
+//     evaluates its runs at once, one per lane, and a row with the same base index
+//     as the previous one reuses each lane's share; with fewer, rows queue their
+//     base index and a drain evaluates the runs of several rows together.  Longer
+//     rows compact their flagged cells into a per-wave LDS queue (prefix count from
+//     ballots), evaluated 64 at a time; a chunk holding more than 64 of them is
+//     evaluated in place.
 //   - Rows with outer offsets: every cell counts.  Cells with equal results share
 //     one evaluation: a stretch of equal entries without last-dim offsets (same
 //     index, same neighbours), or of flagged cells marked equal to their left
 //     neighbour.  For rows of one chunk these runs are listed once per row range,
-//     and a row evaluates each run once, one per lane, times its length.
+//     and a row evaluates each run once, one per lane, times its length; a row whose
+//     offsets come from the slower outer dims only reuses the previous such row's
+//     shares while its fast outer entry and the slower outer coordinates repeat.
 // Evaluating a cell: its owner o = T[v], then the owners T[v + delta] over the row
 // offsets and the cell's last-dim offsets; the distinct ones other than o are
 // counted (and those on another node).  Lanes count in registers, waves reduce,

@@ -486,3 +486,41 @@ def test_limits(tm):
     ext, f = (2048, 2048, 1024), (4, 8, 4)
     cells = sum(2 * 2 * (f[m] - 1) * (ext[0] * ext[1] * ext[2] // ext[m]) for m in range(3))
     assert got[0] == cells and got[2] == 8 * cells and 0 < got[1] < got[0]
+
+
+def test_row_reuse_paths(tm):
+    """Candidates aimed at the counting kernel's row paths, bit-exact against the
+    oracle: rows without outer offsets with 8 or more runs (evaluated at once, reused
+    while the base repeats) and with fewer (row queue); rows with outer offsets from
+    the slower outer dims only (reused while the fast entry repeats) and from the fast
+    outer dim; rows without runs; rows of several chunks; cyclic last dims; launch
+    rank 4; halos 1 to 4 (per dim); node-level counts for the same candidates."""
+    say("row reuse paths")
+    P = 16
+    cases = []
+    for ext, F in [((24, 40, 512), (1, 1, 16)), ((24, 40, 512), (1, 2, 8)), ((24, 40, 512), (2, 2, 4)),
+                   ((24, 40, 512), (16, 1, 1)), ((24, 40, 512), (4, 4, 1)), ((24, 40, 512), (1, 16, 1)),
+                   ((9, 13, 509), (2, 1, 8)), ((6, 10, 1300), (2, 2, 4)), ((5, 7, 520), (1, 1, 16))]:
+        for nodes, g in ((4, 4), (16, 1), (1, 16)):
+            cases.append(W.candidate(ext, nodes, g, [merge(0, 1), decompose(0, F)]))
+    cyc = W.candidate((24, 40, 512), 4, 4, [merge(0, 1), decompose(0, (2, 1, 8))],
+                      proj=[(0, W.BLOCK), (1, W.BLOCK), (2, W.CYCLIC)])
+    cases.append(cyc)
+    wide = W.candidate((24, 40, 512), 8, 8, [merge(0, 1), decompose(0, (1, 1, 64))])
+    cases.append(wide)
+    cands = W.batch(cases)
+    for halo in [(1, 1, 1), (2, 2, 2), (3, 1, 4), (4, 4, 2)]:
+        st = W.stencil(halo, 8)
+        exp = oracle.stencil_cost_batch(cands, st)
+        assert (gpu_costs(tm, cands, st) == exp).all(), halo
+    st = W.stencil((2, 3, 2), 8)
+    exp = oracle.stencil_node_cost_batch(cands, st)
+    import torch
+    got = tm.tm_eval_stencil_node_batch(cands, st)
+    torch.cuda.synchronize()
+    assert (got.cpu().numpy() == exp).all()
+    # launch rank 4: three outer dims (two in the slower prefix)
+    r4 = W.batch([W.candidate((4, 6, 10, 300), 4, 4, [merge(0, 1), decompose(0, F)])
+                  for F in [(2, 1, 2, 4), (1, 4, 1, 4), (4, 1, 1, 4), (1, 1, 1, 16)]])
+    st4 = W.stencil((2, 1, 3, 2), 8)
+    assert (gpu_costs(tm, r4, st4) == oracle.stencil_cost_batch(r4, st4)).all()
