@@ -19,9 +19,10 @@ namespace tmk {
     } while (0)
 
 constexpr int64_t kDefaultCellsPerItem = 1 << 17;
-// Map launches: workgroups per CU (a wave writes every (grid * 4)-th row).  32 keeps
-// more rows in flight than the 8 the occupancy allows at once: 5.15 -> 5.40 TB/s on a
-// 512^3 map, while many more workgroups pay for staging their tables each.
+// Map launches: workgroups per CU (a wave writes every (grid * 4)-th row).  32 gives
+// smaller work units than the 8 that are resident at once (about 8 rows per wave on a
+// 512^3 map) and a better-balanced end: 5.15 -> 5.40 TB/s; many more workgroups pay
+// for staging their tables each (256 per CU: 4.05 TB/s).
 constexpr int kMapWgPerCu = 32;
 
 // ------------------------------------------------------------------ batch compilation
