@@ -814,11 +814,12 @@ __device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const 
     }
 }
 
-// Waves per SIMD: six for H >= 2 (fits 80 VGPRs without spilling); five for H = 1,
-// whose instantiations want ~119 VGPRs -- the few bytes they then spill cost less
-// than the lost occupancy (measured: 13 % faster than four waves, six and eight slower).
+// Waves per SIMD: seven for H >= 2 and six for H = 1 (measured on the 512^3 halo-2
+// workload and the random halo-1 batch: 5 / 6 / 7 / 8 waves 4.47 / 4.02 / 3.89 /
+// 3.94 ms at H = 2; 4 / 5 / 6 / 7 waves 19.4 / 16.5 / 15.1 / 15.4 ms at H = 1); the
+// compiler then spills a few registers to scratch, which these times include.
 template <int K, int H>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 5 : 6))) void k_count(const DevHeader* __restrict__ hdr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 6 : 7))) void k_count(const DevHeader* __restrict__ hdr,
                                                const DevCand* __restrict__ cands,
                                                const int32_t* __restrict__ arena,
                                                unsigned long long* __restrict__ counter,
