@@ -335,7 +335,6 @@ extern "C" int tm_eval_redistribution_batch(const tm_candidate* src, const tm_ca
     int rc = compile_batch(both.data(), 2 * n, nullptr, 0, true, cp);
     if (rc != TM_OK) return rc;
     if (n == 0) return TM_OK;
-    if (!d_out) return set_error(TM_EINVAL, "null output");
     // work items over the pairs (the first mapping's rows); both tables in LDS
     int64_t items = 0;
     int32_t lds_words = 0;
@@ -352,6 +351,7 @@ extern "C" int tm_eval_redistribution_batch(const tm_candidate* src, const tm_ca
         a.item_first = items;
         items += (a.rows + rpi - 1) / rpi;
     }
+    if (!d_out) return set_error(TM_EINVAL, "null output");
     DeviceBatch db;
     rc = upload_batch(cp, db, s);
     if (rc == TM_OK) {
