@@ -277,7 +277,7 @@ int tm_parse_index_task_map(const char* source, const char* task, int32_t lrank,
  * rank, halo, table size) class: reset -> table build -> one persistent counting
  * launch over a work queue of (candidate, row block) items -> bytes + selection.
  * d_out: tm_stencil_cost[n]; d_best: int64[1] (may be NULL).  Work items hold
- * cells_per_item cells (0 = autotuned default). */
+ * cells_per_item cells (0 = autotuned default; at most 2^26, else TM_EINVAL). */
 typedef struct tm_plan tm_plan;
 
 int tm_plan_create(int64_t max_cands, int64_t max_words, tm_plan** out);
@@ -300,7 +300,8 @@ int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cells_per_item
 /* Sets the launch configuration of the loaded batch without timing anything: work
  * items of cells_per_item cells (0 = default) and at most wg_per_cu counting
  * workgroups per CU (0 = as many as occupancy allows) -- e.g. a configuration found
- * by tm_plan_autotune earlier.  TM_EINVAL on negative values. */
+ * by tm_plan_autotune earlier.  TM_EINVAL on negative values or cells_per_item above
+ * 2^26. */
 int tm_plan_set_launch(tm_plan* p, int64_t cells_per_item, int32_t wg_per_cu, void* stream);
 /* Counts of the loaded batch: candidates, work items, total points (host, nullable). */
 int tm_plan_info(const tm_plan* p, int64_t* n, int64_t* items, int64_t* points);

@@ -19,6 +19,9 @@ namespace tmk {
     } while (0)
 
 constexpr int64_t kDefaultCellsPerItem = 1 << 17;
+// Largest work item: a lane's 32-bit counts over one item stay below 2^31 (at most 32
+// foreign owners per cell, a quarter of the item's rows per wave).
+constexpr int64_t kMaxCellsPerItem = int64_t(1) << 26;
 // Map launches: workgroups per CU (a wave writes every (grid * 4)-th row).  32 gives
 // smaller work units than the 8 that are resident at once (about 8 rows per wave on a
 // 512^3 map) and a better-balanced end: 5.15 -> 5.40 TB/s; many more workgroups pay
@@ -637,7 +640,8 @@ extern "C" int tm_plan_load(tm_plan* p, const tm_candidate* c, int64_t n, const 
                             int64_t cells_per_item, void* stream) {
     if (!p) return set_error(TM_EINVAL, "null plan");
     if (!st) return set_error(TM_EINVAL, "null stencil");
-    if (cells_per_item < 0) return set_error(TM_EINVAL, "cells_per_item %lld", (long long)cells_per_item);
+    if (cells_per_item < 0 || cells_per_item > kMaxCellsPerItem)
+        return set_error(TM_EINVAL, "cells_per_item %lld (at most 2^26)", (long long)cells_per_item);
     hipStream_t s = (hipStream_t)stream;
     Compiled cp;
     int rc = compile_batch(c, n, st, cells_per_item > 0 ? cells_per_item : p->cells_per_item, true, cp);
@@ -777,8 +781,9 @@ extern "C" int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cel
 
 extern "C" int tm_plan_set_launch(tm_plan* p, int64_t cells_per_item, int32_t wg_per_cu, void* stream) {
     if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
-    if (cells_per_item < 0 || wg_per_cu < 0)
-        return set_error(TM_EINVAL, "cells_per_item %lld, wg_per_cu %d", (long long)cells_per_item, wg_per_cu);
+    if (cells_per_item < 0 || cells_per_item > kMaxCellsPerItem || wg_per_cu < 0)
+        return set_error(TM_EINVAL, "cells_per_item %lld (at most 2^26), wg_per_cu %d", (long long)cells_per_item,
+                         wg_per_cu);
     p->cells_per_item = cells_per_item;
     p->wg_per_cu = wg_per_cu;
     if (p->cp.hdr.n == 0) return TM_OK;

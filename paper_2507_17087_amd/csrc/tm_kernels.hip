@@ -35,10 +35,13 @@ __device__ __forceinline__ int32_t uniform32(int32_t x) {
     return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
 }
 
-__device__ __forceinline__ int wave_sum(int v) {
+// Sum over the wave of non-negative per-lane counts, in 64 bits (a wave's counts for
+// one work item can exceed 2^31 on very long rows).
+__device__ __forceinline__ unsigned long long wave_sum64(int v) {
+    unsigned long long s = (unsigned long long)(unsigned)v;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
 }
 
 // ------------------------------------------------------------------ table build
@@ -901,11 +904,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 6 
                 count_rows<K, H>(lds, garena, garena + off[K - 1], garena + dlo, off, ext, hal, ra, rb, 4, L, gbits,
                                  lane, s_rl[wid], s_qv[wid], s_qx[wid], s_ob[wid], cnt, icnt);
         }
-        cnt = wave_sum(cnt);
-        icnt = wave_sum(icnt);
-        if (lane == 0 && (cnt | icnt)) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].ghost_cells), (unsigned long long)cnt);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].inter_cells), (unsigned long long)icnt);
+        const unsigned long long c64 = wave_sum64(cnt), i64 = wave_sum64(icnt);
+        if (lane == 0 && (c64 | i64)) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].ghost_cells), c64);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].inter_cells), i64);
         }
     }
 }

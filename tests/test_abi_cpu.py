@@ -192,3 +192,4 @@ def test_redistribution_validation_before_any_launch():
     # a valid pair passes validation and stops at the null output
     assert L.tm_eval_redistribution_batch(a.ctypes.data, a.ctypes.data, 1, 8, None, None) == tm.TM_EINVAL
     assert b"null output" in L.tm_last_error()
+

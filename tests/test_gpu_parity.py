@@ -524,3 +524,25 @@ def test_row_reuse_paths(tm):
                   for F in [(2, 1, 2, 4), (1, 4, 1, 4), (4, 1, 1, 4), (1, 1, 1, 16)]])
     st4 = W.stencil((2, 1, 3, 2), 8)
     assert (gpu_costs(tm, r4, st4) == oracle.stencil_cost_batch(r4, st4)).all()
+
+
+def test_cells_per_item_limit(tm):
+    """Work items of more than 2^26 cells are rejected before anything runs (the
+    counting kernel's 32-bit per-lane counts stay below 2^31 within one item); 2^26
+    itself is accepted and gives the same costs."""
+    import torch
+    say("cells per item limit")
+    cands = W.batch([W.candidate((64, 40, 96), 2, 4, [merge(0, 1), decompose(0, (2, 2, 2))])])
+    st = W.stencil((2, 1, 2), 8)
+    plan = tm.Plan(4, 1)
+    with pytest.raises(tm.TaskmapError) as e:
+        plan.load(cands, st, cells_per_item=(1 << 26) + 1)
+    assert e.value.code == tm.TM_EINVAL
+    plan.load(cands, st, cells_per_item=1 << 26)
+    out = torch.empty((1, 4), dtype=torch.int64, device="cuda")
+    plan.run(out)
+    torch.cuda.synchronize()
+    assert (out.cpu().numpy() == oracle.stencil_cost_batch(cands, st)).all()
+    with pytest.raises(tm.TaskmapError):
+        plan.set_launch((1 << 26) + 1, 0)
+    plan.close()
