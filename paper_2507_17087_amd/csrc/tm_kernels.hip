@@ -8,13 +8,16 @@
 // that owner identity and node are both one integer operation away; and (2) one
 // coordinate table per launch dim d: C_d[x] = sum over final dims j projected
 // from d of a_j(x) * stride_j (block: floor(x*s_j/l_d), cyclic: x mod s_j), with
-// bit 31 set when a star neighbour within the halo along d has a different value.
+// the number of distinct non-zero index offsets to the star neighbours within the
+// halo along d in bits 24..27 (and, for the last dim, the offsets themselves in a
+// list beside it and the flags described in tm_internal.h in bits 28..29).
 // The linear final coordinate of point q is then v(q) = sum_d C_d[q_d] and its
 // owner is T[v(q)]: the chain is evaluated once per coordinate, not per point.
 //
 // Kernels: table build; processor map (streaming int32 writes); stencil counting
 // (persistent, work queue over (candidate, row block) items, tables in LDS); bytes
-// and selection; matmul tile bitmaps.  All arithmetic is exact integer.
+// and selection; matmul tile bitmaps; redistribution counting.  All arithmetic is
+// exact integer.
 #include <hip/hip_runtime.h>
 
 #include "tm_internal.h"
@@ -181,8 +184,11 @@ hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_
 // counted (and those on another node).  Lanes count in registers, waves reduce,
 // and one 64-bit atomic per wave and item adds to the candidate's totals.
 
-constexpr int kQueueCap = 256;  // drained 128 at a time (two per lane); a push adds <= 64; the row
-                                 // queue's run list is staged in [128, 256)
+// Per-wave LDS arrays of kQueueCap words, qv and qx: the queue of flagged cells of
+// long rows (drained 128 at a time, two per lane; a push adds <= 64), or, for rows of
+// one chunk, the run maps (qx[0..128): runs of rows without outer offsets, qx[128..):
+// flagged runs and qv[128..): interior runs of rows with them).
+constexpr int kQueueCap = 256;
 constexpr int kCellsPerLane = 8;
 constexpr int kChunk = 64 * kCellsPerLane;
 
