@@ -480,6 +480,8 @@ def main():
     count = np.mean([evs[k][0].elapsed_time(evs[k][1]) for k in range(args.steps)])
     sel = np.mean([evs[k][1].elapsed_time(evs[k][2]) for k in range(args.steps)])
     mapk = np.mean([evs[k][2].elapsed_time(evs[k][3]) for k in range(args.steps)])
+    # each step's GPU time (events around the whole replay): median and spread
+    step_gpu = np.array([e_start[k].elapsed_time(evs[k][3]) for k in range(args.steps)])
 
     costs = out.cpu().numpy()
     b = int(best.cpu()[0])
@@ -513,6 +515,8 @@ def main():
                          "frac": map_bw / PEAK_HBM, "traffic": measured_traffic("k_map"), "kernel": "k_map",
                          "bytes_per_point": 4, "kernel_ms": mapk},
         "stages_ms": {"tables": prep, "count": count, "select": sel, "map": mapk},
+        "step_gpu_ms": {"median": float(np.median(step_gpu)), "min": float(step_gpu.min()),
+                        "max": float(step_gpu.max())},
         "count_point_evals_per_s": points / (count * 1e-3),
         "map_points_per_s": L ** 3 / (mapk * 1e-3),
         "selected": {"index": b, "factorization": list(fs[b // 6]), "chain": b % 6,
