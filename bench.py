@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--transpose", action="store_true", help="also run the all-to-all transpose leg")
     ap.add_argument("--c3", action="store_true", help="also run the 4,096-candidate random batch")
     ap.add_argument("--c4", action="store_true", help="also run the matmul batch")
+    ap.add_argument("--c3-cyclic", action="store_true",
+                    help="also run the random batch with 25%% of projections cyclic")
     ap.add_argument("--search-train", type=int, default=1_000_000, help="training candidates (exact costs)")
     ap.add_argument("--search-eval", type=int, default=1_000_000, help="evaluation candidates")
     ap.add_argument("--search-epochs", type=int, default=8)
@@ -351,13 +353,14 @@ def transpose_leg(tm, W, reps=3):
     return res
 
 
-def c3_leg(tm, W, reps=5):
+def c3_leg(tm, W, reps=5, cyclic_pct=0):
     """The batched workload: 4,096 random candidates (seed 17087; ranks 2 and 3,
     extents log-uniform 32..1023, 1..64 nodes x {1,2,4,8} GPUs, 0-4 random
     transformations), halo 1, one plan per launch rank, autotuned, timed as graph
-    replays of the whole evaluation (tables, counting, selection)."""
+    replays of the whole evaluation (tables, counting, selection).  cyclic_pct: the
+    share of projections drawn cyclic (the coverage variant)."""
     import torch
-    cs = W.c3_candidates(4096)
+    cs = W.c3_candidates(4096, cyclic_pct=cyclic_pct)
     res = {"candidates": int(len(cs))}
     total_pts, total_ms = 0, 0.0
     for k in (2, 3):
@@ -534,6 +537,8 @@ def main():
         res["transpose"] = transpose_leg(tm, W)
     if args.c3:
         res["c3"] = c3_leg(tm, W)
+    if args.c3_cyclic:
+        res["c3_cyclic"] = c3_leg(tm, W, cyclic_pct=25)
     if args.c4:
         res["c4"] = c4_leg(tm, W)
     if not args.no_cpu_baseline:
