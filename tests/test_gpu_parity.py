@@ -196,6 +196,18 @@ def test_c2_full_size_plan(tm):
     # every processor gets exactly 512^3/128 points (bijective block chain, f | 512)
     counts = torch.bincount(m.long(), minlength=128).cpu().numpy()
     assert (counts == 512 ** 3 // 128).all()
+    # the launch configurations the benchmark times: its autotuner's pick and the
+    # 2^19 cells per item it settles on; identical costs and selection
+    out2 = torch.empty_like(out)
+    cpi, wg = plan.autotune(out2)
+    say("  autotuned launch", cpi, wg)
+    plan.run(out2, best)
+    torch.cuda.synchronize()
+    assert (out2.cpu().numpy() == got).all() and int(best.cpu()[0]) == b
+    plan.set_launch(1 << 19, 0)
+    plan.run(out2, best)
+    torch.cuda.synchronize()
+    assert (out2.cpu().numpy() == got).all() and int(best.cpu()[0]) == b
     plan.close()
 
 
