@@ -277,7 +277,8 @@ int tm_parse_index_task_map(const char* source, const char* task, int32_t lrank,
  * rank, halo, table size) class: reset -> table build -> one persistent counting
  * launch over a work queue of (candidate, row block) items -> bytes + selection.
  * d_out: tm_stencil_cost[n]; d_best: int64[1] (may be NULL).  Work items hold
- * cells_per_item cells (0 = autotuned default; at most 2^26, else TM_EINVAL). */
+ * cells_per_item cells (0 = a default from the batch size: about 64 items per CU,
+ * 2^15 to 2^19 cells; at most 2^26, else TM_EINVAL). */
 typedef struct tm_plan tm_plan;
 
 int tm_plan_create(int64_t max_cands, int64_t max_words, tm_plan** out);

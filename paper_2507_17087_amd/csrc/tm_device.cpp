@@ -18,7 +18,16 @@ namespace tmk {
         if (e_ != hipSuccess) return set_error(TM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int64_t kDefaultCellsPerItem = 1 << 17;
+// Default work-item size when the caller gives none: about 64 items per CU over the
+// whole batch, between 2^15 and 2^19 cells (the sizes the autotuner picks for small and
+// large batches).
+static int num_cus();
+static int64_t default_cells_per_item(int64_t points) {
+    const int64_t target = points / (int64_t(num_cus()) * 64);
+    int64_t c = int64_t(1) << 15;
+    while (c < target && c < (int64_t(1) << 19)) c <<= 1;
+    return c;
+}
 // Largest work item: a lane's 32-bit counts over one item stay below 2^31 (at most 32
 // foreign owners per cell, a quarter of the item's rows per wave).
 constexpr int64_t kMaxCellsPerItem = int64_t(1) << 26;
@@ -141,7 +150,7 @@ static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
     }
     cp.arena_words = words;
     cp.hdr.max_words = cp.max_words;
-    layout_items(cp, cells_per_item > 0 ? cells_per_item : kDefaultCellsPerItem);
+    layout_items(cp, cells_per_item > 0 ? cells_per_item : default_cells_per_item(cp.points));
     return TM_OK;
 }
 
@@ -341,6 +350,7 @@ extern "C" int tm_eval_redistribution_batch(const tm_candidate* src, const tm_ca
     // work items over the pairs (the first mapping's rows); both tables in LDS
     int64_t items = 0;
     int32_t lds_words = 0;
+    const int64_t pair_cells = int64_t(1) << 17;  // measured: 4.0 ms vs 4.3 ms at 2^19 (108 pairs of 512^3)
     for (int64_t i = 0; i < n; ++i) {
         DevCand& a = cp.cands[(size_t)i];
         const DevCand& b = cp.cands[(size_t)(n + i)];
@@ -349,7 +359,7 @@ extern "C" int tm_eval_redistribution_batch(const tm_candidate* src, const tm_ca
             return set_error(TM_ENOTSUP, "pair %lld: %lld table words exceed the LDS budget of %d", (long long)i,
                              (long long)w, kMaxLdsWords);
         lds_words = std::max<int32_t>(lds_words, (int32_t)w);
-        const int64_t rpi = rows_per_item_for(a, kDefaultCellsPerItem);
+        const int64_t rpi = rows_per_item_for(a, pair_cells);
         a.rows_per_item = (int32_t)rpi;
         a.item_first = items;
         items += (a.rows + rpi - 1) / rpi;
@@ -731,7 +741,7 @@ extern "C" int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cel
     const int64_t cells_opts[] = {1 << 15, 1 << 17, 1 << 19};
     const int wg_opts[] = {0, 2, 1};
     float best_ms = 1e30f;
-    int64_t best_c = kDefaultCellsPerItem;
+    int64_t best_c = default_cells_per_item(p->cp.points);
     int best_w = 0;
     int rc = TM_OK;
     for (int64_t cpi : cells_opts) {
@@ -787,7 +797,7 @@ extern "C" int tm_plan_set_launch(tm_plan* p, int64_t cells_per_item, int32_t wg
     p->cells_per_item = cells_per_item;
     p->wg_per_cu = wg_per_cu;
     if (p->cp.hdr.n == 0) return TM_OK;
-    layout_items(p->cp, cells_per_item > 0 ? cells_per_item : kDefaultCellsPerItem);
+    layout_items(p->cp, cells_per_item > 0 ? cells_per_item : default_cells_per_item(p->cp.points));
     plan_drop_graphs(p);
     return plan_upload(p, (hipStream_t)stream);
 }
@@ -802,7 +812,7 @@ int32_t plan_max_vol(const tm_plan* p) { return p->cp.max_vol; }
 const int32_t* plan_halo(const tm_plan* p) { return p->d_hdr->halo; }
 const DevHeader* plan_hdr(const tm_plan* p) { return p->d_hdr; }
 int64_t plan_cells_per_item(const tm_plan* p) {
-    return p->cells_per_item > 0 ? p->cells_per_item : kDefaultCellsPerItem;
+    return p->cells_per_item > 0 ? p->cells_per_item : default_cells_per_item(p->cp.points);
 }
 
 int plan_features(const tm_plan* p, float* d_feat, hipStream_t s) {
