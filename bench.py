@@ -43,7 +43,7 @@ PEAK_HBM = 8.0e12                     # bytes/s
 KERNEL_SOURCES = ["paper_2507_17087_amd/csrc/tm_kernels.hip", "paper_2507_17087_amd/csrc/tm_chain.h",
                   "paper_2507_17087_amd/csrc/tm_internal.h"]
 TRAFFIC_SOURCE_HASH = "97c2ca6752771339"
-TRAFFIC_BYTES = {"k_count<3,2>": 105.39e6, "k_map": 537.69e6}
+TRAFFIC_BYTES = {"k_count<3,2>": 105.42e6, "k_map": 537.66e6}
 
 
 def measured_traffic(kernel):
