@@ -60,8 +60,8 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
                                                      double* __restrict__ est) {
     __shared__ DevCand sc;
     extern __shared__ int32_t key[];  // the batch's largest final-space volume (at most kCrossMax)
-    __shared__ int32_t red[3][256];
-    __shared__ double dred[2][256];
+    __shared__ int32_t red[kMaxMrankCross][4][3];  // per final dim and wave: pairs, node and owner changes
+    __shared__ double dred[4][2];
     for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
         __syncthreads();
         stage_cand(&sc, &cands[ci]);
@@ -75,38 +75,48 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
         }
         for (int32_t v = threadIdx.x; v < vol; v += blockDim.x) key[v] = owner_key(sc, v);
         __syncthreads();
-        // crossing fractions per final dim
-        for (int j = 0; j < kMaxMrankCross; ++j) {
+        // crossing fractions per final dim: counts summed within each wave by
+        // shuffles, then over the four waves
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int nj = sc.frank < kMaxMrankCross ? sc.frank : kMaxMrankCross;
+        for (int j = 0; j < nj; ++j) {
             int pairs = 0, dn = 0, dp = 0;
-            if (j < sc.frank) {
-                const int32_t S = sc.fshape[j], st = sc.fstride[j];
-                for (int32_t v = threadIdx.x; v < vol; v += blockDim.x) {
-                    if ((v / st) % S < S - 1) {
-                        ++pairs;
-                        dp += key[v] != key[v + st];
-                        dn += (key[v] >> gb) != (key[v + st] >> gb);
-                    }
+            const int32_t S = sc.fshape[j], st = sc.fstride[j];
+            for (int32_t v = threadIdx.x; v < vol; v += blockDim.x) {
+                if ((v / st) % S < S - 1) {
+                    ++pairs;
+                    dp += key[v] != key[v + st];
+                    dn += (key[v] >> gb) != (key[v + st] >> gb);
                 }
             }
-            red[0][threadIdx.x] = pairs;
-            red[1][threadIdx.x] = dn;
-            red[2][threadIdx.x] = dp;
-            __syncthreads();
-            for (int w = 128; w > 0; w >>= 1) {
-                if ((int)threadIdx.x < w) {
-                    red[0][threadIdx.x] += red[0][threadIdx.x + w];
-                    red[1][threadIdx.x] += red[1][threadIdx.x + w];
-                    red[2][threadIdx.x] += red[2][threadIdx.x + w];
-                }
-                __syncthreads();
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                pairs += __shfl_xor(pairs, o, 64);
+                dn += __shfl_xor(dn, o, 64);
+                dp += __shfl_xor(dp, o, 64);
             }
-            if (threadIdx.x == 0) {
-                const float inv = red[0][0] ? 1.f / (float)red[0][0] : 0.f;
-                cross[ci * 2 * kMaxMrankCross + j] = (float)red[1][0] * inv;
-                cross[ci * 2 * kMaxMrankCross + kMaxMrankCross + j] = (float)red[2][0] * inv;
+            if (lane == 0) {
+                red[j][wv][0] = pairs;
+                red[j][wv][1] = dn;
+                red[j][wv][2] = dp;
             }
-            __syncthreads();
         }
+        __syncthreads();
+        if ((int)threadIdx.x < kMaxMrankCross) {
+            const int j = threadIdx.x;
+            float fn = 0.f, fp = 0.f;
+            if (j < nj) {
+                const int pairs = red[j][0][0] + red[j][1][0] + red[j][2][0] + red[j][3][0];
+                const int dn = red[j][0][1] + red[j][1][1] + red[j][2][1] + red[j][3][1];
+                const int dp = red[j][0][2] + red[j][1][2] + red[j][2][2] + red[j][3][2];
+                const float inv = pairs ? 1.f / (float)pairs : 0.f;
+                fn = (float)dn * inv;
+                fp = (float)dp * inv;
+            }
+            cross[ci * 2 * kMaxMrankCross + j] = fn;
+            cross[ci * 2 * kMaxMrankCross + kMaxMrankCross + j] = fp;
+        }
+        __syncthreads();
         // is every launch dim projected (block) onto exactly one final dim?
         int fdim[4] = {-1, -1, -1, -1};
         bool simple = sc.frank == K;
@@ -186,17 +196,19 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
                 inter += part * pts * cn;
             }
         }
-        dred[0][threadIdx.x] = tot;
-        dred[1][threadIdx.x] = inter;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                dred[0][threadIdx.x] += dred[0][threadIdx.x + w];
-                dred[1][threadIdx.x] += dred[1][threadIdx.x + w];
-            }
-            __syncthreads();
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            tot += __shfl_xor(tot, o, 64);
+            inter += __shfl_xor(inter, o, 64);
         }
-        if (threadIdx.x < 2) est[ci * 2 + threadIdx.x] = dred[threadIdx.x][0];
+        if (lane == 0) {
+            dred[wv][0] = tot;
+            dred[wv][1] = inter;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2)
+            est[ci * 2 + threadIdx.x] = dred[0][threadIdx.x] + dred[1][threadIdx.x] + dred[2][threadIdx.x] +
+                                        dred[3][threadIdx.x];
     }
 }
 
