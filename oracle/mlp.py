@@ -1,9 +1,10 @@
-"""Float64 reference of the learned ranker -- TEST INFRASTRUCTURE ONLY.
+"""Reference of the learned ranker (sums in float64) -- TEST INFRASTRUCTURE ONLY.
 
 Plain numpy, written independently of the HIP kernels: the feature encoding of a
-candidate, the 64 -> 256 -> 256 -> 256 -> 2 ReLU network, its mean-squared-error
-gradient by hand-written backpropagation, and one Adam step.  Only the tests and
-the benchmark's CPU leg use it.
+candidate, the 64 -> 256 -> 256 -> 256 -> 2 ReLU network in its defined arithmetic
+(bf16 weights and activations, sums at fp32 precision or better; see `_rounders`),
+its mean-squared-error gradient by hand-written backpropagation through the same
+arithmetic, and one Adam step.  Only the tests and the benchmark's CPU leg use it.
 
 Parameter vector layout (flat): W1[64][256], b1[256], W2[256][256], b2[256],
 W3[256][256], b3[256], W4[256][2], b4[2]; rows index inputs.
@@ -39,42 +40,73 @@ def unpack(p):
 
 
 def bf16_round(x):
-    """Round float32 values to bfloat16 (nearest even), returned as float64."""
+    """Round to bfloat16 (nearest even) through float32, returned as float64: a value
+    held in a float32 register and then stored as bf16 is rounded twice, and so is
+    this one."""
     a = np.ascontiguousarray(x, dtype=np.float32)
     u = a.view(np.uint32).astype(np.uint64)
     u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
     return (u.astype(np.uint32)).view(np.float32).astype(np.float64)
 
 
-def forward(p, X):
+def _identity(x):
+    return np.asarray(x, dtype=np.float64)
+
+
+def _rounders(arith):
+    """The arithmetic of the network.
+
+    "bf16": the ranker's defined arithmetic -- bf16 inputs, bf16 weight matrices and
+    bf16 hidden activations, every product summed at (at least) fp32 precision.  Here
+    the sums are taken in float64 and each one is rounded to float32 and then to bf16
+    where the definition stores a bf16 value: a hidden activation after bias and ReLU
+    (forward), a hidden-layer gradient after the ReLU mask (backward).  Biases, the two
+    outputs and the output gradient stay at full precision.
+    "f64": every value float64 (the plain network; its gradient is pinned to finite
+    differences).
+    """
+    if arith == "bf16":
+        return bf16_round
+    if arith == "f64":
+        return _identity
+    raise ValueError(arith)
+
+
+def forward(p, X, arith="bf16"):
+    """Outputs y [n][2] and the layer inputs (x, h1, h2, h3) as the network sees them."""
+    q = _rounders(arith)
     w1, b1, w2, b2, w3, b3, w4, b4 = unpack(p)
-    z1 = X @ w1 + b1
-    h1 = np.maximum(z1, 0)
-    z2 = h1 @ w2 + b2
-    h2 = np.maximum(z2, 0)
-    z3 = h2 @ w3 + b3
-    h3 = np.maximum(z3, 0)
+    w1, w2, w3, w4 = q(w1), q(w2), q(w3), q(w4)
+    x = q(X)
+    h1 = q(np.maximum(x @ w1 + b1, 0))
+    h2 = q(np.maximum(h1 @ w2 + b2, 0))
+    h3 = q(np.maximum(h2 @ w3 + b3, 0))
     y = h3 @ w4 + b4
-    return y, (X, h1, h2, h3)
+    return y, (x, h1, h2, h3)
 
 
-def loss_and_grad(p, X, T):
-    """Mean over rows and outputs of (y - t)^2, and its gradient (flat)."""
+def loss_and_grad(p, X, T, arith="bf16"):
+    """Mean over rows and outputs of (y - t)^2, and its gradient (flat), by
+    backpropagation through the same arithmetic as `forward`: each hidden-layer
+    gradient is the next layer's gradient times the (rounded) transposed weights,
+    masked where the forward activation was zero, and rounded like an activation."""
+    q = _rounders(arith)
     w1, b1, w2, b2, w3, b3, w4, b4 = unpack(p)
-    y, (x, h1, h2, h3) = forward(p, X)
+    w2, w3, w4 = q(w2), q(w3), q(w4)
+    y, (x, h1, h2, h3) = forward(p, X, arith)
     n = X.shape[0]
     d = y - T
     loss = float((d * d).sum() / (n * O))
     dy = 2.0 * d / (n * O)
     gw4 = h3.T @ dy
     gb4 = dy.sum(0)
-    dh3 = (dy @ w4.T) * (h3 > 0)
+    dh3 = q((dy @ w4.T) * (h3 > 0))
     gw3 = h2.T @ dh3
     gb3 = dh3.sum(0)
-    dh2 = (dh3 @ w3.T) * (h2 > 0)
+    dh2 = q((dh3 @ w3.T) * (h2 > 0))
     gw2 = h1.T @ dh2
     gb2 = dh2.sum(0)
-    dh1 = (dh2 @ w2.T) * (h1 > 0)
+    dh1 = q((dh2 @ w2.T) * (h1 > 0))
     gw1 = x.T @ dh1
     gb1 = dh1.sum(0)
     g = np.concatenate([gw1.ravel(), gb1, gw2.ravel(), gb2, gw3.ravel(), gb3, gw4.ravel(), gb4])

@@ -1,5 +1,5 @@
 """GPU tests of the learned ranker and the ranked search: features, forward and
-gradient against the float64 reference (same bf16-rounded operands), one Adam step,
+gradient element by element against the reference in the same bf16 arithmetic, one Adam step,
 training progress, save/load, and search quality against exhaustive search."""
 import os
 import sys
@@ -56,50 +56,52 @@ def test_features_parity(tm):
     assert np.abs(got - exp).max() < 1e-5
 
 
-def _bf16_params(r):
-    return mlp.bf16_round(r.get_params().cpu().numpy())
+# Element-wise bar of the ranker kernels against the reference in the same bf16
+# arithmetic: |got - ref| <= RTOL |ref| + ATOL max|ref| per tensor.  What remains
+# between the two is the order of the fp32 sums (the reference sums in float64):
+# it moves a stored bf16 activation or gradient by one bf16 step now and then, which
+# an fp32 emulation of the kernels puts at <= 2.2e-4 of a tensor's largest value.
+RTOL, ATOL = 1e-2, 1e-3
 
 
-def _exact_params(r):
-    """bf16 weight matrices, fp32 biases: what the kernels compute with."""
-    p = r.get_params().cpu().numpy().astype(np.float64)
-    L = mlp.layout()
-    q = p.copy()
-    for k in ("w1", "w2", "w3", "w4"):
-        a, b = L[k]
-        q[a:b] = mlp.bf16_round(p[a:b].astype(np.float32))
-    return q
+def _elementwise_ok(got, ref, what):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    lim = RTOL * np.abs(ref) + ATOL * max(np.abs(ref).max(), 1e-30)
+    err = np.abs(got - ref)
+    bad = int((err > lim).sum())
+    say(f"  {what}: {ref.size} values, max err / max|ref| {err.max() / max(np.abs(ref).max(), 1e-30):.2e}, "
+        f"over the bar: {bad}")
+    return bad == 0
 
 
-def test_forward_parity(tm):
+@pytest.mark.parametrize("rows,seed", [(333, 3), (1000, 4), (64, 6)])
+def test_forward_parity(tm, rows, seed):
     import torch
-    say("forward")
-    r = tm.Ranker(seed=3)
-    rng = np.random.default_rng(0)
-    X = rng.uniform(-1, 1, size=(333, mlp.F)).astype(np.float32)
+    say(f"forward rows={rows} seed={seed}")
+    r = tm.Ranker(seed=seed)
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1, 1, size=(rows, mlp.F)).astype(np.float32)
     y = r.forward(torch.from_numpy(X).cuda()).cpu().numpy()
-    ref, _ = mlp.forward(_exact_params(r), mlp.bf16_round(X))
-    scale = max(1.0, np.abs(ref).max())
-    assert np.abs(y - ref).max() <= 0.03 * scale
-    assert np.corrcoef(y.ravel(), ref.ravel())[0, 1] > 0.999
+    p = r.get_params().cpu().numpy().astype(np.float64)
+    ref, _ = mlp.forward(p, X.astype(np.float64), "bf16")
+    assert _elementwise_ok(y, ref, "outputs")
 
 
-def test_gradient_parity(tm):
+@pytest.mark.parametrize("rows,seed", [(1000, 5), (1537, 7)])
+def test_gradient_parity(tm, rows, seed):
     import torch
-    say("gradient")
-    r = tm.Ranker(seed=5)
-    rng = np.random.default_rng(1)
-    X = rng.uniform(-1, 1, size=(1000, mlp.F)).astype(np.float32)
-    T = rng.normal(0, 1, size=(1000, mlp.O)).astype(np.float32)
+    say(f"gradient rows={rows} seed={seed}")
+    r = tm.Ranker(seed=seed)
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1, 1, size=(rows, mlp.F)).astype(np.float32)
+    T = rng.normal(0, 1, size=(rows, mlp.O)).astype(np.float32)
     g = r.grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()).cpu().numpy().astype(np.float64)
-    _, ref = mlp.loss_and_grad(_exact_params(r), mlp.bf16_round(X), T.astype(np.float64))
+    p = r.get_params().cpu().numpy().astype(np.float64)
+    _, ref = mlp.loss_and_grad(p, X.astype(np.float64), T.astype(np.float64), "bf16")
     L = mlp.layout()
-    for k in ("w1", "b1", "w2", "b2", "w3", "b3", "w4", "b4"):
-        a, b = L[k]
-        d = np.linalg.norm(g[a:b] - ref[a:b]) / max(np.linalg.norm(ref[a:b]), 1e-12)
-        cos = float(g[a:b] @ ref[a:b] / max(np.linalg.norm(g[a:b]) * np.linalg.norm(ref[a:b]), 1e-30))
-        say(f"  {k}: rel {d:.4f} cos {cos:.6f}")
-        assert d < 0.05 and cos > 0.998
+    ok = [_elementwise_ok(g[a:b], ref[a:b], k) for k, (a, b) in
+          ((k, L[k]) for k in ("w1", "b1", "w2", "b2", "w3", "b3", "w4", "b4"))]
+    assert all(ok)
 
 
 def test_one_adam_step(tm):

@@ -1,5 +1,6 @@
-"""Pins for the float64 ranker reference: finite differences for the gradient,
-a hand-worked feature vector, and Adam's first step."""
+"""Pins for the ranker reference: finite differences for the gradient of the plain
+network, hand-worked values of its bf16 arithmetic (where rounding happens and where
+it does not), hand-worked feature vectors, and Adam's first step."""
 import math
 
 import numpy as np
@@ -21,7 +22,7 @@ def test_gradient_matches_central_differences():
     p = small_params()
     X = rng.normal(0, 1, size=(6, mlp.F))
     T = rng.normal(0, 1, size=(6, mlp.O))
-    _, g = mlp.loss_and_grad(p, X, T)
+    _, g = mlp.loss_and_grad(p, X, T, arith="f64")
     L = mlp.layout()
     idx = np.concatenate([rng.integers(a, b, size=6) for a, b in
                           [L[k] for k in ("w1", "b1", "w2", "b2", "w3", "b3", "w4", "b4")]])
@@ -29,9 +30,9 @@ def test_gradient_matches_central_differences():
     for i in idx:
         q = p.copy()
         q[i] += h
-        lp, _ = mlp.loss_and_grad(q, X, T)
+        lp, _ = mlp.loss_and_grad(q, X, T, arith="f64")
         q[i] -= 2 * h
-        lm, _ = mlp.loss_and_grad(q, X, T)
+        lm, _ = mlp.loss_and_grad(q, X, T, arith="f64")
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8
 
@@ -47,8 +48,97 @@ def test_forward_of_identity_like_network():
     p[L["b4"][0]] = 0.5
     X = np.zeros((3, mlp.F))
     X[:, 0] = [0.25, 1.5, -2]
-    y, _ = mlp.forward(p, X)
-    assert np.allclose(y[:, 0], 0.5) and np.allclose(y[:, 1], [0.5, 3.0, 0.0])
+    for arith in ("f64", "bf16"):
+        y, _ = mlp.forward(p, X, arith)
+        assert np.allclose(y[:, 0], 0.5) and np.allclose(y[:, 1], [0.5, 3.0, 0.0])
+
+
+def _path_network(w=1.0, b1=0.0, b4=0.0):
+    """Input 0 -> hidden unit 0 of every layer -> output 0, weights w, 1, 1, 1."""
+    L = mlp.layout()
+    p = np.zeros(L["count"])
+    p[L["w1"][0]] = w
+    p[L["b1"][0]] = b1
+    p[L["w2"][0]] = 1
+    p[L["w3"][0]] = 1
+    p[L["w4"][0]] = 1
+    p[L["b4"][0]] = b4
+    return p
+
+
+def test_bf16_arithmetic_rounds_activations_not_biases():
+    """The defined arithmetic stores every hidden activation in bf16 (7 explicit
+    mantissa bits: spacing 2^-7 just above 1) and keeps biases and outputs at full
+    precision.  With x = 1 and bias 2^-9 + 2^-12 the first activation is
+    1.00220703125, stored as 1.0; the output bias 2^-12 survives in the output."""
+    p = _path_network(b1=2.0 ** -9 + 2.0 ** -12, b4=2.0 ** -12)
+    X = np.zeros((1, mlp.F))
+    X[0, 0] = 1.0
+    y64, (_, h1_64, _, _) = mlp.forward(p, X, "f64")
+    y16, (_, h1_16, _, _) = mlp.forward(p, X, "bf16")
+    assert h1_64[0, 0] == 1 + 2.0 ** -9 + 2.0 ** -12 and h1_16[0, 0] == 1.0
+    assert y64[0, 0] == 1 + 2.0 ** -9 + 2.0 ** -11 and y16[0, 0] == 1 + 2.0 ** -12
+    # an activation exactly between two bf16 values goes to the even one:
+    # 1 + 2^-8 lies between 1 and 1 + 2^-7 -> 1;  1 + 3 * 2^-8 -> 1 + 2^-6
+    for b, exp in ((2.0 ** -8, 1.0), (3 * 2.0 ** -8, 1 + 2.0 ** -6)):
+        _, (_, h1, _, _) = mlp.forward(_path_network(b1=b), X, "bf16")
+        assert h1[0, 0] == exp
+    # weights and inputs are bf16 too: w = 1 + 2^-9 and x = 1 + 2^-9 both read as 1
+    y, _ = mlp.forward(_path_network(w=1 + 2.0 ** -9), X, "bf16")
+    assert y[0, 0] == 1.0
+    X2 = X.copy()
+    X2[0, 0] = 1 + 2.0 ** -9
+    y, _ = mlp.forward(_path_network(), X2, "bf16")
+    assert y[0, 0] == 1.0
+
+
+def test_bf16_arithmetic_rounds_hidden_gradients():
+    """Backward: the output gradient dy = 2 (y - t) / (rows * outputs) stays at full
+    precision (it weights W4's gradient directly); each hidden-layer gradient is
+    stored in bf16.  One row, two outputs: dy = y - t.  With t0 = y0 - (1 + 2^-9) the
+    output gradient is 1 + 2^-9, W4's gradient h3 * dy keeps it, the last hidden
+    layer's gradient dy * w4 = 1 + 2^-9 is stored as 1.0 (so are b3's and W3's)."""
+    p = _path_network()
+    X = np.zeros((1, mlp.F))
+    X[0, 0] = 1.0
+    T = np.zeros((1, mlp.O))
+    T[0, 0] = 1.0 - (1 + 2.0 ** -9)
+    L = mlp.layout()
+    _, g64 = mlp.loss_and_grad(p, X, T, "f64")
+    _, g16 = mlp.loss_and_grad(p, X, T, "bf16")
+    at = lambda g, k, i=0: g[L[k][0] + i]
+    assert at(g64, "w4") == 1 + 2.0 ** -9 and at(g16, "w4") == 1 + 2.0 ** -9
+    assert at(g64, "b4") == 1 + 2.0 ** -9 and at(g16, "b4") == 1 + 2.0 ** -9
+    assert at(g64, "b3") == 1 + 2.0 ** -9 and at(g16, "b3") == 1.0
+    assert at(g64, "w3") == 1 + 2.0 ** -9 and at(g16, "w3") == 1.0
+    assert at(g16, "b1") == 1.0 and at(g16, "w1") == 1.0
+    # units off the path get nothing: their activations are zero (ReLU mask)
+    assert np.count_nonzero(g16) == np.count_nonzero(g64) == 8
+
+
+def test_bf16_arithmetic_exact_when_representable():
+    """With small-integer weights and inputs, sparse enough that every sum stays
+    below 2^8, and a dyadic output gradient, nothing needs rounding: the bf16
+    arithmetic gives exactly the plain network's outputs and gradient."""
+    rng = np.random.default_rng(3)
+    L = mlp.layout()
+    p = np.zeros(L["count"])
+    for k in ("w1", "w2", "w3", "w4"):
+        a, b = L[k]
+        m = rng.random(b - a) < 0.01
+        p[a:b] = np.where(m, rng.integers(-1, 2, b - a), 0)
+    for k in ("b1", "b2", "b3", "b4"):
+        a, b = L[k]
+        p[a:b] = rng.integers(0, 3, b - a)
+    X = rng.integers(-2, 3, size=(8, mlp.F)).astype(np.float64)
+    y64, acts = mlp.forward(p, X, "f64")
+    assert max(np.abs(a).max() for a in acts[1:]) < 256 and np.abs(y64).max() < 256
+    y16, _ = mlp.forward(p, X, "bf16")
+    assert (y16 == y64).all()
+    T = y64 - rng.integers(-3, 4, size=y64.shape)  # 2 (y - t) / 16: multiples of 1/8
+    l64, g64 = mlp.loss_and_grad(p, X, T, "f64")
+    l16, g16 = mlp.loss_and_grad(p, X, T, "bf16")
+    assert l64 == l16 and (g64 == g16).all() and np.count_nonzero(g64) > 50
 
 
 def test_adam_first_step_is_signed_lr():
@@ -100,6 +190,35 @@ def test_features_hand_worked():
     # and the block model is exact here: the oracle's ghost count agrees
     gc, ic, _, _ = oracle.stencil_cost(c, W.stencil((1, 1), 8))
     assert (gc, ic) == (448, 384)
+
+
+def test_features_hand_worked_cyclic():
+    """The estimate's second branch (some launch dim not block-projected onto exactly
+    one final dim).  (8, 6) on 2 nodes x 2 GPUs, merge(0,1) + decompose(0, (2, 2)),
+    final dim 0 BLOCK from launch dim 0, final dim 1 CYCLIC from launch dim 1, halo
+    (2, 1).  The chain gives node = a0, gpu = a1 (a = a0 + 2 a1; node = a mod 2),
+    so proc = 2 a0 + a1.
+      launch dim 0: block index x // 4, linear contribution 2 (x // 4) =
+        [0,0,0,0,2,2,2,2]; cells with a differing value within 2 steps: x = 2..5,
+        one distinct offset each -> 4, times 48 / 8 rows = 24 cells; along final
+        dim 0 every step changes processor and node -> 24 total, 24 inter-node.
+      launch dim 1: cyclic x mod 2 = [0,1,0,1,0,1]; every cell has one distinct
+        offset -> 6, times 48 / 6 = 48 cells; along final dim 1 every step changes
+        processor, never node -> 48 total, 0 inter-node.
+    Estimate: 72 ghost cells, 24 inter-node; exact here (each cell's two foreign
+    owners differ): the oracle's count agrees."""
+    import oracle
+    c = W.candidate((8, 6), 2, 2, [merge(0, 1), decompose(0, (2, 2))],
+                    proj=[(0, W.BLOCK), (1, W.CYCLIC)])
+    f = mlp.features(c, (2, 1), oracle.chain_table)
+    assert math.isclose(f[23], math.log2(1 + 72) / 32) and math.isclose(f[60], math.log2(1 + 24) / 32)
+    assert f[36] == 1.0 and f[37] == 1.0  # processor crossings per launch dim
+    assert f[61] == 1.0 and f[62] == 0.0  # node crossings per launch dim
+    assert f[49] == 0.0 and f[50] == 1.0  # the cyclic flag of final dim 1
+    assert math.isclose(f[15], 1 / 9) and math.isclose(f[16], 1 / 9)  # 2 blocks per launch dim
+    assert math.isclose(f[54], 2 / 4) and math.isclose(f[55], 1 / 4)
+    gc, ic, _, _ = oracle.stencil_cost(c, W.stencil((2, 1), 8))
+    assert (gc, ic) == (72, 24)
 
 
 def test_block_estimate_exact_for_bijective_block_chains():
