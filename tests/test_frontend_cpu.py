@@ -1,7 +1,10 @@
 """Front end: mapping-language mappers translated into candidates (host only).
 Each mapper below is written for these tests in the language of the syntax figure
-of Sec. 7; the expected candidates are built by hand from the transformation
-primitives (Fig. 6) and projections (Fig. 1, Fig. 3, App. A.1)."""
+of Sec. 7 (none is one of the paper's listings): a block distribution, a two-level
+node-block / GPU-cyclic distribution of the kind App. A.1 uses for the matmul
+mappers, a merge+split row mapper and a swapped, halo-weighted decompose.  The
+expected candidates are built by hand from the transformation primitives (Fig. 6)
+and projections (Fig. 1, Fig. 3, App. A.1)."""
 import numpy as np
 import pytest
 
@@ -31,12 +34,13 @@ def same(a, b):
 
 
 TILES = """
-# block tiles of a 2-D launch over the node x GPU grid
-m = Machine(GPU)
+# a block distribution of a 2-D launch over the node x GPU grid: the point is
+# scaled as a tuple, divided by the launch domain and unpacked into the index
+gpus = Machine(GPU)
 
-def tiles2d(Tuple p, Tuple dom):
-    q = p * m.size / dom
-    return m[*q]
+def tiles2d(Task t):
+    scaled = t.ipoint * gpus.size
+    return gpus[*(scaled / t.ispace)]
 
 IndexTaskMap stencil_step tiles2d
 Region * * GPU FBMEM
@@ -50,17 +54,18 @@ def test_elementwise_block(tm):
 
 
 HIER = """
-def hier(Task t):
-    dom = t.ispace
-    pt = t.ipoint
-    grid = Machine(GPU).decompose(0, dom)      # nodes tiled over the domain
-    full = grid.decompose(2, dom / grid[:-1])  # each node's GPUs over its tile
-    node_part = (pt[0] * full[0] / dom[0],
-                 pt[1] * full[1] / dom[1])
-    gpu_part = (pt[0] % full[2], pt[1] % full[3])
-    return full[*node_part, *gpu_part]
+# two levels: decompose tiles the nodes over the domain, then each node's GPUs
+# over one node's share of it; a point takes its node by blocks and its GPU round
+# robin, one coordinate at a time
+def node_then_gpu(Tuple p, Tuple dom):
+    nodes = Machine(GPU).decompose(0, dom)
+    share = dom / nodes[:-1]
+    two = nodes.decompose(2, share)
+    n0 = p[0] * two[0] / dom[0]
+    n1 = p[1] * two[1] / dom[1]
+    return two[n0, n1, p[0] % two[2], p[1] % two[3]]
 
-IndexTaskMap cannon_tiles hier
+IndexTaskMap cannon_tiles node_then_gpu
 """
 
 
