@@ -8,14 +8,18 @@ candidate exactly (processor of each of the 216 x 134,217,728 launch points, and
 the distinct-owner ghost volume with its intra/inter-node split), selects the
 cheapest by (bytes, inter-node bytes, index), and materialises the selected
 candidate's int32 processor map (512 MiB).  Inputs (candidate descriptors) are
-resident on the device before timing starts.
+resident on the device before timing starts.  The ghost volume of a candidate is
+counted exactly over its coordinate classes (runs of coordinates with the same
+contribution and neighbour offsets along each launch dim), so the counting work is
+its class tuples, not its points; the map is written point by point.
 
 The metric's second part -- candidates ranked per second by the learned ranker vs
 exhaustive exact evaluation, at the exhaustive optimum -- is the "search" object of
 the same line (trained on 1M exact costs from the random-chain generator, evaluated
-on ~1M candidates of 457 search instances; --no-search skips it).  Optional legs:
---study (decompose vs Alg. A1 volumes), --two-level (hierarchical decompositions),
---c3 (4,096-candidate random batch), --c4 (matmul batch).
+on ~1M candidates of 457 search instances; --no-search skips it).  Also by default:
+"c3" (the 4,096-candidate random batch, one plan) and "c4" (the matmul batch).
+Optional legs: --study (decompose vs Alg. A1 volumes), --two-level (hierarchical
+decompositions), --transpose (all-to-all transposes), --c3-cyclic.
 
 Prints one JSON line (see the keys below).  Only one GPU is supported.
 """
@@ -33,7 +37,11 @@ if ROOT not in sys.path:
 
 METRIC = "mapping point-evals/sec; candidates ranked/sec surrogate vs exhaustive at =opt"
 PEAK_LANE_OPS = 256 * 64 * 2.4e9      # 32-bit VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
-OPS_PER_POINT = 2                     # table read + boundary test: the least any point costs
+# Integer operations of one exact cell evaluation for a 3-D halo-2 star: one owner
+# lookup, up to 2 * sum(h) = 12 neighbour lookups, compares and the de-duplication of
+# a small set -- about 50 to 70; the midpoint prices one class-tuple evaluation (a
+# class tuple is evaluated exactly like one of its cells).
+OPS_PER_TUPLE = 60
 PEAK_HBM = 8.0e12                     # bytes/s
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by a
@@ -42,8 +50,8 @@ PEAK_HBM = 8.0e12                     # bytes/s
 # profiles/k_count_k_map_c2_512cube_hbm_traffic.txt.
 KERNEL_SOURCES = ["paper_2507_17087_amd/csrc/tm_kernels.hip", "paper_2507_17087_amd/csrc/tm_chain.h",
                   "paper_2507_17087_amd/csrc/tm_internal.h"]
-TRAFFIC_SOURCE_HASH = "97c2ca6752771339"
-TRAFFIC_BYTES = {"k_count<3,2>": 105.42e6, "k_map": 537.66e6}
+TRAFFIC_SOURCE_HASH = "unmeasured"
+TRAFFIC_BYTES = {}
 
 
 def measured_traffic(kernel):
@@ -73,8 +81,11 @@ def parse():
     ap.add_argument("--study", action="store_true", help="also run the decompose-vs-Alg.-A1 volume study")
     ap.add_argument("--two-level", action="store_true", help="also run the two-level decomposition leg")
     ap.add_argument("--transpose", action="store_true", help="also run the all-to-all transpose leg")
-    ap.add_argument("--c3", action="store_true", help="also run the 4,096-candidate random batch")
-    ap.add_argument("--c4", action="store_true", help="also run the matmul batch")
+    ap.add_argument("--c3", dest="c3", action="store_true", default=True,
+                    help="run the 4,096-candidate random batch (the default)")
+    ap.add_argument("--no-c3", dest="c3", action="store_false", help="skip the random batch")
+    ap.add_argument("--c4", dest="c4", action="store_true", default=True, help="run the matmul batch (the default)")
+    ap.add_argument("--no-c4", dest="c4", action="store_false", help="skip the matmul batch")
     ap.add_argument("--c3-cyclic", action="store_true",
                     help="also run the random batch with 25%% of projections cyclic")
     ap.add_argument("--search-train", type=int, default=1_000_000, help="training candidates (exact costs)")
@@ -90,23 +101,43 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(cands, st, extent, threads):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cands, st, extent, threads, gpu_costs):
     """The oracle (plain C, single-threaded per call) on `threads` full-size candidates
-    of the workload, one per host thread (ctypes releases the GIL during each call):
-    the same evaluator, run side by side on the machine's cores."""
+    of the workload, one per host thread (ctypes releases the GIL during each call),
+    then one of them alone on one thread; the oracle's results are compared with the
+    GPU's cost rows of the same candidates."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
     picks = [(i * 37) % len(cands) for i in range(threads)]
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        list(ex.map(lambda i: oracle.stencil_cost(cands[i], st), picks))
+        res = list(ex.map(lambda i: oracle.stencil_cost(cands[i], st), picks))
     dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    one = oracle.stencil_cost(cands[picks[0]], st)
+    dt1 = time.perf_counter() - t1
     pts = threads * extent ** 3
+    equal = sum(1 for i, r in zip(picks, res) if tuple(int(x) for x in gpu_costs[i]) == r)
     return {"value": pts / dt, "unit": "point-evals/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": extent ** 3 / dt1, "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(),
             "sample": f"{threads} of the {len(cands)} candidates (indices {picks[0]}, {picks[1] if threads > 1 else ''}"
                       f"... step 37 mod {len(cands)}) on the full {extent}^3 domain, one oracle call per "
-                      f"host thread: {pts} point-evals in {dt:.2f} s"}
+                      f"host thread: {pts} point-evals in {dt:.2f} s; then candidate {picks[0]} alone on one "
+                      f"thread in {dt1:.2f} s",
+            "parity": {"checked": len(picks), "equal": equal, "single_thread_equal": one == res[0]}}
 
 
 def instances_with(tm, W, seed, target, octaves, min_cands=1024):
@@ -353,63 +384,81 @@ def transpose_leg(tm, W, reps=3):
     return res
 
 
-def c3_leg(tm, W, reps=5, cyclic_pct=0):
-    """The batched workload: 4,096 random candidates (seed 17087; ranks 2 and 3,
-    extents log-uniform 32..1023, 1..64 nodes x {1,2,4,8} GPUs, 0-4 random
-    transformations), halo 1, one plan per launch rank, autotuned, timed as graph
-    replays of the whole evaluation (tables, counting, selection).  cyclic_pct: the
-    share of projections drawn cyclic (the coverage variant)."""
+def c3_leg(tm, W, reps=20, cyclic_pct=0):
+    """The batched workload: 4,096 random candidates (seed 17087; launch ranks 2 and 3
+    mixed, extents log-uniform 32..1023, 1..64 nodes x {1,2,4,8} GPUs, 0-4 random
+    transformations), halo 1, in one plan (one counting launch), autotuned, timed as
+    graph replays of the whole evaluation (reset, tables, counting, selection) with
+    HIP events on the plan's stream.  cyclic_pct: the share of projections drawn
+    cyclic (the coverage variant)."""
     import torch
     cs = W.c3_candidates(4096, cyclic_pct=cyclic_pct)
-    res = {"candidates": int(len(cs))}
-    total_pts, total_ms = 0, 0.0
-    for k in (2, 3):
-        sub = cs[cs["lrank"] == k]
-        st = W.c3_stencil(k)
-        plan = tm.Plan(len(sub), 1)
-        plan.load(sub, st)
-        out = torch.empty((len(sub), 4), dtype=torch.int64, device="cuda")
-        plan.run(out)
-        cpi, wg = plan.autotune(out)
-        ts = []
-        for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            plan.run(out)
-            e1.record()
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        _, _, pts = plan.info()
-        plan.close()
-        ms = float(np.median(ts))
-        res[f"rank{k}"] = {"candidates": int(len(sub)), "points": int(pts), "ms": ms,
-                           "point_evals_per_s": pts / (ms * 1e-3), "cells_per_item": cpi, "wg_per_cu": wg}
-        total_pts += pts
-        total_ms += ms
-    res["point_evals_per_s"] = total_pts / (total_ms * 1e-3)
-    return res
+    plan = tm.Plan(len(cs), 1)
+    plan.load(cs, W.c3_stencil(3))  # a rank-2 candidate takes the first two halo widths
+    out = torch.empty((len(cs), 4), dtype=torch.int64, device="cuda")
+    best = torch.empty(1, dtype=torch.int64, device="cuda")
+    plan.run(out, best)
+    cpi, wg = plan.autotune(out)
+    plan.run(out, best)
+    torch.cuda.synchronize()
+    ts, tc = [], []
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        plan.run_stage(0, out, best)
+        e[1].record()
+        plan.run_stage(1, out, best)
+        e[2].record()
+        plan.run_stage(2, out, best)
+        e[3].record()
+        torch.cuda.synchronize()
+        ts.append(e[0].elapsed_time(e[3]))
+        tc.append(e[1].elapsed_time(e[2]))
+    _, items, pts = plan.info()
+    tuples = plan.class_tuples()
+    plan.close()
+    ms, cms = float(np.median(ts)), float(np.median(tc))
+    ach = OPS_PER_TUPLE * tuples / (cms * 1e-3)
+    return {"candidates": int(len(cs)), "ranks": sorted(int(k) for k in set(cs["lrank"])), "points": int(pts),
+            "ms": ms, "ms_spread": [float(min(ts)), float(max(ts))], "point_evals_per_s": pts / (ms * 1e-3),
+            "count_ms": cms, "class_tuples": int(tuples), "work_items": int(items),
+            "tuples_per_item": cpi, "wg_per_cu": wg,
+            "roofline_count": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                               "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "kernel": "k_count",
+                               "ops_per_tuple": OPS_PER_TUPLE}}
 
 
-def c4_leg(tm, W, reps=5):
+def c4_leg(tm, W, reps=10):
     """The matmul workload: 256^3 task points on 16 nodes x 4 GPUs, every
     3-factorization of 64 (with and without swap(0,1)) plus the hierarchical Cannon
-    mapper: 57 candidates, 8 MiB tiles; one call per evaluation (host-inclusive:
-    validation, upload, tables, counting)."""
+    mapper: 57 candidates, 8 MiB tiles; one call per evaluation, timed on the host
+    (validation, upload, tables, counting) and with HIP events on the call's stream.
+    Roofline: an owner lookup and three bit-ORs per task point (the per-tile bitmaps
+    of A, B, C), at the GPU time of the whole call (which also holds the uploads and
+    the table build: a lower bound on the counting kernel's rate)."""
     import torch
     fs = tm.tm_enumerate_factorizations(64, 3)
     mc = W.c4_candidates(fs)
     tm.tm_eval_matmul_batch(mc, W.C4_TILE_BYTES)
     torch.cuda.synchronize()
-    ts = []
+    ts, tg = [], []
     for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
+        e0.record()
         tm.tm_eval_matmul_batch(mc, W.C4_TILE_BYTES)
+        e1.record()
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
-    dt = float(np.median(ts))
+        tg.append(e0.elapsed_time(e1))
+    dt, gms = float(np.median(ts)), float(np.median(tg))
     pts = len(mc) * 256 ** 3
+    ach = 4.0 * pts / (gms * 1e-3)
     return {"candidates": int(len(mc)), "task_points": int(pts), "ms_host_inclusive": dt * 1e3,
-            "point_evals_per_s": pts / dt}
+            "gpu_ms": gms, "point_evals_per_s": pts / dt, "point_evals_per_s_gpu": pts / (gms * 1e-3),
+            "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                         "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "kernel": "k_matmul",
+                         "ops_per_task_point": 4}}
 
 
 def main():
@@ -488,9 +537,16 @@ def main():
 
     costs = out.cpu().numpy()
     b = int(best.cpu()[0])
+    tuples = plan.class_tuples()
     value = points / (ms_step * 1e-3)
-    ach = OPS_PER_POINT * points / (count * 1e-3)
+    cnt_ach = OPS_PER_TUPLE * tuples / (count * 1e-3)
     map_bw = 4.0 * L ** 3 / (mapk * 1e-3)
+    roof_map = {"bound": "hbm", "achieved": map_bw / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": map_bw / PEAK_HBM, "traffic": measured_traffic("k_map"), "kernel": "k_map",
+                "bytes_per_point": 4, "kernel_ms": mapk}
+    roof_count = {"bound": "alu", "achieved": cnt_ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                  "unit": "Tlane-op/s", "frac": cnt_ach / PEAK_LANE_OPS, "traffic": measured_traffic("k_count"),
+                  "kernel": "k_count", "class_tuples": tuples, "ops_per_tuple": OPS_PER_TUPLE, "kernel_ms": count}
     res = {
         "metric": METRIC,
         "value": value,
@@ -509,18 +565,16 @@ def main():
                                f"candidate + selection + int32 map of the winner",
                    "candidates": n, "points_per_candidate": L ** 3, "halo": 2,
                    "machine": [16, 8], "work_items": items,
-                   "cells_per_item": tuned[0], "wg_per_cu": tuned[1]},
-        "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "Tlane-op/s", "frac": ach / PEAK_LANE_OPS, "traffic": measured_traffic("k_count<3,2>"),
-                     "kernel": "k_count<3,2>", "ops_per_point": OPS_PER_POINT,
-                     "kernel_ms": count},
-        "roofline_map": {"bound": "hbm", "achieved": map_bw / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                         "frac": map_bw / PEAK_HBM, "traffic": measured_traffic("k_map"), "kernel": "k_map",
-                         "bytes_per_point": 4, "kernel_ms": mapk},
+                   "tuples_per_item": tuned[0], "wg_per_cu": tuned[1]},
+        # the step's dominant kernel (largest mean time of the timed stages)
+        "roofline": roof_map if mapk >= max(count, prep) else roof_count,
+        "roofline_map": roof_map,
+        "roofline_count": roof_count,
         "stages_ms": {"tables": prep, "count": count, "select": sel, "map": mapk},
         "step_gpu_ms": {"median": float(np.median(step_gpu)), "min": float(step_gpu.min()),
                         "max": float(step_gpu.max())},
         "count_point_evals_per_s": points / (count * 1e-3),
+        "count_class_tuples_per_s": tuples / (count * 1e-3),
         "map_points_per_s": L ** 3 / (mapk * 1e-3),
         "selected": {"index": b, "factorization": list(fs[b // 6]), "chain": b % 6,
                      "bytes": int(costs[b][2]), "inter_bytes": int(costs[b][3])},
@@ -542,7 +596,7 @@ def main():
     if args.c4:
         res["c4"] = c4_leg(tm, W)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(cands, st, L, args.cpu_threads)
+        res["cpu_baseline"] = cpu_baseline(cands, st, L, args.cpu_threads, costs)
     print(json.dumps(res))
 
 

@@ -110,7 +110,8 @@ typedef struct {
 } tm_candidate;
 
 /* Star stencil, non-periodic: halo[d] cells along each axis (0..65535), elements of
- * elem_bytes bytes.  lrank must equal the candidates' launch rank. */
+ * elem_bytes bytes.  lrank must be at least every candidate's launch rank; a
+ * candidate of launch rank k takes halo[0..k), so one batch may mix launch ranks. */
 typedef struct {
     int32_t lrank, elem_bytes;
     int32_t halo[TM_MAX_LRANK];
@@ -207,11 +208,16 @@ int tm_chain_table(const tm_candidate* c, int32_t* d_out, int64_t cap, int64_t* 
 int tm_proc_map(const tm_candidate* c, int32_t* d_map, int64_t len, void* stream);
 
 /* Stencil cost of n candidates (host array) sharing one stencil (host); results to
- * d_out (device, tm_stencil_cost[n]).  All candidates must have launch rank
- * st->lrank.  TM_ENOTSUP if a halo exceeds 4, a candidate's owner table (its
- * final-space volume) exceeds the per-workgroup LDS budget of 32768 words, or it
- * has more than 2^30 rows (points / last extent); the coordinate tables have no
- * size limit (long ones are read from global memory). */
+ * d_out (device, tm_stencil_cost[n]).  Candidates may differ in launch rank (each
+ * at most st->lrank; TM_EINVAL otherwise).  Counted exactly as a weighted sum over
+ * coordinate classes: along each launch dim, consecutive coordinates with the same
+ * contribution to the final index and the same offsets to their star neighbours
+ * form a class, and every cell of a tuple of classes has the same distinct foreign
+ * owners (Sec. 4.2's volume, evaluated once per class tuple and multiplied by the
+ * cells it stands for).  TM_ENOTSUP if a halo exceeds 4, a candidate's owner table
+ * (its final-space volume) exceeds the per-workgroup LDS budget of 32768 words, or
+ * it has more than 2^30 rows (points / last extent); the coordinate tables and
+ * classes have no size limit (large ones are read from global memory). */
 int tm_eval_stencil_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
                           tm_stencil_cost* d_out, void* stream);
 
@@ -273,12 +279,14 @@ int tm_parse_index_task_map(const char* source, const char* task, int32_t lrank,
 /* ---------------------------------------------------------------- batch plans
  * A plan owns device memory for up to max_cands candidates and max_words table
  * words.  tm_plan_load validates a batch on the host and uploads its descriptors
- * (asynchronously, on `stream`); tm_plan_run replays one hipGraph per (launch
- * rank, halo, table size) class: reset -> table build -> one persistent counting
- * launch over a work queue of (candidate, row block) items -> bytes + selection.
- * d_out: tm_stencil_cost[n]; d_best: int64[1] (may be NULL).  Work items hold
- * cells_per_item cells (0 = a default from the batch size: about 64 items per CU,
- * 2^15 to 2^19 cells; at most 2^26, else TM_EINVAL). */
+ * (asynchronously, on `stream`); tm_plan_run replays one hipGraph: reset -> table
+ * build (owner tables, coordinate tables, coordinate classes) -> one persistent
+ * counting launch over a work queue of (candidate, range of class tuples) items,
+ * whatever the candidates' launch ranks -> bytes + selection.  d_out:
+ * tm_stencil_cost[n]; d_best: int64[1] (may be NULL).  Work items hold about
+ * cells_per_item class tuples of the candidate's bound (0 = a default from the
+ * batch: about 16 items per CU, 2^10 to 2^16 tuples; at most 2^26, else
+ * TM_EINVAL). */
 typedef struct tm_plan tm_plan;
 
 int tm_plan_create(int64_t max_cands, int64_t max_words, tm_plan** out);
@@ -294,6 +302,11 @@ int tm_plan_run_stage(tm_plan* p, int32_t stage, tm_stencil_cost* d_out, int64_t
  * hold the largest candidate of the batch. */
 int tm_plan_materialize(tm_plan* p, const int64_t* d_index, int64_t host_index, int32_t* d_map,
                         int64_t cap, void* stream);
+/* Class tuples of the loaded batch (the counting kernel's work): the sum over its
+ * candidates of the product of their per-dim class counts, as built by the last
+ * run -> *tuples (host).  Synchronous: waits for `stream`.  TM_EINVAL before the
+ * first run. */
+int tm_plan_class_tuples(tm_plan* p, int64_t* tuples, void* stream);
 /* Times cells_per_item and grid variants of the loaded batch, keeps the fastest;
  * writes the chosen cells_per_item and workgroups per CU (host pointers, nullable). */
 int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cells_per_item,

@@ -71,6 +71,7 @@ def lib():
             "tm_parse_index_task_map": [ctypes.c_char_p, ctypes.c_char_p, I32, P, I32, I32, P, P],
             "tm_plan_set_launch": [P, I64, I32, P],
             "tm_plan_info": [P, P, P, P],
+            "tm_plan_class_tuples": [P, P, P],
             "tm_plan_destroy": [P],
         }
         for name, args in sig.items():
@@ -359,6 +360,12 @@ class Plan:
         n, it, pts = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().tm_plan_info(self._p, ctypes.byref(n), ctypes.byref(it), ctypes.byref(pts)))
         return n.value, it.value, pts.value
+
+    def class_tuples(self):
+        """Class tuples the counting kernel evaluates for the loaded batch (after a run)."""
+        t = ctypes.c_int64()
+        _check(lib().tm_plan_class_tuples(self._p, ctypes.byref(t), _stream()))
+        return t.value
 
     def close(self):
         if self._p:

@@ -18,18 +18,16 @@ namespace tmk {
         if (e_ != hipSuccess) return set_error(TM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-// Default work-item size when the caller gives none: about 64 items per CU over the
-// whole batch, between 2^15 and 2^19 cells (the sizes the autotuner picks for small and
-// large batches).
+// Default counting work-item size when the caller gives none: about 16 items per
+// CU over the batch's class-tuple bound, between 2^10 and 2^16 tuples.
 static int num_cus();
-static int64_t default_cells_per_item(int64_t points) {
-    const int64_t target = points / (int64_t(num_cus()) * 64);
-    int64_t c = int64_t(1) << 15;
-    while (c < target && c < (int64_t(1) << 19)) c <<= 1;
+static int64_t default_tuples_per_item(int64_t tuples) {
+    const int64_t target = tuples / (int64_t(num_cus()) * 16);
+    int64_t c = int64_t(1) << 10;
+    while (c < target && c < (int64_t(1) << 16)) c <<= 1;
     return c;
 }
-// Largest work item: a lane's 32-bit counts over one item stay below 2^31 (at most 32
-// foreign owners per cell, a quarter of the item's rows per wave).
+// Largest work item accepted from a caller.
 constexpr int64_t kMaxCellsPerItem = int64_t(1) << 26;
 // Map launches: workgroups per CU (a wave writes every (grid * 4)-th row).  32 gives
 // smaller work units than the 8 that are resident at once (about 8 rows per wave on a
@@ -47,37 +45,44 @@ static int64_t rows_per_item_for(const DevCand& d, int64_t cells_per_item) {
 static int64_t up4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
 // Arena layout of one candidate: owner table T, the last dim's coordinate table
-// (16-byte aligned, zero-padded to whole 512-entry chunks), the last dim's offset
-// lists (H > 0), then the other dims' coordinate tables.  The counting and map
-// kernels stage the longest prefix that fits the LDS budget -- T always, then the
-// last dim's table, then its offset lists -- and read the rest (the outer tables,
-// used once per row, and whatever did not fit) from global memory.  H = 0: no
-// offset lists.
-static int layout_tables(DevCand& d, int H) {
+// (16-byte aligned, zero-padded to whole 512-entry chunks), the other dims'
+// coordinate tables, then (stencil batches: halo != nullptr) the class record (the
+// class count of each dim, written by the table build) and each dim's class block
+// (entries, starts, offset lists of 2H words; capacities from class_cap).  The map
+// and redistribution kernels stage the prefix T + last dim's table in LDS when it
+// fits (else T only); the counting kernel stages T and the class blocks.
+static int layout_tables(DevCand& d, int H, const int32_t* halo) {
     const int K = d.lrank;
     int64_t off = up4(d.vol);
     const int64_t t_end = off + 4;
     d.coord_off[K - 1] = (int32_t)std::min<int64_t>(off, INT32_MAX);
     off += (d.extent[K - 1] + 511) & ~int64_t(511);  // zero-padded to whole 512-entry chunks
     const int64_t c_end = off + 4;                   // slack for the last four-entry read of a ragged row
-    d.hstride = 2 * H;
-    for (int k = 0; k < K; ++k) d.dl_off[k] = 0;     // outer dims: offsets come from the tables
-    int64_t d_end = c_end;
-    if (H > 0) {
-        off = up4(off);
-        d.dl_off[K - 1] = (int32_t)std::min<int64_t>(off, INT32_MAX);
-        off += 2 * H * d.extent[K - 1];
-        off = up4(off);
-        d_end = off + 4;
-    }
-    off = std::max(off, d_end);
+    off = std::max(off, c_end);
     for (int k = 0; k < K - 1; ++k) {
         d.coord_off[k] = (int32_t)std::min<int64_t>(off, INT32_MAX);
         off += d.extent[k];
     }
+    d.hstride = 2 * H;
+    for (int k = 0; k < TM_MAX_LRANK; ++k) d.cls_off[k] = d.cls_cap[k] = 0;
+    d.cls_base = d.cls_words = 0;
+    if (halo) {
+        off = up4(off);
+        const int64_t cb = off;
+        off += 4;
+        for (int k = 0; k < K; ++k) {
+            const int64_t cap = class_cap(d, k, halo[k]);
+            if (off > INT32_MAX || cap > INT32_MAX / std::max(1, 2 * H)) return TM_EOVERFLOW;
+            d.cls_cap[k] = (int32_t)cap;
+            d.cls_off[k] = (int32_t)off;
+            off += up4(cap) + up4(cap + 1) + up4(cap * 2 * H);
+        }
+        if (off - cb > INT32_MAX) return TM_EOVERFLOW;
+        d.cls_base = (int32_t)cb;
+        d.cls_words = (int32_t)(off - cb);
+    }
     d.cl_lds = c_end <= kMaxLdsWords ? 1 : 0;
-    d.dl_lds = H > 0 && d_end <= kMaxLdsWords ? 1 : 0;
-    const int64_t staged = d.dl_lds ? d_end : (d.cl_lds ? c_end : t_end);
+    const int64_t staged = d.cl_lds ? c_end : t_end;
     const int64_t words = up4(std::max(off, staged));  // the next candidate's tables start 16-byte aligned
     if (words > INT32_MAX) return TM_EOVERFLOW;
     d.lds_words = (int32_t)staged;
@@ -85,13 +90,12 @@ static int layout_tables(DevCand& d, int H) {
     return TM_OK;
 }
 
-static void layout_items(Compiled& cp, int64_t cells_per_item) {
+static void layout_items(Compiled& cp, int64_t tuples_per_item) {
     int64_t items = 0;
     for (auto& d : cp.cands) {
-        const int64_t rpi = rows_per_item_for(d, cells_per_item);
-        d.rows_per_item = (int32_t)rpi;
+        d.citems = count_items(d, tuples_per_item);
         d.item_first = items;
-        items += (d.rows + rpi - 1) / rpi;
+        items += d.citems;
     }
     cp.items = items;
     cp.hdr.total_items = items;
@@ -99,7 +103,7 @@ static void layout_items(Compiled& cp, int64_t cells_per_item) {
 
 // Validates and compiles n candidates.  st == nullptr: tables without halo flags.
 // need_lds: every candidate's tables must fit the LDS budget of the kernels.
-static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st, int64_t cells_per_item,
+static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st, int64_t tuples_per_item,
                          bool need_lds, Compiled& cp) {
     if (n < 0) return set_error(TM_EINVAL, "n = %lld", (long long)n);
     if (n > 0 && !c) return set_error(TM_EINVAL, "null candidate array");
@@ -116,7 +120,7 @@ static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
             cp.hdr.halo[d] = st->halo[d];
         }
         if (hmax > kMaxHalo) return set_error(TM_ENOTSUP, "halo %d above the kernels' limit of %d", hmax, kMaxHalo);
-        cp.K = st->lrank;
+        cp.K = 0;  // the largest launch rank in the batch
         cp.H = std::max(1, hmax);
         cp.hdr.elem_bytes = st->elem_bytes;
         cp.hdr.lrank = st->lrank;
@@ -127,12 +131,13 @@ static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
         Shapes sh;
         int rc = validate_shapes(&c[i], &sh);
         if (rc != TM_OK) return set_error(rc, "candidate %lld: %s", (long long)i, tm_last_error());
-        if (st && c[i].lrank != st->lrank)
+        // a candidate of launch rank k takes the stencil's first k halo widths
+        if (st && c[i].lrank > st->lrank)
             return set_error(TM_EINVAL, "candidate %lld: lrank %d but the stencil has %d", (long long)i, c[i].lrank,
                              st->lrank);
         DevCand& d = cp.cands[(size_t)i];
         rc = fill_devcand(&c[i], sh, &d);
-        if (rc == TM_OK) rc = layout_tables(d, st ? cp.H : 0);
+        if (rc == TM_OK) rc = layout_tables(d, st ? cp.H : 0, st ? cp.hdr.halo : nullptr);
         if (rc != TM_OK) return set_error(rc, "candidate %lld: tables too large", (long long)i);
         if (need_lds && d.lds_words > kMaxLdsWords)
             return set_error(TM_ENOTSUP, "candidate %lld: %d table words exceed the LDS budget of %d", (long long)i,
@@ -144,13 +149,22 @@ static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
         words += d.words;
         cp.max_words = std::max(cp.max_words, d.lds_words);
         cp.max_all_words = std::max(cp.max_all_words, d.words);
+        if (st) {
+            const int64_t cw = up4(d.vol) + d.cls_words;  // counting: staged when it fits, else read in place
+            if (cw <= kMaxLdsWords) cp.cnt_words = std::max<int32_t>(cp.cnt_words, (int32_t)cw);
+            int64_t b = 1;
+            for (int k = 0; k < d.lrank; ++k) b = std::min<int64_t>(b * d.cls_cap[k], int64_t(1) << 50);
+            cp.tuples += b;
+            cp.K = std::max(cp.K, (int)d.lrank);
+        }
         cp.points += d.npoints;
         cp.max_points = std::max(cp.max_points, d.npoints);
         cp.max_vol = std::max(cp.max_vol, d.vol);
     }
     cp.arena_words = words;
     cp.hdr.max_words = cp.max_words;
-    layout_items(cp, cells_per_item > 0 ? cells_per_item : default_cells_per_item(cp.points));
+    cp.hdr.cnt_words = cp.cnt_words;
+    layout_items(cp, tuples_per_item > 0 ? tuples_per_item : default_tuples_per_item(cp.tuples));
     return TM_OK;
 }
 
@@ -238,9 +252,9 @@ static int num_cus() {
     return n;
 }
 
-static int count_grid(int K, int H, int lds_words, int64_t items, int wg_per_cu) {
+static int count_grid(int lds_words, int64_t items, int wg_per_cu) {
     int per_cu = 0;
-    if (count_kernel_occupancy(K, H, lds_words, &per_cu) != 0 || per_cu < 1) per_cu = 1;
+    if (count_kernel_occupancy(lds_words, &per_cu) != 0 || per_cu < 1) per_cu = 1;
     if (wg_per_cu > 0) per_cu = std::min(per_cu, wg_per_cu);
     const int64_t g = (int64_t)per_cu * num_cus();
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, items));
@@ -304,11 +318,10 @@ static int eval_stencil(const tm_candidate* c, int64_t n, const tm_stencil* st, 
     DeviceBatch db;
     rc = upload_batch(cp, db, s);
     if (rc == TM_OK) {
-        const int grid = count_grid(cp.K, cp.H, cp.max_words, cp.items, 0);
+        const int grid = count_grid(cp.cnt_words, cp.items, 0);
         hipError_t e = launch_reset(db.hdr, db.counter, d_out, n, s);
         if (e == hipSuccess) e = launch_build_tables(db.hdr, db.cands, n, db.arena, 1, s);
-        if (e == hipSuccess)
-            e = launch_count(cp.K, cp.H, db.hdr, db.cands, db.arena, db.counter, d_out, grid, cp.max_words, s);
+        if (e == hipSuccess) e = launch_count(db.hdr, db.cands, db.arena, db.counter, d_out, grid, cp.cnt_words, s);
         if (e == hipSuccess) e = launch_finalize_select(db.hdr, d_out, nullptr, s);
         if (e != hipSuccess) rc = set_error(TM_EDEVICE, "stencil launch: %s", hipGetErrorString(e));
     }
@@ -570,7 +583,7 @@ static hipError_t plan_enqueue(tm_plan* p, int stage, tm_stencil_cost* out, int6
         if (e != hipSuccess) return e;
     }
     if (stage == 1 || stage < 0) {
-        e = launch_count(cp.K, cp.H, p->d_hdr, p->d_cands, p->d_arena, p->d_counter, out, grid, cp.max_words, s);
+        e = launch_count(p->d_hdr, p->d_cands, p->d_arena, p->d_counter, out, grid, cp.cnt_words, s);
         if (e != hipSuccess) return e;
     }
     if (stage == 2 || stage < 0) e = launch_finalize_select(p->d_hdr, out, best, s);
@@ -594,7 +607,7 @@ static int capture(tm_plan* p, int stage, tm_stencil_cost* out, int64_t* best, i
 }
 
 static int plan_graphs(tm_plan* p, tm_stencil_cost* out, int64_t* best) {
-    const int grid = count_grid(p->cp.K, p->cp.H, p->cp.max_words, p->cp.items, p->wg_per_cu);
+    const int grid = count_grid(p->cp.cnt_words, p->cp.items, p->wg_per_cu);
     if (p->g_valid && p->g_grid == grid && p->g_out == out && p->g_best == best) return TM_OK;
     plan_drop_graphs(p);
     int rc = capture(p, -1, out, best, grid, &p->g_full);
@@ -727,6 +740,26 @@ extern "C" int tm_plan_info(const tm_plan* p, int64_t* n, int64_t* items, int64_
     return TM_OK;
 }
 
+extern "C" int tm_plan_class_tuples(tm_plan* p, int64_t* tuples, void* stream) {
+    if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
+    if (!tuples) return set_error(TM_EINVAL, "null output");
+    *tuples = 0;
+    if (p->cp.hdr.n == 0) return TM_OK;
+    if (!p->d_arena || p->cap_words < p->cp.arena_words) return set_error(TM_EINVAL, "no tables yet: run the plan first");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* d_tot = nullptr;
+    TM_HIP(hipMallocAsync((void**)&d_tot, 8, s));
+    unsigned long long h = 0;
+    hipError_t e = hipMemsetAsync(d_tot, 0, 8, s);
+    if (e == hipSuccess) e = launch_class_tuples(p->d_cands, p->cp.hdr.n, p->d_arena, d_tot, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, d_tot, 8, hipMemcpyDeviceToHost, s);
+    (void)hipFreeAsync(d_tot, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_error(TM_EDEVICE, "class tuples: %s", hipGetErrorString(e));
+    *tuples = (int64_t)h;
+    return TM_OK;
+}
+
 extern "C" int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cells_per_item, int32_t* wg_per_cu,
                                 void* stream) {
     if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
@@ -738,10 +771,10 @@ extern "C" int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cel
     hipEvent_t e0, e1;
     TM_HIP(hipEventCreate(&e0));
     TM_HIP(hipEventCreate(&e1));
-    const int64_t cells_opts[] = {1 << 15, 1 << 17, 1 << 19};
+    const int64_t cells_opts[] = {1 << 10, 1 << 12, 1 << 14};
     const int wg_opts[] = {0, 2, 1};
     float best_ms = 1e30f;
-    int64_t best_c = default_cells_per_item(p->cp.points);
+    int64_t best_c = default_tuples_per_item(p->cp.tuples);
     int best_w = 0;
     int rc = TM_OK;
     for (int64_t cpi : cells_opts) {
@@ -754,7 +787,7 @@ extern "C" int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cel
             break;
         }
         for (int w : wg_opts) {
-            const int grid = count_grid(p->cp.K, p->cp.H, p->cp.max_words, p->cp.items, w);
+            const int grid = count_grid(p->cp.cnt_words, p->cp.items, w);
             float tot = 0.f;
             for (int rep = 0; rep < 3 && rc == TM_OK; ++rep) {
                 hipError_t e = launch_reset(p->d_hdr, p->d_counter, d_out, p->cp.hdr.n, s);
@@ -797,7 +830,7 @@ extern "C" int tm_plan_set_launch(tm_plan* p, int64_t cells_per_item, int32_t wg
     p->cells_per_item = cells_per_item;
     p->wg_per_cu = wg_per_cu;
     if (p->cp.hdr.n == 0) return TM_OK;
-    layout_items(p->cp, cells_per_item > 0 ? cells_per_item : default_cells_per_item(p->cp.points));
+    layout_items(p->cp, cells_per_item > 0 ? cells_per_item : default_tuples_per_item(p->cp.tuples));
     plan_drop_graphs(p);
     return plan_upload(p, (hipStream_t)stream);
 }
@@ -812,7 +845,7 @@ int32_t plan_max_vol(const tm_plan* p) { return p->cp.max_vol; }
 const int32_t* plan_halo(const tm_plan* p) { return p->d_hdr->halo; }
 const DevHeader* plan_hdr(const tm_plan* p) { return p->d_hdr; }
 int64_t plan_cells_per_item(const tm_plan* p) {
-    return p->cells_per_item > 0 ? p->cells_per_item : default_cells_per_item(p->cp.points);
+    return p->cells_per_item > 0 ? p->cells_per_item : default_tuples_per_item(p->cp.tuples);
 }
 
 int plan_features(const tm_plan* p, float* d_feat, hipStream_t s) {
@@ -964,13 +997,9 @@ hipError_t plan_eval_sub(tm_plan* p, SearchBufs* sb, hipStream_t s) {
     if (e == hipSuccess) {
         // survivors' work items are bounded by the batch's largest candidate
         int64_t max_items = 0;
-        for (const auto& d : cp.cands) {
-            const int64_t rpi = std::max<int64_t>(1, plan_cells_per_item(p) / std::max<int32_t>(d.L, 1));
-            max_items = std::max<int64_t>(max_items, (d.rows + rpi - 1) / rpi);
-        }
-        const int grid = count_grid(cp.K, cp.H, cp.max_words, std::max<int64_t>(1, max_items * nsel), p->wg_per_cu);
-        e = launch_count(cp.K, cp.H, sb->sub_hdr, sb->sub, sb->sub_arena, sb->sub_counter, sb->sub_out, grid,
-                         cp.max_words, s);
+        for (const auto& d : cp.cands) max_items = std::max<int64_t>(max_items, count_items(d, plan_cells_per_item(p)));
+        const int grid = count_grid(cp.cnt_words, std::max<int64_t>(1, max_items * nsel), p->wg_per_cu);
+        e = launch_count(sb->sub_hdr, sb->sub, sb->sub_arena, sb->sub_counter, sb->sub_out, grid, cp.cnt_words, s);
     }
     if (e == hipSuccess) e = launch_finalize_select(sb->sub_hdr, sb->sub_out, nullptr, s);
     return e;
@@ -983,7 +1012,7 @@ int plan_exhaustive_search(tm_plan* p, const int64_t* seg, int64_t nseg, int64_t
     int rc = plan_search_prepare(p, seg, nseg, 0, false, &sb, s);
     if (rc == TM_OK) rc = plan_ensure_arena(p, s);
     if (rc != TM_OK) return rc;
-    const int grid = count_grid(p->cp.K, p->cp.H, p->cp.max_words, p->cp.items, p->wg_per_cu);
+    const int grid = count_grid(p->cp.cnt_words, p->cp.items, p->wg_per_cu);
     hipError_t e = plan_enqueue(p, -1, sb->all_out, nullptr, grid, s);
     if (e == hipSuccess) e = launch_select_segments(sb->all_out, sb->seg, nseg, d_best, s);
     if (e == hipSuccess) e = launch_pick_costs(d_best, sb->seg, sb->all_out, nseg, d_best_cost, s);

@@ -420,17 +420,23 @@ int tm_greedy_grid(int64_t P, int32_t k, int32_t* out_f) {
     int rc = check_pk(P, k);
     if (rc != TM_OK) return rc;
     if (!out_f) return set_error(TM_EINVAL, "null argument");
+    // App. A.2: every prime of P, smallest first, multiplies a currently smallest
+    // factor.  Equal factors are interchangeable, so the factors are kept in
+    // descending order: the prime multiplies the last one, which then moves left
+    // past the factors it has overtaken; the result needs no final sort.
     std::vector<std::pair<int64_t, int>> pe;
     factorize(P, pe);
-    int64_t f[4] = {1, 1, 1, 1};
-    for (auto& [p, a] : pe)
+    int64_t f[TM_MAX_LRANK] = {1, 1, 1, 1};
+    for (const auto& [p, a] : pe)
         for (int e = 0; e < a; ++e) {
-            int j = 0;
-            for (int m = 1; m < k; ++m)
-                if (f[m] < f[j]) j = m;
-            f[j] *= p;
+            int j = k - 1;
+            const int64_t v = f[j] * p;
+            while (j > 0 && f[j - 1] < v) {
+                f[j] = f[j - 1];
+                --j;
+            }
+            f[j] = v;
         }
-    std::sort(f, f + k, [](int64_t x, int64_t y) { return x > y; });
     for (int m = 0; m < k; ++m) out_f[m] = (int32_t)f[m];
     return TM_OK;
 }

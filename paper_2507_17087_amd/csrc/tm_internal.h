@@ -21,11 +21,13 @@ struct DevCand {
     int64_t arena_off;                  // word offset of this candidate's tables
     int64_t item_first;                 // first work item of this candidate
     int64_t rows;                       // points / extent[lrank-1]
-    int32_t rows_per_item, L;           // rows per work item; row length = last extent
+    int32_t rows_per_item, L;           // rows per work item (redistribution); row length = last extent
     int32_t coord_off[TM_MAX_LRANK];    // table offsets of the per-dim coordinate tables
-    int32_t dl_off[TM_MAX_LRANK];       // table offsets of the per-dim neighbour-offset lists
-    int32_t lds_words, hstride;         // leading words staged in LDS; list stride (2*H)
-    int32_t dl_lds, cl_lds;             // last dim's offset lists / coordinate table are in the staged prefix
+    int32_t cls_off[TM_MAX_LRANK];      // table offsets of the per-dim coordinate-class blocks
+    int32_t cls_cap[TM_MAX_LRANK];      // class capacity of each dim (an upper bound on the class count)
+    int32_t cls_base, cls_words;        // class record (four class counts) + the blocks: offset and words
+    int32_t lds_words, hstride;         // leading words staged in LDS by the map kernel; offset-list stride (2*H)
+    int32_t citems, cl_lds;             // counting work items; last dim's coordinate table is in the staged prefix
     int32_t fshape[TM_MAX_MRANK], fstride[TM_MAX_MRANK];
     int8_t proj_src[TM_MAX_MRANK], proj_mode[TM_MAX_MRANK];
     int32_t rank[TM_MAX_OPS];                    // rank before op t
@@ -40,9 +42,9 @@ struct DevHeader {
     int64_t total_items;  // work items over all candidates
     int32_t halo[TM_MAX_LRANK];
     int32_t elem_bytes, lrank;
-    int32_t max_words, H;  // largest staged table; max halo (0: no neighbour lists)
+    int32_t max_words, H;  // largest table prefix staged by the map kernel; max halo (offset-list stride 2H)
     int32_t node_level;    // owner tables hold nodes only (node-level exchange volume)
-    int32_t pad0;
+    int32_t cnt_words;     // LDS words of the counting launch (owner table + class blocks staged)
 };
 
 // Host-side result of validation.
@@ -51,26 +53,57 @@ struct Shapes {
     int64_t size[TM_MAX_OPS + 1][TM_MAX_MRANK];
 };
 
-// Word layout of an entry of a per-dim coordinate table: bits 0..23 hold the
-// contribution of that coordinate to the linear final-space index (volumes are at
-// most 2^24), bits 24..27 the number of distinct non-zero index offsets from that
-// coordinate to its star neighbours along the dim (within the halo).  That list of
-// offsets is stored separately, 2*H words per coordinate, zero-padded.
+// An entry of a per-dim coordinate table holds the contribution of that coordinate
+// to the linear final-space index (volumes are at most 2^24).
+//
+// Coordinate classes (stencil batches).  Along launch dim d, coordinate x has a
+// contribution C_d[x] and a set of distinct non-zero index offsets C_d[x +- s] -
+// C_d[x] to its in-domain star neighbours (1 <= s <= h_d).  The distinct foreign
+// owners of a cell depend on nothing else: cells whose coordinates fall in the same
+// class along every dim have equal counts.  A class is a maximal run of consecutive
+// coordinates with equal contribution and equal offset set; its block stores, for
+// class k, the entry (contribution | offset count << kCntShift), the first
+// coordinate (k = R is the extent, so the run length is start[k+1] - start[k]) and
+// the sorted offsets (2*H words, zero-padded).
 constexpr int32_t kValMask = 0x00ffffff;
 constexpr int kCntShift = 24;
-// Bit 28 of a last-dim entry with offsets: cell x - 1 has the same contribution and
-// the same offset list, so (in the same row) the same foreign owners.
-constexpr int kSameShift = 28;
-// Bit 29: cells x - 1 and x each have a single offset, pointing at the other's
-// coordinate (the two sides of one block boundary compare the same pair of owners),
-// so in a row without outer offsets both count the same foreign owners.
-constexpr int kMirrorShift = 29;
 constexpr int32_t kMaxLdsWords = 32768;
 // Redistribution: LDS words for the joint runs of a pair's last dim (rows of at most
 // kRedistMaxL cells), staged after the pair's two tables.
 constexpr int32_t kRedistRuns = 512;
 constexpr int32_t kRedistMaxL = 4096;
 constexpr int kMaxHalo = 4;
+
+// Upper bound on the class count of launch dim d (its block capacity): a class
+// boundary at x needs a change of contribution within the halo of x (at some c with
+// x - h <= c <= x + h), so there are at most 1 + changes * (2h + 1) classes, and
+// never more than the extent.  Block projections change at most s - 1 times along
+// the dim, cyclic ones at every step.
+__host__ __device__ inline int64_t class_cap(const DevCand& c, int d, int h) {
+    const int64_t l = c.extent[d];
+    int64_t ch = 0;
+    for (int j = 0; j < c.frank; ++j) {
+        if (c.proj_src[j] != d) continue;
+        const int64_t s = c.fshape[j];
+        ch += c.proj_mode[j] == TM_BLOCK ? (s - 1 < l - 1 ? s - 1 : l - 1) : l - 1;
+    }
+    if (ch > l - 1) ch = l - 1;
+    const int64_t r = 1 + ch * (2 * (int64_t)h + 1);
+    return r < l ? r : l;
+}
+
+// Counting work items of a candidate: its class-tuple bound (product of the
+// capacities) split into items of about `per_item` tuples (at least one item).
+__host__ __device__ inline int32_t count_items(const DevCand& c, int64_t per_item) {
+    int64_t b = 1;
+    for (int d = 0; d < c.lrank; ++d) {
+        b *= c.cls_cap[d] > 0 ? c.cls_cap[d] : 1;
+        if (b > (int64_t(1) << 50)) b = int64_t(1) << 50;
+    }
+    if (per_item < 1) per_item = 1;
+    const int64_t it = (b + per_item - 1) / per_item;
+    return (int32_t)(it < 1 ? 1 : (it > (int64_t(1) << 30) ? (int64_t(1) << 30) : it));
+}
 
 int set_error(int code, const char* fmt, ...);
 int validate_shapes(const tm_candidate* c, Shapes* sh);
@@ -81,9 +114,11 @@ hipError_t launch_build_tables(const DevHeader* hdr, const DevCand* cands, int64
                                int32_t mode_halo, hipStream_t s);
 hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_cost* out, int64_t n,
                         hipStream_t s);
-hipError_t launch_count(int K, int H, const DevHeader* hdr, const DevCand* cands, const int32_t* arena,
+hipError_t launch_count(const DevHeader* hdr, const DevCand* cands, const int32_t* arena,
                         unsigned long long* counter, tm_stencil_cost* out, int grid, int lds_words,
                         hipStream_t s);
+hipError_t launch_class_tuples(const DevCand* cands, int64_t n, const int32_t* arena, unsigned long long* total,
+                               hipStream_t s);
 hipError_t launch_finalize_select(const DevHeader* hdr, tm_stencil_cost* out, int64_t* best,
                                   hipStream_t s);
 hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* seg, int64_t nseg,
@@ -99,6 +134,6 @@ hipError_t launch_matmul(const DevCand* cands, int64_t n, const int32_t* arena, 
 hipError_t launch_matmul_finalize(const DevCand* cands, int64_t n, const int64_t* proc_off,
                                   const unsigned long long* per_proc, int64_t tile_bytes,
                                   tm_matmul_cost* out, int64_t* out_per_proc, hipStream_t s);
-int count_kernel_occupancy(int K, int H, int lds_words, int* blocks_per_cu);
+int count_kernel_occupancy(int lds_words, int* blocks_per_cu);
 
 }  // namespace tmk

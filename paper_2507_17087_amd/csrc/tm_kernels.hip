@@ -20,6 +20,8 @@
 // exact integer.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tm_internal.h"
 #include "tm_chain.h"
 
@@ -49,14 +51,49 @@ __device__ __forceinline__ unsigned long long wave_sum64(int v) {
 
 // ------------------------------------------------------------------ table build
 
-// One workgroup per candidate (grid-stride over candidates).  With halos (use_halo),
-// each coordinate x of launch dim d gets the number of distinct non-zero offsets
-// C_d[x +- s] - C_d[x] (1 <= s <= h_d, in-domain neighbours) in its entry, and for
-// the last launch dim the list of those offsets.
+// Sorted distinct non-zero offsets C[x +- s] - C[x] (1 <= s <= h, in-domain
+// neighbours) of coordinate x, in slots o[0..n); unused slots hold INT32_MAX.
+__device__ __forceinline__ int coord_offsets(const int32_t* __restrict__ C, int64_t x, int64_t l, int h,
+                                             int32_t (&o)[2 * kMaxHalo]) {
+#pragma unroll
+    for (int i = 0; i < 2 * kMaxHalo; ++i) o[i] = INT32_MAX;
+    const int32_t cv = C[x];
+    int n = 0;
+#pragma unroll
+    for (int s = 1; s <= kMaxHalo; ++s) {
+#pragma unroll
+        for (int dir = 0; dir < 2; ++dir) {
+            const int64_t xx = dir ? x + s : x - s;
+            if (s > h || xx < 0 || xx >= l) continue;
+            const int32_t dv = C[xx] - cv;
+            bool seen = dv == 0;
+#pragma unroll
+            for (int i = 0; i < 2 * kMaxHalo; ++i) seen = seen || o[i] == dv;
+            if (seen) continue;
+            // insert into the sorted slots (static indices only: no scratch)
+#pragma unroll
+            for (int i = 2 * kMaxHalo - 1; i >= 0; --i) {
+                const bool shift = i > 0 && o[i - 1] > dv;
+                const bool here = i == 0 ? o[0] > dv : (o[i - 1] <= dv && o[i] > dv);
+                o[i] = shift ? o[i - 1] : (here ? dv : o[i]);
+            }
+            ++n;
+        }
+    }
+    return n;
+}
+
+// One workgroup per candidate (grid-stride over candidates): the owner table
+// T[v] of every final-space coordinate and the coordinate tables C_d.  With halos
+// (use_halo), also the coordinate classes of every launch dim (see tm_internal.h):
+// a coordinate starts a class when its contribution or offset set differs from its
+// left neighbour's; class indices come from a workgroup prefix count of the starts.
 __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restrict__ hdr,
                                                       const DevCand* __restrict__ cands,
                                                       int32_t* __restrict__ arena, int use_halo) {
     __shared__ DevCand sc;
+    __shared__ int32_t s_wt[4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t n = hdr->n;
     for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
         __syncthreads();
@@ -66,54 +103,67 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
         // node-level tables keep the node of each owner (GPU bits cleared): the
         // counting kernel then counts distinct other nodes per cell
         const int32_t keep = hdr->node_level ? ~((1 << sc.gbits) - 1) : -1;
-        for (int32_t v = threadIdx.x; v < sc.vol; v += blockDim.x) base[v] = owner_key(sc, v) & keep;
-        const int hs = sc.hstride;
+        for (int32_t v = tid; v < sc.vol; v += blockDim.x) base[v] = owner_key(sc, v) & keep;
         for (int d = 0; d < sc.lrank; ++d) {
             const int64_t l = sc.extent[d];
-            const int h = use_halo ? hdr->halo[d] : 0;
             int32_t* ct = base + sc.coord_off[d];
-            const bool last = d == sc.lrank - 1;
-            int32_t* dl = base + sc.dl_off[d];
-            for (int64_t x = threadIdx.x; x < l; x += blockDim.x) {
-                const int32_t val = coord_value(sc, d, x);
-                int32_t found[2 * kMaxHalo];
-                int cnt = 0;
-                for (int s = 1; s <= h; ++s) {
-                    for (int dir = 0; dir < 2; ++dir) {
-                        const int64_t xx = dir ? x + s : x - s;
-                        if (xx < 0 || xx >= l) continue;
-                        const int32_t dv = coord_value(sc, d, xx) - val;
-                        if (dv == 0) continue;
-                        bool seen = false;
-                        for (int i = 0; i < cnt; ++i) seen = seen || (found[i] == dv);
-                        if (!seen) found[cnt++] = dv;
+            for (int64_t x = tid; x < l; x += blockDim.x) ct[x] = coord_value(sc, d, x);
+            if (d == sc.lrank - 1)  // zero entries up to a multiple of 512 (read in whole chunks)
+                for (int64_t x = l + tid; x < ((l + 511) & ~int64_t(511)); x += blockDim.x) ct[x] = 0;
+        }
+        if (!use_halo) continue;
+        __syncthreads();  // coordinate tables complete
+        const int hs = sc.hstride;
+        int32_t* rec = base + sc.cls_base;
+        for (int d = 0; d < sc.lrank; ++d) {
+            const int64_t l = sc.extent[d];
+            const int h = hdr->halo[d];
+            const int32_t* ct = base + sc.coord_off[d];
+            const int64_t cap = sc.cls_cap[d];
+            int32_t* ce = base + sc.cls_off[d];
+            int32_t* cs = ce + ((cap + 3) & ~int64_t(3));
+            int32_t* co = cs + ((cap + 4) & ~int64_t(3));
+            int64_t run = 0;  // classes so far (the same in every thread)
+            for (int64_t x0 = 0; x0 < l; x0 += blockDim.x) {
+                const int64_t x = x0 + tid;
+                bool start = false;
+                int32_t val = 0, o[2 * kMaxHalo];
+                int no = 0;
+                if (x < l) {
+                    val = ct[x];
+                    no = coord_offsets(ct, x, l, h, o);
+                    start = x == 0;
+                    if (!start) {
+                        int32_t p[2 * kMaxHalo];
+                        (void)coord_offsets(ct, x - 1, l, h, p);
+                        start = ct[x - 1] != val;
+#pragma unroll
+                        for (int i = 0; i < 2 * kMaxHalo; ++i) start = start || p[i] != o[i];
                     }
                 }
-                if (last)  // only the last dim's lists are stored (outer dims use the tables)
-                    for (int i = 0; i < hs; ++i) dl[x * hs + i] = i < cnt ? found[i] : 0;
-                ct[x] = val | (cnt << kCntShift);
-            }
-            if (d == sc.lrank - 1)  // zero entries up to a multiple of 512 (scanned eight per lane)
-                for (int64_t x = l + threadIdx.x; x < ((l + 511) & ~int64_t(511)); x += blockDim.x) ct[x] = 0;
-            if (last && hs > 0) {
-                // mark cells whose counts equal their left neighbour's (bits 28..31 of
-                // the entries are otherwise zero): same contribution and offset list
-                // (bit 28, every row), or single offsets pointing at each other (bit
-                // 29, rows without outer offsets)
+                const uint64_t m = __ballot(start);
+                if (lane == 0) s_wt[wid] = __popcll(m);
                 __syncthreads();
-                for (int64_t x = 1 + threadIdx.x; x < l; x += blockDim.x) {
-                    const int32_t e = ct[x] & 0x0fffffff, ep = ct[x - 1] & 0x0fffffff;
-                    const int n = (e >> kCntShift) & 0xf, np = (ep >> kCntShift) & 0xf;
-                    if (n == 0) continue;
-                    bool same = e == ep;
-                    for (int i = 0; i < hs && same; ++i) same = dl[x * hs + i] == dl[(x - 1) * hs + i];
-                    bool mirror = false;
-                    if (!same && n == 1 && np == 1) {
-                        const int32_t dv = dl[(x - 1) * hs];
-                        mirror = dv == (e & kValMask) - (ep & kValMask) && dl[x * hs] == -dv;
-                    }
-                    if (same || mirror) ct[x] = e | (1 << (same ? kSameShift : kMirrorShift));
+                int64_t below = 0, tot = 0;
+                for (int w = 0; w < 4; ++w) {
+                    below += w < wid ? s_wt[w] : 0;
+                    tot += s_wt[w];
                 }
+                if (start) {
+                    const int64_t idx = run + below + __builtin_amdgcn_mbcnt_hi(
+                                                              (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    if (idx < cap) {  // the capacity bounds the count (class_cap); never exceeded
+                        ce[idx] = val | (no << kCntShift);
+                        cs[idx] = (int32_t)x;
+                        for (int i = 0; i < hs; ++i) co[idx * hs + i] = i < no ? o[i] : 0;
+                    }
+                }
+                run += tot;
+                __syncthreads();  // s_wt is rewritten by the next chunk
+            }
+            if (tid == 0) {
+                if (run <= cap) cs[run] = (int32_t)l;
+                rec[d] = run <= cap ? (int32_t)run : -1;  // -1: poisoned (counted as such)
             }
         }
     }
@@ -148,713 +198,50 @@ hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_
 
 // ------------------------------------------------------------------ stencil counting
 //
-// A work item is a block of consecutive rows (all launch dims but the last fixed)
-// of one candidate.  A workgroup takes items from a global atomic counter (the
-// next one is requested while the current one runs), stages the candidate's owner
-// table and, when they fit, the last dim's coordinate table and offset lists in LDS
-// when the candidate changes (the outer dims' tables are read from global memory),
-// and gives each wave every fourth row of the item, in batches of 64 rows whose
-// fast outer entries and offsets one lane each works out at once, stepping the
-// outer coordinates without divisions.  Every cell of every row is read and
-// tested: a lane reads the coordinate entries of eight consecutive cells with two
-// LDS loads, and the test (does the row hold cells with last-dim offsets) gates
-// what follows.
-//   - A row's outer coordinates fix its base index and the distinct non-zero
-//     offsets to its outer neighbours, computed from the coordinate tables when
-//     the row lies within a halo of a block boundary of an outer dim.
-//   - Rows without outer offsets: a cell can have a foreign neighbour only along
-//     the last dim, i.e. when its entry's offset count is non-zero.  In rows of
-//     one chunk such cells form runs with equal results (listed once per row
-//     range); consecutive such rows run in a tight loop.  With 8 or more runs a row
-//     evaluates its runs at once, one per lane, and a row with the same base index
-//     as the previous one reuses each lane's share; with fewer, rows queue their
-//     base index and a drain evaluates the runs of several rows together.  Longer
-//     rows compact their flagged cells into a per-wave LDS queue (prefix count from
-//     ballots), evaluated 64 at a time; a chunk holding more than 64 of them is
-//     evaluated in place.
-//   - Rows with outer offsets: every cell counts.  Cells with equal results share
-//     one evaluation: a stretch of equal entries without last-dim offsets (same
-//     index, same neighbours), or of flagged cells marked equal to their left
-//     neighbour.  For rows of one chunk these runs are listed once per row range,
-//     and a row evaluates each run once, one per lane, times its length; a row whose
-//     offsets come from the slower outer dims only reuses the previous such row's
-//     shares while its fast outer entry and the slower outer coordinates repeat.
-// Evaluating a cell: its owner o = T[v], then the owners T[v + delta] over the row
-// offsets and the cell's last-dim offsets; the distinct ones other than o are
-// counted (and those on another node).  Lanes count in registers, waves reduce,
-// and one 64-bit atomic per wave and item adds to the candidate's totals.
+// The distinct foreign owners of a cell depend only on the class of its coordinate
+// along every launch dim (tm_internal.h): the cell's linear final index is the sum
+// of the classes' contributions, and its star neighbours sit at that index plus
+// the classes' offsets.  So a candidate's count is a sum over the tuples of its
+// per-dim classes (the Cartesian product), each tuple evaluated once and weighted
+// by the number of cells it stands for, the product of its classes' run lengths.
+//
+// A work item is a contiguous range of one candidate's class tuples in C order
+// (last dim fastest); a candidate's items split its tuples evenly.  Workgroups take
+// items from a global atomic counter (the next one is requested while the current
+// one runs) and stage the candidate's owner table and class blocks in LDS when the
+// candidate changes and they fit (else they are read from global memory).  Each
+// thread evaluates every 256th tuple of the item: owner o = T[v], then the owners
+// T[v + delta] over the classes' offsets; the distinct ones other than o are
+// counted (and those on another node) times the tuple's weight, in 64 bits.  Waves
+// reduce, and one 64-bit atomic per wave and item adds to the candidate's totals.
 
-// Per-wave LDS arrays of kQueueCap words, qv and qx: the queue of flagged cells of
-// long rows (drained 128 at a time, two per lane; a push adds <= 64), or, for rows of
-// one chunk, the run maps (qx[0..128): runs of rows without outer offsets, qx[128..):
-// flagged runs and qv[128..): interior runs of rows with them).
-constexpr int kQueueCap = 256;
-constexpr int kCellsPerLane = 8;
-constexpr int kChunk = 64 * kCellsPerLane;
+constexpr int kFoundCache = 8;  // distinct foreign owners held in registers per tuple
 
-__device__ __forceinline__ int32_t cval(int32_t e) { return e & kValMask; }
-__device__ __forceinline__ int32_t ccnt(int32_t e) { return (e >> kCntShift) & 0xf; }
-
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Distinct owners, other than o, among T[v + delta] for delta in rl[0..nr) then
-// xl[0..nx).  Offsets are distinct within each list; equal owners are merged.
-// The first two owners are handled in straight-line code (the usual case).
-template <typename XP>
-__device__ __forceinline__ void eval_cell(const int32_t* __restrict__ T, int32_t v, const int32_t* rl, int nr,
-                                          XP xl, int nx, int gbits, int& cnt, int& icnt) {
-    const int n = nr + nx;
-    if (n == 0) return;
-    const int32_t o = T[v];
-    const int32_t onode = o >> gbits;
-    const int32_t d0 = nr > 0 ? rl[0] : xl[0];
-    const int32_t o0 = T[v + d0];
-    const bool f0 = o0 != o;
-    cnt += f0;
-    icnt += (f0 && (o0 >> gbits) != onode) ? 1 : 0;
-    if (n == 1) return;
-    const int32_t d1 = nr > 1 ? rl[1] : xl[1 - nr];
-    const int32_t o1 = T[v + d1];
-    const bool f1 = o1 != o && o1 != o0;
-    cnt += f1;
-    icnt += (f1 && (o1 >> gbits) != onode) ? 1 : 0;
-    for (int t = 2; t < n; ++t) {
-        const int32_t dt = t < nr ? rl[t] : xl[t - nr];
-        const int32_t ot = T[v + dt];
-        bool fresh = ot != o && ot != o0 && ot != o1;
-        for (int s = 2; s < t && fresh; ++s) {
-            const int32_t ds = s < nr ? rl[s] : xl[s - nr];
-            fresh = T[v + ds] != ot;
-        }
-        if (fresh) {
-            ++cnt;
-            icnt += ((ot >> gbits) != onode) ? 1 : 0;
-        }
-    }
-}
-
-// Evaluates the cells x0 .. x0+7 of a row (see above).  only_flagged: skip cells
-// without last-dim offsets (rows without outer offsets).
-template <int32_t SAME, typename XP>
-__device__ __forceinline__ void eval_group(const int32_t* __restrict__ T, XP DL, int HS,
-                                           const int32_t (&e8)[kCellsPerLane], int x0, int L, int32_t base,
-                                           const int32_t* rl, int nr, int gbits, bool only_flagged, int& cnt,
-                                           int& icnt) {
-    int32_t ep = -1;  // never a valid entry (bits 29..31 are zero)
-    int cp = 0, ip = 0;
-#pragma unroll
-    for (int j = 0; j < kCellsPerLane; ++j) {
-        const int x = x0 + j;
-        const int32_t e = e8[j];
-        const int nx = ccnt(e);
-        if (x >= L || (only_flagged && nx == 0)) continue;
-        // a flagged cell whose entry carries one of the SAME bits has the result of
-        // its left neighbour (evaluated just before, in this lane)
-        const bool same = SAME != 0 && j > 0 && (e & SAME) != 0;
-        if (!same && (e != ep || nx != 0)) {
-            cp = 0;
-            ip = 0;
-            eval_cell(T, base + cval(e), rl, nr, DL + x * HS, nx, gbits, cp, ip);
-            ep = nx == 0 ? e : -1;
-        }
-        cnt += cp;
-        icnt += ip;
-    }
-}
-
-// Distinct owners, other than T[v], among T[v + rl[t]] for t < nr (nr >= 1).
-__device__ __forceinline__ void eval_row_offsets(const int32_t* __restrict__ T, int32_t v, const int32_t* rl, int nr,
-                                                 int gbits, int& cnt, int& icnt) {
-    const int32_t o = T[v];
-    const int32_t onode = o >> gbits;
-    const int32_t o0 = T[v + rl[0]];
-    const int32_t o1 = T[v + (nr > 1 ? rl[1] : 0)];
-    const bool f0 = o0 != o;
-    const bool f1 = o1 != o && o1 != o0;
-    cnt += (int)f0 + (int)f1;
-    icnt += (f0 && (o0 >> gbits) != onode ? 1 : 0) + (f1 && (o1 >> gbits) != onode ? 1 : 0);
-    for (int t = 2; t < nr; ++t) {
-        const int32_t ot = T[v + rl[t]];
-        bool fresh = ot != o && ot != o0 && ot != o1;
-        for (int s2 = 2; s2 < t && fresh; ++s2) fresh = T[v + rl[s2]] != ot;
-        if (fresh) {
-            ++cnt;
-            icnt += ((ot >> gbits) != onode) ? 1 : 0;
-        }
-    }
-}
-
-// One queued cell (row base index bq, last-dim coordinate xq) of a row without
-// outer offsets: only its last-dim neighbours can be foreign.  The first two
-// offsets are loaded without branches (a cell's list always has HS >= 2 slots;
-// unused offsets are replaced by 0, which reads the cell's own owner), so the
-// owner lookups of the usual one- and two-offset cells issue together.
-template <typename XP>
-__device__ __forceinline__ void eval_queued(const int32_t* __restrict__ T, const int32_t* __restrict__ CL, XP DL,
-                                            int HS, int32_t bq, int32_t xq, int gbits, int& cnt, int& icnt) {
-    const int32_t e = CL[xq];
-    const int32_t d0 = DL[xq * HS], d1 = DL[xq * HS + 1];
-    const int32_t v = bq + cval(e);
-    const int nx = ccnt(e);
-    const int32_t o = T[v];
-    const int32_t o0 = T[v + (nx > 0 ? d0 : 0)];
-    const int32_t o1 = T[v + (nx > 1 ? d1 : 0)];
-    const int32_t onode = o >> gbits;
-    const bool f0 = o0 != o;
-    const bool f1 = o1 != o && o1 != o0;
-    cnt += (int)f0 + (int)f1;
-    icnt += (f0 && (o0 >> gbits) != onode ? 1 : 0) + (f1 && (o1 >> gbits) != onode ? 1 : 0);
-    for (int t = 2; t < nx; ++t) {
-        const int32_t ot = T[v + DL[xq * HS + t]];
-        bool fresh = ot != o && ot != o0 && ot != o1;
-        for (int s2 = 2; s2 < t && fresh; ++s2) fresh = T[v + DL[xq * HS + s2]] != ot;
-        if (fresh) {
-            ++cnt;
-            icnt += ((ot >> gbits) != onode) ? 1 : 0;
-        }
-    }
-}
-
-// Number of set bits of m in the lanes below this one.
-__device__ __forceinline__ int lanes_below(uint64_t m) {
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-// Flags of a lane's eight cells (bit j: cell j has last-dim offsets), the number of
-// flagged cells in the lanes below (prefix over the wave, from the ballots of the
-// four bit planes of the per-lane counts 0..8) and the wave's total.
-__device__ __forceinline__ void chunk_flags(const int32_t (&e8)[kCellsPerLane], uint32_t& fl, int& pre, int& tot) {
-    fl = 0;
-#pragma unroll
-    for (int j = 0; j < kCellsPerLane; ++j) fl |= ((uint32_t)e8[j] > (uint32_t)kValMask ? 1u : 0u) << j;
-    const int c = __popc(fl);
-    pre = 0;
-    tot = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const uint64_t m = __ballot((c >> b) & 1);
-        pre += lanes_below(m) << b;
-        tot += __popcll(m) << b;
-    }
-}
-
-__device__ __forceinline__ void load8(const int32_t* p, int32_t (&e8)[kCellsPerLane]) {
-    const i32x4 a = *reinterpret_cast<const i32x4*>(p);
-    const i32x4 b = *reinterpret_cast<const i32x4*>(p + 4);
-    e8[0] = a.x;
-    e8[1] = a.y;
-    e8[2] = a.z;
-    e8[3] = a.w;
-    e8[4] = b.x;
-    e8[5] = b.y;
-    e8[6] = b.z;
-    e8[7] = b.w;
-}
-
-// Distinct non-zero offsets from coordinate q of outer dim d to its in-domain
-// neighbours within the halo, appended to rl[nr..) (uniform: every lane writes the
-// same values).  Offsets equal to the previous one in the same direction are
-// dropped (a block holds consecutive coordinates).
-template <int H>
-__device__ __forceinline__ int outer_offsets(const int32_t* __restrict__ C, int32_t q, int32_t ext, int h,
-                                             int32_t* rl, int nr) {
-    const int32_t ev = cval(C[q]);
-#pragma unroll
-    for (int dir = 0; dir < 2; ++dir) {
-        int32_t prev = 0;
-#pragma unroll
-        for (int s = 1; s <= H; ++s) {
-            const int32_t xx = dir ? q + s : q - s;
-            if (s <= h && xx >= 0 && xx < ext) {
-                const int32_t dv = cval(C[xx]) - ev;
-                if (dv != 0 && dv != prev) rl[nr++] = dv;
-                prev = dv;
-            }
-        }
-    }
-    return nr;
-}
-
-// The rows [ra, rb) of the staged candidate, for one wave.
-template <int K, int H, typename XP>
-__device__ __forceinline__ void count_rows(const int32_t* __restrict__ T, const int32_t* __restrict__ G,
-                                           const int32_t* __restrict__ CL, XP DL,
-                                           const int32_t (&off)[K], const int32_t (&ext)[K], const int (&hal)[K],
-                                           int32_t ra, int32_t rb, int rs, int L, int gbits, int lane, int32_t* rl,
-                                           int32_t* qv, int32_t* qx, int32_t* ob, int& cnt, int& icnt) {
-    constexpr int HS = 2 * H;
-    constexpr int KO = K > 1 ? K - 1 : 1;
-    int qn = 0;  // wave-uniform queue length
-    // Rows that fit one chunk: in rows without outer offsets the flags of a lane's
-    // cells depend on the last coordinate only, so their compaction (per-lane
-    // flags, prefix over the wave, total) is computed once here.
-    const bool one_chunk = L <= kChunk;
-    uint32_t hfl = 0, rfl = 0, dfl = 0, ifl = 0;
-    int hpre = 0, htot = 0, rpre = 0, rtot = 0, dpre = 0, dtot = 0, ipre = 0, itot = 0;
-    if (one_chunk) {
-        int32_t e8[kCellsPerLane];
-        load8(CL + kCellsPerLane * lane, e8);
-        chunk_flags(e8, hfl, hpre, htot);
-        // runs: a flagged cell whose counts equal its left neighbour's has that
-        // neighbour's result; only run starts are kept -- rfl for rows without outer
-        // offsets (either bit), dfl for rows with them (equal entries only)
-#pragma unroll
-        for (int j = 0; j < kCellsPerLane; ++j) {
-            const bool f = (hfl >> j) & 1u;
-            rfl |= (f && !((e8[j] >> kSameShift) & 3) ? 1u : 0u) << j;
-            dfl |= (f && !((e8[j] >> kSameShift) & 1) ? 1u : 0u) << j;
-            // interior runs: cells without last-dim offsets, a run per maximal stretch
-            // of equal entries (same index, same neighbours in every row)
-            const int32_t x = kCellsPerLane * lane + j;
-            const int32_t el = j > 0 ? e8[j - 1] : (lane > 0 ? CL[x - 1] : -1);
-            ifl |= (x < L && !f && e8[j] != el ? 1u : 0u) << j;
-        }
-        const int ci = __popc(ifl);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint64_t mi = __ballot((ci >> b) & 1);
-            ipre += lanes_below(mi) << b;
-            itot += __popcll(mi) << b;
-        }
-        const int c = __popc(rfl), cd = __popc(dfl);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint64_t m = __ballot((c >> b) & 1), md = __ballot((cd >> b) & 1);
-            rpre += lanes_below(m) << b;
-            rtot += __popcll(m) << b;
-            dpre += lanes_below(md) << b;
-            dtot += __popcll(md) << b;
-        }
-    }
-    // Row queue (single-chunk rows with 1..128 runs of flagged cells): a row without
-    // outer offsets queues only its base index (lane i of qrow holds that of queued
-    // row i, fetched in the drain with a lane permute); a drain of rq_rows rows evaluates
-    // rq_rows * rtot <= 128 run starts, entry idx being run idx % rtot of queued row
-    // idx / rtot, each counted times its run length.  qx[0..128) holds that map as
-    // (run length << 18) | (x << 8) | row, built once here (staged in qx[128..256));
-    // qx[128..128 + dtot) then holds the flagged runs of rows with outer offsets and
-    // qv[128..128 + itot) their interior runs (rowd: when there are at most 128 of
-    // each; else such rows take the general dense path).
-    const bool rowq = one_chunk && rtot > 0 && rtot <= 128;
-    const bool fastq = one_chunk && rtot <= 128;  // rows without outer offsets in the tight loop (rowq, or no runs)
-    const bool rowd = one_chunk && dtot <= 128 && itot <= 128;
-    const int rq_rows = rowq ? (rtot == 1 ? 64 : 128 / rtot) : 0;  // at most 64: one row base per lane
-    const int rq_cells = rq_rows * rtot;
-    int nrow = 0;
-    if (rowq || rowd) {
-        auto stage_runs = [&](uint32_t f, int pos, int32_t bits) {
-            while (f) {
-                const int j = __builtin_ctz(f);
-                f &= f - 1;
-                const int32_t x = kCellsPerLane * lane + j;
-                int32_t run = 1;
-                while (x + run < L && (CL[x + run] & bits) != 0) ++run;
-                qx[pos++] = x | (run << 10);
-            }
-        };
-        if (rowd) {  // interior runs to qv[128..128 + itot): (len << 18) | (x << 8)
-            uint32_t f = ifl;
-            int pos = 128 + ipre;
-            while (f) {
-                const int j = __builtin_ctz(f);
-                f &= f - 1;
-                const int32_t x = kCellsPerLane * lane + j;
-                const int32_t e = CL[x];
-                int32_t run = 1;
-                while (x + run < L && CL[x + run] == e) ++run;
-                qv[pos++] = (x << 8) | (run << 18);
-            }
-        }
-        if (rowq) {
-            stage_runs(rfl, 128 + rpre, 3 << kSameShift);
-            wave_sync_lds();
-            int32_t m0 = 0, m1 = 0;
-            if (lane < rq_cells) {
-                const int r = lane / rtot;
-                m0 = (qx[128 + lane - r * rtot] << 8) | r;
-            }
-            if (lane + 64 < rq_cells) {
-                const int r = (lane + 64) / rtot;
-                m1 = (qx[128 + lane + 64 - r * rtot] << 8) | r;
-            }
-            wave_sync_lds();
-            if (lane < rq_cells) qx[lane] = m0;
-            if (lane + 64 < rq_cells) qx[lane + 64] = m1;
-        }
-        if (rowd) {
-            stage_runs(dfl, 128 + dpre, 1 << kSameShift);
-            wave_sync_lds();
-            if (lane < dtot) qx[128 + lane] <<= 8;
-            if (lane + 64 < dtot) qx[192 + lane] <<= 8;
-        }
-        wave_sync_lds();
-    }
-    auto run_x = [](int32_t m) { return (m >> 8) & 0x3ff; };
-    auto run_len = [](int32_t m) { return (m >> 18) & 0x3ff; };
-    // queued row bases: lane i holds that of queued row i
-    int32_t qrow = 0;
-    auto drain_rows = [&](int ncell) {
-#pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            const int idx = lane + 64 * half;
-            const int32_t m = qx[idx];
-            // every lane takes part in the permute (entries past ncell are not used)
-            const int32_t bq = __builtin_amdgcn_ds_bpermute((m & 63) << 2, qrow);
-            if (idx < ncell) {
-                int c = 0, ic = 0;
-                eval_queued(T, CL, DL, HS, bq, run_x(m), gbits, c, ic);
-                cnt += run_len(m) * c;
-                icnt += run_len(m) * ic;
-            }
-        }
-    };
-    int32_t q[KO];
-    {
-        uint32_t rr = (uint32_t)ra;
-#pragma unroll
-        for (int d = K - 2; d >= 0; --d) {
-            q[d] = (int32_t)(rr % (uint32_t)ext[d]);
-            rr /= (uint32_t)ext[d];
-        }
-    }
-    // prefix over dims 0..K-3: base index and offsets, refreshed on carries
-    int32_t base_o = 0;
-    int no = 0;
-    // the last row with outer offsets from dims 0..K-3 only: its dim K-2 entry, and
-    // each lane's share of its counts (rows with the same entry under the same
-    // prefix have the same index and neighbours)
-    int32_t dkey = -1;
-    bool dflag = false;
-    int dmc = 0, dmic = 0;
-    auto load_prefix = [&]() {
-        base_o = 0;
-        no = 0;
-        dkey = -1;
-#pragma unroll
-        for (int d = 0; d < K - 2; ++d) {
-            const int32_t e = uniform32(G[off[d] + q[d]]);
-            base_o += cval(e);
-            if (ccnt(e)) no = outer_offsets<H>(G + off[d], q[d], ext[d], hal[d], rl, no);
-        }
-    };
-    load_prefix();
-    // entries of dim K-2 for this wave's next 64 rows, one per lane (lane i: the row
-    // i steps of rs ahead), so a row takes its entry with a lane read instead of a
-    // memory round trip.  A lane also works out its row's offsets along dim K-2 (the
-    // rule of outer_offsets, neighbour entries loaded together): the first two go to
-    // ob[2i], ob[2i+1], their number to bits 28..31 of the entry (15: more than two,
-    // left to outer_offsets).
-    int32_t eb = 0;
-    auto load_batch = [&]() {
-        if constexpr (K > 1) {
-            const int32_t* C = G + off[K - 2];
-            const int32_t qi = (int32_t)((uint32_t)(q[K - 2] + lane * rs) % (uint32_t)ext[K - 2]);
-            eb = C[qi];
-            if (ccnt(eb)) {
-                const int32_t ev = cval(eb);
-                int c = 0;
-                int32_t o0 = 0, o1 = 0;
-#pragma unroll
-                for (int dir = 0; dir < 2; ++dir) {
-                    int32_t prev = 0;
-#pragma unroll
-                    for (int s = 1; s <= H; ++s) {
-                        const int32_t xx = dir ? qi + s : qi - s;
-                        if (s <= hal[K - 2] && xx >= 0 && xx < ext[K - 2]) {
-                            const int32_t dv = cval(C[xx]) - ev;
-                            if (dv != 0 && dv != prev) {
-                                if (c == 0) o0 = dv;
-                                if (c == 1) o1 = dv;
-                                ++c;
-                            }
-                            prev = dv;
-                        }
-                    }
-                }
-                ob[2 * lane] = o0;
-                ob[2 * lane + 1] = o1;
-                eb |= (c > 2 ? 15 : c) << 28;
-            }
-            wave_sync_lds();
-        }
-    };
-    // the wave's rows ra, ra + rs, ... below rb, in batches of up to 64
-    const int nrows = (rb - ra + rs - 1) / rs;
-    // sparse single-chunk row: every cell is read and tested; the row's flagged cells
-    // are the precomputed ones, so only its base is queued
-    // Rows with several runs (crowd: 8 or more) are evaluated at once, one run per
-    // lane, and a row with the same base index as the previous one of this wave (the
-    // same outer blocks) has the same result: each lane adds its share again.  Rows
-    // with fewer runs go to the row queue, which fills the lanes from several rows.
-    const bool crowd = rtot >= 8;
-    int32_t mbase = -1, mc = 0, mic = 0;
-    auto sparse_row = [&](int32_t base) {
-        int32_t e8[kCellsPerLane];
-        load8(CL + kCellsPerLane * lane, e8);
-        int32_t any = 0;
-#pragma unroll
-        for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
-        if (__ballot((uint32_t)any > (uint32_t)kValMask) == 0ull) return;
-        if (crowd) {
-            if (base != mbase) {
-                mc = 0;
-                mic = 0;
-#pragma unroll
-                for (int half = 0; half < 2; ++half) {
-                    const int k = lane + 64 * half;
-                    if (k < rtot) {
-                        const int32_t m = qx[k];  // run k of map row 0
-                        int c = 0, ic = 0;
-                        eval_queued(T, CL, DL, HS, base, run_x(m), gbits, c, ic);
-                        mc += run_len(m) * c;
-                        mic += run_len(m) * ic;
-                    }
-                }
-                mbase = base;
-            }
-            cnt += mc;
-            icnt += mic;
-        } else {
-            qrow = lane == nrow ? base : qrow;
-            ++nrow;
-            if (nrow == rq_rows) {
-                wave_sync_lds();
-                drain_rows(rq_cells);
-                wave_sync_lds();
-                nrow = 0;
-            }
-        }
-    };
-    // next row of this wave (row index i of nrows): step the outer coordinates by rs,
-    // carried into the outer dims only while rows remain, so they never leave the domain
-    auto step_row = [&](int i) {
-        if constexpr (K > 1) {
-            q[K - 2] += rs;
-            if (__builtin_expect(q[K - 2] >= ext[K - 2], 0) && i + 1 < nrows) {
-                int32_t c = 0;
-                while (q[K - 2] >= ext[K - 2]) {
-                    q[K - 2] -= ext[K - 2];
-                    ++c;
-                }
-#pragma unroll
-                for (int d = K - 3; d >= 0; --d) {
-                    q[d] += c;
-                    c = 0;
-                    while (q[d] >= ext[d]) {
-                        q[d] -= ext[d];
-                        ++c;
-                    }
-                }
-                load_prefix();
-                wave_sync_lds();
-            }
-        }
-    };
-    for (int done = 0; done < nrows; done += 64) {
-      load_batch();
-      const int nb = nrows - done < 64 ? nrows - done : 64;
-      for (int tb = 0; tb < nb; ++tb) {
-        if constexpr (K > 1) {
-            // consecutive rows without outer offsets (the common case) in a tight loop
-            // (with no runs, a row only has its cells read and tested); the first row
-            // with offsets falls through to the general code below
-            if (fastq && no == 0) {
-                while (tb < nb) {
-                    const int32_t e = __builtin_amdgcn_readlane(eb, tb);
-                    if (ccnt(e)) break;
-                    sparse_row(base_o + cval(e));
-                    ++tb;
-                    q[K - 2] += rs;
-                    if (q[K - 2] >= ext[K - 2]) {  // a carry: the general code takes the next row
-                        q[K - 2] -= rs;
-                        step_row(done + tb - 1);
-                        break;
-                    }
-                }
-                if (tb == nb) break;
-            }
-        }
-        int32_t base = base_o;
-        int nr = no;
-        int32_t erow = -1;  // dim K-2 entry of a row whose offsets come from the prefix only
-        if constexpr (K > 1) {
-            const int32_t e = __builtin_amdgcn_readlane(eb, tb);
-            if (ccnt(e) == 0) erow = e;
-            base += cval(e);
-            if (ccnt(e)) {
-                const int c = (int)((uint32_t)e >> 28);
-                if (c <= 2) {
-                    rl[no] = ob[2 * tb];
-                    rl[no + 1] = ob[2 * tb + 1];
-                    nr = no + c;
-                } else {
-                    nr = outer_offsets<H>(G + off[K - 2], q[K - 2], ext[K - 2], hal[K - 2], rl, no);
-                }
-            }
-        }
-        if (nr == 0) {
-          if (rowq) {
-            sparse_row(base);
-          } else {
-            // ---- sparse row: cells with last-dim offsets go to the queue one by one
-            for (int xb = 0; xb < L; xb += kChunk) {
-                const int x0 = xb + kCellsPerLane * lane;
-                int32_t e8[kCellsPerLane];
-                load8(CL + x0, e8);  // zero-padded past L
-                int32_t any = 0;
-#pragma unroll
-                for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
-                const bool hit = (uint32_t)any > (uint32_t)kValMask;
-                if (__ballot(hit) == 0ull) continue;
-                uint32_t fl = hfl;
-                int pre = hpre, tot = htot;
-                if (!one_chunk) chunk_flags(e8, fl, pre, tot);
-                if (tot > 64) {  // a crowded chunk: evaluate it in place
-                    eval_group<(H > 1 ? 3 << kSameShift : 0)>(T, DL, HS, e8, x0, L, base, rl, 0, gbits, true,
-                                                               cnt, icnt);
-                    continue;
-                }
-                int pos = qn + pre;
-                while (fl) {
-                    const int j = __builtin_ctz(fl);
-                    fl &= fl - 1;
-                    qv[pos] = base;
-                    qx[pos] = x0 + j;
-                    ++pos;
-                }
-                qn += tot;
-                wave_sync_lds();
-                if (qn >= 128) {
-                    eval_queued(T, CL, DL, HS, qv[lane], qx[lane], gbits, cnt, icnt);
-                    eval_queued(T, CL, DL, HS, qv[lane + 64], qx[lane + 64], gbits, cnt, icnt);
-                    wave_sync_lds();
-                    if (lane < qn - 128) {
-                        qv[lane] = qv[lane + 128];
-                        qx[lane] = qx[lane + 128];
-                    }
-                    qn -= 128;
-                    wave_sync_lds();
-                }
-            }
-          }
-        } else {
-            // ---- rows with outer offsets: every cell counts.  Every cell is read and
-            // tested (whether the row holds flagged cells, which gates their runs and is
-            // part of the memo's check); a row repeating the remembered entry under the
-            // same prefix adds the remembered shares.
-            int32_t e8[kCellsPerLane];
-            load8(CL + kCellsPerLane * lane, e8);
-            int32_t any = 0;
-#pragma unroll
-            for (int j = 0; j < kCellsPerLane; ++j) any |= e8[j];
-            const bool has_flagged = __ballot((uint32_t)any > (uint32_t)kValMask) != 0ull;
-            if (erow >= 0 && erow == dkey && has_flagged == dflag) {
-                cnt += dmc;
-                icnt += dmic;
-            } else {
-                int rc = 0, ric = 0;
-                if (rowd) {
-                    // single chunk: interior runs, then flagged runs, one per lane from the maps
-#pragma unroll
-                    for (int half = 0; half < 2; ++half) {
-                        const int k = lane + 64 * half;
-                        if (k < itot) {
-                            const int32_t m = qv[128 + k];
-                            int c = 0, ic = 0;
-                            eval_row_offsets(T, base + cval(CL[run_x(m)]), rl, nr, gbits, c, ic);
-                            rc += run_len(m) * c;
-                            ric += run_len(m) * ic;
-                        }
-                    }
-                    if (has_flagged) {
-#pragma unroll
-                        for (int half = 0; half < 2; ++half) {
-                            const int k = lane + 64 * half;
-                            if (k < dtot) {
-                                const int32_t m = qx[128 + k];
-                                const int32_t x = run_x(m);
-                                const int32_t e = CL[x];
-                                int c = 0, ic = 0;
-                                eval_cell(T, base + cval(e), rl, nr, DL + x * HS, ccnt(e), gbits, c, ic);
-                                rc += run_len(m) * c;
-                                ric += run_len(m) * ic;
-                            }
-                        }
-                    }
-                } else {
-                    // every chunk, eight cells per lane (memoised on equal entries)
-                    for (int xb = 0; xb < L; xb += kChunk) {
-                        const int x0 = xb + kCellsPerLane * lane;
-                        if (x0 >= L) continue;
-                        int32_t f8[kCellsPerLane];
-                        load8(CL + x0, f8);
-                        eval_group<(H > 1 ? 1 << kSameShift : 0)>(T, DL, HS, f8, x0, L, base, rl, nr, gbits, false,
-                                                                   rc, ric);
-                    }
-                }
-                cnt += rc;
-                icnt += ric;
-                if (erow >= 0) {
-                    dkey = erow;
-                    dflag = has_flagged;
-                    dmc = rc;
-                    dmic = ric;
-                }
-            }
-            wave_sync_lds();
-        }
-        step_row(done + tb);
-      }
-    }
-    // drain the queues
-    if (nrow > 0) {
-        wave_sync_lds();
-        drain_rows(nrow * rtot);
-        wave_sync_lds();
-    }
-    if (qn > 0) {
-        if (lane < qn) eval_queued(T, CL, DL, HS, qv[lane], qx[lane], gbits, cnt, icnt);
-        if (lane + 64 < qn) eval_queued(T, CL, DL, HS, qv[lane + 64], qx[lane + 64], gbits, cnt, icnt);
-        wave_sync_lds();
-    }
-}
-
-// Waves per SIMD: seven for H >= 2 and six for H = 1 (measured on the 512^3 halo-2
-// workload and the random halo-1 batch: 5 / 6 / 7 / 8 waves 4.47 / 4.02 / 3.89 /
-// 3.94 ms at H = 2; 4 / 5 / 6 / 7 waves 19.4 / 16.5 / 15.1 / 15.4 ms at H = 1); the
-// compiler then spills a few registers to scratch, which these times include.
-template <int K, int H>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 6 : 7))) void k_count(const DevHeader* __restrict__ hdr,
-                                               const DevCand* __restrict__ cands,
+__global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr, const DevCand* __restrict__ cands,
                                                const int32_t* __restrict__ arena,
                                                unsigned long long* __restrict__ counter,
                                                tm_stencil_cost* __restrict__ out) {
-    extern __shared__ __attribute__((aligned(16))) int32_t lds[];  // 16-byte aligned: ds_read_b128 of staged tables
+    extern __shared__ __attribute__((aligned(16))) int32_t lds[];
     __shared__ long long s_item;
-    __shared__ int32_t s_qv[4][kQueueCap], s_qx[4][kQueueCap];
-    __shared__ int32_t s_rl[4][32];
-    __shared__ int32_t s_ob[4][128];
-
     const int tid = threadIdx.x, lane = tid & 63;
-    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps the row loops scalar
     const int64_t total = uniform64(hdr->total_items);
     const int64_t n = uniform64(hdr->n);
-    int hal[K];
-#pragma unroll
-    for (int d = 0; d < K; ++d) hal[d] = uniform32(hdr->halo[d]);
+    const int32_t budget = uniform32(hdr->cnt_words);  // LDS words of this launch
 
     int64_t cur = -1;
-    int32_t L = 0, gbits = 0, rpi = 1, dl_lds = 0;
-    int64_t rows = 0, ifirst = 0;
-    int32_t off[K], ext[K];
-    int32_t dlo = 0;
-    const int32_t* garena = arena;
+    int K = 1, gbits = 0, hs = 0, nit = 1;
+    int64_t ifirst = 0;
+    bool poisoned = false;
+    int32_t R[TM_MAX_LRANK];
+    const int32_t* T = arena;
+    const int32_t* CE[TM_MAX_LRANK];
+    const int32_t* CS[TM_MAX_LRANK];
+    const int32_t* CO[TM_MAX_LRANK];
 #pragma unroll
-    for (int d = 0; d < K; ++d) off[d] = ext[d] = 0;
+    for (int d = 0; d < TM_MAX_LRANK; ++d) {
+        R[d] = 1;
+        CE[d] = CS[d] = CO[d] = arena;
+    }
 
     unsigned long long next = 0;
     if (tid == 0) next = atomicAdd(counter, 1ull);
@@ -876,83 +263,168 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(H == 1 ? 6 
         lo = uniform64(lo);
         if (lo != cur) {
             const DevCand* c = &cands[lo];
-            const int32_t words = uniform32(c->lds_words);
             const int32_t* src = arena + c->arena_off;
-            for (int i = tid; i < words; i += 256) lds[i] = src[i];
-            garena = src;
-            L = uniform32(c->L);
-            gbits = uniform32(c->gbits);
-            rpi = uniform32(c->rows_per_item);
-            rows = uniform64(c->rows);
-            ifirst = uniform64(c->item_first);
-#pragma unroll
-            for (int d = 0; d < K; ++d) {
-                off[d] = uniform32(c->coord_off[d]);
-                ext[d] = uniform32((int32_t)c->extent[d]);
+            const int32_t vol = uniform32(c->vol), cb = uniform32(c->cls_base), cw = uniform32(c->cls_words);
+            const int32_t tw = (vol + 3) & ~3;
+            const bool staged = tw + cw <= budget;
+            __syncthreads();  // the previous candidate's staged tables are no longer read
+            if (staged) {
+                for (int i = tid; i < vol; i += 256) lds[i] = src[i];
+                for (int i = tid; i < cw; i += 256) lds[tw + i] = src[cb + i];
             }
-            dlo = uniform32(c->dl_off[K - 1]);
-            dl_lds = uniform32(c->dl_lds);
+            T = staged ? lds : src;
+            K = uniform32(c->lrank);
+            gbits = uniform32(c->gbits);
+            hs = uniform32(c->hstride);
+            nit = uniform32(c->citems);
+            ifirst = uniform64(c->item_first);
+            poisoned = false;
+#pragma unroll
+            for (int d = 0; d < TM_MAX_LRANK; ++d) {
+                R[d] = 1;
+                if (d < K) {
+                    R[d] = uniform32(src[cb + d]);
+                    poisoned = poisoned || R[d] < 0;
+                    const int64_t cap = uniform32(c->cls_cap[d]);
+                    const int32_t rel = uniform32(c->cls_off[d]);  // dim d's block, from the arena or LDS
+                    CE[d] = staged ? lds + tw + (rel - cb) : src + rel;
+                    CS[d] = CE[d] + ((cap + 3) & ~int64_t(3));
+                    CO[d] = CS[d] + ((cap + 4) & ~int64_t(3));
+                }
+            }
             cur = lo;
             __syncthreads();
         }
-        // this wave's rows of the item: every fourth, so rows near block boundaries
-        // (dense ones cluster there) spread evenly over the waves
-        // rows of a candidate fit 31 bits (checked on the host)
-        const int32_t r0 = (int32_t)(item - ifirst) * rpi;
-        const int32_t rb = (int64_t)r0 + rpi < rows ? r0 + rpi : (int32_t)rows;
-        const int32_t ra = r0 + wid;
-        int cnt = 0, icnt = 0;
-        if (ra < rb) {
-            if (dl_lds)  // last dim's table and offset lists in LDS
-                count_rows<K, H>(lds, garena, lds + off[K - 1], lds + dlo, off, ext, hal, ra, rb, 4, L, gbits, lane,
-                                 s_rl[wid], s_qv[wid], s_qx[wid], s_ob[wid], cnt, icnt);
-            else  // long rows: both read from global memory (one code path keeps the kernel small)
-                count_rows<K, H>(lds, garena, garena + off[K - 1], garena + dlo, off, ext, hal, ra, rb, 4, L, gbits,
-                                 lane, s_rl[wid], s_qv[wid], s_qx[wid], s_ob[wid], cnt, icnt);
+        if (poisoned) {  // a class block overflowed its capacity: make the result unmistakable
+            if (tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].ghost_cells), 1ull << 62);
+            continue;
         }
-        const unsigned long long c64 = wave_sum64(cnt), i64 = wave_sum64(icnt);
-        if (lane == 0 && (c64 | i64)) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].ghost_cells), c64);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].inter_cells), i64);
+        // this item's tuples [ta, tb) of the candidate's N = prod R_d, split evenly
+        const int64_t j = item - ifirst;
+        int64_t N = 1;
+        for (int d = 0; d < K; ++d) N *= R[d];
+        const int64_t q = N / nit, r = N % nit;
+        const int64_t ta = j * q + (j < r ? j : r);
+        const int64_t tb = ta + q + (j < r ? 1 : 0);
+        const int32_t RL = R[K - 1];
+        // tuple t -> (row, k): row over the outer dims, k the last dim's class; each
+        // thread steps by 256 tuples
+        int64_t t = ta + tid;
+        int32_t row = (int32_t)(t / RL), k = (int32_t)(t - (int64_t)row * RL);
+        const int32_t q256 = 256 / RL, r256 = 256 % RL;
+        int32_t mrow = -1, vo = 0;
+        int64_t wo = 1;
+        int32_t kap[TM_MAX_LRANK];
+#pragma unroll
+        for (int d = 0; d < TM_MAX_LRANK; ++d) kap[d] = 0;
+        unsigned long long cnt = 0, icnt = 0;
+        for (; t < tb; t += 256) {
+            if (row != mrow) {  // outer classes of this row: contribution and weight
+                uint32_t rr = (uint32_t)row;
+                vo = 0;
+                wo = 1;
+                for (int d = K - 2; d >= 0; --d) {
+                    const uint32_t kd = rr % (uint32_t)R[d];
+                    rr /= (uint32_t)R[d];
+                    kap[d] = (int32_t)kd;
+                    vo += CE[d][kd] & kValMask;
+                    wo *= CS[d][kd + 1] - CS[d][kd];
+                }
+                mrow = row;
+            }
+            kap[K - 1] = k;
+            const int32_t el = CE[K - 1][k];
+            const int32_t v = vo + (el & kValMask);
+            const int64_t w = wo * (int64_t)(CS[K - 1][k + 1] - CS[K - 1][k]);
+            const int32_t o = T[v];
+            const int32_t onode = o >> gbits;
+            int32_t f[kFoundCache];
+            int nf = 0, c = 0, ic = 0;
+            for (int d = 0; d < K; ++d) {
+                const int32_t nd = ((d == K - 1 ? el : CE[d][kap[d]]) >> kCntShift) & 0xf;
+                const int32_t* od = CO[d] + kap[d] * hs;
+                for (int i = 0; i < nd; ++i) {
+                    const int32_t ot = T[v + od[i]];
+                    if (ot == o) continue;
+                    bool seen = false;
+#pragma unroll
+                    for (int u = 0; u < kFoundCache; ++u) seen = seen || (u < nf && f[u] == ot);
+                    if (!seen && nf > kFoundCache) {
+                        // more distinct owners than the cache holds: look at every earlier offset
+                        for (int d2 = 0; d2 <= d && !seen; ++d2) {
+                            const int32_t n2 = ((d2 == K - 1 ? el : CE[d2][kap[d2]]) >> kCntShift) & 0xf;
+                            const int32_t* o2 = CO[d2] + kap[d2] * hs;
+                            const int e2 = d2 < d ? n2 : i;
+                            for (int i2 = 0; i2 < e2 && !seen; ++i2) seen = T[v + o2[i2]] == ot;
+                        }
+                    }
+                    if (seen) continue;
+#pragma unroll
+                    for (int u = 0; u < kFoundCache; ++u) f[u] = u == nf ? ot : f[u];
+                    ++nf;
+                    ++c;
+                    ic += (ot >> gbits) != onode ? 1 : 0;
+                }
+            }
+            cnt += (unsigned long long)w * (unsigned long long)c;
+            icnt += (unsigned long long)w * (unsigned long long)ic;
+            k += r256;
+            row += q256;
+            if (k >= RL) {
+                k -= RL;
+                ++row;
+            }
+        }
+#pragma unroll
+        for (int o2 = 32; o2 > 0; o2 >>= 1) {
+            cnt += __shfl_xor(cnt, o2, 64);
+            icnt += __shfl_xor(icnt, o2, 64);
+        }
+        if (lane == 0 && (cnt | icnt)) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].ghost_cells), cnt);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].inter_cells), icnt);
         }
     }
 }
 
-template <int K, int H>
-static void* count_fn() {
-    return reinterpret_cast<void*>(&k_count<K, H>);
-}
-
-static void* pick_count(int K, int H) {
-#define TM_PICK(k)                              \
-    if (K == k) {                               \
-        if (H == 1) return count_fn<k, 1>();    \
-        if (H == 2) return count_fn<k, 2>();    \
-        if (H == 3) return count_fn<k, 3>();    \
-        if (H == 4) return count_fn<k, 4>();    \
-    }
-    TM_PICK(1) TM_PICK(2) TM_PICK(3) TM_PICK(4)
-#undef TM_PICK
-    return nullptr;
-}
-
-int count_kernel_occupancy(int K, int H, int lds_words, int* blocks_per_cu) {
-    void* fn = pick_count(K, H);
-    if (!fn) return -1;
+int count_kernel_occupancy(int lds_words, int* blocks_per_cu) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, (size_t)lds_words * 4) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_count), 256,
+                                                     (size_t)lds_words * 4) != hipSuccess)
         return -1;
     *blocks_per_cu = nb;
     return 0;
 }
 
-hipError_t launch_count(int K, int H, const DevHeader* hdr, const DevCand* cands, const int32_t* arena,
+hipError_t launch_count(const DevHeader* hdr, const DevCand* cands, const int32_t* arena,
                         unsigned long long* counter, tm_stencil_cost* out, int grid, int lds_words,
                         hipStream_t s) {
-    void* fn = pick_count(K, H);
-    if (!fn) return hipErrorInvalidValue;
-    void* args[] = {(void*)&hdr, (void*)&cands, (void*)&arena, (void*)&counter, (void*)&out};
-    return hipLaunchKernel(fn, dim3(grid), dim3(256), args, (size_t)lds_words * 4, s);
+    hipLaunchKernelGGL(k_count, dim3(grid), dim3(256), (size_t)lds_words * 4, s, hdr, cands, arena, counter, out);
+    return hipGetLastError();
+}
+
+// Sum over candidates of the product of their class counts (the counting work).
+__global__ __launch_bounds__(256) void k_class_tuples(const DevCand* __restrict__ cands, int64_t n,
+                                                      const int32_t* __restrict__ arena,
+                                                      unsigned long long* __restrict__ total) {
+    unsigned long long acc = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const DevCand& c = cands[i];
+        const int32_t* rec = arena + c.arena_off + c.cls_base;
+        unsigned long long t = 1;
+        for (int d = 0; d < c.lrank; ++d) t *= (unsigned long long)(rec[d] > 0 ? rec[d] : 0);
+        acc += t;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd(total, acc);
+}
+
+hipError_t launch_class_tuples(const DevCand* cands, int64_t n, const int32_t* arena, unsigned long long* total,
+                               hipStream_t s) {
+    const int64_t grid = std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 1024);
+    hipLaunchKernelGGL(k_class_tuples, dim3((unsigned)grid), dim3(256), 0, s, cands, n, arena, total);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ bytes + selection

@@ -18,6 +18,8 @@ struct Compiled {
     int32_t max_words = 0;      // largest LDS-staged prefix
     int32_t max_all_words = 0;  // largest whole table block of one candidate
     int32_t max_vol = 0;        // largest final-space volume
+    int32_t cnt_words = 0;      // LDS words of the counting launch (largest staged owner table + class blocks)
+    int64_t tuples = 0;         // class-tuple bound of the batch (sum of the candidates')
     int K = 0, H = 1;
 };
 

@@ -660,14 +660,17 @@ __global__ __launch_bounds__(256) void k_topk(const float* __restrict__ score, c
 
 // Ranking score: predicted log2(1 + bytes) + lambda * predicted log2(1 + inter-node
 // bytes), each = estimate base (the same fp32 value training used) + un-standardised
-// residual head.
+// residual head; +inf when that is not finite.
 __global__ void k_combine(const float* __restrict__ Y, const double* __restrict__ est, int64_t n, float mu0,
                           float s0, float mu1, float s1, float lambda, float* __restrict__ s) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float b0 = kBaseScale * (lg2(1.0 + est[i * 2]) / kBaseScale);
     const float b1 = kBaseScale * (lg2(1.0 + est[i * 2 + 1]) / kBaseScale);
-    s[i] = (b0 + mu0 + s0 * Y[i * kOut]) + lambda * (b1 + mu1 + s1 * Y[i * kOut + 1]);
+    const float v = (b0 + mu0 + s0 * Y[i * kOut]) + lambda * (b1 + mu1 + s1 * Y[i * kOut + 1]);
+    // a non-finite score (diverged or corrupt parameters) ranks last, by index, so
+    // such candidates stay selectable and every instance keeps its survivors
+    s[i] = __builtin_isfinite(v) ? v : INFINITY;
 }
 
 // ------------------------------------------------------------------ survivors
@@ -697,10 +700,8 @@ __global__ __launch_bounds__(1024) void k_gather(const DevCand* __restrict__ can
             ci = sel[s];
             if (ci >= 0) {
                 const DevCand& c = cands[ci];
-                const int64_t rpi0 = cells_per_item / (c.L > 0 ? c.L : 1);
-                const int64_t rpi = rpi0 < 1 ? 1 : (rpi0 > c.rows ? (c.rows > 0 ? c.rows : 1) : rpi0);
                 words = c.words;
-                items = (c.rows + rpi - 1) / rpi;
+                items = count_items(c, cells_per_item);
                 present = 1;
             }
         }
@@ -724,8 +725,7 @@ __global__ __launch_bounds__(1024) void k_gather(const DevCand* __restrict__ can
         if (present) {
             const int64_t j = carry_c + s_cnt[threadIdx.x] - 1;
             DevCand c = cands[ci];
-            const int64_t rpi0 = cells_per_item / (c.L > 0 ? c.L : 1);
-            c.rows_per_item = (int32_t)(rpi0 < 1 ? 1 : (rpi0 > c.rows ? (c.rows > 0 ? c.rows : 1) : rpi0));
+            c.citems = (int32_t)items;
             c.arena_off = carry_w + s_words[threadIdx.x] - words;
             c.item_first = carry_i + s_items[threadIdx.x] - items;
             sub[j] = c;

@@ -143,6 +143,9 @@ def test_empty_batch_and_invalid_input(tm):
     with pytest.raises(tm.TaskmapError) as e:
         tm.tm_eval_stencil_batch(bad[:1], W.stencil((5, 1)), out)
     assert e.value.code == tm.TM_ENOTSUP
+    with pytest.raises(tm.TaskmapError) as e:  # a stencil of lower rank than a candidate
+        tm.tm_eval_stencil_batch(bad[:1], W.stencil((1,)), out)
+    assert e.value.code == tm.TM_EINVAL
     torch.cuda.synchronize()
     assert (out.cpu() == -7).all()  # nothing was launched
 
@@ -157,7 +160,12 @@ def test_c2_scaled_all_candidates(tm):
 
 
 def test_c2_full_size_plan(tm):
+    """The benchmark workload at full size (216 candidates of 512^3, halo 2) in the
+    launch configurations the benchmark times: every total against the block closed
+    form, 16 candidates covering all six chains against the oracle cell by cell, and
+    the selected candidate's whole int32 map against the oracle's."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     say("c2 full 512^3 plan")
     fs = oracle.enumerate_factorizations(128, 3)
     cands = W.c2_candidates(fs)
@@ -169,42 +177,39 @@ def test_c2_full_size_plan(tm):
     plan.run(out, best)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
-    # identity chains: every block is 512/f >= 4 >= h wide, so the closed form holds
-    for i, f in enumerate(fs):
-        row = got[6 * i]
-        assert row[0] == sum(2 * 2 * (fm - 1) * 512 * 512 for fm in f)
-        assert row[2] == 8 * row[0]
-    # one full-size candidate through the oracle, cell by cell
-    i = fs.index((4, 4, 8)) * 6
-    say("  oracle on candidate", i, "(134M points)")
-    assert tuple(got[i]) == oracle.stencil_cost(cands[i], st)
+    # every chain is a bijective block chain whose final dim j is projected from
+    # launch dim j: its factors along the launch dims are the final shape, every
+    # block is 512/f >= 4 >= h wide, and V = sum_m 2h (f_m - 1) prod_{j != m} l_j
+    for i, c in enumerate(cands):
+        rc, fsh = oracle.validate(c)
+        assert rc == 0 and len(fsh) == 3
+        assert got[i, 0] == sum(2 * 2 * (fm - 1) * 512 * 512 for fm in fsh), (i, fsh)
+        assert got[i, 2] == 8 * got[i, 0] and got[i, 3] == 8 * got[i, 1]
+    # 16 full-size candidates (all six chains) through the oracle, one per host thread
+    picks = [(37 * i) % len(cands) for i in range(16)]
+    assert sorted(set(p % 6 for p in picks)) == list(range(6))
+    say("  oracle on 16 candidates of 134M points")
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        exp = list(ex.map(lambda i: oracle.stencil_cost(cands[i], st), picks))
+    for i, e in zip(picks, exp):
+        assert tuple(got[i]) == e, (i, tuple(got[i]), e)
     b = int(best.cpu()[0])
     assert b == oracle.select_best(got)
-    # materialised map of the selected candidate at sampled points
+    # the selected candidate's whole map
     m = torch.empty(512 ** 3, dtype=torch.int32, device="cuda")
     plan.materialize(m, d_index=best)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(5)
-    pts = rng.integers(0, 512, size=(3000, 3))
-    mm = m.view(512, 512, 512)
-    idx = torch.from_numpy(pts).cuda()
-    vals = mm[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
-    g = int(cands[b]["gpus"])
-    for p, v in zip(pts, vals):
-        nd, gp = oracle.point_owner(cands[b], tuple(int(x) for x in p))
-        assert v == nd * g + gp
-    # every processor gets exactly 512^3/128 points (bijective block chain, f | 512)
-    counts = torch.bincount(m.long(), minlength=128).cpu().numpy()
-    assert (counts == 512 ** 3 // 128).all()
-    # the launch configurations the benchmark times: its autotuner's pick and the
-    # 2^19 cells per item it settles on; identical costs and selection
+    say("  whole map of candidate", b)
+    assert np.array_equal(m.cpu().numpy().reshape(512, 512, 512), oracle.proc_map(cands[b]))
+    # the launch configurations the benchmark times: its autotuner's pick and a fixed
+    # item size; identical costs and selection
     out2 = torch.empty_like(out)
     cpi, wg = plan.autotune(out2)
     say("  autotuned launch", cpi, wg)
     plan.run(out2, best)
     torch.cuda.synchronize()
     assert (out2.cpu().numpy() == got).all() and int(best.cpu()[0]) == b
-    plan.set_launch(1 << 19, 0)
+    plan.set_launch(1 << 12, 0)
     plan.run(out2, best)
     torch.cuda.synchronize()
     assert (out2.cpu().numpy() == got).all() and int(best.cpu()[0]) == b
@@ -222,16 +227,55 @@ def test_c3_scaled_all(tm):
 
 
 def test_c3_full_extents_subset(tm):
-    say("c3 full-extent subset")
+    """A seeded subset of 256 of the 4,096 random candidates at full extents (2.8e9
+    points), launch ranks 2 and 3 mixed in one plan (one counting launch), against
+    the oracle, one candidate per host thread."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    say("c3 full-extent subset of 256, one plan")
     cs = W.c3_candidates(4096)
-    pts = np.prod(np.where(np.arange(4)[None, :] < cs["lrank"][:, None], cs["extent"], 1), axis=1)
     rng = np.random.default_rng(17087)
-    small = np.nonzero(pts <= 3_000_000)[0]
-    pick = np.sort(rng.choice(small, size=24, replace=False))
-    sub = cs[pick]
-    for k, idx, s in by_rank(sub):
-        st = W.c3_stencil(k)
-        assert (gpu_costs(tm, s, st) == oracle.stencil_cost_batch(s, st)).all()
+    sub = cs[np.sort(rng.choice(len(cs), size=256, replace=False))]
+    assert set(int(k) for k in sub["lrank"]) == {2, 3}
+    plan = tm.Plan(len(sub), 1)
+    plan.load(sub, W.c3_stencil(3))  # a rank-2 candidate takes the first two halo widths
+    out = torch.empty((len(sub), 4), dtype=torch.int64, device="cuda")
+    best = torch.empty(1, dtype=torch.int64, device="cuda")
+    plan.run(out, best)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        exp = list(ex.map(lambda c: oracle.stencil_cost(c, W.c3_stencil(int(c["lrank"]))), sub))
+    assert (got == np.array(exp)).all()
+    assert int(best.cpu()[0]) == oracle.select_best(got)
+    plan.close()
+
+
+def test_mixed_rank_plan(tm):
+    """Launch ranks 1 to 4 in one plan with per-dim halos: a candidate of rank k
+    takes the stencil's first k halo widths; costs, selection and replays against
+    the oracle per rank."""
+    import torch
+    say("mixed ranks 1..4 in one plan")
+    cs = W.random_candidates(400, seed=11, ranks=(1, 2, 3, 4), octaves=(0, 4), nodes_max=16, max_ops=4,
+                             cyclic_pct=25)
+    halo = (2, 1, 3, 1)
+    plan = tm.Plan(len(cs), 1)
+    plan.load(cs, W.stencil(halo, 8))
+    out = torch.empty((len(cs), 4), dtype=torch.int64, device="cuda")
+    best = torch.empty(1, dtype=torch.int64, device="cuda")
+    exp = np.zeros((len(cs), 4), np.int64)
+    for k, idx in W.split_by_rank(cs).items():
+        exp[idx] = oracle.stencil_cost_batch(cs[idx], W.stencil(halo[:k], 8))
+    for rep in range(3):
+        out.fill_(-1)
+        plan.run(out, best)
+        torch.cuda.synchronize()
+        assert (out.cpu().numpy() == exp).all(), rep
+        assert int(best.cpu()[0]) == oracle.select_best(exp)
+    # the single-shot call takes the same mixed batch
+    assert (gpu_costs(tm, cs, W.stencil(halo, 8)) == exp).all()
+    plan.close()
 
 
 # ---------------------------------------------------------------- c4: matmul
@@ -500,14 +544,13 @@ def test_limits(tm):
     assert got[0] == cells and got[2] == 8 * cells and 0 < got[1] < got[0]
 
 
-def test_row_reuse_paths(tm):
-    """Candidates aimed at the counting kernel's row paths, bit-exact against the
-    oracle: rows without outer offsets with 8 or more runs (evaluated at once, reused
-    while the base repeats) and with fewer (row queue); rows with outer offsets from
-    the slower outer dims only (reused while the fast entry repeats) and from the fast
-    outer dim; rows without runs; rows of several chunks; cyclic last dims; launch
-    rank 4; halos 1 to 4 (per dim); node-level counts for the same candidates."""
-    say("row reuse paths")
+def test_class_structures(tm):
+    """Candidates with many and few coordinate classes per dim, bit-exact against
+    the oracle: blocks narrower and wider than the halo, one to 64 blocks along a
+    dim, long last dims (512 to 1300 cells), cyclic last dims (a class per
+    coordinate), launch rank 4, halos 1 to 4 per dim, and node-level counts for the
+    same candidates."""
+    say("class structures")
     P = 16
     cases = []
     for ext, F in [((24, 40, 512), (1, 1, 16)), ((24, 40, 512), (1, 2, 8)), ((24, 40, 512), (2, 2, 4)),

@@ -327,3 +327,25 @@ def test_search_margin(tm, trained, held_out):
     assert _lex_le(ce, c5).all()
     with pytest.raises(tm.TaskmapError):
         tm.tm_search(plan, r, seg, topk=64, margin=-1.0)
+
+
+def test_search_with_nonfinite_scores(tm, held_out):
+    """A network whose parameters are all NaN scores every candidate +inf: the top-k
+    then takes each instance's first k candidates by index, evaluates them exactly
+    and returns the best of them, so no instance is left without a survivor."""
+    import torch
+    say("search with non-finite scores")
+    inst, cands, seg, plan, ce = held_out
+    r = tm.Ranker(seed=3)
+    r.set_params(torch.full((tm.tm_ranker_param_count(),), float("nan"), dtype=torch.float32, device="cuda"))
+    k = 4
+    b, c = tm.tm_search(plan, r, seg, topk=k)
+    out = torch.empty((len(cands), 4), dtype=torch.int64, device="cuda")
+    plan.run(out)
+    torch.cuda.synchronize()
+    allc, b, c = out.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()
+    for s in range(len(seg) - 1):
+        first = allc[seg[s]:seg[s] + k]
+        e = int(np.lexsort((np.arange(len(first)), first[:, 3], first[:, 2]))[0])
+        assert b[s] == e and tuple(c[s]) == tuple(first[e]), s
+    r.close()

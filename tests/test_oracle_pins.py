@@ -61,6 +61,33 @@ def test_greedy_grid_paper():
     assert oracle.greedy_grid(e["P"], e["k"]) == tuple(e["grid"])
 
 
+def test_greedy_grid_properties():
+    """Alg. A1 (App. A.2) by what it guarantees: the factors multiply to P and come
+    sorted descending; each prime (smallest first) goes to a smallest factor, so the
+    largest factor is at most the smallest times the largest prime of P; a k-th power
+    of a prime splits evenly.  Hand-worked: 8 -> (4, 2), 72 -> (12, 6) (primes 2, 2,
+    2, 3, 3), 128 on three dims -> (8, 4, 4)."""
+    def largest_prime(P):
+        q, d = 1, 2
+        while P > 1:
+            while P % d == 0:
+                q, P = d, P // d
+            d += 1
+        return q
+    for P in range(1, 700):
+        for k in range(1, 5):
+            f = oracle.greedy_grid(P, k)
+            assert len(f) == k and int(np.prod(f)) == P
+            assert list(f) == sorted(f, reverse=True)
+            assert f[0] <= f[-1] * largest_prime(P)
+    for p in (2, 3, 5, 7):
+        for k in range(1, 5):
+            assert oracle.greedy_grid(p ** k, k) == (p,) * k
+    assert oracle.greedy_grid(8, 2) == (4, 2)
+    assert oracle.greedy_grid(72, 2) == (12, 6)
+    assert oracle.greedy_grid(128, 3) == (8, 4, 4)
+
+
 def ghost(extent, F, halo, n=None, g=1, tail=(), proj=None):
     P = int(np.prod(F))
     n = n if n is not None else P // g

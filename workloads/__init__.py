@@ -233,8 +233,8 @@ def c3_stencil(lrank):
 
 
 def split_by_rank(cands):
-    """c3 mixes ranks 2 and 3; a stencil fixes the rank, so batches are evaluated per
-    rank.  Returns {rank: index array}."""
+    """c3 mixes ranks 2 and 3; the oracle's stencil fixes the rank, so its batches
+    are evaluated per rank.  Returns {rank: index array}."""
     return {int(k): np.nonzero(cands["lrank"] == k)[0] for k in np.unique(cands["lrank"])}
 
 

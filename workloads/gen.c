@@ -80,16 +80,33 @@ static int64_t uniform_divisor(rng_t* r, int64_t v) {
     return divs[below(r, (uint64_t)n)];
 }
 
-/* random ordered k-factorization of P: f_0 uniform divisor of P, f_1 uniform divisor
- * of what is left, ..., the last factor takes the remainder */
-static void random_factorization(rng_t* r, int64_t P, int k, int32_t* f) {
-    int64_t rem = P;
-    for (int m = 0; m < k - 1; m++) {
-        int64_t d = uniform_divisor(r, rem);
-        f[m] = (int32_t)d;
-        rem /= d;
+/* ordered k-factorizations of P, written as k-tuples to out (up to cap of them);
+ * returns how many there are (a divisor walk: the first factor, then the
+ * factorizations of what is left) */
+static int64_t factorizations(int64_t P, int k, int32_t* prefix, int depth, int32_t* out, int64_t n,
+                              int64_t cap) {
+    if (depth == k - 1) {
+        if (n < cap) {
+            for (int m = 0; m < k - 1; m++) out[n * k + m] = prefix[m];
+            out[n * k + k - 1] = (int32_t)P;
+        }
+        return n + 1;
     }
-    f[k - 1] = (int32_t)rem;
+    for (int64_t d = 1; d <= P; d++) {
+        if (P % d) continue;
+        prefix[depth] = (int32_t)d;
+        n = factorizations(P / d, k, prefix, depth + 1, out, n, cap);
+    }
+    return n;
+}
+
+/* random ordered k-factorization of P, uniform over all of them */
+static void random_factorization(rng_t* r, int64_t P, int k, int32_t* f) {
+    static _Thread_local int32_t all[4 * 8192];
+    int32_t prefix[4];
+    const int64_t n = factorizations(P, k, prefix, 0, all, 0, 8192);
+    const int64_t pick = (int64_t)below(r, (uint64_t)(n < 8192 ? n : 8192));
+    for (int m = 0; m < k; m++) f[m] = all[pick * k + m];
 }
 
 static int64_t vol(const int64_t* s, int r) {
