@@ -221,6 +221,22 @@ int tm_proc_map(const tm_candidate* c, int32_t* d_map, int64_t len, void* stream
 int tm_eval_stencil_batch(const tm_candidate* c, int64_t n, const tm_stencil* st,
                           tm_stencil_cost* d_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): tm_eval_stencil_batch
+ * with the same arguments, results and validation, allocating no device memory and
+ * no pinned host memory.
+ * The batch header, descriptors, tables and work counter live in a device array of
+ * TM_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the
+ * process ends; TM_ECAPACITY (nothing launched) when the batch needs more.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (on other
+ * streams or threads) race, and the caller must serialise them.  The descriptors are
+ * copied from host memory before the call returns (it waits for `stream` to finish
+ * those copies, and so for the work enqueued before them); the counting itself runs
+ * asynchronously on `stream`. */
+#define TM_NOALLOC_SCRATCH_BYTES (64 << 20)
+int tm_eval_stencil_batch_noalloc(const tm_candidate* c, int64_t n, const tm_stencil* st,
+                                  tm_stencil_cost* d_out, void* stream);
+
 /* Node-level exchange volume (two-level mappings, where a node receives each remote
  * cell once however many of its GPUs read it; App. A.1's hierarchical mappers):
  * for every cell, the distinct nodes other than its owner's node that own one of

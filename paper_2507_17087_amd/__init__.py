@@ -58,6 +58,7 @@ def lib():
             "tm_proc_map": [P, P, I64, P],
             "tm_eval_stencil_batch": [P, I64, P, P, P],
             "tm_eval_stencil_node_batch": [P, I64, P, P, P],
+            "tm_eval_stencil_batch_noalloc": [P, I64, P, P, P],
             "tm_eval_redistribution_batch": [P, P, I64, I64, P, P],
             "tm_transpose_target": [P, I32, I32, P],
             "tm_eval_matmul_batch": [P, I64, P, P, P, P],
@@ -252,6 +253,18 @@ def tm_eval_stencil_batch(c, st, out=None):
         out = torch.empty((n, 4), dtype=torch.int64, device="cuda")
     _check(lib().tm_eval_stencil_batch(a.ctypes.data, n, s.ctypes.data, _dev_ptr(out, torch.int64, 4 * n),
                                        _stream()))
+    return out
+
+
+def tm_eval_stencil_batch_noalloc(c, st, out):
+    """tm_eval_stencil_batch through the entry point that allocates no device memory:
+    `out` (int64 [n,4] device tensor) is required."""
+    import torch
+    a = _cands(c)
+    s = _st(st)
+    n = len(a)
+    _check(lib().tm_eval_stencil_batch_noalloc(a.ctypes.data, n, s.ctypes.data, _dev_ptr(out, torch.int64, 4 * n),
+                                               _stream()))
     return out
 
 

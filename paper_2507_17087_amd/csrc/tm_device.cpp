@@ -103,8 +103,8 @@ static void layout_items(Compiled& cp, int64_t tuples_per_item) {
 
 // Validates and compiles n candidates.  st == nullptr: tables without halo flags.
 // need_lds: every candidate's tables must fit the LDS budget of the kernels.
-static int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st, int64_t tuples_per_item,
-                         bool need_lds, Compiled& cp) {
+int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st, int64_t tuples_per_item, bool need_lds,
+                  Compiled& cp) {
     if (n < 0) return set_error(TM_EINVAL, "n = %lld", (long long)n);
     if (n > 0 && !c) return set_error(TM_EINVAL, "null candidate array");
     cp.cands.resize((size_t)n);
@@ -252,7 +252,7 @@ static int num_cus() {
     return n;
 }
 
-static int count_grid(int lds_words, int64_t items, int wg_per_cu) {
+int count_grid(int lds_words, int64_t items, int wg_per_cu) {
     int per_cu = 0;
     if (count_kernel_occupancy(lds_words, &per_cu) != 0 || per_cu < 1) per_cu = 1;
     if (wg_per_cu > 0) per_cu = std::min(per_cu, wg_per_cu);

@@ -74,6 +74,13 @@ struct tm_plan {
 
 namespace tmk {
 
+// Validates and compiles n candidates on the host (st == nullptr: tables without
+// classes; need_lds: every owner table must fit the kernels' LDS budget).
+int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st, int64_t tuples_per_item, bool need_lds,
+                  Compiled& cp);
+// Grid of the persistent counting launch for `items` work items.
+int count_grid(int lds_words, int64_t items, int wg_per_cu);
+
 int64_t plan_size(const tm_plan* p);
 const DevCand* plan_cands(const tm_plan* p);
 int32_t plan_max_vol(const tm_plan* p);
