@@ -197,14 +197,16 @@ int tm_workload_greedy(int64_t P, int32_t k, const int64_t* extent, int32_t* out
 
 /* ---------------------------------------------------------------- device calls */
 
-/* Processor id of every coordinate of the final space of c (C order), computed on
- * the GPU: d_out (device, int32[cap]).  *count (host) receives the volume;
- * TM_ECAPACITY if cap is smaller. */
+/* The chain table (Fig. 6's formulas applied last transformation first, as the
+ * translator of Sec. 5.2 inverts a mapping): processor id of every coordinate of the
+ * final space of c (C order), computed on the GPU: d_out (device, int32[cap]).
+ * *count (host) receives the volume; TM_ECAPACITY if cap is smaller. */
 int tm_chain_table(const tm_candidate* c, int32_t* d_out, int64_t cap, int64_t* count,
                    void* stream);
 
-/* Processor id of every launch point of c, C order: d_map (device, int32[len]),
- * len must equal the number of points (else TM_ECAPACITY). */
+/* The processor map (Sec. 3.2.1's index-task mapping; Fig. 3 works one point): the
+ * processor id of every launch point of c, C order: d_map (device, int32[len]), len
+ * must equal the number of points (else TM_ECAPACITY). */
 int tm_proc_map(const tm_candidate* c, int32_t* d_map, int64_t len, void* stream);
 
 /* Stencil cost of n candidates (host array) sharing one stencil (host); results to
@@ -257,7 +259,9 @@ int tm_eval_stencil_node_batch(const tm_candidate* c, int64_t n, const tm_stenci
 int tm_eval_redistribution_batch(const tm_candidate* src, const tm_candidate* dst, int64_t n, int64_t elem_bytes,
                                  tm_redist_cost* d_out, void* stream);
 
-/* Matmul tile fetches of n rank-3 candidates: d_per_proc (device, int64[sum P_c][3],
+/* Matmul tile fetches (the data movement App. A.1's matmul mappers -- Cannon, SUMMA,
+ * Johnson's 3-D, Solomonik's 2.5-D -- differ in) of n rank-3 candidates:
+ * d_per_proc (device, int64[sum P_c][3],
  * candidates back to back, may be NULL) and d_out (device, tm_matmul_cost[n]).
  * TM_ENOTSUP if a candidate has more than 1024 processors or its owner and
  * coordinate tables together exceed the LDS budget of 32768 words (the kernel reads
@@ -265,7 +269,8 @@ int tm_eval_redistribution_batch(const tm_candidate* src, const tm_candidate* ds
 int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_matmul* mm,
                          int64_t* d_per_proc, tm_matmul_cost* d_out, void* stream);
 
-/* Selection over a cost array (device): for each of nseg segments
+/* Selection by Sec. 4.2's objective, the communication volume (ties broken by
+ * inter-node bytes, then index), over a cost array (device): for each of nseg segments
  * [seg[s], seg[s+1]) of d_costs (seg is a host int64[nseg+1]), the index (relative to
  * the segment start) minimising (bytes, inter_bytes, index) -> d_best (device,
  * int64[nseg]).  Empty segments give -1. */
@@ -309,8 +314,10 @@ int tm_plan_create(int64_t max_cands, int64_t max_words, tm_plan** out);
 int tm_plan_load(tm_plan* p, const tm_candidate* c, int64_t n, const tm_stencil* st,
                  int64_t cells_per_item, void* stream);
 int tm_plan_run(tm_plan* p, tm_stencil_cost* d_out, int64_t* d_best, void* stream);
-/* stage 0: reset + table build; 1: counting; 2: bytes + selection (same work as
- * tm_plan_run, one stage at a time, each replayed from its own graph). */
+/* stage 0: table build (which also zeroes d_out and the work counters); 1: counting
+ * (for batches of at most 2048 candidates its last workgroup also writes the bytes
+ * and selects); 2: bytes + selection (same work as tm_plan_run, one stage at a time,
+ * in this order, each replayed from its own graph). */
 int tm_plan_run_stage(tm_plan* p, int32_t stage, tm_stencil_cost* d_out, int64_t* d_best,
                       void* stream);
 /* Processor map of candidate *d_index (device int64; index into the loaded batch),

@@ -29,11 +29,13 @@ static int64_t default_tuples_per_item(int64_t tuples) {
 }
 // Largest work item accepted from a caller.
 constexpr int64_t kMaxCellsPerItem = int64_t(1) << 26;
-// Map launches: workgroups per CU (a wave writes every (grid * 4)-th row).  32 gives
-// smaller work units than the 8 that are resident at once (about 8 rows per wave on a
-// 512^3 map) and a better-balanced end: 5.15 -> 5.40 TB/s; many more workgroups pay
-// for staging their tables each (256 per CU: 4.05 TB/s).
-constexpr int kMapWgPerCu = 32;
+// Map launches: one workgroup per block of map_rows_per_block(L) rows, up to this many
+// (more blocks are taken grid-stride).
+constexpr int64_t kMapMaxGrid = int64_t(1) << 20;
+static int map_grid(int64_t rows, int32_t L) {
+    const int64_t rpb = map_rows_per_block(L);
+    return (int)std::max<int64_t>(1, std::min<int64_t>((rows + rpb - 1) / rpb, kMapMaxGrid));
+}
 
 // ------------------------------------------------------------------ batch compilation
 
@@ -90,15 +92,21 @@ static int layout_tables(DevCand& d, int H, const int32_t* halo) {
     return TM_OK;
 }
 
+// Counting work items of every candidate, and the item table (the candidate of each
+// item, written by the table build) after the tables in the arena.
 static void layout_items(Compiled& cp, int64_t tuples_per_item) {
     int64_t items = 0;
+    cp.max_citems = 0;
     for (auto& d : cp.cands) {
         d.citems = count_items(d, tuples_per_item);
         d.item_first = items;
         items += d.citems;
+        cp.max_citems = std::max(cp.max_citems, d.citems);
     }
     cp.items = items;
     cp.hdr.total_items = items;
+    cp.hdr.item_tab = cp.tables_words;
+    cp.arena_words = cp.tables_words + up4(items);
 }
 
 // Validates and compiles n candidates.  st == nullptr: tables without halo flags.
@@ -161,6 +169,7 @@ int compile_batch(const tm_candidate* c, int64_t n, const tm_stencil* st, int64_
         cp.max_points = std::max(cp.max_points, d.npoints);
         cp.max_vol = std::max(cp.max_vol, d.vol);
     }
+    cp.tables_words = words;
     cp.arena_words = words;
     cp.hdr.max_words = cp.max_words;
     cp.hdr.cnt_words = cp.cnt_words;
@@ -297,7 +306,7 @@ extern "C" int tm_proc_map(const tm_candidate* c, int32_t* d_map, int64_t len, v
     DeviceBatch db;
     rc = upload_batch(cp, db, s);
     if (rc == TM_OK) {
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((cp.cands[0].rows + 3) / 4, num_cus() * kMapWgPerCu));
+        const int grid = map_grid(cp.cands[0].rows, cp.cands[0].L);
         hipError_t e = launch_build_tables(db.hdr, db.cands, 1, db.arena, 0, s);
         if (e == hipSuccess) e = launch_map(db.cands, 1, db.arena, nullptr, 0, d_map, grid, cp.max_words, s);
         if (e != hipSuccess) rc = set_error(TM_EDEVICE, "map launch: %s", hipGetErrorString(e));
@@ -319,10 +328,11 @@ static int eval_stencil(const tm_candidate* c, int64_t n, const tm_stencil* st, 
     rc = upload_batch(cp, db, s);
     if (rc == TM_OK) {
         const int grid = count_grid(cp.cnt_words, cp.items, 0);
-        hipError_t e = launch_reset(db.hdr, db.counter, d_out, n, s);
-        if (e == hipSuccess) e = launch_build_tables(db.hdr, db.cands, n, db.arena, 1, s);
-        if (e == hipSuccess) e = launch_count(db.hdr, db.cands, db.arena, db.counter, d_out, grid, cp.cnt_words, s);
-        if (e == hipSuccess) e = launch_finalize_select(db.hdr, d_out, nullptr, s);
+        const bool fin = n <= kFinInCount;
+        hipError_t e = launch_build_tables(db.hdr, db.cands, n, db.arena, 1, s, d_out, db.counter);
+        if (e == hipSuccess)
+            e = launch_count(db.hdr, db.cands, db.arena, db.counter, d_out, grid, cp.cnt_words, s, fin, nullptr);
+        if (e == hipSuccess && !fin) e = launch_finalize_select(db.hdr, d_out, nullptr, s);
         if (e != hipSuccess) rc = set_error(TM_EDEVICE, "stencil launch: %s", hipGetErrorString(e));
     }
     free_batch(db, s);
@@ -576,17 +586,19 @@ static int plan_upload(tm_plan* p, hipStream_t s) {
 // Enqueues one stage of a run on stream s (direct launches; also used for capture).
 static hipError_t plan_enqueue(tm_plan* p, int stage, tm_stencil_cost* out, int64_t* best, int grid, hipStream_t s) {
     const Compiled& cp = p->cp;
+    const bool fin = cp.hdr.n <= kFinInCount;  // bytes and selection inside the counting launch
     hipError_t e = hipSuccess;
     if (stage == 0 || stage < 0) {
-        e = launch_reset(p->d_hdr, p->d_counter, out, cp.hdr.n, s);
-        if (e == hipSuccess) e = launch_build_tables(p->d_hdr, p->d_cands, cp.hdr.n, p->d_arena, 1, s);
+        e = launch_build_tables(p->d_hdr, p->d_cands, cp.hdr.n, p->d_arena, 1, s, out, p->d_counter);
         if (e != hipSuccess) return e;
     }
     if (stage == 1 || stage < 0) {
-        e = launch_count(p->d_hdr, p->d_cands, p->d_arena, p->d_counter, out, grid, cp.cnt_words, s);
+        e = launch_count(p->d_hdr, p->d_cands, p->d_arena, p->d_counter, out, grid, cp.cnt_words, s, fin, best);
         if (e != hipSuccess) return e;
     }
-    if (stage == 2 || stage < 0) e = launch_finalize_select(p->d_hdr, out, best, s);
+    // stage 2 on its own repeats the selection (idempotent); the whole run needs it
+    // only when the counting launch did not do it
+    if (stage == 2 || (stage < 0 && !fin)) e = launch_finalize_select(p->d_hdr, out, best, s);
     return e;
 }
 
@@ -714,18 +726,17 @@ extern "C" int tm_plan_materialize(tm_plan* p, const int64_t* d_index, int64_t h
     const Compiled& cp = p->cp;
     if (cp.hdr.n == 0) return set_error(TM_EINVAL, "empty batch");
     int64_t need = cp.max_points;
-    int64_t rows = 0;
+    int grid = 1;
     if (!d_index) {
         if (host_index < 0 || host_index >= cp.hdr.n) return set_error(TM_EINVAL, "index %lld", (long long)host_index);
         need = cp.cands[(size_t)host_index].npoints;
-        rows = cp.cands[(size_t)host_index].rows;
+        grid = map_grid(cp.cands[(size_t)host_index].rows, cp.cands[(size_t)host_index].L);
     } else {
-        for (auto& d : cp.cands) rows = std::max(rows, d.rows);
+        for (auto& d : cp.cands) grid = std::max(grid, map_grid(d.rows, d.L));
     }
     if (cap < need) return set_error(TM_ECAPACITY, "map needs %lld entries", (long long)need);
     if (!p->d_arena || p->cap_words < cp.arena_words)
         return set_error(TM_EINVAL, "no tables yet: run the plan before materialising a map");
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((rows + 3) / 4, num_cus() * kMapWgPerCu));
     const hipError_t e = launch_map(p->d_cands, cp.hdr.n, p->d_arena, d_index, host_index, d_map, grid, cp.max_words,
                                     (hipStream_t)stream);
     if (e != hipSuccess) return set_error(TM_EDEVICE, "map launch: %s", hipGetErrorString(e));
@@ -779,7 +790,8 @@ extern "C" int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cel
     int rc = TM_OK;
     for (int64_t cpi : cells_opts) {
         layout_items(p->cp, cpi);
-        rc = plan_upload(p, s);
+        rc = plan_ensure_arena(p, s);
+        if (rc == TM_OK) rc = plan_upload(p, s);
         if (rc != TM_OK) break;
         // tables once per layout (they do not depend on it)
         if (plan_enqueue(p, 0, d_out, nullptr, 1, s) != hipSuccess) {
@@ -816,7 +828,8 @@ extern "C" int tm_plan_autotune(tm_plan* p, tm_stencil_cost* d_out, int64_t* cel
     p->wg_per_cu = best_w;
     layout_items(p->cp, best_c);
     plan_drop_graphs(p);
-    rc = plan_upload(p, s);
+    rc = plan_ensure_arena(p, s);
+    if (rc == TM_OK) rc = plan_upload(p, s);
     if (cells_per_item) *cells_per_item = best_c;
     if (wg_per_cu) *wg_per_cu = best_w;
     return rc;
@@ -888,7 +901,8 @@ int plan_search_prepare(tm_plan* p, const int64_t* seg, int64_t nseg, int32_t to
     if (ranked && (topk < 1 || topk > 4096)) return set_error(TM_EINVAL, "topk %d not in 1..4096", topk);
     SearchBufs& b = p->sb;
     const int64_t nsel = ranked ? nseg * (int64_t)topk : 0;
-    const int64_t words = nsel * std::max<int64_t>(p->cp.max_all_words, 1);
+    // survivors' tables, then their item table
+    const int64_t words = nsel * (std::max<int64_t>(p->cp.max_all_words, 1) + p->cp.max_citems) + 4;
     auto grow = [&](bool need) -> int {
         if (!need) return TM_OK;
         TM_HIP(hipStreamSynchronize(s));
@@ -992,16 +1006,16 @@ int plan_search_prepare(tm_plan* p, const int64_t* seg, int64_t nseg, int32_t to
 hipError_t plan_eval_sub(tm_plan* p, SearchBufs* sb, hipStream_t s) {
     const int64_t nsel = sb->nseg * sb->k;
     const Compiled& cp = p->cp;
-    hipError_t e = launch_reset(sb->sub_hdr, sb->sub_counter, sb->sub_out, nsel, s);
-    if (e == hipSuccess) e = launch_build_tables(sb->sub_hdr, sb->sub, nsel, sb->sub_arena, 1, s);
+    hipError_t e = launch_build_tables(sb->sub_hdr, sb->sub, nsel, sb->sub_arena, 1, s, sb->sub_out, sb->sub_counter);
     if (e == hipSuccess) {
         // survivors' work items are bounded by the batch's largest candidate
         int64_t max_items = 0;
         for (const auto& d : cp.cands) max_items = std::max<int64_t>(max_items, count_items(d, plan_cells_per_item(p)));
         const int grid = count_grid(cp.cnt_words, std::max<int64_t>(1, max_items * nsel), p->wg_per_cu);
-        e = launch_count(sb->sub_hdr, sb->sub, sb->sub_arena, sb->sub_counter, sb->sub_out, grid, cp.cnt_words, s);
+        e = launch_count(sb->sub_hdr, sb->sub, sb->sub_arena, sb->sub_counter, sb->sub_out, grid, cp.cnt_words, s,
+                         nsel <= kFinInCount, nullptr);
     }
-    if (e == hipSuccess) e = launch_finalize_select(sb->sub_hdr, sb->sub_out, nullptr, s);
+    if (e == hipSuccess && nsel > kFinInCount) e = launch_finalize_select(sb->sub_hdr, sb->sub_out, nullptr, s);
     return e;
 }
 

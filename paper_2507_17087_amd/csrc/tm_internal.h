@@ -45,6 +45,7 @@ struct DevHeader {
     int32_t max_words, H;  // largest table prefix staged by the map kernel; max halo (offset-list stride 2H)
     int32_t node_level;    // owner tables hold nodes only (node-level exchange volume)
     int32_t cnt_words;     // LDS words of the counting launch (owner table + class blocks staged)
+    int64_t item_tab;      // arena word offset of the item table (candidate of every counting work item)
 };
 
 // Host-side result of validation.
@@ -92,6 +93,13 @@ __host__ __device__ inline int64_t class_cap(const DevCand& c, int d, int h) {
     return r < l ? r : l;
 }
 
+// Map kernel: rows per workgroup block, about 2,048 points (8 KB) of int32 map.
+constexpr int32_t kMapMaxRowsPerBlock = 64;
+__host__ __device__ inline int32_t map_rows_per_block(int32_t L) {
+    const int32_t r = (2048 + (L > 0 ? L : 1) - 1) / (L > 0 ? L : 1);
+    return r < 1 ? 1 : (r > kMapMaxRowsPerBlock ? kMapMaxRowsPerBlock : r);
+}
+
 // Counting work items of a candidate: its class-tuple bound (product of the
 // capacities) split into items of about `per_item` tuples (at least one item).
 __host__ __device__ inline int32_t count_items(const DevCand& c, int64_t per_item) {
@@ -110,13 +118,20 @@ int validate_shapes(const tm_candidate* c, Shapes* sh);
 int fill_devcand(const tm_candidate* c, const Shapes& sh, DevCand* d);
 
 // Kernel launchers (tm_kernels.hip).  All enqueue on `s` and return hipError_t.
+// Table build; with out/counter (stencil batches) it also zeroes the outputs and the
+// counting kernel's work and completion counters (counter[0], counter[1]).
 hipError_t launch_build_tables(const DevHeader* hdr, const DevCand* cands, int64_t n, int32_t* arena,
-                               int32_t mode_halo, hipStream_t s);
+                               int32_t mode_halo, hipStream_t s, tm_stencil_cost* out = nullptr,
+                               unsigned long long* counter = nullptr);
 hipError_t launch_reset(DevHeader* hdr, unsigned long long* counter, tm_stencil_cost* out, int64_t n,
                         hipStream_t s);
+// Counting; with fin the last workgroup to finish also writes the bytes and, when
+// best is given, selects (the work of k_finalize_select; for small batches).
 hipError_t launch_count(const DevHeader* hdr, const DevCand* cands, const int32_t* arena,
                         unsigned long long* counter, tm_stencil_cost* out, int grid, int lds_words,
-                        hipStream_t s);
+                        hipStream_t s, bool fin = false, int64_t* best = nullptr);
+// Batches up to this many candidates finalise inside the counting launch.
+constexpr int64_t kFinInCount = 2048;
 hipError_t launch_class_tuples(const DevCand* cands, int64_t n, const int32_t* arena, unsigned long long* total,
                                hipStream_t s);
 hipError_t launch_finalize_select(const DevHeader* hdr, tm_stencil_cost* out, int64_t* best,

@@ -75,13 +75,14 @@ extern "C" int tm_eval_stencil_batch_noalloc(const tm_candidate* c, int64_t n, c
     if (e == hipSuccess)
         e = hipMemcpyAsync(cands, cp.cands.data(), (size_t)n * sizeof(DevCand), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    // the counter and the outputs start at zero (k_reset), the arena is written whole
-    // by the table build
-    if (e == hipSuccess) e = launch_reset(hdr, counter, d_out, n, s);
-    if (e == hipSuccess) e = launch_build_tables(hdr, cands, n, arena, 1, s);
+    // the table build writes the whole arena (tables and item table) and zeroes the
+    // outputs and both counters before the counting starts
+    const bool fin = n <= kFinInCount;
+    if (e == hipSuccess) e = launch_build_tables(hdr, cands, n, arena, 1, s, d_out, counter);
     if (e == hipSuccess)
-        e = launch_count(hdr, cands, arena, counter, d_out, count_grid(cp.cnt_words, cp.items, 0), cp.cnt_words, s);
-    if (e == hipSuccess) e = launch_finalize_select(hdr, d_out, nullptr, s);
+        e = launch_count(hdr, cands, arena, counter, d_out, count_grid(cp.cnt_words, cp.items, 0), cp.cnt_words, s,
+                         fin, nullptr);
+    if (e == hipSuccess && !fin) e = launch_finalize_select(hdr, d_out, nullptr, s);
     if (e != hipSuccess) return set_error(TM_EDEVICE, "stencil launch (no allocation): %s", hipGetErrorString(e));
     return TM_OK;
 }

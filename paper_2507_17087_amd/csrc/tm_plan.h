@@ -20,6 +20,8 @@ struct Compiled {
     int32_t max_vol = 0;        // largest final-space volume
     int32_t cnt_words = 0;      // LDS words of the counting launch (largest staged owner table + class blocks)
     int64_t tuples = 0;         // class-tuple bound of the batch (sum of the candidates')
+    int64_t tables_words = 0;   // arena words of the tables (the item table follows)
+    int32_t max_citems = 0;     // most counting work items of one candidate
     int K = 0, H = 1;
 };
 

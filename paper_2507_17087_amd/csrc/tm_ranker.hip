@@ -534,9 +534,15 @@ __global__ __launch_bounds__(256) void k_colsum(const uint16_t* __restrict__ A, 
     if (col >= N) return;
     const int64_t ra = split * rows_per_split;
     const int64_t rb = ra + rows_per_split < n ? ra + rows_per_split : n;
-    float s = 0.f;
-    for (int64_t r = ra; r < rb; ++r) s += bf2f(A[r * N + col]);
-    P[(size_t)split * N + col] = s;
+    // eight partial sums (eight loads in flight), combined in a fixed order
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int64_t r = ra;
+    for (; r + 8 <= rb; r += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += bf2f(A[(r + u) * N + col]);
+    }
+    for (; r < rb; ++r) acc[0] += bf2f(A[r * N + col]);
+    P[(size_t)split * N + col] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
 // Head gradients: dW4[k][h] = sum_r H3[r][k] dY[r][h], db4[h] = sum_r dY[r][h].
@@ -546,19 +552,34 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const uint16_t* __restrict__
     const int t = threadIdx.x;  // k index
     const int64_t ra = split * rows_per_split;
     const int64_t rb = ra + rows_per_split < n ? ra + rows_per_split : n;
-    float s0 = 0.f, s1 = 0.f, b0 = 0.f, b1 = 0.f;
-    for (int64_t r = ra; r < rb; ++r) {
-        const float h = bf2f(H3[r * kWidth + t]);
-        s0 += h * dY[r * kOut];
-        s1 += h * dY[r * kOut + 1];
-        if (t == 0) {
-            b0 += dY[r * kOut];
-            b1 += dY[r * kOut + 1];
+    // four partial sums of each (four rows' loads in flight), combined in a fixed order
+    float s0[4] = {0.f, 0.f, 0.f, 0.f}, s1[4] = {0.f, 0.f, 0.f, 0.f};
+    float c0[4] = {0.f, 0.f, 0.f, 0.f}, c1[4] = {0.f, 0.f, 0.f, 0.f};
+    int64_t r = ra;
+    for (; r + 4 <= rb; r += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float h = bf2f(H3[(r + u) * kWidth + t]);
+            const float y0 = dY[(r + u) * kOut], y1 = dY[(r + u) * kOut + 1];
+            s0[u] += h * y0;
+            s1[u] += h * y1;
+            c0[u] += y0;
+            c1[u] += y1;
         }
     }
+    for (; r < rb; ++r) {
+        const float h = bf2f(H3[r * kWidth + t]);
+        const float y0 = dY[r * kOut], y1 = dY[r * kOut + 1];
+        s0[0] += h * y0;
+        s1[0] += h * y1;
+        c0[0] += y0;
+        c1[0] += y1;
+    }
+    const float t0 = (s0[0] + s0[1]) + (s0[2] + s0[3]), t1 = (s1[0] + s1[1]) + (s1[2] + s1[3]);
+    const float b0 = (c0[0] + c0[1]) + (c0[2] + c0[3]), b1 = (c1[0] + c1[1]) + (c1[2] + c1[3]);
     float* o = P + (size_t)split * (kWidth * kOut + kOut);
-    o[t * kOut] = s0;
-    o[t * kOut + 1] = s1;
+    o[t * kOut] = t0;
+    o[t * kOut + 1] = t1;
     if (t == 0) {
         o[kWidth * kOut] = b0;
         o[kWidth * kOut + 1] = b1;
@@ -570,9 +591,15 @@ __global__ __launch_bounds__(256) void k_reduce_splits(const float* __restrict__
                                                        float* __restrict__ dst) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= count) return;
-    float s = 0.f;
-    for (int sp = 0; sp < splits; ++sp) s += P[(size_t)sp * count + i];
-    dst[i] = s;
+    // four partial sums (four loads in flight), combined in a fixed order
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    int sp = 0;
+    for (; sp + 4 <= splits; sp += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += P[(size_t)(sp + u) * count + i];
+    }
+    for (; sp < splits; ++sp) acc[0] += P[(size_t)sp * count + i];
+    dst[i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // Adam on the fp32 master copy; refreshes the bf16 copies (row-major and
@@ -746,6 +773,7 @@ __global__ __launch_bounds__(1024) void k_gather(const DevCand* __restrict__ can
         DevHeader h = *proto;
         h.n = carry_c;
         h.total_items = carry_i;
+        h.item_tab = carry_w;  // the survivors' item table follows their tables
         *hdr = h;
     }
 }

@@ -243,7 +243,7 @@ def _lex_le(a, b):
 
 @pytest.fixture(scope="module")
 def held_out(tm):
-    inst = search_instances(tm, 64, seed=2, octaves=(3, 6))
+    inst = search_instances(tm, 200, seed=2, octaves=(3, 6))
     cands, seg = build_batch(inst)
     plan = loaded_plan(tm, cands, W.c3_stencil(3))
     b_ex, c_ex = tm.tm_search(plan, None, seg)
@@ -262,28 +262,73 @@ def test_ranked_search_quality(tm, trained, held_out):
     say(f"  {ok.sum()}/{len(ok)} instances at the exhaustive optimum; candidates {len(cands)}; "
         f"misses on total bytes {int((ce[:, 2] != cr[:, 2]).sum())}, on inter-node bytes only "
         f"{int(((ce[:, 2] == cr[:, 2]) & (ce[:, 3] != cr[:, 3])).sum())}")
-    assert ok.mean() >= 0.98
+    assert len(ok) >= 200 and ok.mean() >= 0.99
     # never better than the optimum
     assert _lex_le(ce, cr).all()
 
 
+@pytest.mark.parametrize("k", [3, 7, 20])
+def test_topk_selection(tm, held_out, k):
+    """The per-instance top-k below the instance's size, checked through the search:
+    with an all-zero network and lambda = 0 a candidate's score is its block-model
+    ghost estimate plus the (zero) mean, the same fp32 value as 32 times feature 23,
+    so the k smallest (score, index) pairs of each instance are known on the host;
+    the search must return the cheapest of exactly those (ties in the estimate are
+    common, so the index order of equal scores matters)."""
+    import torch
+    say(f"top-{k} selection")
+    inst, cands, seg, plan, ce = held_out
+    r = tm.Ranker(seed=4)
+    r.set_params(torch.zeros(tm.tm_ranker_param_count(), dtype=torch.float32, device="cuda"))
+    mu0 = np.float32(r.scaling()[0])
+    feat = tm.tm_ranker_features(plan).cpu().numpy()
+    score = np.float32(32) * feat[:, 23].astype(np.float32) + mu0
+    b, c = tm.tm_search(plan, r, seg, topk=k, lam=0.0)
+    out = torch.empty((len(cands), 4), dtype=torch.int64, device="cuda")
+    plan.run(out)
+    torch.cuda.synchronize()
+    allc, b, c = out.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()
+    for s_ in range(len(seg) - 1):
+        a, e = int(seg[s_]), int(seg[s_ + 1])
+        assert e - a > k
+        idx = np.arange(a, e)
+        sel = idx[np.lexsort((idx, score[a:e]))[:k]]
+        sub = allc[sel]
+        best = sel[np.lexsort((sel, sub[:, 3], sub[:, 2]))[0]]
+        assert b[s_] == best - a and tuple(c[s_]) == tuple(allc[best]), s_
+    r.close()
+
+
 def test_network_gain(tm, trained, held_out):
-    """What the trained network adds: (a) over the same search with an untrained
-    network, at equal top-k; (b) over the paper's own choice without any search --
-    decompose's argmin factorization of the surface-area objective (Sec. 4.3), under
-    the better of the two machine orders -- evaluated exactly."""
+    """What the trained network adds to the search, measured against the method
+    without it -- ranking by the block-model estimates alone (an all-zero network:
+    the score is the estimate) -- as the share of held-out instances whose top-k
+    holds the exhaustive optimum, k = 1 .. 64; and what the search adds over the
+    paper's own choice without any search, decompose's argmin factorization of the
+    surface-area objective (Sec. 4.3) under the better of the two machine orders,
+    evaluated exactly.  Measured result: the network gains nothing over the estimate
+    (the curves coincide for a network trained on the search instances' own
+    distribution), so the test holds it to not losing to the estimate."""
     import torch
     say("network gain")
     r, _ = trained
     inst, cands, seg, plan, ce = held_out
+    r0 = tm.Ranker(seed=1)
+    r0.set_params(torch.zeros(tm.tm_ranker_param_count(), dtype=torch.float32, device="cuda"))
+    rates = {}
+    for k in (1, 4, 16, 64):
+        _, c_tr = tm.tm_search(plan, r, seg, topk=k)
+        _, c_0 = tm.tm_search(plan, r0, seg, topk=k)
+        torch.cuda.synchronize()
+        rates[k] = (_at_opt(ce, c_tr.cpu().numpy()).mean(), _at_opt(ce, c_0.cpu().numpy()).mean())
+    say("  at the optimum (trained, estimate only): " +
+        ", ".join(f"top-{k} {a:.3f} {b:.3f}" for k, (a, b) in rates.items()))
+    for k, (a, b) in rates.items():
+        assert a >= b - 0.02, (k, a, b)
+    assert rates[64][0] >= 0.99 and rates[64][1] >= 0.99
     _, c_rk = tm.tm_search(plan, r, seg, topk=64)
-    ru = tm.Ranker(seed=2)
-    _, c_un = tm.tm_search(plan, ru, seg, topk=64)
-    torch.cuda.synchronize()
-    cr, cu = c_rk.cpu().numpy(), c_un.cpu().numpy()
-    rate_tr, rate_un = _at_opt(ce, cr).mean(), _at_opt(ce, cu).mean()
-    say(f"  at the optimum with top-64: trained {rate_tr:.3f}, untrained {rate_un:.3f}")
-    assert rate_tr >= rate_un + 0.1
+    cr = c_rk.cpu().numpy()
+    rate_tr = _at_opt(ce, cr).mean()
     # decompose's pick, both machine orders, exact costs
     st = W.c3_stencil(3)
     base = []
@@ -304,7 +349,7 @@ def test_network_gain(tm, trained, held_out):
         f"{worse.sum()}; total bytes -{100 * red_b:.1f} %, inter-node bytes -{100 * red_i:.1f} %")
     assert worse.mean() <= 1 - rate_tr + 1e-9
     assert better.sum() > 0
-    ru.close()
+    r0.close()
 
 
 def test_search_margin(tm, trained, held_out):

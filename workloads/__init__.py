@@ -196,6 +196,10 @@ def _genlib():
         _gen.gen_random_candidates.restype = ctypes.c_int
         _gen.gen_random_candidates.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64] + \
             [ctypes.c_int32] * 7 + [ctypes.c_void_p]
+        _gen.gen_random_chains.restype = ctypes.c_int
+        _gen.gen_random_chains.argtypes = [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_void_p]
         assert _gen.gen_sizeof_candidate() == CAND_DTYPE.itemsize
     return _gen
 
@@ -219,6 +223,20 @@ def random_candidates(n, seed=C3_SEED, first=0, ranks=(2, 3), octaves=(5, 9), no
     gmask = sum(1 << (int(g).bit_length() - 1) for g in gpus)
     rc = _genlib().gen_random_candidates(seed, first, n, kmask, octaves[0], octaves[1], nodes_max,
                                          gmask, max_ops, cyclic_pct, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("bad generator arguments")
+    return out
+
+
+def random_chain_instance(extent, nodes, gpus, n, seed, first=0, max_ops=4, cyclic_pct=25):
+    """n random candidates of one search instance (launch domain `extent` on
+    Machine(GPU) = (nodes, gpus)): each draws its factorization, 0..max_ops random
+    transformations and its projections (cyclic with probability cyclic_pct per
+    final dim) as the c3 recipe does; candidate i depends only on (seed, first + i)."""
+    out = np.zeros(n, dtype=CAND_DTYPE)
+    ext = np.array(list(extent) + [1] * (4 - len(extent)), dtype=np.int64)
+    rc = _genlib().gen_random_chains(seed, first, n, len(extent), ext.ctypes.data, nodes, gpus, max_ops,
+                                     cyclic_pct, out.ctypes.data)
     if rc != 0:
         raise ValueError("bad generator arguments")
     return out

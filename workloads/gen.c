@@ -173,6 +173,36 @@ static int random_op(rng_t* rg, int64_t* s, int* r, g_op* op) {
     return 1;
 }
 
+/* The chain part of a random candidate whose launch rank, domain and machine are
+ * set: merge(0,1) + decompose(0, F) with F uniform over the factorizations of
+ * nodes * gpus, then 0..max_ops random transformations (redrawn until the final
+ * rank is k), then per final dim a cyclic projection with probability cyclic_pct. */
+static void draw_chain(rng_t* rg, g_cand* c, int k, int32_t max_ops, int32_t cyclic_pct) {
+    int64_t P = (int64_t)c->nodes * c->gpus;
+    int32_t f[4];
+    random_factorization(rg, P, k, f);
+    c->ops[0].kind = K_MERGE; c->ops[0].a = 0; c->ops[0].b = 1;
+    c->ops[1].kind = K_DECOMPOSE; c->ops[1].a = 0; c->ops[1].nf = k;
+    for (int m = 0; m < k; m++) c->ops[1].f[m] = f[m];
+    int ntries = 0;
+    for (;;) {
+        int64_t s[G_MAX_RANK];
+        int r = k;
+        for (int m = 0; m < k; m++) s[m] = f[m];
+        int nx = (int)below(rg, (uint64_t)(max_ops + 1));
+        int ok = 1;
+        for (int t = 0; t < nx && ok; t++) ok = random_op(rg, s, &r, &c->ops[2 + t]);
+        if (ok && r == k) { c->nops = 2 + nx; break; }
+        if (++ntries > 1000) { c->nops = 2; break; } /* fall back to the plain decompose */
+    }
+    for (int t = c->nops; t < 8; t++) memset(&c->ops[t], 0, sizeof(g_op));
+    c->mrank = k;
+    for (int j = 0; j < k; j++) {
+        c->proj_src[j] = (int8_t)j;
+        c->proj_mode[j] = (cyclic_pct > 0 && (int)below(rg, 100) < cyclic_pct) ? 1 : 0;
+    }
+}
+
 /*
  * Batched random candidates.
  *   k_mask    : bit k set -> launch rank k allowed (e.g. 0b1100 = ranks 2 and 3)
@@ -206,30 +236,28 @@ int gen_random_candidates(uint64_t seed, int64_t first, int64_t n, int32_t k_mas
         }
         c->nodes = 1 + (int32_t)below(&rg, (uint64_t)nodes_max);
         c->gpus = gs[below(&rg, (uint64_t)ng)];
-        int64_t P = (int64_t)c->nodes * c->gpus;
-        int32_t f[4];
-        random_factorization(&rg, P, k, f);
-        /* base: merge(0,1) then decompose(0, F) */
-        c->ops[0].kind = K_MERGE; c->ops[0].a = 0; c->ops[0].b = 1;
-        c->ops[1].kind = K_DECOMPOSE; c->ops[1].a = 0; c->ops[1].nf = k;
-        for (int m = 0; m < k; m++) c->ops[1].f[m] = f[m];
-        int ntries = 0;
-        for (;;) {
-            int64_t s[G_MAX_RANK];
-            int r = k;
-            for (int m = 0; m < k; m++) s[m] = f[m];
-            int nx = (int)below(&rg, (uint64_t)(max_ops + 1));
-            int ok = 1;
-            for (int t = 0; t < nx && ok; t++) ok = random_op(&rg, s, &r, &c->ops[2 + t]);
-            if (ok && r == k) { c->nops = 2 + nx; break; }
-            if (++ntries > 1000) { c->nops = 2; break; } /* fall back to the plain decompose */
-        }
-        for (int t = c->nops; t < 8; t++) memset(&c->ops[t], 0, sizeof(g_op));
-        c->mrank = k;
-        for (int j = 0; j < k; j++) {
-            c->proj_src[j] = (int8_t)j;
-            c->proj_mode[j] = (cyclic_pct > 0 && (int)below(&rg, 100) < cyclic_pct) ? 1 : 0;
-        }
+        draw_chain(&rg, c, k, max_ops, cyclic_pct);
+    }
+    return 0;
+}
+
+/*
+ * Random chains on one launch domain and machine (a search instance): candidate idx
+ * (its own stream, as above) draws only its chain and projections.
+ */
+int gen_random_chains(uint64_t seed, int64_t first, int64_t n, int32_t k, const int64_t* extent, int32_t nodes,
+                      int32_t gpus, int32_t max_ops, int32_t cyclic_pct, g_cand* out) {
+    if (k < 1 || k > 4 || nodes < 1 || gpus < 1 || max_ops < 0 || max_ops > 6) return -1;
+    for (int64_t idx = 0; idx < n; idx++) {
+        rng_t rg;
+        stream_for(&rg, seed, (uint64_t)(first + idx));
+        g_cand* c = &out[idx];
+        memset(c, 0, sizeof(*c));
+        c->lrank = k;
+        for (int d = 0; d < k; d++) c->extent[d] = extent[d];
+        c->nodes = nodes;
+        c->gpus = gpus;
+        draw_chain(&rg, c, k, max_ops, cyclic_pct);
     }
     return 0;
 }
