@@ -251,11 +251,13 @@ int tm_eval_stencil_node_batch(const tm_candidate* c, int64_t n, const tm_stenci
  * domain on the same Machine(GPU) (host arrays): the cells whose owner under src
  * differs from their owner under dst -- the data a change of mapping moves, e.g. a
  * transpose by all-to-all exchanges (App. A.3; dst from tm_transpose_target) -- and
- * the part whose owner's node changes.  d_out (device, tm_redist_cost[n]).  TM_EINVAL
- * if a pair differs in launch rank, extents or machine (validation messages number
- * src[i] as candidate i and dst[i] as candidate n + i); TM_ENOTSUP if a pair's owner
- * tables and last-dim coordinate tables together exceed the LDS budget of 32768
- * words (a last-dim table that does not fit on its own is read from global memory). */
+ * the part whose owner's node changes.  d_out (device, tm_redist_cost[n]).  Counted
+ * exactly over joint coordinate classes: along each launch dim, consecutive
+ * coordinates with the same contributions under both mappings form a class, and the
+ * cells of a tuple of classes all move or all stay.  TM_EINVAL if a pair differs in
+ * launch rank, extents or machine (validation messages number src[i] as candidate i
+ * and dst[i] as candidate n + i).  Owner tables and classes have no size limit
+ * (those that do not fit the LDS budget together are read from global memory). */
 int tm_eval_redistribution_batch(const tm_candidate* src, const tm_candidate* dst, int64_t n, int64_t elem_bytes,
                                  tm_redist_cost* d_out, void* stream);
 

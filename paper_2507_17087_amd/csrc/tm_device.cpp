@@ -39,11 +39,6 @@ static int map_grid(int64_t rows, int32_t L) {
 
 // ------------------------------------------------------------------ batch compilation
 
-static int64_t rows_per_item_for(const DevCand& d, int64_t cells_per_item) {
-    const int64_t rpi = std::max<int64_t>(1, cells_per_item / std::max<int32_t>(d.L, 1));
-    return std::min<int64_t>(rpi, std::max<int64_t>(d.rows, 1));
-}
-
 static int64_t up4(int64_t x) { return (x + 3) & ~int64_t(3); }
 
 // Arena layout of one candidate: owner table T, the last dim's coordinate table
@@ -367,33 +362,54 @@ extern "C" int tm_eval_redistribution_batch(const tm_candidate* src, const tm_ca
         std::memcpy(both.data() + n, dst, (size_t)n * sizeof(tm_candidate));
     }
     Compiled cp;
-    int rc = compile_batch(both.data(), 2 * n, nullptr, 0, true, cp);
+    int rc = compile_batch(both.data(), 2 * n, nullptr, 0, false, cp);
     if (rc != TM_OK) return rc;
     if (n == 0) return TM_OK;
-    // work items over the pairs (the first mapping's rows); both tables in LDS
-    int64_t items = 0;
-    int32_t lds_words = 0;
-    const int64_t pair_cells = int64_t(1) << 17;  // measured: 4.0 ms vs 4.3 ms at 2^19 (108 pairs of 512^3)
-    for (int64_t i = 0; i < n; ++i) {
-        DevCand& a = cp.cands[(size_t)i];
-        const DevCand& b = cp.cands[(size_t)(n + i)];
-        const int64_t w = up4(a.lds_words) + up4(b.lds_words) + kRedistRuns;
-        if (w > kMaxLdsWords)
-            return set_error(TM_ENOTSUP, "pair %lld: %lld table words exceed the LDS budget of %d", (long long)i,
-                             (long long)w, kMaxLdsWords);
-        lds_words = std::max<int32_t>(lds_words, (int32_t)w);
-        const int64_t rpi = rows_per_item_for(a, pair_cells);
-        a.rows_per_item = (int32_t)rpi;
-        a.item_first = items;
-        items += (a.rows + rpi - 1) / rpi;
-    }
     if (!d_out) return set_error(TM_EINVAL, "null output");
+    // each pair's joint-class block goes into its a-side table block: the record, then
+    // per dim the a entries, the b entries and the run starts of its classes; a dim's
+    // joint classes start where either mapping's contribution changes, so there are at
+    // most 1 + changes_a + changes_b of them.  Work items split the pair's class-tuple
+    // bound; the item table follows the tables.
+    const int64_t tuples_per_item = int64_t(1) << 12;
+    int64_t words = 0, items = 0;
+    int32_t lds_words = 0;
+    for (int64_t i = 0; i < 2 * n; ++i) {
+        DevCand& d = cp.cands[(size_t)i];
+        if (i < n) {
+            const DevCand& b = cp.cands[(size_t)(n + i)];
+            int64_t off = up4(d.words), bound = 1;
+            d.cls_base = (int32_t)std::min<int64_t>(off, INT32_MAX);
+            off += 4;
+            for (int k = 0; k < d.lrank; ++k) {
+                const int64_t cap = std::min<int64_t>(d.extent[k], class_cap(d, k, 0) + class_cap(b, k, 0) - 1);
+                d.cls_cap[k] = (int32_t)cap;
+                d.cls_off[k] = (int32_t)std::min<int64_t>(off, INT32_MAX);
+                off += 2 * up4(cap) + up4(cap + 1);
+                bound = std::min<int64_t>(bound * cap, int64_t(1) << 50);
+            }
+            if (off > INT32_MAX) return set_error(TM_EOVERFLOW, "pair %lld: tables too large", (long long)i);
+            d.cls_words = (int32_t)(off - d.cls_base);
+            d.words = (int32_t)off;
+            d.citems = (int32_t)std::min<int64_t>(std::max<int64_t>((bound + tuples_per_item - 1) / tuples_per_item, 1),
+                                                  int64_t(1) << 30);
+            d.item_first = items;
+            items += d.citems;
+            const int64_t need = up4(d.vol) + up4(b.vol) + d.cls_words;  // staged when it fits the budget
+            if (need <= kMaxLdsWords) lds_words = std::max<int32_t>(lds_words, (int32_t)need);
+        }
+        d.arena_off = words;
+        words += d.words;
+    }
+    const int64_t item_tab = words;
+    cp.arena_words = words + up4(items);
     DeviceBatch db;
     rc = upload_batch(cp, db, s);
     if (rc == TM_OK) {
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)num_cus() * 8));
         hipError_t e = launch_build_tables(db.hdr, db.cands, 2 * n, db.arena, 0, s);
-        if (e == hipSuccess) e = launch_redist(db.cands, n, db.arena, items, elem_bytes, d_out, grid, lds_words, s);
+        if (e == hipSuccess)
+            e = launch_redist(db.cands, n, db.arena, item_tab, items, elem_bytes, d_out, db.counter, grid, lds_words, s);
         if (e != hipSuccess) rc = set_error(TM_EDEVICE, "redistribution launch: %s", hipGetErrorString(e));
     }
     free_batch(db, s);

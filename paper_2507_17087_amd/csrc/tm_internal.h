@@ -21,7 +21,7 @@ struct DevCand {
     int64_t arena_off;                  // word offset of this candidate's tables
     int64_t item_first;                 // first work item of this candidate
     int64_t rows;                       // points / extent[lrank-1]
-    int32_t rows_per_item, L;           // rows per work item (redistribution); row length = last extent
+    int32_t L, pad1;                    // row length = last extent
     int32_t coord_off[TM_MAX_LRANK];    // table offsets of the per-dim coordinate tables
     int32_t cls_off[TM_MAX_LRANK];      // table offsets of the per-dim coordinate-class blocks
     int32_t cls_cap[TM_MAX_LRANK];      // class capacity of each dim (an upper bound on the class count)
@@ -69,10 +69,6 @@ struct Shapes {
 constexpr int32_t kValMask = 0x00ffffff;
 constexpr int kCntShift = 24;
 constexpr int32_t kMaxLdsWords = 32768;
-// Redistribution: LDS words for the joint runs of a pair's last dim (rows of at most
-// kRedistMaxL cells), staged after the pair's two tables.
-constexpr int32_t kRedistRuns = 512;
-constexpr int32_t kRedistMaxL = 4096;
 constexpr int kMaxHalo = 4;
 
 // Upper bound on the class count of launch dim d (its block capacity): a class
@@ -93,10 +89,10 @@ __host__ __device__ inline int64_t class_cap(const DevCand& c, int d, int h) {
     return r < l ? r : l;
 }
 
-// Map kernel: rows per workgroup block, about 2,048 points (8 KB) of int32 map.
+// Map kernel: rows per workgroup block, about 4,096 points (16 KB) of int32 map.
 constexpr int32_t kMapMaxRowsPerBlock = 64;
 __host__ __device__ inline int32_t map_rows_per_block(int32_t L) {
-    const int32_t r = (2048 + (L > 0 ? L : 1) - 1) / (L > 0 ? L : 1);
+    const int32_t r = (4096 + (L > 0 ? L : 1) - 1) / (L > 0 ? L : 1);
     return r < 1 ? 1 : (r > kMapMaxRowsPerBlock ? kMapMaxRowsPerBlock : r);
 }
 
@@ -141,8 +137,11 @@ hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* s
 hipError_t launch_map(const DevCand* cands, int64_t n, const int32_t* arena, const int64_t* d_index,
                       int64_t index, int32_t* out, int grid, int lds_words, hipStream_t s);
 hipError_t launch_chain_table(const DevCand* cand, const int32_t* arena, int32_t* out, hipStream_t s);
-hipError_t launch_redist(const DevCand* cands, int64_t npair, const int32_t* arena, int64_t items,
-                         int64_t elem_bytes, tm_redist_cost* out, int grid, int lds_words, hipStream_t s);
+// Redistribution of npair pairs (joint classes, then counting over a work queue,
+// then bytes); the arena holds both mappings' tables and each pair's class block.
+hipError_t launch_redist(const DevCand* cands, int64_t npair, int32_t* arena, int64_t item_tab, int64_t items,
+                         int64_t elem_bytes, tm_redist_cost* out, unsigned long long* counter, int grid,
+                         int lds_words, hipStream_t s);
 hipError_t launch_matmul(const DevCand* cands, int64_t n, const int32_t* arena, int words_max,
                          int pmax, const int64_t* proc_off, unsigned long long* per_proc,
                          int64_t total_blocks, const int64_t* block_first, hipStream_t s);

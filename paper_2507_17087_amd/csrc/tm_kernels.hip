@@ -40,6 +40,24 @@ __device__ __forceinline__ int32_t uniform32(int32_t x) {
     return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
 }
 
+// Copies `words` int32 (a multiple of 4, both ends 16-byte aligned) from global
+// memory to LDS with the workgroup's 256 threads: 16-byte loads, four in flight.
+__device__ __forceinline__ void stage_words(int32_t* __restrict__ dst, const int32_t* __restrict__ src,
+                                            int32_t words) {
+    const i32x4* s4 = reinterpret_cast<const i32x4*>(src);
+    i32x4* d4 = reinterpret_cast<i32x4*>(dst);
+    const int32_t n4 = words >> 2;
+    int32_t i = threadIdx.x;
+    for (; i + 3 * 256 < n4; i += 4 * 256) {
+        const i32x4 a = s4[i], b = s4[i + 256], c = s4[i + 512], d = s4[i + 768];
+        d4[i] = a;
+        d4[i + 256] = b;
+        d4[i + 512] = c;
+        d4[i + 768] = d;
+    }
+    for (; i < n4; i += 256) d4[i] = s4[i];
+}
+
 // Sum over the wave of non-negative per-lane counts, in 64 bits (a wave's counts for
 // one work item can exceed 2^31 on very long rows).
 __device__ __forceinline__ unsigned long long wave_sum64(int v) {
@@ -386,9 +404,9 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
             const int32_t tw = (vol + 3) & ~3;
             const bool staged = tw + cw <= budget;
             __syncthreads();  // the previous candidate's staged tables are no longer read
-            if (staged) {
-                for (int i = tid; i < vol; i += 256) lds[i] = src[i];
-                for (int i = tid; i < cw; i += 256) lds[tw + i] = src[cb + i];
+            if (staged) {  // both regions 16-byte aligned, whole multiples of 4 words
+                stage_words(lds, src, tw);
+                stage_words(lds + tw, src + cb, cw);
             }
             T = staged ? lds : src;
             K = uniform32(c->lrank);
@@ -618,7 +636,7 @@ __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, 
     const DevCand* __restrict__ c = &cands[ci];
     const int32_t words = uniform32(c->lds_words);
     const int32_t* G = arena + uniform64(c->arena_off);  // outer tables (and a last-dim table that did not fit)
-    for (int i = threadIdx.x; i < words; i += blockDim.x) lds[i] = G[i];
+    stage_words(lds, G, (words + 3) & ~3);
     const int K = uniform32(c->lrank);
     const int32_t L = uniform32(c->L);
     const int64_t rows = uniform64(c->rows);
@@ -703,24 +721,222 @@ hipError_t launch_chain_table(const DevCand* cand, const int32_t* arena, int32_t
 // ------------------------------------------------------------------ redistribution
 //
 // Pairs (a, b) of mappings of one launch domain: candidates [0, npair) of the batch
-// are the a's, [npair, 2 npair) the b's, and a's item_first / rows_per_item give the
-// pair's work items (blocks of rows).  A workgroup stages both owner tables and
-// last-dim coordinate tables of its item's pair in LDS when the pair changes, and the
-// pair's joint runs along the last dim: maximal stretches of cells whose entries in
-// both tables equal their left neighbour's (same owners in every row).  Each wave
-// takes every fourth row of the item and works out the row's base index under both
-// mappings from the outer tables.  Every cell's two entries are read (a row whose
-// entries are all zero has one owner pair), then the runs are evaluated one per lane,
-// times their length; a row with the same two base indices as the previous one of the
-// wave (the same outer blocks in both) reuses each lane's share.  Rows longer than
-// kRedistMaxL cells, or with more than kRedistRuns runs, compare the two owner keys
-// of four consecutive cells per lane instead.  Counts go to the pair's totals with
-// one atomic per wave and item.
+// are the a's, [npair, 2 npair) the b's.  A cell moves when its owner under a
+// differs from its owner under b, and both owners are fixed by the pair of its
+// coordinate's contributions along every launch dim: consecutive coordinates with
+// the same pair (C^a_d[x], C^b_d[x]) form a joint class, and the moved cells are a
+// sum over tuples of joint classes, one owner comparison per tuple weighted by the
+// cells it stands for (exactly the per-cell count, regrouped).  k_pair_classes
+// builds each pair's joint classes (one workgroup per pair, a workgroup prefix count
+// of class starts), writes the item table and zeroes the pair's outputs; k_pair_count
+// takes (pair, tuple range) items from a work queue, as the stencil counting does.
+// The pair's class block sits in a's table block (cls_base, cls_off, cls_cap of the
+// a-side descriptor): record of the class counts, then per dim the a entries, the b
+// entries and the run starts of its classes.
 
-__global__ void k_redist_zero(tm_redist_cost* __restrict__ out, int64_t npair) {
-    int64_t* o = reinterpret_cast<int64_t*>(out);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 4 * npair; i += (int64_t)gridDim.x * blockDim.x)
-        o[i] = 0;
+__global__ __launch_bounds__(256) void k_pair_classes(const DevCand* __restrict__ cands, int64_t npair,
+                                                      int32_t* __restrict__ arena, int64_t item_tab,
+                                                      tm_redist_cost* __restrict__ out,
+                                                      unsigned long long* __restrict__ counter) {
+    __shared__ int32_t s_wt[4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (blockIdx.x == 0 && tid < 2) counter[tid] = 0ull;
+    for (int64_t i = blockIdx.x; i < npair; i += gridDim.x) {
+        const DevCand* __restrict__ a = &cands[i];
+        const DevCand* __restrict__ b = &cands[npair + i];
+        const int K = uniform32(a->lrank);
+        int32_t* A = arena + uniform64(a->arena_off);
+        const int32_t* B = arena + uniform64(b->arena_off);
+        if (tid < 4) reinterpret_cast<int64_t*>(&out[i])[tid] = 0;
+        const int32_t nit = uniform32(a->citems);
+        const int64_t first = uniform64(a->item_first);
+        for (int32_t j = tid; j < nit; j += blockDim.x) arena[item_tab + first + j] = (int32_t)i;
+        int32_t* rec = A + uniform32(a->cls_base);
+        for (int d = 0; d < K; ++d) {
+            const int64_t l = uniform64(a->extent[d]);
+            const int32_t* ca = A + uniform32(a->coord_off[d]);
+            const int32_t* cb = B + uniform32(b->coord_off[d]);
+            const int64_t cap = uniform32(a->cls_cap[d]);
+            int32_t* ea = A + uniform32(a->cls_off[d]);
+            int32_t* eb = ea + ((cap + 3) & ~int64_t(3));
+            int32_t* cs = eb + ((cap + 3) & ~int64_t(3));
+            int64_t run = 0;  // classes so far (the same in every thread)
+            for (int64_t x0 = 0; x0 < l; x0 += blockDim.x) {
+                const int64_t x = x0 + tid;
+                int32_t va = 0, vb = 0;
+                bool start = false;
+                if (x < l) {
+                    va = ca[x] & kValMask;
+                    vb = cb[x] & kValMask;
+                    start = x == 0 || (ca[x - 1] & kValMask) != va || (cb[x - 1] & kValMask) != vb;
+                }
+                const uint64_t m = __ballot(start);
+                if (lane == 0) s_wt[wid] = __popcll(m);
+                __syncthreads();
+                int64_t below = 0, tot = 0;
+                for (int w = 0; w < 4; ++w) {
+                    below += w < wid ? s_wt[w] : 0;
+                    tot += s_wt[w];
+                }
+                if (start) {
+                    const int64_t idx =
+                        run + below + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    if (idx < cap) {  // the capacity bounds the count; never exceeded
+                        ea[idx] = va;
+                        eb[idx] = vb;
+                        cs[idx] = (int32_t)x;
+                    }
+                }
+                run += tot;
+                __syncthreads();  // s_wt is rewritten by the next chunk
+            }
+            if (tid == 0) {
+                if (run <= cap) cs[run] = (int32_t)l;
+                rec[d] = run <= cap ? (int32_t)run : -1;  // -1: poisoned (counted as such)
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pair_count(const DevCand* __restrict__ cands, int64_t npair,
+                                                    const int32_t* __restrict__ arena, int64_t item_tab,
+                                                    int64_t total, int32_t budget,
+                                                    unsigned long long* __restrict__ counter,
+                                                    tm_redist_cost* __restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) int32_t lds[];
+    __shared__ long long s_item;
+    __shared__ int32_t s_pair;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int32_t* __restrict__ itab = arena + item_tab;
+    int64_t cur = -1;
+    int K = 1, gbits = 0, nit = 1;
+    int64_t ifirst = 0;
+    bool poisoned = false;
+    int32_t R[TM_MAX_LRANK];
+    const int32_t* TA = arena;
+    const int32_t* TB = arena;
+    const int32_t* EA[TM_MAX_LRANK];
+    const int32_t* EB[TM_MAX_LRANK];
+    const int32_t* CS[TM_MAX_LRANK];
+#pragma unroll
+    for (int d = 0; d < TM_MAX_LRANK; ++d) {
+        R[d] = 1;
+        EA[d] = EB[d] = CS[d] = arena;
+    }
+    unsigned long long next = 0;
+    int32_t next_p = 0;
+    if (tid == 0) {
+        next = atomicAdd(counter, 1ull);
+        next_p = (int64_t)next < total ? itab[next] : 0;
+    }
+    for (;;) {
+        if (tid == 0) {
+            s_item = (long long)next;
+            s_pair = next_p;
+        }
+        __syncthreads();
+        const int64_t item = uniform64(s_item);
+        const int64_t pi = uniform32(s_pair);
+        __syncthreads();
+        if (item >= total) break;
+        if (tid == 0) {
+            next = atomicAdd(counter, 1ull);
+            next_p = (int64_t)next < total ? itab[next] : 0;
+        }
+        if (pi != cur) {
+            const DevCand* a = &cands[pi];
+            const DevCand* b = &cands[npair + pi];
+            const int32_t* A = arena + uniform64(a->arena_off);
+            const int32_t* B = arena + uniform64(b->arena_off);
+            const int32_t va = uniform32(a->vol), vb = uniform32(b->vol);
+            const int32_t cbase = uniform32(a->cls_base), cw = uniform32(a->cls_words);
+            const int32_t ta = (va + 3) & ~3, tb = (vb + 3) & ~3;
+            const bool staged = ta + tb + cw <= budget;
+            __syncthreads();  // the previous pair's staged tables are no longer read
+            if (staged) {  // 16-byte aligned regions, whole multiples of 4 words
+                stage_words(lds, A, ta);
+                stage_words(lds + ta, B, tb);
+                stage_words(lds + ta + tb, A + cbase, cw);
+            }
+            TA = staged ? lds : A;
+            TB = staged ? lds + ta : B;
+            K = uniform32(a->lrank);
+            gbits = uniform32(a->gbits);
+            nit = uniform32(a->citems);
+            ifirst = uniform64(a->item_first);
+            poisoned = false;
+#pragma unroll
+            for (int d = 0; d < TM_MAX_LRANK; ++d) {
+                R[d] = 1;
+                if (d < K) {
+                    R[d] = uniform32(A[cbase + d]);
+                    poisoned = poisoned || R[d] < 0;
+                    const int64_t cap = uniform32(a->cls_cap[d]);
+                    const int32_t rel = uniform32(a->cls_off[d]);
+                    EA[d] = staged ? lds + ta + tb + (rel - cbase) : A + rel;
+                    EB[d] = EA[d] + ((cap + 3) & ~int64_t(3));
+                    CS[d] = EB[d] + ((cap + 3) & ~int64_t(3));
+                }
+            }
+            cur = pi;
+            __syncthreads();
+        }
+        if (poisoned) {  // a class block overflowed its capacity: make the result unmistakable
+            if (tid == 0) atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].moved_cells), 1ull << 62);
+            continue;
+        }
+        // this item's tuples [t0, t1) of the pair's N = prod R_d, split evenly
+        const int64_t j = item - ifirst;
+        int64_t N = 1;
+        for (int d = 0; d < K; ++d) N *= R[d];
+        const int64_t q = N / nit, r = N % nit;
+        const int64_t t0 = j * q + (j < r ? j : r);
+        const int64_t t1 = t0 + q + (j < r ? 1 : 0);
+        const int32_t RL = R[K - 1];
+        int64_t t = t0 + tid;
+        int32_t row = (int32_t)(t / RL), k = (int32_t)(t - (int64_t)row * RL);
+        const int32_t qs = 256 / RL, rs = 256 % RL;
+        int32_t mrow = -1, ao = 0, bo = 0;
+        int64_t wo = 1;
+        unsigned long long mv = 0, iv = 0;
+        for (; t < t1; t += 256) {
+            if (row != mrow) {  // outer classes of this row: both contributions and the weight
+                uint32_t rr = (uint32_t)row;
+                ao = 0;
+                bo = 0;
+                wo = 1;
+#pragma unroll
+                for (int d = TM_MAX_LRANK - 2; d >= 0; --d) {
+                    if (d > K - 2) continue;
+                    const uint32_t kd = rr % (uint32_t)R[d];
+                    rr /= (uint32_t)R[d];
+                    ao += EA[d][kd];
+                    bo += EB[d][kd];
+                    wo *= CS[d][kd + 1] - CS[d][kd];
+                }
+                mrow = row;
+            }
+            const int32_t oa = TA[ao + EA[K - 1][k]], ob = TB[bo + EB[K - 1][k]];
+            const int64_t w = wo * (int64_t)(CS[K - 1][k + 1] - CS[K - 1][k]);
+            mv += oa != ob ? (unsigned long long)w : 0ull;
+            iv += (oa >> gbits) != (ob >> gbits) ? (unsigned long long)w : 0ull;
+            k += rs;
+            row += qs;
+            if (k >= RL) {
+                k -= RL;
+                ++row;
+            }
+        }
+#pragma unroll
+        for (int o2 = 32; o2 > 0; o2 >>= 1) {
+            mv += __shfl_xor(mv, o2, 64);
+            iv += __shfl_xor(iv, o2, 64);
+        }
+        if (lane == 0 && (mv | iv)) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].moved_cells), mv);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].inter_cells), iv);
+        }
+    }
 }
 
 __global__ void k_redist_bytes(tm_redist_cost* __restrict__ out, int64_t npair, int64_t elem_bytes) {
@@ -730,203 +946,14 @@ __global__ void k_redist_bytes(tm_redist_cost* __restrict__ out, int64_t npair, 
     }
 }
 
-__global__ __launch_bounds__(256) void k_redist(const DevCand* __restrict__ cands, int64_t npair,
-                                                const int32_t* __restrict__ arena, int64_t total_items,
-                                                tm_redist_cost* __restrict__ out) {
-    extern __shared__ __attribute__((aligned(16))) int32_t lds[];  // 16-byte aligned: ds_read_b128 of the tables
-    __shared__ int32_t s_scan[4];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
-    int64_t cur = -1, rows = 0, ifirst = 0;
-    int32_t K = 1, L = 0, gbits = 0, rpi = 1, wa = 0, wb = 0, nrun = 0;
-    int32_t offa[TM_MAX_LRANK] = {0, 0, 0, 0}, offb[TM_MAX_LRANK] = {0, 0, 0, 0}, ext[TM_MAX_LRANK] = {1, 1, 1, 1};
-    const int32_t *GA = arena, *GB = arena, *CA = lds, *CB = lds;
-    // a contiguous range of items per workgroup: consecutive items share a pair, so
-    // its tables and runs are staged once per range rather than once per item
-    const int64_t per = (total_items + gridDim.x - 1) / gridDim.x;
-    const int64_t i0 = (int64_t)blockIdx.x * per, i1 = i0 + per < total_items ? i0 + per : total_items;
-    for (int64_t item = i0; item < i1; ++item) {
-        int64_t lo = 0, hi = npair - 1;
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (cands[mid].item_first <= item) lo = mid;
-            else hi = mid - 1;
-        }
-        lo = uniform64(lo);
-        if (lo != cur) {
-            __syncthreads();  // no wave still reads the previous pair's tables
-            const DevCand* a = &cands[lo];
-            const DevCand* b = &cands[npair + lo];
-            const int32_t na = uniform32(a->lds_words), nb = uniform32(b->lds_words);
-            wa = (na + 3) & ~3;
-            wb = (nb + 3) & ~3;
-            GA = arena + uniform64(a->arena_off);
-            GB = arena + uniform64(b->arena_off);
-            for (int i = tid; i < na; i += 256) lds[i] = GA[i];
-            for (int i = tid; i < nb; i += 256) lds[wa + i] = GB[i];
-            K = uniform32(a->lrank);
-            L = uniform32(a->L);
-            gbits = uniform32(a->gbits);
-            rpi = uniform32(a->rows_per_item);
-            rows = uniform64(a->rows);
-            ifirst = uniform64(a->item_first);
-            for (int d = 0; d < TM_MAX_LRANK; ++d) {
-                offa[d] = uniform32(a->coord_off[d]);
-                offb[d] = uniform32(b->coord_off[d]);
-                ext[d] = d < K ? uniform32((int32_t)a->extent[d]) : 1;
-            }
-            CA = uniform32(a->cl_lds) ? lds + offa[K - 1] : GA + offa[K - 1];
-            CB = uniform32(b->cl_lds) ? lds + wa + offb[K - 1] : GB + offb[K - 1];
-            cur = lo;
-            __syncthreads();
-            // joint runs of the last dim: each thread counts the run starts of its
-            // stretch of cells, a scan places them, then each writes (length << 16) | x
-            int32_t* runs = lds + wa + wb;
-            nrun = 0;
-            if (L <= kRedistMaxL) {
-                const int seg = (L + 255) / 256;
-                const int x0 = tid * seg, x1 = x0 + seg < L ? x0 + seg : L;
-                int c = 0;
-                for (int x = x0; x < x1; ++x) c += (x == 0 || CA[x] != CA[x - 1] || CB[x] != CB[x - 1]) ? 1 : 0;
-                // exclusive scan over the workgroup: within each wave by shuffles, then
-                // the four wave totals
-                int v = c;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int t = __shfl_up(v, o, 64);
-                    if (lane >= o) v += t;
-                }
-                if (lane == 63) s_scan[wid] = v;
-                __syncthreads();
-                int wbase = 0;
-                for (int w = 0; w < wid; ++w) wbase += s_scan[w];
-                const int total = s_scan[0] + s_scan[1] + s_scan[2] + s_scan[3];
-                __syncthreads();
-                if (total <= kRedistRuns) {
-                    int pos = wbase + v - c;
-                    for (int x = x0; x < x1; ++x) {
-                        if (x == 0 || CA[x] != CA[x - 1] || CB[x] != CB[x - 1]) {
-                            int y = x + 1;
-                            while (y < L && CA[y] == CA[x] && CB[y] == CB[x]) ++y;
-                            runs[pos++] = x | ((y - x) << 16);
-                        }
-                    }
-                    nrun = total;
-                }
-                __syncthreads();
-            }
-            nrun = uniform32(nrun);
-        }
-        const int32_t* TA = lds;
-        const int32_t* TB = lds + wa;
-        const int32_t* runs = lds + wa + wb;
-        const int64_t r0 = (item - ifirst) * rpi;
-        const int64_t rb = r0 + rpi < rows ? r0 + rpi : rows;
-        uint32_t moved = 0, inter = 0;
-        int32_t mba = -1, mbb = -1;
-        uint32_t mm = 0, mi = 0;
-        // base indices of the wave's next 64 rows, one row per lane (loads in parallel)
-        int32_t bab = 0, bbb = 0;
-        int t = 64;
-        for (int64_t r = r0 + wid; r < rb; r += 4) {
-            if (t == 64) {
-                t = 0;
-                const int64_t ri = r + 4 * (int64_t)lane;
-                bab = 0;
-                bbb = 0;
-                if (ri < rb) {
-                    uint32_t rr = (uint32_t)ri;  // rows <= 2^30 (checked on the host)
-                    for (int d = K - 2; d >= 0; --d) {
-                        const uint32_t e = (uint32_t)ext[d];
-                        const int32_t q = (int32_t)(rr % e);
-                        rr /= e;
-                        bab += GA[offa[d] + q] & kValMask;
-                        bbb += GB[offb[d] + q] & kValMask;
-                    }
-                }
-            }
-            const int32_t ba = __builtin_amdgcn_readlane(bab, t);
-            const int32_t bb = __builtin_amdgcn_readlane(bbb, t);
-            ++t;
-            if (nrun > 0) {
-                // every cell's two entries read; all zero: one owner pair for the row
-                int32_t any = 0;
-                for (int x = 4 * lane; x < L; x += 256) {
-                    const i32x4 ea = *reinterpret_cast<const i32x4*>(CA + x);
-                    const i32x4 eb = *reinterpret_cast<const i32x4*>(CB + x);
-                    any |= ea.x | ea.y | ea.z | ea.w | eb.x | eb.y | eb.z | eb.w;  // zero past L
-                }
-                if (__ballot(any != 0) == 0ull) {
-                    const int32_t ka = TA[ba], kb = TB[bb];
-                    if (lane == 0) {
-                        moved += ka != kb ? (uint32_t)L : 0u;
-                        inter += (ka >> gbits) != (kb >> gbits) ? (uint32_t)L : 0u;
-                    }
-                    continue;
-                }
-                if (ba != mba || bb != mbb) {
-                    mm = 0;
-                    mi = 0;
-                    for (int k = lane; k < nrun; k += 64) {
-                        const int32_t run = runs[k];
-                        const int32_t x = run & 0xffff;
-                        const uint32_t len = (uint32_t)run >> 16;
-                        const int32_t ka = TA[ba + (CA[x] & kValMask)];
-                        const int32_t kb = TB[bb + (CB[x] & kValMask)];
-                        mm += ka != kb ? len : 0u;
-                        mi += (ka >> gbits) != (kb >> gbits) ? len : 0u;
-                    }
-                    mba = ba;
-                    mbb = bb;
-                }
-                moved += mm;
-                inter += mi;
-                continue;
-            }
-            int32_t pa = -1, pb = -1;
-            uint32_t pm = 0, pi = 0;
-            for (int x = 4 * lane; x < L; x += 256) {
-                // tables are zero-padded to whole 512-entry chunks: x + 3 is in bounds
-                const i32x4 ea = *reinterpret_cast<const i32x4*>(CA + x);
-                const i32x4 eb = *reinterpret_cast<const i32x4*>(CB + x);
-                const int32_t va[4] = {ea.x, ea.y, ea.z, ea.w}, vb[4] = {eb.x, eb.y, eb.z, eb.w};
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (x + j >= L) break;
-                    if (va[j] != pa || vb[j] != pb) {
-                        const int32_t ka = TA[ba + (va[j] & kValMask)];
-                        const int32_t kb = TB[bb + (vb[j] & kValMask)];
-                        pm = ka != kb ? 1u : 0u;
-                        pi = (ka >> gbits) != (kb >> gbits) ? 1u : 0u;
-                        pa = va[j];
-                        pb = vb[j];
-                    }
-                    moved += pm;
-                    inter += pi;
-                }
-            }
-        }
-        unsigned long long m64 = moved, i64 = inter;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            m64 += __shfl_xor(m64, o, 64);
-            i64 += __shfl_xor(i64, o, 64);
-        }
-        if (lane == 0 && (m64 | i64)) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].moved_cells), m64);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&out[cur].inter_cells), i64);
-        }
-    }
-}
-
-hipError_t launch_redist(const DevCand* cands, int64_t npair, const int32_t* arena, int64_t items,
-                         int64_t elem_bytes, tm_redist_cost* out, int grid, int lds_words, hipStream_t s) {
-    const int64_t zb = (4 * npair + 255) / 256;
-    const int zg = zb < 1 ? 1 : (zb > 1024 ? 1024 : (int)zb);
-    hipLaunchKernelGGL(k_redist_zero, dim3(zg), dim3(256), 0, s, out, npair);
-    if (items > 0)
-        hipLaunchKernelGGL(k_redist, dim3(grid), dim3(256), (size_t)lds_words * 4, s, cands, npair, arena, items,
-                           out);
+hipError_t launch_redist(const DevCand* cands, int64_t npair, int32_t* arena, int64_t item_tab, int64_t items,
+                         int64_t elem_bytes, tm_redist_cost* out, unsigned long long* counter, int grid,
+                         int lds_words, hipStream_t s) {
+    const int64_t pg = npair < 65536 ? (npair > 0 ? npair : 1) : 65536;
+    hipLaunchKernelGGL(k_pair_classes, dim3((unsigned)pg), dim3(256), 0, s, cands, npair, arena, item_tab, out, counter);
+    hipLaunchKernelGGL(k_pair_count, dim3(grid), dim3(256), (size_t)lds_words * 4, s, cands, npair,
+                       (const int32_t*)arena, item_tab, items, lds_words, counter, out);
+    const int zg = (int)std::min<int64_t>((npair + 255) / 256 + 1, 1024);
     hipLaunchKernelGGL(k_redist_bytes, dim3(zg), dim3(256), 0, s, out, npair, elem_bytes);
     return hipGetLastError();
 }

@@ -176,8 +176,8 @@ def test_row_limit_rejected_before_any_launch():
 def test_redistribution_validation_before_any_launch():
     """Host-side checks of tm_eval_redistribution_batch, all before device work: pairs
     on different machines or domains and a negative element size are TM_EINVAL, an
-    empty batch is TM_OK, a pair whose two owner tables exceed the LDS budget together
-    is TM_ENOTSUP (a null output is never reached)."""
+    empty batch is TM_OK; owner tables larger than the LDS budget together are
+    accepted (they are read in place), so such a pair stops at the null output."""
     L = tm.lib()
     a = W.batch([W.candidate((8, 8), 1, 4, [merge(0, 1), decompose(0, (2, 2))])])
     other_machine = W.batch([W.candidate((8, 8), 2, 2, [merge(0, 1), decompose(0, (2, 2))])])
@@ -188,7 +188,8 @@ def test_redistribution_validation_before_any_launch():
     assert L.tm_eval_redistribution_batch(a.ctypes.data, a.ctypes.data, 1, -1, None, None) == tm.TM_EINVAL
     assert L.tm_eval_redistribution_batch(None, None, 0, 8, None, None) == tm.TM_OK
     big = W.batch([W.candidate((64, 512), 128, 128, [merge(0, 1), decompose(0, (128, 128))])])
-    assert L.tm_eval_redistribution_batch(big.ctypes.data, big.ctypes.data, 1, 8, None, None) == tm.TM_ENOTSUP
+    assert L.tm_eval_redistribution_batch(big.ctypes.data, big.ctypes.data, 1, 8, None, None) == tm.TM_EINVAL
+    assert b"null output" in L.tm_last_error()
     # a valid pair passes validation and stops at the null output
     assert L.tm_eval_redistribution_batch(a.ctypes.data, a.ctypes.data, 1, 8, None, None) == tm.TM_EINVAL
     assert b"null output" in L.tm_last_error()

@@ -115,8 +115,7 @@ def test_redistribution_edges(tm):
     got = gpu_redist(tm, src, dst, 8)
     assert (got == exp).all()
     assert tuple(got[0]) == (0, 0, 0, 0)
-    # a pair on different machines or domains; negative element size; a pair whose
-    # owner tables do not fit the LDS budget together
+    # a pair on different machines or domains; negative element size
     with pytest.raises(tm.TaskmapError) as e:
         tm.tm_eval_redistribution_batch(W.batch([_grid((8, 8), (2, 2), 1, 4)]), W.batch([_grid((8, 8), (2, 2), 2, 2)]))
     assert e.value.code == tm.TM_EINVAL
@@ -124,10 +123,13 @@ def test_redistribution_edges(tm):
         tm.tm_eval_redistribution_batch(W.batch([_grid((8, 8), (2, 2), 1, 4)]), W.batch([_grid((8, 9), (2, 2), 1, 4)]))
     with pytest.raises(tm.TaskmapError):
         tm.tm_eval_redistribution_batch(W.batch([cases[0][0]]), W.batch([cases[0][1]]), -1)
+    # owner tables of 16,384 processors each (together over the LDS budget: read in
+    # place), against a swapped spelling and a transposed grid
     big = _grid((64, 512), (128, 128), 128, 128)
-    with pytest.raises(tm.TaskmapError) as e:
-        tm.tm_eval_redistribution_batch(W.batch([big]), W.batch([big]))
-    assert e.value.code == tm.TM_ENOTSUP
+    src = W.batch([big, big])
+    dst = W.batch([_grid((64, 512), (128, 128), 128, 128, tail=[swap(0, 1), swap(0, 1)]),
+                   _grid((64, 512), (64, 256), 128, 128)])
+    assert (gpu_redist(tm, src, dst, 8) == oracle.redistribution_cost_batch(src, dst, 8)).all()
     torch.cuda.synchronize()
 
 
