@@ -265,9 +265,11 @@ int tm_eval_redistribution_batch(const tm_candidate* src, const tm_candidate* ds
  * Johnson's 3-D, Solomonik's 2.5-D -- differ in) of n rank-3 candidates:
  * d_per_proc (device, int64[sum P_c][3],
  * candidates back to back, may be NULL) and d_out (device, tm_matmul_cost[n]).
- * TM_ENOTSUP if a candidate has more than 1024 processors or its owner and
- * coordinate tables together exceed the LDS budget of 32768 words (the kernel reads
- * all three coordinate tables per task point). */
+ * Counted over coordinate classes: along each launch dim, consecutive coordinates
+ * with the same contribution to the final index form a class; all tiles of one pair
+ * of classes have the same owner set along the reduction dim, so each owner of the
+ * pair counts its tiles at once.  TM_ENOTSUP if a candidate has more than 1024
+ * processors or a matrix has more than 2^31 tiles. */
 int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_matmul* mm,
                          int64_t* d_per_proc, tm_matmul_cost* d_out, void* stream);
 

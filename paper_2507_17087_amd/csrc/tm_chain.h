@@ -15,6 +15,17 @@ __device__ __forceinline__ void stage_cand(DevCand* dst, const DevCand* src) {
     for (int i = threadIdx.x; i < (int)(sizeof(DevCand) / 4); i += blockDim.x) d[i] = s[i];
 }
 
+// floor(a / b) and a mod b for a >= 0, b >= 1: a 32-bit division when both operands
+// fit in 32 bits (nearly always), else the 64-bit one.
+__device__ __forceinline__ int64_t div_nn(int64_t a, int64_t b) {
+    if ((((uint64_t)a | (uint64_t)b) >> 32) == 0) return (int64_t)((uint32_t)a / (uint32_t)b);
+    return a / b;
+}
+__device__ __forceinline__ int64_t mod_nn(int64_t a, int64_t b) {
+    if ((((uint64_t)a | (uint64_t)b) >> 32) == 0) return (int64_t)((uint32_t)a % (uint32_t)b);
+    return a % b;
+}
+
 // Owner key of final-space coordinate v: decode v (C order), then undo the ops.
 __device__ inline int32_t owner_key(const DevCand& c, int32_t v) {
     int32_t a[TM_MAX_MRANK], b[TM_MAX_MRANK];
@@ -48,10 +59,10 @@ __device__ inline int32_t owner_key(const DevCand& c, int32_t v) {
                 break;
             case TM_BALANCE_SPLIT: {
                 const int64_t si = s[pa];
-                const int64_t cc = (si + pb - 1) / pb;
+                const int64_t cc = div_nn(si + pb - 1, pb);
                 const int64_t vv = (int64_t)a[pa] + (int64_t)a[pa + 1] * pb;
                 for (int u = 0; u < pa; ++u) b[u] = a[u];
-                b[pa] = (int32_t)((vv * si) / ((int64_t)pb * cc));
+                b[pa] = (int32_t)div_nn(vv * si, (int64_t)pb * cc);
                 for (int u = pa + 1; u < r; ++u) b[u] = a[u + 1];
                 break;
             }
@@ -76,7 +87,7 @@ __device__ inline int32_t coord_value(const DevCand& c, int d, int64_t x) {
     for (int j = 0; j < c.frank; ++j) {
         if (c.proj_src[j] != d) continue;
         const int64_t s = c.fshape[j];
-        const int64_t a = c.proj_mode[j] == TM_BLOCK ? (x * s) / c.extent[d] : x % s;
+        const int64_t a = c.proj_mode[j] == TM_BLOCK ? div_nn(x * s, c.extent[d]) : mod_nn(x, s);
         v += (int32_t)a * c.fstride[j];
     }
     return v;

@@ -420,19 +420,17 @@ extern "C" int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_m
                                     tm_matmul_cost* d_out, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     if (!mm || mm->tile_bytes < 0) return set_error(TM_EINVAL, "bad matmul descriptor");
+    // coordinate classes with a zero halo: runs of coordinates with equal contributions
+    tm_stencil zs{};
+    zs.lrank = TM_MAX_LRANK;
     Compiled cp;
-    int rc = compile_batch(c, n, nullptr, 0, true, cp);
+    int rc = compile_batch(c, n, &zs, 0, false, cp);
     if (rc != TM_OK) return rc;
     if (n == 0) return TM_OK;
     if (!d_out) return set_error(TM_EINVAL, "null output");
-    // the matmul kernel reads every coordinate table per task point: all of them in LDS
-    if (cp.max_all_words > kMaxLdsWords)
-        return set_error(TM_ENOTSUP, "matmul tables of %d words exceed the LDS budget of %d", cp.max_all_words,
-                         kMaxLdsWords);
     std::vector<int64_t> proc_off((size_t)n + 1), block_first((size_t)n + 1);
     int64_t procs = 0, blocks = 0;
     int pmax = 0;
-    const int64_t per = 256 * 16;
     for (int64_t i = 0; i < n; ++i) {
         const DevCand& d = cp.cands[(size_t)i];
         if (d.lrank != 3) return set_error(TM_EINVAL, "candidate %lld: matmul needs launch rank 3", (long long)i);
@@ -445,8 +443,7 @@ extern "C" int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_m
         proc_off[(size_t)i] = procs;
         block_first[(size_t)i] = blocks;
         procs += P;
-        blocks += (d.extent[0] * d.extent[2] + per - 1) / per + (d.extent[2] * d.extent[1] + per - 1) / per +
-                  (d.extent[0] * d.extent[1] + per - 1) / per;
+        blocks += matmul_blocks(d);
     }
     proc_off[(size_t)n] = procs;
     block_first[(size_t)n] = blocks;
@@ -472,9 +469,9 @@ extern "C" int tm_eval_matmul_batch(const tm_candidate* c, int64_t n, const tm_m
             }
         }
         if (rc == TM_OK && e == hipSuccess) e = hipMemsetAsync(d_pp, 0, (size_t)std::max<int64_t>(procs, 1) * 24, s);
-        if (rc == TM_OK && e == hipSuccess) e = launch_build_tables(db.hdr, db.cands, n, db.arena, 0, s);
+        if (rc == TM_OK && e == hipSuccess) e = launch_build_tables(db.hdr, db.cands, n, db.arena, 1, s);
         if (rc == TM_OK && e == hipSuccess)
-            e = launch_matmul(db.cands, n, db.arena, cp.max_all_words, pmax, d_off, d_pp, blocks, d_bf, s);
+            e = launch_matmul(db.cands, n, db.arena, cp.cnt_words, pmax, d_off, d_pp, blocks, d_bf, s);
         if (rc == TM_OK && e == hipSuccess)
             e = launch_matmul_finalize(db.cands, n, d_off, d_pp, mm->tile_bytes, d_out, d_per_proc, s);
         if (rc == TM_OK && e != hipSuccess) rc = set_error(TM_EDEVICE, "matmul launch: %s", hipGetErrorString(e));
@@ -1024,9 +1021,9 @@ hipError_t plan_eval_sub(tm_plan* p, SearchBufs* sb, hipStream_t s) {
     const Compiled& cp = p->cp;
     hipError_t e = launch_build_tables(sb->sub_hdr, sb->sub, nsel, sb->sub_arena, 1, s, sb->sub_out, sb->sub_counter);
     if (e == hipSuccess) {
-        // survivors' work items are bounded by the batch's largest candidate
-        int64_t max_items = 0;
-        for (const auto& d : cp.cands) max_items = std::max<int64_t>(max_items, count_items(d, plan_cells_per_item(p)));
+        // survivors' work items are bounded by the batch's largest candidate (its item
+        // count under the plan's current layout)
+        const int64_t max_items = cp.max_citems;
         const int grid = count_grid(cp.cnt_words, std::max<int64_t>(1, max_items * nsel), p->wg_per_cu);
         e = launch_count(sb->sub_hdr, sb->sub, sb->sub_arena, sb->sub_counter, sb->sub_out, grid, cp.cnt_words, s,
                          nsel <= kFinInCount, nullptr);

@@ -137,6 +137,18 @@ hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* s
 hipError_t launch_map(const DevCand* cands, int64_t n, const int32_t* arena, const int64_t* d_index,
                       int64_t index, int32_t* out, int grid, int lds_words, hipStream_t s);
 hipError_t launch_chain_table(const DevCand* cand, const int32_t* arena, int32_t* out, hipStream_t s);
+// Matmul work blocks: kMatmulTiles class pairs of one matrix each.  A matrix over
+// launch dims (a, b) has cls_cap[a] * cls_cap[b] class pairs at most; A = (0, 2),
+// B = (2, 1), C = (0, 1).
+constexpr int kMatmulTiles = 4096;
+__host__ __device__ inline int64_t matmul_pair_blocks(int64_t ca, int64_t cb) {
+    return (ca * cb + kMatmulTiles - 1) / kMatmulTiles;
+}
+__host__ __device__ inline int64_t matmul_blocks(const DevCand& d) {
+    return matmul_pair_blocks(d.cls_cap[0], d.cls_cap[2]) + matmul_pair_blocks(d.cls_cap[2], d.cls_cap[1]) +
+           matmul_pair_blocks(d.cls_cap[0], d.cls_cap[1]);
+}
+
 // Redistribution of npair pairs (joint classes, then counting over a work queue,
 // then bytes); the arena holds both mappings' tables and each pair's class block.
 hipError_t launch_redist(const DevCand* cands, int64_t npair, int32_t* arena, int64_t item_tab, int64_t items,

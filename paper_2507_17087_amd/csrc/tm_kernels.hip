@@ -960,25 +960,35 @@ hipError_t launch_redist(const DevCand* cands, int64_t npair, int32_t* arena, in
 
 // ------------------------------------------------------------------ matmul tiles
 //
-// Work block = (candidate, matrix m in {A,B,C}, 16 x 256 consecutive tiles).  A thread
-// owns one tile and walks the reduction index (j for A[i,k], i for B[k,j], k for
-// C[i,j]), OR-ing the owner's bit into a processor bitmap of W 64-bit words held in
-// registers.  Per-processor counts come from wave ballots over the bitmaps; lane p
-// of the wave keeps processor (64*w + p)'s count, and one atomic per wave and word
-// adds it to the global per-processor totals.
-
-constexpr int kMatmulChunks = 16;  // a work block covers 16 x 256 tiles of one matrix
+// A tile of A (i, k) is fetched by every processor that owns some task (i, j, k),
+// and the owners along j depend only on the classes of i and k (runs of coordinates
+// with the same contribution to the final index, built by the table build with a
+// zero halo): all tiles of one pair of classes have the same owner set, and each
+// processor of it counts the pair's tiles, the product of the two run lengths.  The
+// same holds for B (k, j) over i and C (i, j) over k.  Work block = (candidate,
+// matrix m in {A, B, C}, kMatmulTiles class pairs of the candidate's bound); a
+// thread takes one class pair per step and walks the classes of the reduction dim,
+// OR-ing each owner's bit into a bitmap of W 64-bit words in registers, then adds
+// the pair's weight to every processor of its bitmap in LDS; the block's LDS counts
+// go to the per-processor totals with one atomic per processor.
 
 template <int W>
 __global__ __launch_bounds__(256) void k_matmul(const DevCand* __restrict__ cands, int64_t n,
                                                 const int32_t* __restrict__ arena,
                                                 const int64_t* __restrict__ proc_off,
                                                 unsigned long long* __restrict__ per_proc,
-                                                const int64_t* __restrict__ block_first, int64_t total_blocks) {
-    extern __shared__ __attribute__((aligned(16))) int32_t lds[];  // 16-byte aligned: ds_read_b128 of staged tables
-    __shared__ DevCand sc;
-    const int lane = threadIdx.x & 63;
+                                                const int64_t* __restrict__ block_first, int64_t total_blocks,
+                                                int32_t budget) {
+    extern __shared__ __attribute__((aligned(16))) int32_t lds[];  // owner table and class blocks
+    __shared__ unsigned long long s_cnt[64 * W];
+    const int tid = threadIdx.x;
     int64_t cur = -1;
+    const int32_t* T = arena;
+    const int32_t* E[3];
+    const int32_t* S[3];
+    int32_t R[3] = {1, 1, 1};
+    int32_t gb = 0, g = 1, P = 1;
+    for (int i = tid; i < 64 * W; i += 256) s_cnt[i] = 0;
     for (int64_t blk = blockIdx.x; blk < total_blocks; blk += gridDim.x) {
         int64_t lo = 0, hi = n - 1;
         while (lo < hi) {
@@ -986,87 +996,96 @@ __global__ __launch_bounds__(256) void k_matmul(const DevCand* __restrict__ cand
             if (block_first[mid] <= blk) lo = mid;
             else hi = mid - 1;
         }
+        lo = uniform64(lo);
         if (lo != cur) {
-            __syncthreads();
-            stage_cand(&sc, &cands[lo]);
-            __syncthreads();
-            const int32_t* src = arena + sc.arena_off;
-            for (int i = threadIdx.x; i < sc.words; i += blockDim.x) lds[i] = src[i];  // every table
-            __syncthreads();
+            const DevCand* c = &cands[lo];
+            const int32_t* src = arena + uniform64(c->arena_off);
+            const int32_t vol = uniform32(c->vol), cb = uniform32(c->cls_base), cw = uniform32(c->cls_words);
+            const int32_t tw = (vol + 3) & ~3;
+            const bool staged = tw + cw <= budget;
+            __syncthreads();  // the previous candidate's tables are no longer read
+            if (staged) {
+                stage_words(lds, src, tw);
+                stage_words(lds + tw, src + cb, cw);
+            }
+            T = staged ? lds : src;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                R[d] = uniform32(src[cb + d]);
+                const int64_t cap = uniform32(c->cls_cap[d]);
+                const int32_t rel = uniform32(c->cls_off[d]);
+                E[d] = staged ? lds + tw + (rel - cb) : src + rel;
+                S[d] = E[d] + ((cap + 3) & ~int64_t(3));
+            }
+            gb = uniform32(c->gbits);
+            g = uniform32(c->gpus);
+            P = uniform32(c->nodes) * g;
             cur = lo;
+            __syncthreads();
         }
-        const int64_t Ti = sc.extent[0], Tj = sc.extent[1], Tk = sc.extent[2];
-        const int64_t nA = Ti * Tk, nB = Tk * Tj, nC = Ti * Tj;
-        const int64_t per = 256 * kMatmulChunks;
-        const int64_t bA = (nA + per - 1) / per, bB = (nB + per - 1) / per;
-        int64_t local = blk - block_first[lo];
+        const int64_t b0 = block_first[lo];
+        const int64_t c0 = uniform32(cands[lo].cls_cap[0]), c1 = uniform32(cands[lo].cls_cap[1]),
+                      c2 = uniform32(cands[lo].cls_cap[2]);
+        const int64_t bA = matmul_pair_blocks(c0, c2), bB = matmul_pair_blocks(c2, c1);
+        int64_t local = blk - b0;
         int m;
         if (local < bA) m = 0;
         else if (local < bA + bB) { m = 1; local -= bA; }
         else { m = 2; local -= bA + bB; }
-        const int64_t ntile = m == 0 ? nA : (m == 1 ? nB : nC);
-        const int32_t* T = lds;
-        const int32_t* C0 = lds + sc.coord_off[0];
-        const int32_t* C1 = lds + sc.coord_off[1];
-        const int32_t* C2 = lds + sc.coord_off[2];
-        const int32_t gb = sc.gbits, g = sc.gpus, gmask = (1 << sc.gbits) - 1;
-        uint32_t mine[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) mine[w] = 0;
-        for (int ch = 0; ch < kMatmulChunks; ++ch) {
-            const int64_t tile = (local * kMatmulChunks + ch) * 256 + threadIdx.x;
-            if (tile - threadIdx.x >= ntile) break;  // uniform: chunk past the end
+        // the matrix's fixed dims (a, b: tile = ca * R_b + cb) and reduction dim r:
+        // A = (0, 2; 1), B = (2, 1; 0), C = (0, 1; 2), picked by selects (static indices)
+        const bool mA = m == 0, mB = m == 1;
+        const int32_t Ra = mB ? R[2] : R[0], Rb = mA ? R[2] : R[1], Rr = mA ? R[1] : (mB ? R[0] : R[2]);
+        const int32_t* Ea = mB ? E[2] : E[0];
+        const int32_t* Sa = mB ? S[2] : S[0];
+        const int32_t* Eb = mA ? E[2] : E[1];
+        const int32_t* Sb = mA ? S[2] : S[1];
+        const int32_t* Er = mA ? E[1] : (mB ? E[0] : E[2]);
+        unsigned long long* dst = per_proc + proc_off[lo] * 3;
+        if (Ra < 0 || Rb < 0 || Rr < 0) {  // over capacity (never: the capacity bounds the count): poison
+            if (tid == 0) atomicAdd(&dst[m], 1ull << 62);
+            continue;
+        }
+        // t < Ra * Rb <= 2^31 (tile count of a matrix, checked by the host)
+        const uint32_t ntile = (uint32_t)Ra * (uint32_t)Rb, t1 = (uint32_t)(local + 1) * kMatmulTiles;
+        for (uint32_t t = (uint32_t)local * kMatmulTiles + tid; t < t1 && t < ntile; t += 256) {
+            const int32_t ca = (int32_t)(t / (uint32_t)Rb), cbx = (int32_t)(t - (uint32_t)ca * (uint32_t)Rb);
+            const int32_t fixed = (Ea[ca] & kValMask) + (Eb[cbx] & kValMask);
+            const unsigned long long w =
+                (unsigned long long)(Sa[ca + 1] - Sa[ca]) * (unsigned long long)(Sb[cbx + 1] - Sb[cbx]);
             uint64_t bm[W];
 #pragma unroll
-            for (int w = 0; w < W; ++w) bm[w] = 0;
-            if (tile < ntile) {
-                int32_t fixed;
-                const int32_t* red;
-                int64_t nred;
-                if (m == 0) {  // A[i,k]: tile = i*Tk + k, reduce over j
-                    const int64_t i = tile / Tk, k = tile % Tk;
-                    fixed = (C0[i] & kValMask) + (C2[k] & kValMask);
-                    red = C1;
-                    nred = Tj;
-                } else if (m == 1) {  // B[k,j]: tile = k*Tj + j, reduce over i
-                    const int64_t k = tile / Tj, j = tile % Tj;
-                    fixed = (C2[k] & kValMask) + (C1[j] & kValMask);
-                    red = C0;
-                    nred = Ti;
-                } else {  // C[i,j]: tile = i*Tj + j, reduce over k
-                    const int64_t i = tile / Tj, j = tile % Tj;
-                    fixed = (C0[i] & kValMask) + (C1[j] & kValMask);
-                    red = C2;
-                    nred = Tk;
-                }
-                for (int64_t t = 0; t < nred; ++t) {
-                    const int32_t key = T[fixed + (red[t] & kValMask)];
-                    const int32_t p = (key >> gb) * g + (key & gmask);
-                    const uint64_t bit = 1ull << (p & 63);
-                    if (W == 1) {
-                        bm[0] |= bit;
-                    } else {
+            for (int u = 0; u < W; ++u) bm[u] = 0;
+            for (int32_t r = 0; r < Rr; ++r) {
+                const int32_t key = T[fixed + (Er[r] & kValMask)];
+                const int32_t p = (key >> gb) * g + (key & ((1 << gb) - 1));
+                const uint64_t bit = 1ull << (p & 63);
+                if (W == 1) {
+                    bm[0] |= bit;
+                } else {
 #pragma unroll
-                        for (int w = 0; w < W; ++w) bm[w] |= ((p >> 6) == w) ? bit : 0ull;
-                    }
+                    for (int u = 0; u < W; ++u) bm[u] |= ((p >> 6) == u) ? bit : 0ull;
                 }
             }
-            // lane b of the wave counts processor 64*w + b
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                for (int b = 0; b < 64; ++b) {
-                    const uint64_t mask = __ballot((bm[w] >> b) & 1ull);
-                    if (lane == b) mine[w] += (uint32_t)__popcll(mask);
+            for (int u = 0; u < W; ++u) {
+                uint64_t b = bm[u];
+                while (b) {
+                    const int q = __builtin_ctzll(b);
+                    b &= b - 1;
+                    atomicAdd(&s_cnt[u * 64 + q], w);
                 }
             }
         }
-        const int64_t P = (int64_t)sc.nodes * sc.gpus;
-        unsigned long long* dst = per_proc + proc_off[lo] * 3;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            const int64_t p = (int64_t)w * 64 + lane;
-            if (mine[w] && p < P) atomicAdd(&dst[p * 3 + m], (unsigned long long)mine[w]);
+        __syncthreads();
+        for (int i = tid; i < 64 * W; i += 256) {
+            const unsigned long long v = s_cnt[i];
+            if (v) {
+                if (i < P) atomicAdd(&dst[i * 3 + m], v);
+                s_cnt[i] = 0;
+            }
         }
+        __syncthreads();
     }
 }
 
@@ -1080,7 +1099,7 @@ hipError_t launch_matmul(const DevCand* cands, int64_t n, const int32_t* arena, 
 #define TM_MM(w)                                                                                        \
     if (W <= w) {                                                                                       \
         hipLaunchKernelGGL(k_matmul<w>, dim3((unsigned)grid), dim3(256), lds, s, cands, n, arena, proc_off, \
-                           per_proc, block_first, total_blocks);                                        \
+                           per_proc, block_first, total_blocks, words_max);                             \
         return hipGetLastError();                                                                       \
     }
     TM_MM(1) TM_MM(2) TM_MM(4) TM_MM(8) TM_MM(16)

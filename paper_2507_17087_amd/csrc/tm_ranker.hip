@@ -52,27 +52,34 @@ __device__ __forceinline__ float lg2(double x) { return (float)log2(x); }
 // One workgroup per candidate; owners of all final coordinates staged in LDS, sized
 // for the batch's largest volume (volumes above kCrossMax give zeros).
 constexpr int kCrossMax = 16384;
+constexpr int kStatsStage = 2048;     // launch dims up to this extent have their contributions staged in LDS
+constexpr int kStatsSmallVol = 2048;  // owner-table words of the first (small-candidate) launch
 
-__device__ __forceinline__ int64_t block_first(int64_t a, int64_t S, int64_t l) { return (a * l + S - 1) / S; }
+__device__ __forceinline__ int64_t block_first(int64_t a, int64_t S, int64_t l) { return div_nn(a * l + S - 1, S); }
 
 __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__ cands, int64_t n,
                                                      const int32_t* __restrict__ halo, float* __restrict__ cross,
-                                                     double* __restrict__ est) {
+                                                     double* __restrict__ est, int32_t vmin, int32_t vmax) {
     __shared__ DevCand sc;
     extern __shared__ int32_t key[];  // the batch's largest final-space volume (at most kCrossMax)
     __shared__ int32_t red[kMaxMrankCross][4][3];  // per final dim and wave: pairs, node and owner changes
     __shared__ double dred[4][2];
+    __shared__ int32_t s_ct[kStatsStage];  // a launch dim's coordinate contributions
     for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
+        // this launch takes the candidates of volume in (vmin, vmax]; the one whose
+        // vmax is kCrossMax also writes the zeros of those above it
+        const int32_t v0 = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)cands[ci].vol);
+        if (v0 > kCrossMax && vmax == kCrossMax) {
+            if (threadIdx.x < 2 * kMaxMrankCross) cross[ci * 2 * kMaxMrankCross + threadIdx.x] = 0.f;
+            if (threadIdx.x < 2) est[ci * 2 + threadIdx.x] = 0.0;
+            continue;
+        }
+        if (v0 <= vmin || v0 > vmax) continue;
         __syncthreads();
         stage_cand(&sc, &cands[ci]);
         __syncthreads();
         const int32_t vol = sc.vol;
         const int K = sc.lrank, gb = sc.gbits;
-        if (vol > kCrossMax) {
-            if (threadIdx.x < 2 * kMaxMrankCross) cross[ci * 2 * kMaxMrankCross + threadIdx.x] = 0.f;
-            if (threadIdx.x < 2) est[ci * 2 + threadIdx.x] = 0.0;
-            continue;
-        }
         for (int32_t v = threadIdx.x; v < vol; v += blockDim.x) key[v] = owner_key(sc, v);
         __syncthreads();
         // crossing fractions per final dim: counts summed within each wave by
@@ -136,9 +143,10 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
                 // boundaries along d: the first cell b of every non-empty block a >= 1,
                 // against the block holding cell b - 1
                 const int32_t others = vol / (int32_t)S;
-                for (int64_t t = threadIdx.x; t < (S - 1) * others; t += blockDim.x) {
-                    const int32_t aR = (int32_t)(1 + t / others);
-                    int32_t u = (int32_t)(t % others);
+                const int32_t nt = ((int32_t)S - 1) * others;  // < vol <= kCrossMax
+                for (int32_t t = threadIdx.x; t < nt; t += blockDim.x) {
+                    const int32_t aR = 1 + t / others;
+                    int32_t u = t % others;
                     const int64_t b = block_first(aR, S, l);
                     if (b >= l || b >= block_first(aR + 1, S, l)) continue;  // empty block
                     const int32_t aL = (int32_t)((b - 1) * S / l);
@@ -167,21 +175,27 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
                 const int h = halo[d];
                 double part = 0;
                 if (h > 0 && l <= 65536) {
+                    const bool staged = l <= kStatsStage;  // uniform
+                    if (staged) {
+                        for (int32_t x = threadIdx.x; x < (int32_t)l; x += blockDim.x) s_ct[x] = coord_value(sc, d, x);
+                        __syncthreads();
+                    }
                     for (int64_t x = threadIdx.x; x < l; x += blockDim.x) {
-                        const int32_t val = coord_value(sc, d, x);
+                        const int32_t val = staged ? s_ct[x] : coord_value(sc, d, x);
                         int32_t found[2 * kMaxHalo];
                         int cnt = 0;
                         for (int sft = 1; sft <= h && sft <= kMaxHalo; ++sft)
                             for (int dir = 0; dir < 2; ++dir) {
                                 const int64_t xx = dir ? x + sft : x - sft;
                                 if (xx < 0 || xx >= l) continue;
-                                const int32_t dv = coord_value(sc, d, xx) - val;
+                                const int32_t dv = (staged ? s_ct[xx] : coord_value(sc, d, xx)) - val;
                                 bool seen = dv == 0;
                                 for (int i = 0; i < cnt; ++i) seen = seen || found[i] == dv;
                                 if (!seen) found[cnt++] = dv;
                             }
                         part += cnt;
                     }
+                    if (staged) __syncthreads();  // the next dim rewrites s_ct
                 }
                 float cn = 0.f, cp = 0.f;
                 for (int j = 0; j < sc.frank && j < kMaxMrankCross; ++j)
@@ -221,57 +235,92 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const DevCand& c = cands[i];
+    // every index into f and the small arrays below is static once the loops are
+    // unrolled (bounded by the ABI's maxima, the candidate's counts as predicates), so
+    // all of them live in registers
     float f[kFeat];
 #pragma unroll
     for (int t = 0; t < kFeat; ++t) f[t] = 0.f;
-    const int k = c.lrank;
-    f[k - 1] = 1.f;
-    double blocks[4] = {1, 1, 1, 1};
-    for (int j = 0; j < c.frank; ++j) blocks[c.proj_src[j]] *= c.fshape[j];
-    double vol_f = 0;
-    int32_t F[4] = {1, 1, 1, 1};
-    int nf = 0;
-    for (int t = 0; t < c.nops; ++t)
+    const int k = c.lrank, fr = c.frank, nops = c.nops;
+#pragma unroll
+    for (int d = 0; d < TM_MAX_LRANK; ++d) f[d] = d == k - 1 ? 1.f : 0.f;
+    // blocks per launch dim: the product of the final extents it projects onto
+    double blocks[TM_MAX_LRANK] = {1, 1, 1, 1};
+#pragma unroll
+    for (int j = 0; j < TM_MAX_MRANK; ++j) {
+        if (j < fr) {
+            const int src = c.proj_src[j];
+            const double sh = (double)c.fshape[j];
+#pragma unroll
+            for (int d = 0; d < TM_MAX_LRANK; ++d) blocks[d] *= src == d ? sh : 1.0;
+        }
+    }
+    // the factors of the first decompose
+    int tdec = -1;
+    for (int t = 0; t < nops; ++t)
         if (c.op_kind[t] == TM_DECOMPOSE) {
-            nf = c.op_nf[t];
-            for (int m = 0; m < nf; ++m) F[m] = c.op_f[t][m];
+            tdec = t;
             break;
         }
-    for (int d = 0; d < k; ++d) {
-        const double l = (double)c.extent[d];
-        f[4 + d] = lg2(l) / 10.f;
-        f[15 + d] = lg2(blocks[d]) / 9.f;
-        f[19 + d] = (lg2(l) - lg2(blocks[d])) / 10.f;
-        if (d < nf) vol_f += 2.0 * halo[d] * (F[d] - 1.0) / l;
-        f[54 + d] = halo[d] / 4.f;
+    const int nf = tdec >= 0 ? c.op_nf[tdec] : 0;
+    int32_t F[TM_MAX_LRANK];
+#pragma unroll
+    for (int m = 0; m < TM_MAX_LRANK; ++m) F[m] = m < nf ? c.op_f[tdec >= 0 ? tdec : 0][m] : 1;
+    double vol_f = 0;
+#pragma unroll
+    for (int d = 0; d < TM_MAX_LRANK; ++d) {
+        if (d < k) {
+            const double l = (double)c.extent[d];
+            f[4 + d] = lg2(l) / 10.f;
+            f[15 + d] = lg2(blocks[d]) / 9.f;
+            f[19 + d] = (lg2(l) - lg2(blocks[d])) / 10.f;
+            if (d < nf) vol_f += 2.0 * halo[d] * (F[d] - 1.0) / l;
+            f[54 + d] = halo[d] / 4.f;
+        }
     }
     f[8] = lg2((double)c.nodes) / 6.f;
     f[9] = lg2((double)c.gpus) / 3.f;
     f[10] = lg2((double)c.nodes * c.gpus) / 9.f;
-    for (int m = 0; m < nf && m < 4; ++m) f[11 + m] = lg2((double)F[m]) / 9.f;
+#pragma unroll
+    for (int m = 0; m < TM_MAX_LRANK; ++m)
+        if (m < nf) f[11 + m] = lg2((double)F[m]) / 9.f;
     f[24] = lg2(1.0 + vol_f) / 4.f;
-    for (int t = 0; t < c.nops; ++t) {
-        const int kd = c.op_kind[t];
-        if (kd >= 1 && kd <= 5) f[25 + kd - 1] += 0.25f;
-        if (t < 6) {
-            f[30 + t] = kd / 5.f;
-            if (t < 3) f[39 + t] = c.op_a[t] / 8.f;
-            f[42 + t] = kd == TM_DECOMPOSE ? 0.f : lg2(1.0 + (double)c.op_b[t]) / 9.f;
+#pragma unroll
+    for (int t = 0; t < TM_MAX_OPS; ++t) {
+        if (t < nops) {
+            const int kd = c.op_kind[t];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) f[25 + q] += kd == q + 1 ? 0.25f : 0.f;
+            if (t < 6) {
+                f[30 + t] = kd / 5.f;
+                if (t < 3) f[39 + t] = c.op_a[t] / 8.f;
+                f[42 + t] = kd == TM_DECOMPOSE ? 0.f : lg2(1.0 + (double)c.op_b[t]) / 9.f;
+            }
         }
     }
-    f[48] = (c.nops > 0 && c.op_kind[0] == TM_SWAP) ? 1.f : 0.f;
-    for (int j = 0; j < c.frank && j < 4; ++j) f[49 + j] = c.proj_mode[j] ? 1.f : 0.f;
-    f[53] = c.frank / 8.f;
+    f[48] = (nops > 0 && c.op_kind[0] == TM_SWAP) ? 1.f : 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (j < fr) f[49 + j] = c.proj_mode[j] ? 1.f : 0.f;
+    f[53] = fr / 8.f;
     f[58] = c.gbits / 3.f;
     f[59] = 1.f;
     // node / processor crossings per launch dim (largest over the final dims it
     // projects onto) and block-model estimates of the ghost cells, total and
     // inter-node, in the log space of the targets
-    float cn[4] = {0.f, 0.f, 0.f, 0.f}, cp[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int j = 0; j < c.frank && j < kMaxMrankCross; ++j) {
-        const int d = c.proj_src[j];
-        cn[d] = fmaxf(cn[d], cross[i * 2 * kMaxMrankCross + j]);
-        cp[d] = fmaxf(cp[d], cross[i * 2 * kMaxMrankCross + kMaxMrankCross + j]);
+    float cn[TM_MAX_LRANK] = {0.f, 0.f, 0.f, 0.f}, cp[TM_MAX_LRANK] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < kMaxMrankCross; ++j) {
+        if (j < fr) {
+            const int src = c.proj_src[j];
+            const float xn = cross[i * 2 * kMaxMrankCross + j];
+            const float xp = cross[i * 2 * kMaxMrankCross + kMaxMrankCross + j];
+#pragma unroll
+            for (int d = 0; d < TM_MAX_LRANK; ++d) {
+                cn[d] = src == d ? fmaxf(cn[d], xn) : cn[d];
+                cp[d] = src == d ? fmaxf(cp[d], xp) : cp[d];
+            }
+        }
     }
     f[kBaseFeat[0]] = lg2(1.0 + est[i * 2]) / kBaseScale;
     f[kBaseFeat[1]] = lg2(1.0 + est[i * 2 + 1]) / kBaseScale;
@@ -702,25 +751,40 @@ __global__ void k_combine(const float* __restrict__ Y, const double* __restrict_
 
 // ------------------------------------------------------------------ survivors
 
-// Builds the sub-batch of selected candidates on the device: copies their compiled
-// descriptors, lays out their tables and work items (prefix sums in one workgroup)
-// and writes the sub-batch header.  sel[s] < 0 entries are skipped; map[j] gives
-// the original index of sub-batch entry j and seg_out the sub-batch segments.
+// Builds the sub-batch of selected candidates on the device, in two launches.
+// k_gather (one workgroup) lays out their tables and work items by prefix sums over
+// the selection (wave scans, then the waves' totals), writes the sub-batch entry j of
+// every selected candidate -- map[j] = its original index and the three fields that
+// change (arena_off, item_first, citems) -- the sub-batch segments and header;
+// k_gather_copy then copies the rest of the descriptors, word by word across the
+// grid.  sel[s] < 0 entries are skipped; seg_out gives the sub-batch segments.
+constexpr int kDescWords = (int)(sizeof(DevCand) / 4);
+constexpr int kArenaWord = (int)(offsetof(DevCand, arena_off) / 4);
+constexpr int kItemWord = (int)(offsetof(DevCand, item_first) / 4);
+constexpr int kCitemsWord = (int)(offsetof(DevCand, citems) / 4);
+static_assert(sizeof(DevCand) % 4 == 0, "descriptor copied as words");
+
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(v, o, 64);
+        v += lane >= o ? u : 0;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(1024) void k_gather(const DevCand* __restrict__ cands, const int64_t* __restrict__ sel,
                                                  int64_t nsel, int k, int64_t cells_per_item,
                                                  DevCand* __restrict__ sub, int64_t* __restrict__ map,
                                                  int64_t* __restrict__ seg_out, DevHeader* __restrict__ hdr,
                                                  const DevHeader* __restrict__ proto) {
-    __shared__ int64_t s_words[1024], s_items[1024], s_cnt[1024];
-    __shared__ int64_t carry_w, carry_i, carry_c;
-    if (threadIdx.x == 0) {
-        carry_w = 0;
-        carry_i = 0;
-        carry_c = 0;
-    }
+    __shared__ int64_t s_tot[16][3];  // per wave: words, items, present
+    __shared__ int64_t carry[3];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+    if (tid < 3) carry[tid] = 0;
     __syncthreads();
     for (int64_t base = 0; base < nsel; base += blockDim.x) {
-        const int64_t s = base + threadIdx.x;
+        const int64_t s = base + tid;
         int64_t words = 0, items = 0, present = 0;
         int64_t ci = -1;
         if (s < nsel) {
@@ -732,49 +796,59 @@ __global__ __launch_bounds__(1024) void k_gather(const DevCand* __restrict__ can
                 present = 1;
             }
         }
-        s_words[threadIdx.x] = words;
-        s_items[threadIdx.x] = items;
-        s_cnt[threadIdx.x] = present;
+        const int64_t iw = wave_incl_scan(words, lane), ii = wave_incl_scan(items, lane),
+                      ic = wave_incl_scan(present, lane);
+        if (lane == 63) {
+            s_tot[wid][0] = iw;
+            s_tot[wid][1] = ii;
+            s_tot[wid][2] = ic;
+        }
         __syncthreads();
-        for (int o = 1; o < (int)blockDim.x; o <<= 1) {  // inclusive scans
-            int64_t aw = 0, ai = 0, ac = 0;
-            if ((int)threadIdx.x >= o) {
-                aw = s_words[threadIdx.x - o];
-                ai = s_items[threadIdx.x - o];
-                ac = s_cnt[threadIdx.x - o];
-            }
-            __syncthreads();
-            s_words[threadIdx.x] += aw;
-            s_items[threadIdx.x] += ai;
-            s_cnt[threadIdx.x] += ac;
-            __syncthreads();
+        int64_t pw = carry[0], pi = carry[1], pc = carry[2];
+        for (int w = 0; w < wid; ++w) {
+            pw += s_tot[w][0];
+            pi += s_tot[w][1];
+            pc += s_tot[w][2];
         }
         if (present) {
-            const int64_t j = carry_c + s_cnt[threadIdx.x] - 1;
-            DevCand c = cands[ci];
-            c.citems = (int32_t)items;
-            c.arena_off = carry_w + s_words[threadIdx.x] - words;
-            c.item_first = carry_i + s_items[threadIdx.x] - items;
-            sub[j] = c;
+            const int64_t j = pc + ic - 1;
             map[j] = ci;
+            sub[j].arena_off = pw + iw - words;
+            sub[j].item_first = pi + ii - items;
+            sub[j].citems = (int32_t)items;
         }
         // segment starts: first slot of each segment of k
-        if (s < nsel && (s % k) == 0) seg_out[s / k] = carry_c + s_cnt[threadIdx.x] - present;
-        __syncthreads();
-        if (threadIdx.x == blockDim.x - 1) {
-            carry_w += s_words[threadIdx.x];
-            carry_i += s_items[threadIdx.x];
-            carry_c += s_cnt[threadIdx.x];
+        if (s < nsel && (s % k) == 0) seg_out[s / k] = pc + ic - present;
+        __syncthreads();  // every thread has read carry and s_tot
+        if (tid < 3) {
+            int64_t t = 0;
+            for (int w = 0; w < nw; ++w) t += s_tot[w][tid];
+            carry[tid] += t;
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        seg_out[(nsel + k - 1) / k] = carry_c;
+    if (tid == 0) {
+        seg_out[(nsel + k - 1) / k] = carry[2];
         DevHeader h = *proto;
-        h.n = carry_c;
-        h.total_items = carry_i;
-        h.item_tab = carry_w;  // the survivors' item table follows their tables
+        h.n = carry[2];
+        h.total_items = carry[1];
+        h.item_tab = carry[0];  // the survivors' item table follows their tables
         *hdr = h;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather_copy(const DevCand* __restrict__ cands,
+                                                     const int64_t* __restrict__ map,
+                                                     const DevHeader* __restrict__ hdr, DevCand* __restrict__ sub) {
+    const int64_t total = hdr->n * kDescWords;
+    const int32_t* src = reinterpret_cast<const int32_t*>(cands);
+    int32_t* dst = reinterpret_cast<int32_t*>(sub);
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = t / kDescWords;
+        const int w = (int)(t - j * kDescWords);
+        if (w == kArenaWord || w == kArenaWord + 1 || w == kItemWord || w == kItemWord + 1 || w == kCitemsWord)
+            continue;  // written by k_gather
+        dst[t] = src[map[j] * kDescWords + w];
     }
 }
 
@@ -812,8 +886,19 @@ hipError_t launch_features(const DevCand* cands, int64_t n, int32_t max_vol, con
     if (n <= 0) return hipSuccess;
     const int64_t g = n < 65536 ? n : 65536;
     double* est = chain_estimates(cross, n);
-    const size_t key_bytes = (size_t)std::max(1, std::min(max_vol, kCrossMax)) * 4;
-    hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(256), key_bytes, s, cands, n, d_halo, cross, est);
+    // the owner table of a candidate lives in LDS: most candidates are small, so a
+    // first launch with a small table (more workgroups per CU) takes the volumes up to
+    // kStatsSmallVol, and a second one, sized for the batch's largest, the rest
+    const int32_t vtop = std::max(1, std::min(max_vol, kCrossMax));
+    if (vtop <= kStatsSmallVol) {
+        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(256), (size_t)vtop * 4, s, cands, n, d_halo, cross,
+                           est, 0, kCrossMax);
+    } else {
+        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(256), (size_t)kStatsSmallVol * 4, s, cands, n,
+                           d_halo, cross, est, 0, kStatsSmallVol);
+        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(256), (size_t)vtop * 4, s, cands, n, d_halo, cross,
+                           est, kStatsSmallVol, kCrossMax);
+    }
     hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cands, n, d_halo, cross, est,
                        X, f32);
     return hipGetLastError();
@@ -896,6 +981,11 @@ hipError_t launch_gather(const DevCand* cands, const int64_t* sel, int64_t nsel,
                          hipStream_t s) {
     hipLaunchKernelGGL(k_gather, dim3(1), dim3(1024), 0, s, cands, sel, nsel, k, cells_per_item, sub, map, seg_out,
                        hdr, proto);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nsel <= 0) return e;
+    const int64_t blocks = (nsel * kDescWords + 255) / 256;
+    hipLaunchKernelGGL(k_gather_copy, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, cands, map,
+                       hdr, sub);
     return hipGetLastError();
 }
 

@@ -335,6 +335,24 @@ def test_matmul_many_processors(tm):
         off += P
 
 
+def test_matmul_random_chains(tm):
+    say("matmul, random chains with cyclic projections")
+    cs = np.concatenate([W.random_chain_instance((20, 24, 17), 6, 4, 48, seed=11, max_ops=4, cyclic_pct=30),
+                         W.random_chain_instance((33, 9, 40), 8, 8, 24, seed=12, max_ops=5, cyclic_pct=50),
+                         W.random_chain_instance((300, 6, 5), 3, 8, 8, seed=13, max_ops=3, cyclic_pct=100),
+                         # 9000 classes along dim 0: the class blocks do not fit LDS (read in place)
+                         W.batch([W.candidate((9000, 2, 3), 2, 4, [merge(0, 1), decompose(0, (8, 1, 1))],
+                                              proj=[(0, W.CYCLIC), (1, W.BLOCK), (2, W.BLOCK)])])])
+    pp, out = matmul_gpu(tm, cs, 5)
+    off = 0
+    for i, c in enumerate(cs):
+        P = int(c["nodes"]) * int(c["gpus"])
+        per, tot = oracle.matmul_cost(c, 5)
+        assert (pp[off:off + P] == per).all(), i
+        assert tuple(out[i]) == tot, i
+        off += P
+
+
 # ---------------------------------------------------------------- plans and graphs
 
 def test_plan_graph_replay_deterministic(tm):
