@@ -26,59 +26,81 @@ __device__ __forceinline__ int64_t mod_nn(int64_t a, int64_t b) {
     return a % b;
 }
 
-// Owner key of final-space coordinate v: decode v (C order), then undo the ops.
+// A value that is the same in every lane of the wave, moved to a scalar register.
+__device__ __forceinline__ int32_t wave_uniform(int32_t x) {
+    return (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)x);
+}
+__device__ __forceinline__ int64_t wave_uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Owner key of final-space coordinate v: undo the ops on the linear index (C order)
+// of the processor space, last op first, down to Machine(GPU) = (nodes, gpus).  An
+// op touches a contiguous range of dims: with lo the product of the dims after the
+// range, the index is (h * W + x) * lo + l0, where x indexes the range (W its
+// volume); the op maps x between its output and input digits, and h, l0 pass
+// through.  Every index stays below the processor-space volume (<= 2^24), so the
+// arithmetic is 32-bit; the descriptor c must be the same in every lane of the
+// wave (its fields are then scalars).
 __device__ inline int32_t owner_key(const DevCand& c, int32_t v) {
-    int32_t a[TM_MAX_MRANK], b[TM_MAX_MRANK];
-    for (int j = c.frank - 1; j >= 0; --j) {
-        const int32_t s = c.fshape[j];
-        a[j] = v % s;
-        v /= s;
-    }
-    for (int t = c.nops - 1; t >= 0; --t) {
-        const int r = c.rank[t];
-        const int32_t* s = c.shape[t];
-        const int pa = c.op_a[t], pb = c.op_b[t];
-        switch (c.op_kind[t]) {
-            case TM_SPLIT:
-                for (int u = 0; u < pa; ++u) b[u] = a[u];
-                b[pa] = a[pa] + a[pa + 1] * pb;
-                for (int u = pa + 1; u < r; ++u) b[u] = a[u + 1];
-                break;
-            case TM_MERGE:
-                for (int u = 0; u < r; ++u) {
-                    if (u < pa || (u > pa && u < pb)) b[u] = a[u];
-                    else if (u == pa) b[u] = a[pa] % s[pa];
-                    else if (u == pb) b[u] = a[pa] / s[pa];
-                    else b[u] = a[u - 1];
+    uint32_t L = (uint32_t)v;
+    const int nops = wave_uniform(c.nops);
+    for (int t = nops - 1; t >= 0; --t) {
+        const int kind = wave_uniform(c.op_kind[t]);
+        const uint32_t lo = (uint32_t)wave_uniform(c.inv_lo[t]), wi = (uint32_t)wave_uniform(c.inv_win[t]),
+                       wo = (uint32_t)wave_uniform(c.inv_wout[t]);
+        const uint32_t q = L / lo, l0 = L - q * lo;
+        const uint32_t h = q / wo;
+        uint32_t x = q - h * wo, m;
+        if (kind == TM_SPLIT || kind == TM_BALANCE_SPLIT) {
+            // output digits (a, a1) of extents (b, c), x = a * c + a1; input a + a1 * b
+            const uint32_t pb = (uint32_t)wave_uniform(c.op_b[t]), cc = (uint32_t)wave_uniform(c.inv_c[t]);
+            const uint32_t a = x / cc, a1 = x - a * cc;
+            const uint32_t vv = a + a1 * pb;
+            // balance_split folds vv in [0, b * c) onto the input extent (wi <= b * c)
+            m = kind == TM_SPLIT ? vv : (uint32_t)div_nn((int64_t)vv * wi, (int64_t)wo);
+        } else if (kind == TM_MERGE) {
+            // output (a of extent s_pa * s_pb, mid); input (a mod s_pa, mid, a / s_pa)
+            const int pa = wave_uniform(c.op_a[t]), pb = wave_uniform(c.op_b[t]);
+            const uint32_t mid = (uint32_t)wave_uniform(c.inv_mid[t]);
+            const uint32_t spa = (uint32_t)wave_uniform(c.shape[t][pa]), spb = (uint32_t)wave_uniform(c.shape[t][pb]);
+            const uint32_t a = x / mid, xm = x - a * mid;
+            const uint32_t ahi = a / spa, alo = a - ahi * spa;
+            m = (alo * mid + xm) * spb + ahi;
+        } else if (kind == TM_SWAP) {
+            // output (y_lo of extent s_hi, mid, y_hi of extent s_lo); input (y_hi, mid, y_lo)
+            const int pa = wave_uniform(c.op_a[t]), pb = wave_uniform(c.op_b[t]);
+            const int plo = pa < pb ? pa : pb, phi = pa < pb ? pb : pa;
+            const uint32_t mid = (uint32_t)wave_uniform(c.inv_mid[t]);
+            const uint32_t slo = (uint32_t)wave_uniform(c.shape[t][plo]), shi = (uint32_t)wave_uniform(c.shape[t][phi]);
+            const uint32_t ms = mid * slo;
+            const uint32_t ylo = x / ms, rest = x - ylo * ms;
+            const uint32_t xm = rest / slo, yhi = rest - xm * slo;
+            m = (yhi * mid + xm) * shi + ylo;
+        } else {  // TM_DECOMPOSE: output digits of extents f[0..k) in C order; input little-endian
+            const int k = wave_uniform(c.op_nf[t]);
+            uint32_t dg[TM_MAX_LRANK] = {0, 0, 0, 0}, f[TM_MAX_LRANK] = {1, 1, 1, 1};
+#pragma unroll
+            for (int j = 0; j < TM_MAX_LRANK; ++j) f[j] = j < k ? (uint32_t)wave_uniform(c.op_f[t][j]) : 1u;
+#pragma unroll
+            for (int j = TM_MAX_LRANK - 1; j >= 0; --j) {
+                if (j < k) {
+                    const uint32_t qq = x / f[j];
+                    dg[j] = x - qq * f[j];
+                    x = qq;
                 }
-                break;
-            case TM_SWAP:
-                for (int u = 0; u < r; ++u) b[u] = a[u];
-                b[pa] = a[pb];
-                b[pb] = a[pa];
-                break;
-            case TM_BALANCE_SPLIT: {
-                const int64_t si = s[pa];
-                const int64_t cc = div_nn(si + pb - 1, pb);
-                const int64_t vv = (int64_t)a[pa] + (int64_t)a[pa + 1] * pb;
-                for (int u = 0; u < pa; ++u) b[u] = a[u];
-                b[pa] = (int32_t)div_nn(vv * si, (int64_t)pb * cc);
-                for (int u = pa + 1; u < r; ++u) b[u] = a[u + 1];
-                break;
             }
-            default: {  // TM_DECOMPOSE
-                const int k = c.op_nf[t];
-                int32_t acc = 0;
-                for (int m = k - 1; m >= 0; --m) acc = acc * c.op_f[t][m] + a[pa + m];
-                for (int u = 0; u < pa; ++u) b[u] = a[u];
-                b[pa] = acc;
-                for (int u = pa + 1; u < r; ++u) b[u] = a[u + k - 1];
-                break;
-            }
+            m = 0;
+#pragma unroll
+            for (int j = TM_MAX_LRANK - 1; j >= 0; --j) m = j < k ? m * f[j] + dg[j] : m;
         }
-        for (int u = 0; u < r; ++u) a[u] = b[u];
+        L = (h * wi + m) * lo + l0;
     }
-    return (a[0] << c.gbits) | a[1];
+    const uint32_t g = (uint32_t)wave_uniform(c.gpus);
+    const uint32_t node = L / g;
+    return (int32_t)((node << wave_uniform(c.gbits)) | (L - node * g));
 }
 
 // Contribution of coordinate x of launch dim d to the linear final index.

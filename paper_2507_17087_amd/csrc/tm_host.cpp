@@ -186,6 +186,27 @@ int fill_devcand(const tm_candidate* c, const Shapes& sh, DevCand* d) {
         d->op_b[t] = c->ops[t].b;
         d->op_nf[t] = c->ops[t].nf;
         for (int m = 0; m < TM_MAX_LRANK; ++m) d->op_f[t][m] = c->ops[t].f[m];
+        // the op's range [lo, hi] in its input shape and the products around it
+        const int64_t* s = sh.size[t];
+        const int r = sh.rank[t], pa = c->ops[t].a, pb = c->ops[t].b;
+        const int kind = c->ops[t].kind;
+        const bool pair = kind == TM_MERGE || kind == TM_SWAP;
+        const int lo = pair ? std::min(pa, pb) : pa, hi = pair ? std::max(pa, pb) : pa;
+        int64_t after = 1, win = 1, mid = 1;
+        for (int u = hi + 1; u < r; ++u) after *= s[u];
+        for (int u = lo; u <= hi; ++u) win *= s[u];
+        for (int u = lo + 1; u < hi; ++u) mid *= s[u];
+        int64_t sc = 1, wout = win;
+        if (kind == TM_SPLIT) sc = s[pa] / pb;
+        if (kind == TM_BALANCE_SPLIT) {
+            sc = (s[pa] + pb - 1) / pb;
+            wout = (int64_t)pb * sc;
+        }
+        d->inv_lo[t] = (int32_t)after;
+        d->inv_win[t] = (int32_t)win;
+        d->inv_wout[t] = (int32_t)wout;
+        d->inv_mid[t] = (int32_t)mid;
+        d->inv_c[t] = (int32_t)sc;
     }
     return words > INT32_MAX ? TM_EOVERFLOW : TM_OK;
 }

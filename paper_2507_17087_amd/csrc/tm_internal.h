@@ -34,6 +34,15 @@ struct DevCand {
     int32_t shape[TM_MAX_OPS][TM_MAX_MRANK];     // shape before op t
     int32_t op_kind[TM_MAX_OPS], op_a[TM_MAX_OPS], op_b[TM_MAX_OPS], op_nf[TM_MAX_OPS];
     int32_t op_f[TM_MAX_OPS][TM_MAX_LRANK];
+    // Inverse of op t on linear indices: the dims the op touches form a contiguous
+    // range of its input shape (swap and merge: from the lower to the higher
+    // position; the others: one dim), inside which the op maps the range's digits;
+    // the dims before and after the range pass through.  inv_lo: product of the
+    // input dims after the range; inv_win / inv_wout: volume of the range in the
+    // input / output shape; inv_mid: product of the dims strictly inside a swap or
+    // merge range; inv_c: the second output extent of a split or balance_split.
+    int32_t inv_lo[TM_MAX_OPS], inv_win[TM_MAX_OPS], inv_wout[TM_MAX_OPS], inv_mid[TM_MAX_OPS],
+        inv_c[TM_MAX_OPS];
 };
 
 // Batch header: one per plan, in device memory, read by every kernel of a replay.
@@ -137,6 +146,10 @@ hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* s
 hipError_t launch_map(const DevCand* cands, int64_t n, const int32_t* arena, const int64_t* d_index,
                       int64_t index, int32_t* out, int grid, int lds_words, hipStream_t s);
 hipError_t launch_chain_table(const DevCand* cand, const int32_t* arena, int32_t* out, hipStream_t s);
+// Batches of at least this many candidates run the per-candidate table and
+// statistics kernels with one-wave workgroups (more candidates in flight per CU).
+constexpr int64_t kSmallBlockBatch = 8192;
+
 // Matmul work blocks: kMatmulTiles class pairs of one matrix each.  A matrix over
 // launch dims (a, b) has cls_cap[a] * cls_cap[b] class pairs at most; A = (0, 2),
 // B = (2, 1), C = (0, 1).

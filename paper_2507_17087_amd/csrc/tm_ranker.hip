@@ -52,19 +52,76 @@ __device__ __forceinline__ float lg2(double x) { return (float)log2(x); }
 // One workgroup per candidate; owners of all final coordinates staged in LDS, sized
 // for the batch's largest volume (volumes above kCrossMax give zeros).
 constexpr int kCrossMax = 16384;
-constexpr int kStatsStage = 2048;     // launch dims up to this extent have their contributions staged in LDS
+constexpr int kStatsStage = 1024;     // launch dims up to this extent have their contributions staged in LDS
 constexpr int kStatsSmallVol = 2048;  // owner-table words of the first (small-candidate) launch
+constexpr int kStatsTableCap = 4096;  // block-table entries per table (simple candidates)
 
 __device__ __forceinline__ int64_t block_first(int64_t a, int64_t S, int64_t l) { return div_nn(a * l + S - 1, S); }
 
+// Block-model terms of final coordinate v (digits a) for a candidate whose launch
+// dims are each projected (block) onto one final dim: along every dim j where v
+// starts a non-empty block (a_j >= 1), the boundary b = that block's first cell is
+// seen by the min(h, b) + min(h, l - b) cells within the halo of it, times the area
+// of the face (the product of the other dims' block widths), counted where the
+// owners (or nodes) of v and of the cell before b differ.  TAB: block bounds from
+// the LDS tables, else worked out.
+template <bool TAB>
+__device__ __forceinline__ void boundary_terms(int32_t v, const int32_t (&a)[kMaxMrankCross], int fr,
+                                               const int32_t (&fs)[kMaxMrankCross],
+                                               const int32_t (&fst)[kMaxMrankCross],
+                                               const int32_t (&toff)[TM_MAX_LRANK], const int32_t (&hj)[TM_MAX_LRANK],
+                                               const int64_t (&lj)[TM_MAX_LRANK], const int32_t* bft,
+                                               const int32_t* aLt, const int32_t* key, int gb, double& tot,
+                                               double& inter) {
+    int64_t bf0[TM_MAX_LRANK];
+    double wd[TM_MAX_LRANK];
+#pragma unroll
+    for (int j = 0; j < TM_MAX_LRANK; ++j) {
+        int64_t b0 = 0, b1 = 1;
+        if (j < fr) {
+            b0 = TAB ? bft[toff[j] + a[j]] : block_first(a[j], fs[j], lj[j]);
+            b1 = TAB ? bft[toff[j] + a[j] + 1] : block_first(a[j] + 1, fs[j], lj[j]);
+        }
+        bf0[j] = b0;
+        wd[j] = (double)(b1 - b0);
+    }
+    const int32_t kv = key[v];
+#pragma unroll
+    for (int j = 0; j < TM_MAX_LRANK; ++j) {
+        if (j >= fr || a[j] == 0 || hj[j] == 0) continue;
+        const int64_t b = bf0[j], l = lj[j];
+        if (b >= l || wd[j] <= 0.0) continue;  // empty block
+        double face = 1;
+#pragma unroll
+        for (int jj = 0; jj < TM_MAX_LRANK; ++jj)
+            if (jj != j && jj < fr) face *= wd[jj];
+        const int64_t h = hj[j];
+        const double w = (double)((h < b ? h : b) + (h < l - b ? h : l - b));
+        const int32_t aL = TAB ? aLt[toff[j] + a[j]] : (int32_t)div_nn((b - 1) * fs[j], l);
+        const int32_t kl = key[v - (a[j] - aL) * fst[j]];
+        if (kl != kv) tot += w * face;
+        if ((kl >> gb) != (kv >> gb)) inter += w * face;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__ cands, int64_t n,
                                                      const int32_t* __restrict__ halo, float* __restrict__ cross,
-                                                     double* __restrict__ est, int32_t vmin, int32_t vmax) {
+                                                     double* __restrict__ est, int32_t vmin, int32_t vmax,
+                                                     int32_t vcap) {
     __shared__ DevCand sc;
-    extern __shared__ int32_t key[];  // the batch's largest final-space volume (at most kCrossMax)
-    __shared__ int32_t red[kMaxMrankCross][4][3];  // per final dim and wave: pairs, node and owner changes
+    // dynamic LDS: the owner keys (vcap words, the largest volume of this launch),
+    // then a region that holds either, for a simple candidate, its block tables
+    // (per final dim and block a = 0..S: the block's first cell; and the block
+    // holding the cell before it), tcap entries each -- the sum over dims of S + 1 is
+    // at most the volume plus twice the rank -- or, otherwise, a launch dim's
+    // coordinate contributions (kStatsStage entries)
+    extern __shared__ __attribute__((aligned(16))) int32_t key[];
+    const int32_t tcap = vcap + 16 < kStatsTableCap ? vcap + 16 : kStatsTableCap;
+    int32_t* bft = key + ((vcap + 3) & ~3);
+    int32_t* aLt = bft + tcap;
+    int32_t* s_ct = bft;
+    __shared__ int32_t red[kMaxMrankCross][4][2];  // per final dim and wave: node and owner changes
     __shared__ double dred[4][2];
-    __shared__ int32_t s_ct[kStatsStage];  // a launch dim's coordinate contributions
     for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
         // this launch takes the candidates of volume in (vmin, vmax]; the one whose
         // vmax is kCrossMax also writes the zeros of those above it
@@ -79,43 +136,127 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
         stage_cand(&sc, &cands[ci]);
         __syncthreads();
         const int32_t vol = sc.vol;
-        const int K = sc.lrank, gb = sc.gbits;
-        for (int32_t v = threadIdx.x; v < vol; v += blockDim.x) key[v] = owner_key(sc, v);
-        __syncthreads();
-        // crossing fractions per final dim: counts summed within each wave by
-        // shuffles, then over the four waves
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-        const int nj = sc.frank < kMaxMrankCross ? sc.frank : kMaxMrankCross;
-        for (int j = 0; j < nj; ++j) {
-            int pairs = 0, dn = 0, dp = 0;
-            const int32_t S = sc.fshape[j], st = sc.fstride[j];
-            for (int32_t v = threadIdx.x; v < vol; v += blockDim.x) {
-                if ((v / st) % S < S - 1) {
-                    ++pairs;
-                    dp += key[v] != key[v + st];
-                    dn += (key[v] >> gb) != (key[v + st] >> gb);
+        const int K = wave_uniform(sc.lrank), gb = wave_uniform(sc.gbits), fr = wave_uniform(sc.frank);
+        const int nj = fr < kMaxMrankCross ? fr : kMaxMrankCross;
+        const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+        // is every launch dim projected (block) onto exactly one final dim?
+        bool simple = fr == K;
+        uint32_t seen = 0;
+        for (int j = 0; j < fr; ++j) {
+            const int d = sc.proj_src[j];
+            simple = simple && sc.proj_mode[j] == TM_BLOCK && !((seen >> d) & 1u);
+            seen |= 1u << d;
+        }
+        // the final dims' extents and strides; with simple projections, each one's
+        // launch extent and halo and the offset of its block tables
+        int32_t fs[kMaxMrankCross], fst[kMaxMrankCross], toff[TM_MAX_LRANK], hj[TM_MAX_LRANK];
+        int64_t lj[TM_MAX_LRANK];
+#pragma unroll
+        for (int j = 0; j < kMaxMrankCross; ++j) {
+            fs[j] = j < fr ? wave_uniform(sc.fshape[j]) : 1;
+            fst[j] = j < fr ? wave_uniform(sc.fstride[j]) : 0;
+        }
+        int32_t off = 0;
+#pragma unroll
+        for (int j = 0; j < TM_MAX_LRANK; ++j) {
+            const int d = j < fr ? wave_uniform(sc.proj_src[j]) : 0;
+            toff[j] = off;
+            off += j < fr ? fs[j] + 1 : 0;
+            hj[j] = j < fr ? wave_uniform(halo[d]) : 0;
+            lj[j] = j < fr ? wave_uniform64(sc.extent[d]) : 1;
+        }
+        for (int32_t v = tid; v < vol; v += blockDim.x) key[v] = owner_key(sc, v);
+        // the block tables fit when the blocks are few and the extents below 2^31
+        bool tab = simple && off <= tcap;
+#pragma unroll
+        for (int j = 0; j < TM_MAX_LRANK; ++j) tab = tab && lj[j] < INT32_MAX;
+        if (tab) {
+            // per final dim: block_first of every block a (0..S) and, for a >= 1, the
+            // block holding the cell before it
+            for (int j = 0; j < fr; ++j) {
+                const int64_t S = wave_uniform(sc.fshape[j]);
+                const int64_t l = sc.extent[sc.proj_src[j]];
+                int32_t o = 0;
+                for (int jj = 0; jj < j; ++jj) o += wave_uniform(sc.fshape[jj]) + 1;
+                for (int32_t aa = tid; aa <= (int32_t)S; aa += blockDim.x) {
+                    const int64_t b = block_first(aa, S, l);
+                    bft[o + aa] = (int32_t)b;
+                    aLt[o + aa] = (aa >= 1 && b >= 1) ? (int32_t)div_nn((b - 1) * S, l) : 0;
                 }
             }
+        }
+        __syncthreads();  // owner keys and block tables ready
+        // one pass over the final coordinates: per final dim j, the adjacent pairs
+        // (v, v + e_j) and how many of them change owner / node (crossing fractions);
+        // with simple projections also the block-model estimate: every v that starts
+        // a non-empty block along j (a_j >= 1) is a cell boundary b, seen by the
+        // min(h, b) + min(h, l - b) cells within the halo of it times the area of the
+        // face (the product of the other dims' block widths), counted where the owners
+        // (or nodes) of v and of the cell before b differ -- exact for bijective chains
+        // whose blocks are at least h wide.
+        // per final dim: owner changes << 16 | node changes (each at most the volume,
+        // below 2^16, also summed over a wave); the number of pairs is known
+        int32_t ch[kMaxMrankCross];
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                pairs += __shfl_xor(pairs, o, 64);
-                dn += __shfl_xor(dn, o, 64);
-                dp += __shfl_xor(dp, o, 64);
+        for (int j = 0; j < kMaxMrankCross; ++j) ch[j] = 0;
+        double tot = 0, inter = 0;
+        for (int32_t v = tid; v < vol; v += blockDim.x) {
+            int32_t a[kMaxMrankCross];
+            uint32_t rem = (uint32_t)v;
+#pragma unroll
+            for (int j = kMaxMrankCross - 1; j >= 0; --j) {
+                const uint32_t q = j < fr ? rem / (uint32_t)fs[j] : rem;
+                a[j] = j < fr ? (int32_t)(rem - q * (uint32_t)fs[j]) : 0;
+                rem = q;
             }
-            if (lane == 0) {
-                red[j][wv][0] = pairs;
-                red[j][wv][1] = dn;
-                red[j][wv][2] = dp;
+            const int32_t kv = key[v];
+#pragma unroll
+            for (int j = 0; j < kMaxMrankCross; ++j) {
+                if (j < nj && a[j] < fs[j] - 1) {
+                    const int32_t kn = key[v + fst[j]];
+                    ch[j] += ((kn != kv) << 16) | ((kn >> gb) != (kv >> gb));
+                }
+            }
+            if (tab) boundary_terms<true>(v, a, fr, fs, fst, toff, hj, lj, bft, aLt, key, gb, tot, inter);
+        }
+        // the counts summed within each wave by shuffles, then over the waves
+#pragma unroll
+        for (int j = 0; j < kMaxMrankCross; ++j) {
+            if (j < nj) {
+#pragma unroll
+                for (int o2 = 32; o2 > 0; o2 >>= 1) ch[j] += __shfl_xor(ch[j], o2, 64);
+                if (lane == 0) {
+                    red[j][wv][0] = ch[j] & 0xffff;
+                    red[j][wv][1] = ch[j] >> 16;
+                }
+            }
+        }
+        if (simple && !tab) {  // the block tables did not fit: block bounds worked out per cell
+            for (int32_t v = tid; v < vol; v += blockDim.x) {
+                int32_t a[kMaxMrankCross];
+                uint32_t rem = (uint32_t)v;
+#pragma unroll
+                for (int j = kMaxMrankCross - 1; j >= 0; --j) {
+                    const uint32_t q = j < fr ? rem / (uint32_t)fs[j] : rem;
+                    a[j] = j < fr ? (int32_t)(rem - q * (uint32_t)fs[j]) : 0;
+                    rem = q;
+                }
+                boundary_terms<false>(v, a, fr, fs, fst, toff, hj, lj, bft, aLt, key, gb, tot, inter);
             }
         }
         __syncthreads();
-        if ((int)threadIdx.x < kMaxMrankCross) {
-            const int j = threadIdx.x;
+        if (tid < kMaxMrankCross) {
+            const int j = tid;
             float fn = 0.f, fp = 0.f;
             if (j < nj) {
-                const int pairs = red[j][0][0] + red[j][1][0] + red[j][2][0] + red[j][3][0];
-                const int dn = red[j][0][1] + red[j][1][1] + red[j][2][1] + red[j][3][1];
-                const int dp = red[j][0][2] + red[j][1][2] + red[j][2][2] + red[j][3][2];
+                // pairs (v, v + e_j): the coordinates with a_j < S_j - 1
+                const int32_t Sj = sc.fshape[j];
+                const int pairs = (Sj - 1) * (vol / Sj);
+                int dn = 0, dp = 0;
+                for (int w = 0; w < nwv; ++w) {
+                    dn += red[j][w][0];
+                    dp += red[j][w][1];
+                }
                 const float inv = pairs ? 1.f / (float)pairs : 0.f;
                 fn = (float)dn * inv;
                 fp = (float)dp * inv;
@@ -124,52 +265,9 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
             cross[ci * 2 * kMaxMrankCross + kMaxMrankCross + j] = fp;
         }
         __syncthreads();
-        // is every launch dim projected (block) onto exactly one final dim?
-        int fdim[4] = {-1, -1, -1, -1};
-        bool simple = sc.frank == K;
-        for (int j = 0; j < sc.frank && simple; ++j) {
-            const int d = sc.proj_src[j];
-            if (fdim[d] >= 0 || sc.proj_mode[j] != TM_BLOCK) simple = false;
-            else fdim[d] = j;
-        }
-        double tot = 0, inter = 0;
-        if (simple) {
-            for (int d = 0; d < K; ++d) {
-                const int j = fdim[d];
-                const int64_t l = sc.extent[d], S = sc.fshape[j];
-                const int h = halo[d];
-                const int32_t st = sc.fstride[j];
-                if (h == 0 || S == 1) continue;
-                // boundaries along d: the first cell b of every non-empty block a >= 1,
-                // against the block holding cell b - 1
-                const int32_t others = vol / (int32_t)S;
-                const int32_t nt = ((int32_t)S - 1) * others;  // < vol <= kCrossMax
-                for (int32_t t = threadIdx.x; t < nt; t += blockDim.x) {
-                    const int32_t aR = 1 + t / others;
-                    int32_t u = t % others;
-                    const int64_t b = block_first(aR, S, l);
-                    if (b >= l || b >= block_first(aR + 1, S, l)) continue;  // empty block
-                    const int32_t aL = (int32_t)((b - 1) * S / l);
-                    // decode the other coordinates from u (C order over dims != j)
-                    int32_t vR = aR * st, vL = aL * st;
-                    double face = 1;
-                    for (int jj = sc.frank - 1; jj >= 0; --jj) {
-                        if (jj == j) continue;
-                        const int32_t Sj = sc.fshape[jj];
-                        const int32_t aj = u % Sj;
-                        u /= Sj;
-                        vR += aj * sc.fstride[jj];
-                        vL += aj * sc.fstride[jj];
-                        const int64_t lj = sc.extent[sc.proj_src[jj]];
-                        face *= (double)(block_first(aj + 1, Sj, lj) - block_first(aj, Sj, lj));
-                    }
-                    const double w = (double)((h < b ? h : b) + (h < l - b ? h : l - b));
-                    if (key[vL] != key[vR]) tot += w * face;
-                    if ((key[vL] >> gb) != (key[vR] >> gb)) inter += w * face;
-                }
-                __syncthreads();
-            }
-        } else {
+        if (!simple) {
+            // per launch dim, the (cell, distinct foreign coordinate) pairs along it
+            // times the other extents times the crossing fraction
             for (int d = 0; d < K; ++d) {
                 const int64_t l = sc.extent[d];
                 const int h = halo[d];
@@ -220,9 +318,11 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
             dred[wv][1] = inter;
         }
         __syncthreads();
-        if (threadIdx.x < 2)
-            est[ci * 2 + threadIdx.x] = dred[0][threadIdx.x] + dred[1][threadIdx.x] + dred[2][threadIdx.x] +
-                                        dred[3][threadIdx.x];
+        if (threadIdx.x < 2) {
+            double e = 0;
+            for (int w = 0; w < nwv; ++w) e += dred[w][threadIdx.x];
+            est[ci * 2 + threadIdx.x] = e;
+        }
     }
 }
 
@@ -889,15 +989,23 @@ hipError_t launch_features(const DevCand* cands, int64_t n, int32_t max_vol, con
     // the owner table of a candidate lives in LDS: most candidates are small, so a
     // first launch with a small table (more workgroups per CU) takes the volumes up to
     // kStatsSmallVol, and a second one, sized for the batch's largest, the rest
+    // large batches of small candidates: one-wave workgroups, four times as many
+    // candidates in flight per CU (each candidate's work is a few hundred keys)
+    const int bs = n >= kSmallBlockBatch ? 64 : 256;
     const int32_t vtop = std::max(1, std::min(max_vol, kCrossMax));
+    // LDS words: the keys, then the two block tables or a launch dim's contributions
+    auto lds_bytes = [](int32_t vcap) {
+        const int32_t tcap = std::min(vcap + 16, kStatsTableCap);
+        return (size_t)(((vcap + 3) & ~3) + std::max(2 * tcap, kStatsStage)) * 4;
+    };
     if (vtop <= kStatsSmallVol) {
-        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(256), (size_t)vtop * 4, s, cands, n, d_halo, cross,
-                           est, 0, kCrossMax);
+        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(bs), lds_bytes(vtop), s, cands, n, d_halo, cross,
+                           est, 0, kCrossMax, vtop);
     } else {
-        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(256), (size_t)kStatsSmallVol * 4, s, cands, n,
-                           d_halo, cross, est, 0, kStatsSmallVol);
-        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(256), (size_t)vtop * 4, s, cands, n, d_halo, cross,
-                           est, kStatsSmallVol, kCrossMax);
+        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(bs), lds_bytes(kStatsSmallVol), s, cands, n,
+                           d_halo, cross, est, 0, kStatsSmallVol, kStatsSmallVol);
+        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(bs), lds_bytes(vtop), s, cands, n, d_halo, cross,
+                           est, kStatsSmallVol, kCrossMax, vtop);
     }
     hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cands, n, d_halo, cross, est,
                        X, f32);
