@@ -7,7 +7,7 @@ decompose's enumeration) under 6 transformation chains = 216 candidate mappings;
 candidate exactly (processor of each of the 216 x 134,217,728 launch points, and
 the distinct-owner ghost volume with its intra/inter-node split), selects the
 cheapest by (bytes, inter-node bytes, index), and materialises the selected
-candidate's int32 processor map (512 MiB).  Inputs (candidate descriptors) are
+candidate's int32 processor map (512 MiB), all in one graph replay.  Inputs (candidate descriptors) are
 resident on the device before timing starts.  The ghost volume of a candidate is
 counted exactly over its coordinate classes (runs of coordinates with the same
 contribution and neighbour offsets along each launch dim), so the counting work is
@@ -66,8 +66,8 @@ def measured_traffic(kernel):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--extent", type=int, default=512, help="cube side of the launch domain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
@@ -522,23 +522,20 @@ def main():
         tuned = plan.autotune(out)
     _, items, _ = plan.info()
 
-    # A step: one replay of the evaluation graph (reset, tables and classes, counting,
-    # bytes + selection), then the map of the selected candidate.  Events on the
-    # plan's stream (torch's current stream) around the map give its duration.
+    # A step: one graph replay -- the evaluation (tables and classes, counting, bytes
+    # + selection) and then the map of the selected candidate, with no host step in
+    # between.  Events on the plan's stream (torch's current stream) around it.
     def step(ev=None):
         if ev:
             ev[0].record()
-        plan.run(out, best)
+        plan.run_map(out, best, pmap)
         if ev:
             ev[1].record()
-        plan.materialize(pmap, d_index=best)
-        if ev:
-            ev[2].record()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -546,12 +543,18 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    evalk = np.mean([evs[k][0].elapsed_time(evs[k][1]) for k in range(args.steps)])
-    mapk = np.mean([evs[k][1].elapsed_time(evs[k][2]) for k in range(args.steps)])
     # each step's GPU time (events around the whole step): median and spread
-    step_gpu = np.array([evs[k][0].elapsed_time(evs[k][2]) for k in range(args.steps)])
-    # stage breakdown (a second pass over the same steps, the evaluation replayed one
-    # stage graph at a time with events between the stages; not part of `value`)
+    step_gpu = np.array([evs[k][0].elapsed_time(evs[k][1]) for k in range(args.steps)])
+    # breakdown (second and third passes over the same steps; not part of `value`):
+    # the evaluation graph and the map launch with events between them, then the
+    # evaluation one stage graph at a time
+    mev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        mev[k][0].record()
+        plan.run(out, best)
+        mev[k][1].record()
+        plan.materialize(pmap, d_index=best)
+        mev[k][2].record()
     sev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     for k in range(args.steps):
         sev[k][0].record()
@@ -559,6 +562,8 @@ def main():
             plan.run_stage(stage, out, best)
             sev[k][stage + 1].record()
     torch.cuda.synchronize()
+    evalk = np.mean([mev[k][0].elapsed_time(mev[k][1]) for k in range(args.steps)])
+    mapk = np.mean([mev[k][1].elapsed_time(mev[k][2]) for k in range(args.steps)])
     prep = np.mean([sev[k][0].elapsed_time(sev[k][1]) for k in range(args.steps)])
     count = np.mean([sev[k][1].elapsed_time(sev[k][2]) for k in range(args.steps)])
     sel = np.mean([sev[k][2].elapsed_time(sev[k][3]) for k in range(args.steps)])

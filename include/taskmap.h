@@ -329,6 +329,13 @@ int tm_plan_run_stage(tm_plan* p, int32_t stage, tm_stencil_cost* d_out, int64_t
  * hold the largest candidate of the batch. */
 int tm_plan_materialize(tm_plan* p, const int64_t* d_index, int64_t host_index, int32_t* d_map,
                         int64_t cap, void* stream);
+/* tm_plan_run, then the processor map of the selected candidate (*d_best) into
+ * d_map (device int32[cap], cap holding the batch's largest candidate), replayed as
+ * one hipGraph: Sec. 4.2's choice and the map Sec. 3.2 defines for it, with no host
+ * step between them.  d_out, d_best and d_map must not be NULL (TM_EINVAL); an empty
+ * batch is TM_EINVAL, a short map TM_ECAPACITY. */
+int tm_plan_run_map(tm_plan* p, tm_stencil_cost* d_out, int64_t* d_best, int32_t* d_map, int64_t cap,
+                    void* stream);
 /* Class tuples of the loaded batch (the counting kernel's work): the sum over its
  * candidates of the product of their per-dim class counts, as built by the last
  * run -> *tuples (host).  Synchronous: waits for `stream`.  TM_EINVAL before the

@@ -68,6 +68,7 @@ def lib():
             "tm_plan_run": [P, P, P, P],
             "tm_plan_run_stage": [P, I32, P, P, P],
             "tm_plan_materialize": [P, P, I64, P, I64, P],
+            "tm_plan_run_map": [P, P, P, P, I64, P],
             "tm_plan_autotune": [P, P, P, P, P],
             "tm_parse_index_task_map": [ctypes.c_char_p, ctypes.c_char_p, I32, P, I32, I32, P, P],
             "tm_plan_set_launch": [P, I64, I32, P],
@@ -351,6 +352,13 @@ class Plan:
         _check(lib().tm_plan_run_stage(self._p, stage, _dev_ptr(out, torch.int64, 4 * self.n),
                                        _dev_ptr(best, torch.int64, 1) if best is not None else None,
                                        _stream()))
+
+    def run_map(self, out, best, pmap):
+        """run(out, best), then the map of the selected candidate into pmap (int32
+        device tensor), as one graph."""
+        import torch
+        _check(lib().tm_plan_run_map(self._p, _dev_ptr(out, torch.int64, 4 * self.n), _dev_ptr(best, torch.int64, 1),
+                                     _dev_ptr(pmap, torch.int32), pmap.numel(), _stream()))
 
     def materialize(self, out, index=None, d_index=None):
         import torch

@@ -36,71 +36,139 @@ __device__ __forceinline__ int64_t wave_uniform64(int64_t x) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Owner key of final-space coordinate v: undo the ops on the linear index (C order)
-// of the processor space, last op first, down to Machine(GPU) = (nodes, gpus).  An
-// op touches a contiguous range of dims: with lo the product of the dims after the
-// range, the index is (h * W + x) * lo + l0, where x indexes the range (W its
-// volume); the op maps x between its output and input digits, and h, l0 pass
-// through.  Every index stays below the processor-space volume (<= 2^24), so the
-// arithmetic is 32-bit; the descriptor c must be the same in every lane of the
-// wave (its fields are then scalars).
-__device__ inline int32_t owner_key(const DevCand& c, int32_t v) {
-    uint32_t L = (uint32_t)v;
+// floor(n / d) for n < 2^24 and 1 <= d < 2^24, given r = 1 / d rounded to the
+// nearest float.  The float product n * r is within 1 + 2^-25 of n / d (two
+// roundings of relative size 2^-24 each, n / d < 2^23 for d >= 2; exact for d = 1),
+// so its truncation is at most two below and one above the quotient, which the
+// remainder test corrects; q * d < 2^25 fits the 24-bit multiply's result.
+__device__ __forceinline__ uint32_t div24(uint32_t n, uint32_t d, float r) {
+    uint32_t q = (uint32_t)((float)n * r);
+    int32_t rem = (int32_t)(n - __umul24(q, d));
+    if (rem < 0) {
+        --q;
+        rem += (int32_t)d;
+    }
+    if (rem < 0) {
+        --q;
+        rem += (int32_t)d;
+    }
+    if (rem >= (int32_t)d) ++q;
+    return q;
+}
+
+// Owner keys of final-space coordinates v0 + tid, v0 + tid + nt, ... below v1
+// (tid, nt: the thread's index and count), written (AND keep) to out[v - vbase].
+// Each key undoes the ops on the linear index (C order) of the processor space,
+// last op first, down to Machine(GPU) = (nodes, gpus).  An op touches a contiguous
+// range of dims: with lo the product of the dims after the range, the index is
+// (h * W + x) * lo + l0, where x indexes the range (W its volume); the op maps x
+// between its output and input digits, and h, l0 pass through.  Every index stays
+// below the processor-space volume (<= 2^24).  A thread takes KPT coordinates per
+// pass through the ops, so each op's constants and reciprocals are read once per
+// pass; the descriptor c must be the same in every lane of the wave (its fields are
+// then scalars).
+template <int KPT>
+__device__ inline void owner_keys(const DevCand& c, int32_t* __restrict__ out, int32_t vbase, int32_t v0,
+                                  int32_t v1, int32_t keep, int tid, int nt) {
     const int nops = wave_uniform(c.nops);
-    for (int t = nops - 1; t >= 0; --t) {
-        const int kind = wave_uniform(c.op_kind[t]);
-        const uint32_t lo = (uint32_t)wave_uniform(c.inv_lo[t]), wi = (uint32_t)wave_uniform(c.inv_win[t]),
-                       wo = (uint32_t)wave_uniform(c.inv_wout[t]);
-        const uint32_t q = L / lo, l0 = L - q * lo;
-        const uint32_t h = q / wo;
-        uint32_t x = q - h * wo, m;
-        if (kind == TM_SPLIT || kind == TM_BALANCE_SPLIT) {
-            // output digits (a, a1) of extents (b, c), x = a * c + a1; input a + a1 * b
-            const uint32_t pb = (uint32_t)wave_uniform(c.op_b[t]), cc = (uint32_t)wave_uniform(c.inv_c[t]);
-            const uint32_t a = x / cc, a1 = x - a * cc;
-            const uint32_t vv = a + a1 * pb;
-            // balance_split folds vv in [0, b * c) onto the input extent (wi <= b * c)
-            m = kind == TM_SPLIT ? vv : (uint32_t)div_nn((int64_t)vv * wi, (int64_t)wo);
-        } else if (kind == TM_MERGE) {
-            // output (a of extent s_pa * s_pb, mid); input (a mod s_pa, mid, a / s_pa)
-            const int pa = wave_uniform(c.op_a[t]), pb = wave_uniform(c.op_b[t]);
-            const uint32_t mid = (uint32_t)wave_uniform(c.inv_mid[t]);
-            const uint32_t spa = (uint32_t)wave_uniform(c.shape[t][pa]), spb = (uint32_t)wave_uniform(c.shape[t][pb]);
-            const uint32_t a = x / mid, xm = x - a * mid;
-            const uint32_t ahi = a / spa, alo = a - ahi * spa;
-            m = (alo * mid + xm) * spb + ahi;
-        } else if (kind == TM_SWAP) {
-            // output (y_lo of extent s_hi, mid, y_hi of extent s_lo); input (y_hi, mid, y_lo)
-            const int pa = wave_uniform(c.op_a[t]), pb = wave_uniform(c.op_b[t]);
-            const int plo = pa < pb ? pa : pb, phi = pa < pb ? pb : pa;
-            const uint32_t mid = (uint32_t)wave_uniform(c.inv_mid[t]);
-            const uint32_t slo = (uint32_t)wave_uniform(c.shape[t][plo]), shi = (uint32_t)wave_uniform(c.shape[t][phi]);
-            const uint32_t ms = mid * slo;
-            const uint32_t ylo = x / ms, rest = x - ylo * ms;
-            const uint32_t xm = rest / slo, yhi = rest - xm * slo;
-            m = (yhi * mid + xm) * shi + ylo;
-        } else {  // TM_DECOMPOSE: output digits of extents f[0..k) in C order; input little-endian
-            const int k = wave_uniform(c.op_nf[t]);
-            uint32_t dg[TM_MAX_LRANK] = {0, 0, 0, 0}, f[TM_MAX_LRANK] = {1, 1, 1, 1};
+    const uint32_t g = (uint32_t)wave_uniform(c.gpus);
+    const int gb = wave_uniform(c.gbits);
+    const float rg = 1.0f / (float)g;
+    for (int32_t base = v0 + tid; base < v1; base += KPT * nt) {
+        uint32_t L[KPT];
 #pragma unroll
-            for (int j = 0; j < TM_MAX_LRANK; ++j) f[j] = j < k ? (uint32_t)wave_uniform(c.op_f[t][j]) : 1u;
+        for (int i = 0; i < KPT; ++i) {
+            const int32_t v = base + i * nt;
+            L[i] = (uint32_t)(v < v1 ? v : v1 - 1);  // out-of-range slots repeat a valid index
+        }
+        for (int t = nops - 1; t >= 0; --t) {
+            const int kind = wave_uniform(c.op_kind[t]);
+            const uint32_t lo = (uint32_t)wave_uniform(c.inv_lo[t]), wi = (uint32_t)wave_uniform(c.inv_win[t]),
+                           wo = (uint32_t)wave_uniform(c.inv_wout[t]);
+            const float rlo = 1.0f / (float)lo, rwo = 1.0f / (float)wo;
+            if (kind == TM_SPLIT || kind == TM_BALANCE_SPLIT) {
+                // output digits (a, a1) of extents (b, c), x = a * c + a1; input a + a1 * b;
+                // balance_split folds that onto the input extent (wi <= b * c)
+                const uint32_t pb = (uint32_t)wave_uniform(c.op_b[t]), cc = (uint32_t)wave_uniform(c.inv_c[t]);
+                const float rc = 1.0f / (float)cc;
 #pragma unroll
-            for (int j = TM_MAX_LRANK - 1; j >= 0; --j) {
-                if (j < k) {
-                    const uint32_t qq = x / f[j];
-                    dg[j] = x - qq * f[j];
-                    x = qq;
+                for (int i = 0; i < KPT; ++i) {
+                    const uint32_t q = div24(L[i], lo, rlo), l0 = L[i] - q * lo;
+                    const uint32_t h = div24(q, wo, rwo), x = q - h * wo;
+                    const uint32_t aa = div24(x, cc, rc), a1 = x - aa * cc;
+                    const uint32_t vv = aa + a1 * pb;
+                    const uint32_t m = kind == TM_SPLIT ? vv : (uint32_t)div_nn((int64_t)vv * wi, (int64_t)wo);
+                    L[i] = (h * wi + m) * lo + l0;
+                }
+            } else if (kind == TM_MERGE) {
+                // output (a of extent s_pa * s_pb, mid); input (a mod s_pa, mid, a / s_pa)
+                const int pa = wave_uniform(c.op_a[t]), pb = wave_uniform(c.op_b[t]);
+                const uint32_t mid = (uint32_t)wave_uniform(c.inv_mid[t]);
+                const uint32_t spa = (uint32_t)wave_uniform(c.shape[t][pa]), spb = (uint32_t)wave_uniform(c.shape[t][pb]);
+                const float rmid = 1.0f / (float)mid, rspa = 1.0f / (float)spa;
+#pragma unroll
+                for (int i = 0; i < KPT; ++i) {
+                    const uint32_t q = div24(L[i], lo, rlo), l0 = L[i] - q * lo;
+                    const uint32_t h = div24(q, wo, rwo), x = q - h * wo;
+                    const uint32_t aa = div24(x, mid, rmid), xm = x - aa * mid;
+                    const uint32_t ahi = div24(aa, spa, rspa), alo = aa - ahi * spa;
+                    const uint32_t m = (alo * mid + xm) * spb + ahi;
+                    L[i] = (h * wi + m) * lo + l0;
+                }
+            } else if (kind == TM_SWAP) {
+                // output (y_lo of extent s_hi, mid, y_hi of extent s_lo); input (y_hi, mid, y_lo)
+                const int pa = wave_uniform(c.op_a[t]), pb = wave_uniform(c.op_b[t]);
+                const int plo = pa < pb ? pa : pb, phi = pa < pb ? pb : pa;
+                const uint32_t mid = (uint32_t)wave_uniform(c.inv_mid[t]);
+                const uint32_t slo = (uint32_t)wave_uniform(c.shape[t][plo]), shi = (uint32_t)wave_uniform(c.shape[t][phi]);
+                const uint32_t ms = mid * slo;
+                const float rms = 1.0f / (float)ms, rslo = 1.0f / (float)slo;
+#pragma unroll
+                for (int i = 0; i < KPT; ++i) {
+                    const uint32_t q = div24(L[i], lo, rlo), l0 = L[i] - q * lo;
+                    const uint32_t h = div24(q, wo, rwo), x = q - h * wo;
+                    const uint32_t ylo = div24(x, ms, rms), rest = x - ylo * ms;
+                    const uint32_t xm = div24(rest, slo, rslo), yhi = rest - xm * slo;
+                    const uint32_t m = (yhi * mid + xm) * shi + ylo;
+                    L[i] = (h * wi + m) * lo + l0;
+                }
+            } else {  // TM_DECOMPOSE: output digits of extents f[0..k) in C order; input little-endian
+                const int k = wave_uniform(c.op_nf[t]);
+                uint32_t f[TM_MAX_LRANK];
+                float rf[TM_MAX_LRANK];
+#pragma unroll
+                for (int j = 0; j < TM_MAX_LRANK; ++j) {
+                    f[j] = j < k ? (uint32_t)wave_uniform(c.op_f[t][j]) : 1u;
+                    rf[j] = 1.0f / (float)f[j];
+                }
+#pragma unroll
+                for (int i = 0; i < KPT; ++i) {
+                    const uint32_t q = div24(L[i], lo, rlo), l0 = L[i] - q * lo;
+                    const uint32_t h = div24(q, wo, rwo);
+                    uint32_t x = q - h * wo;
+                    uint32_t dg[TM_MAX_LRANK];
+#pragma unroll
+                    for (int j = TM_MAX_LRANK - 1; j >= 0; --j) {
+                        const uint32_t qq = j < k ? div24(x, f[j], rf[j]) : x;
+                        dg[j] = x - qq * f[j];
+                        x = qq;
+                    }
+                    uint32_t m = 0;
+#pragma unroll
+                    for (int j = TM_MAX_LRANK - 1; j >= 0; --j) m = j < k ? m * f[j] + dg[j] : m;
+                    L[i] = (h * wi + m) * lo + l0;
                 }
             }
-            m = 0;
-#pragma unroll
-            for (int j = TM_MAX_LRANK - 1; j >= 0; --j) m = j < k ? m * f[j] + dg[j] : m;
         }
-        L = (h * wi + m) * lo + l0;
+#pragma unroll
+        for (int i = 0; i < KPT; ++i) {
+            const int32_t v = base + i * nt;
+            if (v < v1) {
+                const uint32_t node = div24(L[i], g, rg);
+                out[v - vbase] = (int32_t)((node << gb) | (L[i] - node * g)) & keep;
+            }
+        }
     }
-    const uint32_t g = (uint32_t)wave_uniform(c.gpus);
-    const uint32_t node = L / g;
-    return (int32_t)((node << wave_uniform(c.gbits)) | (L - node * g));
 }
 
 // Contribution of coordinate x of launch dim d to the linear final index.

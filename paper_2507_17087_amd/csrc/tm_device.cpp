@@ -512,9 +512,12 @@ namespace tmk {
 
 static void plan_drop_graphs(tm_plan* p) {
     if (p->g_full) (void)hipGraphExecDestroy(p->g_full);
+    if (p->g_map) (void)hipGraphExecDestroy(p->g_map);
     for (auto& g : p->g_stage)
         if (g) (void)hipGraphExecDestroy(g);
     p->g_full = nullptr;
+    p->g_map = nullptr;
+    p->g_map_ptr = nullptr;
     for (auto& g : p->g_stage) g = nullptr;
     p->g_valid = false;
 }
@@ -631,6 +634,34 @@ static int capture(tm_plan* p, int stage, tm_stencil_cost* out, int64_t* best, i
     return TM_OK;
 }
 
+// Map grid for a device-side index: the largest over the loaded candidates.
+static int plan_map_grid(const tm_plan* p) {
+    int grid = 1;
+    for (auto& d : p->cp.cands) grid = std::max(grid, map_grid(d.rows, d.L));
+    return grid;
+}
+
+// The whole run followed by the map of candidate *best, as one graph.
+static int capture_run_map(tm_plan* p, tm_stencil_cost* out, int64_t* best, int32_t* map, int grid,
+                           hipGraphExec_t* exec) {
+    hipGraph_t g = nullptr;
+    TM_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = plan_enqueue(p, -1, out, best, grid, p->cap_stream);
+    if (e == hipSuccess)
+        e = launch_map(p->d_cands, p->cp.hdr.n, p->d_arena, best, 0, map, plan_map_grid(p), p->cp.max_words,
+                       p->cap_stream);
+    const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return set_error(TM_EDEVICE, "capture: %s", hipGetErrorString(e));
+    }
+    TM_HIP(e2);
+    const hipError_t e3 = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    TM_HIP(e3);
+    return TM_OK;
+}
+
 static int plan_graphs(tm_plan* p, tm_stencil_cost* out, int64_t* best) {
     const int grid = count_grid(p->cp.cnt_words, p->cp.items, p->wg_per_cu);
     if (p->g_valid && p->g_grid == grid && p->g_out == out && p->g_best == best) return TM_OK;
@@ -719,6 +750,25 @@ extern "C" int tm_plan_run(tm_plan* p, tm_stencil_cost* d_out, int64_t* d_best, 
     return TM_OK;
 }
 
+extern "C" int tm_plan_run_map(tm_plan* p, tm_stencil_cost* d_out, int64_t* d_best, int32_t* d_map, int64_t cap,
+                               void* stream) {
+    if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
+    if (p->cp.hdr.n == 0) return set_error(TM_EINVAL, "empty batch");
+    if (!d_out || !d_best || !d_map) return set_error(TM_EINVAL, "null output");
+    if (cap < p->cp.max_points) return set_error(TM_ECAPACITY, "map needs %lld entries", (long long)p->cp.max_points);
+    int rc = plan_ensure_arena(p, (hipStream_t)stream);
+    if (rc == TM_OK) rc = plan_graphs(p, d_out, d_best);
+    if (rc == TM_OK && (!p->g_map || p->g_map_ptr != d_map)) {
+        if (p->g_map) (void)hipGraphExecDestroy(p->g_map);
+        p->g_map = nullptr;
+        rc = capture_run_map(p, d_out, d_best, d_map, p->g_grid, &p->g_map);
+        p->g_map_ptr = rc == TM_OK ? d_map : nullptr;
+    }
+    if (rc != TM_OK) return rc;
+    TM_HIP(hipGraphLaunch(p->g_map, (hipStream_t)stream));
+    return TM_OK;
+}
+
 extern "C" int tm_plan_run_stage(tm_plan* p, int32_t stage, tm_stencil_cost* d_out, int64_t* d_best,
                                  void* stream) {
     if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
@@ -745,7 +795,7 @@ extern "C" int tm_plan_materialize(tm_plan* p, const int64_t* d_index, int64_t h
         need = cp.cands[(size_t)host_index].npoints;
         grid = map_grid(cp.cands[(size_t)host_index].rows, cp.cands[(size_t)host_index].L);
     } else {
-        for (auto& d : cp.cands) grid = std::max(grid, map_grid(d.rows, d.L));
+        grid = plan_map_grid(p);
     }
     if (cap < need) return set_error(TM_ECAPACITY, "map needs %lld entries", (long long)need);
     if (!p->d_arena || p->cap_words < cp.arena_words)

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
         // counting kernel then counts distinct other nodes per cell
         const int32_t keep = hdr->node_level ? ~((1 << sc.gbits) - 1) : -1;
         const int32_t v0 = (int32_t)((int64_t)sc.vol * d / K), v1 = (int32_t)((int64_t)sc.vol * (d + 1) / K);
-        for (int32_t v = v0 + tid; v < v1; v += blockDim.x) base[v] = owner_key(sc, v) & keep;
+        owner_keys<4>(sc, base, 0, v0, v1, keep, tid, blockDim.x);
         const int64_t l = sc.extent[d];
         int32_t* ct = base + sc.coord_off[d];
         // the dim's coordinate table; kept in LDS too when it fits (the class build

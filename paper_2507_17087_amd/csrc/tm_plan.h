@@ -71,6 +71,8 @@ struct tm_plan {
     void* g_out = nullptr;
     void* g_best = nullptr;
     hipGraphExec_t g_full = nullptr, g_stage[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t g_map = nullptr;  // the whole run, then the map of the selected candidate
+    void* g_map_ptr = nullptr;
     tmk::SearchBufs sb;
 };
 

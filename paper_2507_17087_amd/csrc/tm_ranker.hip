@@ -150,11 +150,13 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
         // the final dims' extents and strides; with simple projections, each one's
         // launch extent and halo and the offset of its block tables
         int32_t fs[kMaxMrankCross], fst[kMaxMrankCross], toff[TM_MAX_LRANK], hj[TM_MAX_LRANK];
+        float rfs[kMaxMrankCross];
         int64_t lj[TM_MAX_LRANK];
 #pragma unroll
         for (int j = 0; j < kMaxMrankCross; ++j) {
             fs[j] = j < fr ? wave_uniform(sc.fshape[j]) : 1;
             fst[j] = j < fr ? wave_uniform(sc.fstride[j]) : 0;
+            rfs[j] = 1.0f / (float)fs[j];
         }
         int32_t off = 0;
 #pragma unroll
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
             hj[j] = j < fr ? wave_uniform(halo[d]) : 0;
             lj[j] = j < fr ? wave_uniform64(sc.extent[d]) : 1;
         }
-        for (int32_t v = tid; v < vol; v += blockDim.x) key[v] = owner_key(sc, v);
+        owner_keys<4>(sc, key, 0, 0, vol, -1, tid, blockDim.x);
         // the block tables fit when the blocks are few and the extents below 2^31
         bool tab = simple && off <= tcap;
 #pragma unroll
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
             uint32_t rem = (uint32_t)v;
 #pragma unroll
             for (int j = kMaxMrankCross - 1; j >= 0; --j) {
-                const uint32_t q = j < fr ? rem / (uint32_t)fs[j] : rem;
+                const uint32_t q = j < fr ? div24(rem, (uint32_t)fs[j], rfs[j]) : rem;
                 a[j] = j < fr ? (int32_t)(rem - q * (uint32_t)fs[j]) : 0;
                 rem = q;
             }

@@ -386,6 +386,45 @@ def test_plan_graph_replay_deterministic(tm):
     assert (one == ref).all()
 
 
+def test_plan_run_map_one_graph(tm):
+    """The run and the winner's map in one graph equal a run followed by a separate
+    map launch, on every replay (eager work between them), and again after the
+    map buffer or the batch changes."""
+    import torch
+    say("plan run + map in one graph")
+    st = W.c3_stencil(3)
+    batches = [W.c3_candidates(600, seed=5, ranks=(3,), octaves=(3, 6)),
+               W.c3_candidates(300, seed=6, ranks=(2, 3), octaves=(3, 7))]
+    plan = tm.Plan(16, 16)
+    for cs in batches:
+        plan.load(cs, st)
+        pts = [int(np.prod(c["extent"][: int(c["lrank"])].astype(np.int64))) for c in cs]
+        npts = max(pts)
+        out = torch.empty((len(cs), 4), dtype=torch.int64, device="cuda")
+        best = torch.empty(1, dtype=torch.int64, device="cuda")
+        plan.run(out, best)
+        ref_map = torch.full((npts,), -7, dtype=torch.int32, device="cuda")
+        plan.materialize(ref_map, d_index=best)
+        torch.cuda.synchronize()
+        ref_out, ref_best, ref_m = out.cpu().numpy().copy(), int(best.cpu()[0]), ref_map.cpu().numpy()
+        assert ref_best == oracle.select_best(ref_out)
+        npb = pts[ref_best]
+        assert (ref_m[:npb] == oracle.proc_map(cs[ref_best]).ravel()).all()
+        for m_rep in range(2):  # a second map buffer forces a new graph
+            pmap = torch.full((npts,), -1, dtype=torch.int32, device="cuda")
+            for rep in range(3):
+                out.fill_(-1)
+                plan.run_map(out, best, pmap)
+                torch.cuda.synchronize()
+                _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+                assert (out.cpu().numpy() == ref_out).all()
+                assert int(best.cpu()[0]) == ref_best
+                assert (pmap.cpu().numpy()[:npb] == ref_m[:npb]).all()
+        with pytest.raises(RuntimeError):
+            plan.run_map(out, best, torch.empty(npts - 1, dtype=torch.int32, device="cuda"))
+    plan.close()
+
+
 def test_plan_autotune_keeps_results(tm):
     import torch
     say("plan autotune")
