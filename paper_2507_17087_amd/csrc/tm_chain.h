@@ -36,6 +36,19 @@ __device__ __forceinline__ int64_t wave_uniform64(int64_t x) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Barrier of a workgroup of nw waves, for data passed through LDS.  A one-wave
+// workgroup needs no s_barrier: its LDS accesses execute in program order, so a
+// wavefront fence (which also keeps the compiler from moving them) suffices, and it
+// does not wait for the wave's global memory traffic, as __syncthreads does.
+__device__ __forceinline__ void lds_sync(int nw) {
+    if (nw > 1) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // floor(n / d) for n < 2^24 and 1 <= d < 2^24, given r = 1 / d rounded to the
 // nearest float.  The float product n * r is within 1 + 2^-25 of n / d (two
 // roundings of relative size 2^-24 each, n / d < 2^23 for d >= 2; exact for d = 1),

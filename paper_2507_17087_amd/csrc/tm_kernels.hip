@@ -215,9 +215,9 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
         const int d = (int)(u - ci * TM_MAX_LRANK);
         const int K = (int)__builtin_amdgcn_readfirstlane((uint32_t)cands[ci].lrank);
         if (d >= K) continue;  // uniform
-        __syncthreads();
+        lds_sync(nw);
         stage_cand(&sc, &cands[ci]);
-        __syncthreads();
+        lds_sync(nw);
         int32_t* base = arena + sc.arena_off;
         if (d == 0) {
             if (out && tid < 4) reinterpret_cast<int64_t*>(&out[ci])[tid] = 0;
@@ -243,7 +243,9 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
         if (d == K - 1)  // zero entries up to a multiple of 512 (read in whole chunks)
             for (int64_t x = l + tid; x < ((l + 511) & ~int64_t(511)); x += blockDim.x) ct[x] = 0;
         if (!use_halo) continue;
-        __syncthreads();  // the coordinate table complete (LDS and global)
+        // the coordinate table complete (read from LDS when staged, else from global memory)
+        if (staged) lds_sync(nw);
+        else __syncthreads();
         const int32_t* cr = staged ? s_ct : ct;
         const int hs = sc.hstride;
         int32_t* rec = base + sc.cls_base;
@@ -271,12 +273,15 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
                 }
             }
             const uint64_t m = __ballot(start);
-            if (lane == 0) s_wt[wid] = __popcll(m);
-            __syncthreads();
-            int64_t below = 0, tot = 0;
-            for (int w = 0; w < nw; ++w) {
-                below += w < wid ? s_wt[w] : 0;
-                tot += s_wt[w];
+            int64_t below = 0, tot = __popcll(m);
+            if (nw > 1) {  // the other waves' starts (a one-wave workgroup has them all in m)
+                if (lane == 0) s_wt[wid] = __popcll(m);
+                __syncthreads();
+                tot = 0;
+                for (int w = 0; w < nw; ++w) {
+                    below += w < wid ? s_wt[w] : 0;
+                    tot += s_wt[w];
+                }
             }
             if (start) {
                 const int64_t idx = run + below + __builtin_amdgcn_mbcnt_hi(
@@ -288,7 +293,7 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
                 }
             }
             run += tot;
-            __syncthreads();  // s_wt is rewritten by the next chunk
+            if (nw > 1) __syncthreads();  // s_wt is rewritten by the next chunk
         }
         if (tid == 0) {
             if (run <= cap) cs[run] = (int32_t)l;

@@ -122,6 +122,8 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
     int32_t* s_ct = bft;
     __shared__ int32_t red[kMaxMrankCross][4][2];  // per final dim and wave: node and owner changes
     __shared__ double dred[4][2];
+    __shared__ float s_cross[2 * kMaxMrankCross];  // this candidate's crossing fractions
+    const int nw = blockDim.x >> 6;
     for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
         // this launch takes the candidates of volume in (vmin, vmax]; the one whose
         // vmax is kCrossMax also writes the zeros of those above it
@@ -132,9 +134,9 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
             continue;
         }
         if (v0 <= vmin || v0 > vmax) continue;
-        __syncthreads();
+        lds_sync(nw);
         stage_cand(&sc, &cands[ci]);
-        __syncthreads();
+        lds_sync(nw);
         const int32_t vol = sc.vol;
         const int K = wave_uniform(sc.lrank), gb = wave_uniform(sc.gbits), fr = wave_uniform(sc.frank);
         const int nj = fr < kMaxMrankCross ? fr : kMaxMrankCross;
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
                 }
             }
         }
-        __syncthreads();  // owner keys and block tables ready
+        lds_sync(nw);  // owner keys and block tables ready
         // one pass over the final coordinates: per final dim j, the adjacent pairs
         // (v, v + e_j) and how many of them change owner / node (crossing fractions);
         // with simple projections also the block-model estimate: every v that starts
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
                 boundary_terms<false>(v, a, fr, fs, fst, toff, hj, lj, bft, aLt, key, gb, tot, inter);
             }
         }
-        __syncthreads();
+        lds_sync(nw);
         if (tid < kMaxMrankCross) {
             const int j = tid;
             float fn = 0.f, fp = 0.f;
@@ -265,8 +267,10 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
             }
             cross[ci * 2 * kMaxMrankCross + j] = fn;
             cross[ci * 2 * kMaxMrankCross + kMaxMrankCross + j] = fp;
+            s_cross[j] = fn;
+            s_cross[kMaxMrankCross + j] = fp;
         }
-        __syncthreads();
+        lds_sync(nw);
         if (!simple) {
             // per launch dim, the (cell, distinct foreign coordinate) pairs along it
             // times the other extents times the crossing fraction
@@ -278,7 +282,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
                     const bool staged = l <= kStatsStage;  // uniform
                     if (staged) {
                         for (int32_t x = threadIdx.x; x < (int32_t)l; x += blockDim.x) s_ct[x] = coord_value(sc, d, x);
-                        __syncthreads();
+                        lds_sync(nw);
                     }
                     for (int64_t x = threadIdx.x; x < l; x += blockDim.x) {
                         const int32_t val = staged ? s_ct[x] : coord_value(sc, d, x);
@@ -295,13 +299,13 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
                             }
                         part += cnt;
                     }
-                    if (staged) __syncthreads();  // the next dim rewrites s_ct
+                    if (staged) lds_sync(nw);  // the next dim rewrites s_ct
                 }
                 float cn = 0.f, cp = 0.f;
                 for (int j = 0; j < sc.frank && j < kMaxMrankCross; ++j)
                     if (sc.proj_src[j] == d) {
-                        cn = fmaxf(cn, cross[ci * 2 * kMaxMrankCross + j]);
-                        cp = fmaxf(cp, cross[ci * 2 * kMaxMrankCross + kMaxMrankCross + j]);
+                        cn = fmaxf(cn, s_cross[j]);
+                        cp = fmaxf(cp, s_cross[kMaxMrankCross + j]);
                     }
                 double pts = 1;
                 for (int dd = 0; dd < K; ++dd)
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
             dred[wv][0] = tot;
             dred[wv][1] = inter;
         }
-        __syncthreads();
+        lds_sync(nw);
         if (threadIdx.x < 2) {
             double e = 0;
             for (int w = 0; w < nwv; ++w) e += dred[w][threadIdx.x];
