@@ -149,6 +149,9 @@ hipError_t launch_chain_table(const DevCand* cand, const int32_t* arena, int32_t
 // Batches of at least this many candidates run the per-candidate table and
 // statistics kernels with one-wave workgroups (more candidates in flight per CU).
 constexpr int64_t kSmallBlockBatch = 8192;
+// Batches of at most this many candidates build their tables with one workgroup per
+// (candidate, launch dim) instead of one per candidate.
+constexpr int64_t kSplitBuildBatch = 1024;
 
 // Matmul work blocks: kMatmulTiles class pairs of one matrix each.  A matrix over
 // launch dims (a, b) has cls_cap[a] * cls_cap[b] class pairs at most; A = (0, 2),

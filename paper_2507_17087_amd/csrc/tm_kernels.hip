@@ -69,7 +69,7 @@ __device__ __forceinline__ unsigned long long wave_sum64(int v) {
 
 // ------------------------------------------------------------------ class-tuple counting
 
-constexpr int kFoundCache = 8;  // distinct foreign owners held in registers per tuple
+constexpr int kFoundCache = 4;  // distinct foreign owners held in registers per tuple
 
 
 // Counts the class tuples t0, t0 + step, ... below tb of one candidate (tuples in C
@@ -191,35 +191,39 @@ __device__ __forceinline__ int coord_offsets(const int32_t* __restrict__ C, int6
 
 constexpr int kBuildStage = 2048;  // coordinate-table entries staged in LDS for the class build
 
-// One workgroup per (candidate, launch dim) (grid-stride over both): workgroup d of
-// a candidate writes the d-th K-th of its owner table T[v] (one key per final-space
-// coordinate), the coordinate table C_d and, with halos (use_halo), the coordinate
-// classes of dim d (see tm_internal.h): a coordinate starts a class when its
-// contribution or offset set differs from its left neighbour's; class indices come
-// from a workgroup prefix count of the starts.  Workgroup 0 of a candidate also
-// writes its entries of the item table and, with out/counter, zeroes its outputs
-// (workgroup 0 of the launch the counting kernel's counters).
+// The owner table T[v] (one key per final-space coordinate), the coordinate tables
+// C_d and, with halos (use_halo), the coordinate classes of every launch dim (see
+// tm_internal.h): a coordinate starts a class when its contribution or offset set
+// differs from its left neighbour's; class indices come from a workgroup prefix
+// count of the starts.  With split, one workgroup per (candidate, launch dim) --
+// workgroup d writes the d-th K-th of T, C_d and dim d's classes (small batches:
+// more workgroups in flight) -- else one per candidate, all dims in turn (grid-
+// stride in both cases).  The first workgroup of a candidate also writes its
+// entries of the item table and, with out/counter, zeroes its outputs (workgroup 0
+// of the launch the counting kernel's counters).
 __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restrict__ hdr,
                                                       const DevCand* __restrict__ cands,
                                                       int32_t* __restrict__ arena, int use_halo,
                                                       tm_stencil_cost* __restrict__ out,
-                                                      unsigned long long* __restrict__ counter) {
+                                                      unsigned long long* __restrict__ counter, int split) {
     __shared__ DevCand sc;
     __shared__ int32_t s_wt[4];
     __shared__ int32_t s_ct[kBuildStage];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
-    const int64_t units = hdr->n * TM_MAX_LRANK;
+    const int upc = split ? TM_MAX_LRANK : 1;  // units per candidate
+    const int64_t units = hdr->n * upc;
     if (counter && blockIdx.x == 0 && tid < 2) counter[tid] = 0ull;
     for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-        const int64_t ci = u / TM_MAX_LRANK;
-        const int d = (int)(u - ci * TM_MAX_LRANK);
+        const int64_t ci = u / upc;
+        const int dlo = (int)(u - ci * upc);
         const int K = (int)__builtin_amdgcn_readfirstlane((uint32_t)cands[ci].lrank);
-        if (d >= K) continue;  // uniform
+        if (dlo >= K) continue;  // uniform
+        const int dhi = split ? dlo + 1 : K;
         lds_sync(nw);
         stage_cand(&sc, &cands[ci]);
         lds_sync(nw);
         int32_t* base = arena + sc.arena_off;
-        if (d == 0) {
+        if (dlo == 0) {
             if (out && tid < 4) reinterpret_cast<int64_t*>(&out[ci])[tid] = 0;
             if (use_halo)  // this candidate's entries of the item table (work item -> candidate)
                 for (int32_t j = tid; j < sc.citems; j += blockDim.x)
@@ -228,76 +232,80 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
         // node-level tables keep the node of each owner (GPU bits cleared): the
         // counting kernel then counts distinct other nodes per cell
         const int32_t keep = hdr->node_level ? ~((1 << sc.gbits) - 1) : -1;
-        const int32_t v0 = (int32_t)((int64_t)sc.vol * d / K), v1 = (int32_t)((int64_t)sc.vol * (d + 1) / K);
+        const int32_t v0 = split ? (int32_t)((int64_t)sc.vol * dlo / K) : 0;
+        const int32_t v1 = split ? (int32_t)((int64_t)sc.vol * (dlo + 1) / K) : sc.vol;
         owner_keys<4>(sc, base, 0, v0, v1, keep, tid, blockDim.x);
-        const int64_t l = sc.extent[d];
-        int32_t* ct = base + sc.coord_off[d];
-        // the dim's coordinate table; kept in LDS too when it fits (the class build
-        // reads it 2 (2h + 1) times per coordinate)
-        const bool staged = use_halo && l <= kBuildStage;
-        for (int64_t x = tid; x < l; x += blockDim.x) {
-            const int32_t cv = coord_value(sc, d, x);
-            ct[x] = cv;
-            if (staged) s_ct[x] = cv;
-        }
-        if (d == K - 1)  // zero entries up to a multiple of 512 (read in whole chunks)
-            for (int64_t x = l + tid; x < ((l + 511) & ~int64_t(511)); x += blockDim.x) ct[x] = 0;
-        if (!use_halo) continue;
-        // the coordinate table complete (read from LDS when staged, else from global memory)
-        if (staged) lds_sync(nw);
-        else __syncthreads();
-        const int32_t* cr = staged ? s_ct : ct;
-        const int hs = sc.hstride;
-        int32_t* rec = base + sc.cls_base;
-        const int h = hdr->halo[d];
-        const int64_t cap = sc.cls_cap[d];
-        int32_t* ce = base + sc.cls_off[d];
-        int32_t* cs = ce + ((cap + 3) & ~int64_t(3));
-        int32_t* co = cs + ((cap + 4) & ~int64_t(3));
-        int64_t run = 0;  // classes so far (the same in every thread)
-        for (int64_t x0 = 0; x0 < l; x0 += blockDim.x) {
-            const int64_t x = x0 + tid;
-            bool start = false;
-            int32_t val = 0, o[2 * kMaxHalo];
-            int no = 0;
-            if (x < l) {
-                val = cr[x];
-                no = coord_offsets(cr, x, l, h, o);
-                start = x == 0;
-                if (!start) {
-                    int32_t pv[2 * kMaxHalo];
-                    (void)coord_offsets(cr, x - 1, l, h, pv);
-                    start = cr[x - 1] != val;
+        for (int d = dlo; d < dhi; ++d) {
+            if (d > dlo) lds_sync(nw);  // the previous dim's staged table is no longer read
+            const int64_t l = sc.extent[d];
+            int32_t* ct = base + sc.coord_off[d];
+            // the dim's coordinate table; kept in LDS too when it fits (the class build
+            // reads it 2 (2h + 1) times per coordinate)
+            const bool staged = use_halo && l <= kBuildStage;
+            for (int64_t x = tid; x < l; x += blockDim.x) {
+                const int32_t cv = coord_value(sc, d, x);
+                ct[x] = cv;
+                if (staged) s_ct[x] = cv;
+            }
+            if (d == K - 1)  // zero entries up to a multiple of 512 (read in whole chunks)
+                for (int64_t x = l + tid; x < ((l + 511) & ~int64_t(511)); x += blockDim.x) ct[x] = 0;
+            if (!use_halo) continue;
+            // the coordinate table complete (read from LDS when staged, else from global memory)
+            if (staged) lds_sync(nw);
+            else __syncthreads();
+            const int32_t* cr = staged ? s_ct : ct;
+            const int hs = sc.hstride;
+            int32_t* rec = base + sc.cls_base;
+            const int h = hdr->halo[d];
+            const int64_t cap = sc.cls_cap[d];
+            int32_t* ce = base + sc.cls_off[d];
+            int32_t* cs = ce + ((cap + 3) & ~int64_t(3));
+            int32_t* co = cs + ((cap + 4) & ~int64_t(3));
+            int64_t run = 0;  // classes so far (the same in every thread)
+            for (int64_t x0 = 0; x0 < l; x0 += blockDim.x) {
+                const int64_t x = x0 + tid;
+                bool start = false;
+                int32_t val = 0, o[2 * kMaxHalo];
+                int no = 0;
+                if (x < l) {
+                    val = cr[x];
+                    no = coord_offsets(cr, x, l, h, o);
+                    start = x == 0;
+                    if (!start) {
+                        int32_t pv[2 * kMaxHalo];
+                        (void)coord_offsets(cr, x - 1, l, h, pv);
+                        start = cr[x - 1] != val;
 #pragma unroll
-                    for (int i = 0; i < 2 * kMaxHalo; ++i) start = start || pv[i] != o[i];
+                        for (int i = 0; i < 2 * kMaxHalo; ++i) start = start || pv[i] != o[i];
+                    }
                 }
-            }
-            const uint64_t m = __ballot(start);
-            int64_t below = 0, tot = __popcll(m);
-            if (nw > 1) {  // the other waves' starts (a one-wave workgroup has them all in m)
-                if (lane == 0) s_wt[wid] = __popcll(m);
-                __syncthreads();
-                tot = 0;
-                for (int w = 0; w < nw; ++w) {
-                    below += w < wid ? s_wt[w] : 0;
-                    tot += s_wt[w];
+                const uint64_t m = __ballot(start);
+                int64_t below = 0, tot = __popcll(m);
+                if (nw > 1) {  // the other waves' starts (a one-wave workgroup has them all in m)
+                    if (lane == 0) s_wt[wid] = __popcll(m);
+                    __syncthreads();
+                    tot = 0;
+                    for (int w = 0; w < nw; ++w) {
+                        below += w < wid ? s_wt[w] : 0;
+                        tot += s_wt[w];
+                    }
                 }
-            }
-            if (start) {
-                const int64_t idx = run + below + __builtin_amdgcn_mbcnt_hi(
-                                                          (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                if (idx < cap) {  // the capacity bounds the count (class_cap); never exceeded
-                    ce[idx] = val | (no << kCntShift);
-                    cs[idx] = (int32_t)x;
-                    for (int i = 0; i < hs; ++i) co[idx * hs + i] = i < no ? o[i] : 0;
+                if (start) {
+                    const int64_t idx = run + below + __builtin_amdgcn_mbcnt_hi(
+                                                              (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    if (idx < cap) {  // the capacity bounds the count (class_cap); never exceeded
+                        ce[idx] = val | (no << kCntShift);
+                        cs[idx] = (int32_t)x;
+                        for (int i = 0; i < hs; ++i) co[idx * hs + i] = i < no ? o[i] : 0;
+                    }
                 }
+                run += tot;
+                if (nw > 1) __syncthreads();  // s_wt is rewritten by the next chunk
             }
-            run += tot;
-            if (nw > 1) __syncthreads();  // s_wt is rewritten by the next chunk
-        }
-        if (tid == 0) {
-            if (run <= cap) cs[run] = (int32_t)l;
-            rec[d] = run <= cap ? (int32_t)run : -1;  // -1: poisoned (counted as such)
+            if (tid == 0) {
+                if (run <= cap) cs[run] = (int32_t)l;
+                rec[d] = run <= cap ? (int32_t)run : -1;  // -1: poisoned (counted as such)
+            }
         }
     }
 }
@@ -305,11 +313,13 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
 hipError_t launch_build_tables(const DevHeader* hdr, const DevCand* cands, int64_t n, int32_t* arena,
                                int32_t use_halo, hipStream_t s, tm_stencil_cost* out,
                                unsigned long long* counter) {
-    const int64_t units = n * TM_MAX_LRANK;  // (candidate, launch dim) pairs
+    // small batches: a workgroup per (candidate, launch dim); large ones: per candidate
+    const int split = n <= kSplitBuildBatch ? 1 : 0;
+    const int64_t units = n * (split ? TM_MAX_LRANK : 1);
     const int64_t grid = units < 131072 ? (units > 0 ? units : 1) : 131072;
     const int bs = n >= kSmallBlockBatch ? 64 : 256;
     hipLaunchKernelGGL(k_build_tables, dim3((unsigned)grid), dim3(bs), 0, s, hdr, cands, arena, use_halo, out,
-                       counter);
+                       counter, split);
     return hipGetLastError();
 }
 
