@@ -209,6 +209,7 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
     __shared__ DevCand sc;
     __shared__ int32_t s_wt[4];
     __shared__ int32_t s_ct[kBuildStage];
+    __shared__ float s_rt[kRecipSlots];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
     const int upc = split ? TM_MAX_LRANK : 1;  // units per candidate
     const int64_t units = hdr->n * upc;
@@ -222,6 +223,8 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
         lds_sync(nw);
         stage_cand(&sc, &cands[ci]);
         lds_sync(nw);
+        op_reciprocals(sc, s_rt, tid, blockDim.x);
+        lds_sync(nw);
         int32_t* base = arena + sc.arena_off;
         if (dlo == 0) {
             if (out && tid < 4) reinterpret_cast<int64_t*>(&out[ci])[tid] = 0;
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
         const int32_t keep = hdr->node_level ? ~((1 << sc.gbits) - 1) : -1;
         const int32_t v0 = split ? (int32_t)((int64_t)sc.vol * dlo / K) : 0;
         const int32_t v1 = split ? (int32_t)((int64_t)sc.vol * (dlo + 1) / K) : sc.vol;
-        owner_keys<4>(sc, base, 0, v0, v1, keep, tid, blockDim.x);
+        owner_keys<4>(sc, s_rt, base, 0, v0, v1, keep, tid, blockDim.x);
         for (int d = dlo; d < dhi; ++d) {
             if (d > dlo) lds_sync(nw);  // the previous dim's staged table is no longer read
             const int64_t l = sc.extent[d];

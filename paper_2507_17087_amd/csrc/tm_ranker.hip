@@ -123,6 +123,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
     __shared__ int32_t red[kMaxMrankCross][4][2];  // per final dim and wave: node and owner changes
     __shared__ double dred[4][2];
     __shared__ float s_cross[2 * kMaxMrankCross];  // this candidate's crossing fractions
+    __shared__ float s_rt[kRecipSlots];             // reciprocals of the inverse chain's divisors
     const int nw = blockDim.x >> 6;
     for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
         // this launch takes the candidates of volume in (vmin, vmax]; the one whose
@@ -136,6 +137,8 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
         if (v0 <= vmin || v0 > vmax) continue;
         lds_sync(nw);
         stage_cand(&sc, &cands[ci]);
+        lds_sync(nw);
+        op_reciprocals(sc, s_rt, threadIdx.x, blockDim.x);
         lds_sync(nw);
         const int32_t vol = sc.vol;
         const int K = wave_uniform(sc.lrank), gb = wave_uniform(sc.gbits), fr = wave_uniform(sc.frank);
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
         for (int j = 0; j < kMaxMrankCross; ++j) {
             fs[j] = j < fr ? wave_uniform(sc.fshape[j]) : 1;
             fst[j] = j < fr ? wave_uniform(sc.fstride[j]) : 0;
-            rfs[j] = 1.0f / (float)fs[j];
+            rfs[j] = j < fr ? s_rt[kRecipFinal + j] : 1.0f;
         }
         int32_t off = 0;
 #pragma unroll
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
             hj[j] = j < fr ? wave_uniform(halo[d]) : 0;
             lj[j] = j < fr ? wave_uniform64(sc.extent[d]) : 1;
         }
-        owner_keys<4>(sc, key, 0, 0, vol, -1, tid, blockDim.x);
+        owner_keys<4>(sc, s_rt, key, 0, 0, vol, -1, tid, blockDim.x);
         // the block tables fit when the blocks are few and the extents below 2^31
         bool tab = simple && off <= tcap;
 #pragma unroll
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
 #pragma unroll
             for (int j = kMaxMrankCross - 1; j >= 0; --j) {
                 const uint32_t q = j < fr ? div24(rem, (uint32_t)fs[j], rfs[j]) : rem;
-                a[j] = j < fr ? (int32_t)(rem - q * (uint32_t)fs[j]) : 0;
+                a[j] = j < fr ? (int32_t)(rem - __umul24(q, (uint32_t)fs[j])) : 0;
                 rem = q;
             }
             const int32_t kv = key[v];
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
 #pragma unroll
                 for (int j = kMaxMrankCross - 1; j >= 0; --j) {
                     const uint32_t q = j < fr ? rem / (uint32_t)fs[j] : rem;
-                    a[j] = j < fr ? (int32_t)(rem - q * (uint32_t)fs[j]) : 0;
+                    a[j] = j < fr ? (int32_t)(rem - __umul24(q, (uint32_t)fs[j])) : 0;
                     rem = q;
                 }
                 boundary_terms<false>(v, a, fr, fs, fst, toff, hj, lj, bft, aLt, key, gb, tot, inter);
