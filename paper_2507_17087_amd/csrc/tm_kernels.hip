@@ -88,11 +88,12 @@ __device__ __forceinline__ void count_tuples(const int32_t* __restrict__ T, cons
     const int32_t qs = step / RL, rs = step % RL;
     int32_t mrow = -1, vo = 0;
     int64_t wo = 1;
-    int32_t kap[TM_MAX_LRANK];
+    // per outer dim of the current row: offset count and the offset list's position
+    int32_t ndo[TM_MAX_LRANK], odo[TM_MAX_LRANK];
 #pragma unroll
-    for (int d = 0; d < TM_MAX_LRANK; ++d) kap[d] = 0;
+    for (int d = 0; d < TM_MAX_LRANK; ++d) ndo[d] = odo[d] = 0;
     for (; t < tb; t += step) {
-        if (row != mrow) {  // outer classes of this row: contribution and weight
+        if (row != mrow) {  // outer classes of this row: contribution, weight, offset lists
             uint32_t rr = (uint32_t)row;
             vo = 0;
             wo = 1;
@@ -101,14 +102,14 @@ __device__ __forceinline__ void count_tuples(const int32_t* __restrict__ T, cons
                 if (d > K - 2) continue;
                 const uint32_t kd = rr % (uint32_t)R[d];
                 rr /= (uint32_t)R[d];
-                kap[d] = (int32_t)kd;
-                vo += CE[d][kd] & kValMask;
+                const int32_t e = CE[d][kd];
+                vo += e & kValMask;
+                ndo[d] = (e >> kCntShift) & 0xf;
+                odo[d] = (int32_t)kd * hs;
                 wo *= CS[d][kd + 1] - CS[d][kd];
             }
             mrow = row;
         }
-#pragma unroll
-        for (int d = 0; d < TM_MAX_LRANK; ++d) kap[d] = d == K - 1 ? k : kap[d];
         const int32_t el = CE[K - 1][k];
         const int32_t v = vo + (el & kValMask);
         const int64_t w = wo * (int64_t)(CS[K - 1][k + 1] - CS[K - 1][k]);
@@ -119,8 +120,8 @@ __device__ __forceinline__ void count_tuples(const int32_t* __restrict__ T, cons
 #pragma unroll
         for (int d = 0; d < TM_MAX_LRANK; ++d) {
             if (d >= K) continue;
-            const int32_t nd = ((d == K - 1 ? el : CE[d][kap[d]]) >> kCntShift) & 0xf;
-            const int32_t* od = CO[d] + kap[d] * hs;
+            const int32_t nd = d == K - 1 ? (el >> kCntShift) & 0xf : ndo[d];
+            const int32_t* od = CO[d] + (d == K - 1 ? k * hs : odo[d]);
             for (int i = 0; i < nd; ++i) {
                 const int32_t ot = T[v + od[i]];
                 if (ot == o) continue;
@@ -130,8 +131,8 @@ __device__ __forceinline__ void count_tuples(const int32_t* __restrict__ T, cons
                 if (!seen && nf > kFoundCache) {
                     // more distinct owners than the cache holds: look at every earlier offset
                     for (int d2 = 0; d2 <= d && !seen; ++d2) {
-                        const int32_t n2 = ((d2 == K - 1 ? el : CE[d2][kap[d2]]) >> kCntShift) & 0xf;
-                        const int32_t* o2 = CO[d2] + kap[d2] * hs;
+                        const int32_t n2 = d2 == K - 1 ? (el >> kCntShift) & 0xf : ndo[d2];
+                        const int32_t* o2 = CO[d2] + (d2 == K - 1 ? k * hs : odo[d2]);
                         const int e2 = d2 < d ? n2 : i;
                         for (int i2 = 0; i2 < e2 && !seen; ++i2) seen = T[v + o2[i2]] == ot;
                     }
