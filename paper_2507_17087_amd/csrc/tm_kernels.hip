@@ -398,15 +398,13 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
         CE[d] = CS[d] = CO[d] = arena;
     }
 
-    // the next item and its candidate (from the item table) are fetched while the
-    // current item runs
+    // workgroup b takes item b first; the later items come from the work counter
+    // (items gridDim.x, gridDim.x + 1, ...), the next one and its candidate (from the
+    // item table) fetched while the current item runs
     const int32_t* __restrict__ itab = arena + hdr->item_tab;
-    unsigned long long next = 0;
+    unsigned long long next = blockIdx.x;
     int32_t next_c = 0;
-    if (tid == 0) {
-        next = atomicAdd(counter, 1ull);
-        next_c = (int64_t)next < total ? itab[next] : 0;
-    }
+    if (tid == 0) next_c = (int64_t)next < total ? itab[next] : 0;
     for (;;) {
         if (tid == 0) {
             s_item = (long long)next;
@@ -418,7 +416,7 @@ __global__ __launch_bounds__(256) void k_count(const DevHeader* __restrict__ hdr
         __syncthreads();
         if (item >= total) break;
         if (tid == 0) {
-            next = atomicAdd(counter, 1ull);
+            next = gridDim.x + atomicAdd(counter, 1ull);
             next_c = (int64_t)next < total ? itab[next] : 0;
         }
         if (lo != cur) {
@@ -847,12 +845,10 @@ __global__ __launch_bounds__(256) void k_pair_count(const DevCand* __restrict__ 
         R[d] = 1;
         EA[d] = EB[d] = CS[d] = arena;
     }
-    unsigned long long next = 0;
+    // workgroup b takes item b first, the later ones from the work counter
+    unsigned long long next = blockIdx.x;
     int32_t next_p = 0;
-    if (tid == 0) {
-        next = atomicAdd(counter, 1ull);
-        next_p = (int64_t)next < total ? itab[next] : 0;
-    }
+    if (tid == 0) next_p = (int64_t)next < total ? itab[next] : 0;
     for (;;) {
         if (tid == 0) {
             s_item = (long long)next;
@@ -864,7 +860,7 @@ __global__ __launch_bounds__(256) void k_pair_count(const DevCand* __restrict__ 
         __syncthreads();
         if (item >= total) break;
         if (tid == 0) {
-            next = atomicAdd(counter, 1ull);
+            next = gridDim.x + atomicAdd(counter, 1ull);
             next_p = (int64_t)next < total ? itab[next] : 0;
         }
         if (pi != cur) {
