@@ -7,7 +7,9 @@ decompose's enumeration) under 6 transformation chains = 216 candidate mappings;
 candidate exactly (processor of each of the 216 x 134,217,728 launch points, and
 the distinct-owner ghost volume with its intra/inter-node split), selects the
 cheapest by (bytes, inter-node bytes, index), and materialises the selected
-candidate's int32 processor map (512 MiB), all in one graph replay.  Inputs (candidate descriptors) are
+candidate's int32 processor map (512 MiB), all in one graph replay; consecutive steps
+run round-robin on three streams (a plan and outputs each), so a step's evaluation
+overlaps the previous step's map write.  Inputs (candidate descriptors) are
 resident on the device before timing starts.  The ghost volume of a candidate is
 counted exactly over its coordinate classes (runs of coordinates with the same
 contribution and neighbour offsets along each launch dim), so the counting work is
@@ -67,6 +69,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--streams", type=int, default=3,
+                    help="streams the timed steps are issued on, round-robin (one plan and output set each)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--extent", type=int, default=512, help="cube side of the launch domain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -524,26 +528,49 @@ def main():
 
     # A step: one graph replay -- the evaluation (tables and classes, counting, bytes
     # + selection) and then the map of the selected candidate, with no host step in
-    # between.  Events on the plan's stream (torch's current stream) around it.
-    def step(ev=None):
-        if ev:
-            ev[0].record()
-        plan.run_map(out, best, pmap)
-        if ev:
-            ev[1].record()
+    # between.  The timed steps are issued round-robin on `--streams` streams, each
+    # with its own plan (the same batch) and its own outputs, so that one step's
+    # evaluation (latency-bound) overlaps the previous step's map write (HBM-bound);
+    # every step is a whole pass.  Events around each replay on its stream.
+    ns = max(1, args.streams)
+    lanes = [(plan, out, best, pmap, torch.cuda.current_stream())]
+    for _ in range(ns - 1):
+        p2 = tm.Plan(n, 1)
+        p2.load(cands, st)
+        p2.set_launch(*tuned)
+        lanes.append((p2, torch.empty_like(out), torch.empty_like(best), torch.empty_like(pmap),
+                      torch.cuda.Stream()))
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    def step(k):
+        p_, o_, b_, m_, s_ = lanes[k % ns]
+        with torch.cuda.stream(s_):
+            p_.run_map(o_, b_, m_)
+
+    for k in range(args.warmup * ns):
+        step(k)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        step(k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    # each step's GPU time (events around the whole step): median and spread
+    lanes_agree = all(bool(torch.equal(lanes[i][1], out)) and bool(torch.equal(lanes[i][2], best)) and
+                      bool(torch.equal(lanes[i][3], pmap)) for i in range(ns))
+    # the same steps on one stream (one step at a time), for comparison; then once more
+    # with events around each replay for the per-step GPU time
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for k in range(args.steps):
+        plan.run_map(out, best, pmap)
+    torch.cuda.synchronize()
+    ms_step_one = (time.perf_counter() - t2) * 1e3 / args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        evs[k][0].record()
+        plan.run_map(out, best, pmap)
+        evs[k][1].record()
+    torch.cuda.synchronize()
     step_gpu = np.array([evs[k][0].elapsed_time(evs[k][1]) for k in range(args.steps)])
     # breakdown (second and third passes over the same steps; not part of `value`):
     # the evaluation graph and the map launch with events between them, then the
@@ -606,14 +633,19 @@ def main():
         "stages_ms": {"evaluate": evalk, "map": mapk, "tables": prep, "count": count, "select": sel},
         "step_gpu_ms": {"median": float(np.median(step_gpu)), "min": float(step_gpu.min()),
                         "max": float(step_gpu.max())},
+        "streams": ns,
+        "streams_agree": lanes_agree,
+        "ms_per_step_one_stream": ms_step_one,
+        "value_one_stream": points / (ms_step_one * 1e-3),
         "count_point_evals_per_s": points / (count * 1e-3),
         "count_class_tuples_per_s": tuples / (count * 1e-3),
         "map_points_per_s": L ** 3 / (mapk * 1e-3),
         "selected": {"index": b, "factorization": list(fs[b // 6]), "chain": b % 6,
                      "bytes": int(costs[b][2]), "inter_bytes": int(costs[b][3])},
     }
-    plan.close()
-    del pmap
+    for ln in lanes:
+        ln[0].close()
+    del pmap, lanes
     if args.search:
         res["search"] = search_leg(args, tm, W)
     if args.study:
