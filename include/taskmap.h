@@ -362,8 +362,14 @@ int tm_plan_destroy(tm_plan* p);
  * (ReLU) -> 2 outputs, BF16 weights and activations with FP32 accumulation on the
  * matrix cores, FP32 master weights trained with Adam on the mean squared error
  * against standardised residuals: log2(1 + bytes) and log2(1 + inter-node bytes)
- * of exact costs, each minus the block-model estimate the features carry
- * (32 * feature 23 and 32 * feature 60, in fp32).  Parameters are one flat fp32 vector of tm_ranker_param_count() values:
+ * of exact costs, each minus the base the features carry (32 * feature 23 and
+ * 32 * feature 60, in fp32).  The features come from the descriptor alone (shapes,
+ * factors, op kinds and arguments; no pass over the processor space); feature 23
+ * is the descriptor estimate of the ghost cells -- along each launch dim, 2h cells
+ * of every cross-section at each boundary where the projected final coordinates
+ * change (l - 1 of them under a cyclic projection, else the interior block starts),
+ * exact for bijective chains whose blocks are at least h wide -- and feature 60 is
+ * 0.  Parameters are one flat fp32 vector of tm_ranker_param_count() values:
  * W1[64][256], b1[256], W2[256][256], b2, W3[256][256], b3, W4[256][2], b4[2]
  * (row-major, inputs along rows). */
 typedef struct tm_ranker tm_ranker;
@@ -380,6 +386,10 @@ int tm_ranker_set_params(tm_ranker* r, const float* d_in, void* stream);
 int tm_ranker_get_scaling(const tm_ranker* r, float* mu_sigma);
 /* Features of every candidate loaded in plan p (device fp32 [n][64]). */
 int tm_ranker_features(const tm_plan* p, float* d_feat, void* stream);
+/* Block-model estimates of every candidate loaded in plan p, as tm_search's second
+ * stage computes them: d_est (device fp64 [n][2]) = ghost cells, inter-node ghost
+ * cells (0, 0 for a processor space above 16384 coordinates). */
+int tm_ranker_block_estimates(const tm_plan* p, double* d_est, void* stream);
 /* Network outputs for n feature rows (device fp32 [n][64] -> [n][2]); inputs are
  * rounded to bf16 first. */
 int tm_ranker_forward(tm_ranker* r, const float* d_feat, int64_t n, float* d_out, void* stream);
@@ -398,19 +408,28 @@ int tm_ranker_save(const tm_ranker* r, const char* path);
 int tm_ranker_load(const char* path, tm_ranker** out);
 
 /* Search over the batch loaded in plan p, split into nseg instances by seg (host
- * int64[nseg+1], seg[0] = 0, seg[nseg] = n).  For each instance, d_best (device
- * int64[nseg]) receives the index (relative to the instance) of the candidate
- * minimising (bytes, inter_bytes, index) and d_best_cost (device, nullable) its
- * cost.  r == NULL: every candidate is evaluated exactly.  Otherwise the ranker
- * scores every candidate by predicted log2(1 + bytes) + lambda * predicted
- * log2(1 + inter-node bytes) (estimate + residual head), the topk lowest per instance are
- * evaluated exactly on the GPU, and the best of those is returned.  margin > 0 keeps
- * of those only the candidates scoring at most `margin` above the instance's best
- * score (log2 units: 0.05 = predicted costs within ~3.5 %), so fewer are evaluated;
- * margin = 0 keeps all topk; negative: TM_EINVAL.  Everything after the segment
- * upload runs on the device, on `stream`. */
-int tm_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t topk, float lambda,
-              float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, void* stream);
+ * int64[nseg+1], seg[0] = 0, seg[nseg] = n, each at most 2^31 - 1 long).  For each
+ * instance, d_best (device int64[nseg]) receives the index (relative to the
+ * instance) of the candidate minimising (bytes, inter_bytes, index) and d_best_cost
+ * (device, nullable) its cost.  r == NULL: every candidate is evaluated exactly.
+ * Otherwise the ranker scores every candidate by predicted log2(1 + bytes) + lambda
+ * * predicted log2(1 + inter-node bytes) (base + residual head) and:
+ *   prefilter == 0: the topk lowest (score, index) per instance are evaluated
+ *     exactly;
+ *   prefilter in topk..65536: the prefilter lowest per instance are kept, their
+ *     block-model estimates (the owner of every processor-space coordinate, then
+ *     per block boundary the halo cells times the face area where the owners --
+ *     or nodes -- on its two sides differ; crossing fractions times the distinct
+ *     neighbour offsets otherwise) score them as log2(1 + cells) + lambda *
+ *     log2(1 + inter-node cells), and the topk lowest of those are evaluated
+ *     exactly.
+ * The best of the evaluated candidates is returned.  margin > 0 keeps of the last
+ * stage's topk only the candidates scoring at most `margin` above the instance's
+ * best score (log2 units: 0.05 = costs within ~3.5 %), so fewer are evaluated;
+ * margin = 0 keeps all topk; negative, topk outside 1..4096 or another prefilter:
+ * TM_EINVAL.  Everything after the segment upload runs on the device, on `stream`. */
+int tm_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t prefilter, int32_t topk,
+              float lambda, float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, void* stream);
 
 #ifdef __cplusplus
 }

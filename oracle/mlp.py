@@ -145,9 +145,39 @@ def final_shape_and_blocks(c):
     return s, blocks
 
 
-def features(c, halo, chain_table=None):
-    """The 64 ranker features of one candidate (float64); chain_table(c) gives the
-    processor of every final-space coordinate (needed for the node crossings)."""
+def descriptor_estimate(c, halo):
+    """Ghost cells from the shapes alone, assuming every change of the final
+    coordinates projected from a launch dim changes the processor (a bijective
+    chain): along launch dim d the processor changes at l - 1 coordinate boundaries
+    when a final dim of size > 1 is projected onto it cyclically, else at the
+    interior block starts of its block-projected final dims (counted as the sum of
+    their sizes less one each, at most l - 1); each boundary puts 2h cells of every
+    cross-section (the product of the other extents) into the halo.  Exact for
+    bijective chains with one final dim per launch dim and blocks at least h wide."""
+    s, _ = final_shape_and_blocks(c)
+    k = int(c["lrank"])
+    cells = 0.0
+    for d in range(k):
+        l = int(c["extent"][d])
+        nb, cyc = 0, False
+        for j in range(len(s)):
+            if int(c["proj_src"][j]) != d:
+                continue
+            if int(c["proj_mode"][j]) != 0:
+                cyc = cyc or s[j] > 1
+            else:
+                nb += s[j] - 1
+        nb = l - 1 if cyc else min(nb, l - 1)
+        face = 1.0
+        for e in range(k):
+            if e != d:
+                face *= float(c["extent"][e])
+        cells += 2.0 * halo[d] * float(nb) * face
+    return cells
+
+
+def features(c, halo):
+    """The 64 ranker features of one candidate (float64), from its descriptor alone."""
     f = np.zeros(F)
     k = int(c["lrank"])
     f[k - 1] = 1
@@ -191,12 +221,23 @@ def features(c, halo, chain_table=None):
     f[53] = len(s) / 8
     f[58] = math.ceil(math.log2(g)) / 3 if g > 1 else 0.0
     f[59] = 1.0
+    f[23] = math.log2(1 + descriptor_estimate(c, halo)) / 32
+    return f
+
+
+def block_estimates(c, halo, chain_table):
+    """Block-model estimates of a candidate's ghost cells, total and inter-node (the
+    second stage of a ranked search), from chain_table(c), the processor of every
+    final-space coordinate."""
+    k = int(c["lrank"])
+    s, _ = final_shape_and_blocks(c)
+    g = int(c["gpus"])
     # node / processor crossings: per final dim, the fractions of adjacent coordinate
     # pairs whose owners are on different nodes / are different processors (from the
     # oracle's own chain table); block-model estimates of ghost cells from them
     cross_n = [0.0] * len(s)
     cross_p = [0.0] * len(s)
-    if chain_table is not None and int(np.prod(s)) <= 16384:
+    if int(np.prod(s)) <= 16384:
         proc = np.asarray(chain_table(c)).reshape(s)
         node = proc // g
         for j in range(len(s)):
@@ -220,7 +261,7 @@ def features(c, halo, chain_table=None):
     est_t = est_i = 0.0
     proj = [(int(c["proj_src"][j]), int(c["proj_mode"][j])) for j in range(len(s))]
     simple = len(s) == k and sorted(p for p, _ in proj) == list(range(k)) and all(m == 0 for _, m in proj)
-    have = chain_table is not None and int(np.prod(s)) <= 16384
+    have = int(np.prod(s)) <= 16384
     if have and simple:
         def width(a, S, l):
             return -(-(a + 1) * l // S) - (-(-a * l // S))
@@ -272,9 +313,4 @@ def features(c, halo, chain_table=None):
             cells = nb * (pts / l)
             est_t += cells * cp[d]
             est_i += cells * cn[d]
-    f[23] = math.log2(1 + est_t) / 32
-    f[60] = math.log2(1 + est_i) / 32
-    for d in range(3):
-        f[61 + d] = cn[d]
-        f[36 + d] = cp[d]
-    return f
+    return est_t, est_i

@@ -414,6 +414,15 @@ def tm_ranker_features(plan):
     return out[: plan.n]
 
 
+def tm_ranker_block_estimates(plan):
+    """fp64 [n, 2] block-model estimates (ghost cells, inter-node ghost cells) of the
+    batch loaded in `plan` (device tensor)."""
+    import torch
+    out = torch.empty((max(plan.n, 1), 2), dtype=torch.float64, device="cuda")
+    _check(lib().tm_ranker_block_estimates(plan._p, _dev_ptr(out, torch.float64), _stream()))
+    return out[: plan.n]
+
+
 class Ranker:
     """tm_ranker: BF16-MFMA MLP surrogate of the exact cost (see taskmap.h)."""
 
@@ -477,15 +486,17 @@ class Ranker:
             pass
 
 
-def tm_search(plan, ranker, seg, topk=64, lam=0.05, margin=0.0):
+def tm_search(plan, ranker, seg, topk=64, lam=0.05, margin=0.0, prefilter=0):
     """Per instance [seg[s], seg[s+1]) of the batch loaded in `plan`: (best index
     relative to the instance, its cost) as device tensors.  ranker None = exhaustive;
-    margin > 0 re-evaluates only the top-k scoring within `margin` of the best."""
+    prefilter > 0: the network keeps that many per instance and their block-model
+    estimates choose the topk evaluated exactly; margin > 0 re-evaluates only the
+    topk scoring within `margin` of the best."""
     import torch
     sg = np.ascontiguousarray(seg, dtype=np.int64)
     nseg = len(sg) - 1
     best = torch.empty(max(nseg, 1), dtype=torch.int64, device="cuda")
     cost = torch.empty((max(nseg, 1), 4), dtype=torch.int64, device="cuda")
-    _check(lib().tm_search(plan._p, ranker._r if ranker is not None else None, sg.ctypes.data, nseg, topk, lam,
-                           margin, _dev_ptr(best, torch.int64), _dev_ptr(cost, torch.int64), _stream()))
+    _check(lib().tm_search(plan._p, ranker._r if ranker is not None else None, sg.ctypes.data, nseg, prefilter, topk,
+                           lam, margin, _dev_ptr(best, torch.int64), _dev_ptr(cost, torch.int64), _stream()))
     return best[:nseg], cost[:nseg]

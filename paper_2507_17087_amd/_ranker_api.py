@@ -12,12 +12,13 @@ SIGNATURES = {
     "tm_ranker_set_params": [P, P, P],
     "tm_ranker_get_scaling": [P, P],
     "tm_ranker_features": [P, P, P],
+    "tm_ranker_block_estimates": [P, P, P],
     "tm_ranker_forward": [P, P, I64, P, P],
     "tm_ranker_grad": [P, P, P, I64, P, P],
     "tm_ranker_train": [P, P, P, I64, I32, I32, F32, U64, P, P],
     "tm_ranker_save": [P, ctypes.c_char_p],
     "tm_ranker_load": [ctypes.c_char_p, P],
-    "tm_search": [P, P, P, I64, I32, F32, F32, P, P, P],
+    "tm_search": [P, P, P, I64, I32, I32, F32, F32, P, P, P],
 }
 
 

@@ -523,7 +523,7 @@ static void plan_drop_graphs(tm_plan* p) {
 }
 
 static void search_free(SearchBufs& b) {
-    void* ptrs[] = {b.X, b.Y, b.score, b.scratch, b.cross, b.seg, b.sel, b.sub, b.map, b.sub_seg, b.sub_hdr,
+    void* ptrs[] = {b.X, b.Y, b.score, b.pre, b.cross, b.seg, b.sel, b.sub, b.map, b.sub_seg, b.sub_hdr,
                     b.sub_arena, b.sub_counter, b.sub_out, b.sub_best, b.all_out};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -924,46 +924,79 @@ int64_t plan_cells_per_item(const tm_plan* p) {
     return p->cells_per_item > 0 ? p->cells_per_item : default_tuples_per_item(p->cp.tuples);
 }
 
+// Ranker buffers: features and outputs of n rows; scores and chain statistics of
+// max(n, m) entries (m: the second stage's survivors of a ranked search).
+static int ensure_rank_bufs(SearchBufs& b, int64_t n, int64_t m, hipStream_t s) {
+    const int64_t sc = std::max<int64_t>(std::max(n, m), 1);
+    if (b.cap_n < n) {
+        TM_HIP(hipStreamSynchronize(s));
+        if (b.X) (void)hipFree(b.X);
+        if (b.Y) (void)hipFree(b.Y);
+        b.X = nullptr;
+        b.Y = nullptr;
+        b.cap_n = 0;
+        if (hipMalloc((void**)&b.X, (size_t)std::max<int64_t>(n, 1) * kFeat * 2) != hipSuccess ||
+            hipMalloc((void**)&b.Y, (size_t)std::max<int64_t>(n, 1) * kOut * 4) != hipSuccess)
+            return set_error(TM_ENOMEM, "feature buffers");
+        b.cap_n = n;
+    }
+    if (b.cap_sc < sc) {
+        TM_HIP(hipStreamSynchronize(s));
+        if (b.score) (void)hipFree(b.score);
+        if (b.cross) (void)hipFree(b.cross);
+        b.score = b.cross = nullptr;
+        b.cap_sc = 0;
+        if (hipMalloc((void**)&b.score, (size_t)sc * 4) != hipSuccess ||
+            hipMalloc((void**)&b.cross, (size_t)sc * (kCrossFloats + 4) * 4) != hipSuccess)
+            return set_error(TM_ENOMEM, "score buffers");
+        b.cap_sc = sc;
+    }
+    return TM_OK;
+}
+
 int plan_features(const tm_plan* p, float* d_feat, hipStream_t s) {
     if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
     if (!d_feat) return set_error(TM_EINVAL, "null output");
     tm_plan* q = const_cast<tm_plan*>(p);
     SearchBufs& b = q->sb;
     const int64_t n = p->cp.hdr.n;
-    if (b.cap_n < n) {
-        TM_HIP(hipStreamSynchronize(s));
-        if (b.X) (void)hipFree(b.X);
-        b.X = nullptr;
-        b.cap_n = 0;
-        if (b.Y) (void)hipFree(b.Y);
-        if (b.score) (void)hipFree(b.score);
-        if (b.scratch) (void)hipFree(b.scratch);
-        if (b.cross) (void)hipFree(b.cross);
-        b.Y = b.score = b.scratch = b.cross = nullptr;
-        if (hipMalloc((void**)&b.X, (size_t)std::max<int64_t>(n, 1) * kFeat * 2) != hipSuccess ||
-            hipMalloc((void**)&b.Y, (size_t)std::max<int64_t>(n, 1) * kOut * 4) != hipSuccess ||
-            hipMalloc((void**)&b.score, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
-            hipMalloc((void**)&b.scratch, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
-            hipMalloc((void**)&b.cross, (size_t)std::max<int64_t>(n, 1) * (2 * kMaxMrankCross + 4) * 4) != hipSuccess)
-            return set_error(TM_ENOMEM, "feature buffers");
-        b.cap_n = n;
-    }
-    TM_HIP(launch_features(p->d_cands, n, plan_max_vol(p), p->d_hdr->halo, b.cross, b.X, d_feat, s));
+    const int rc = ensure_rank_bufs(b, n, 0, s);
+    if (rc != TM_OK) return rc;
+    TM_HIP(launch_features(p->d_cands, n, p->d_hdr->halo, chain_estimates(b.cross, n), b.X, d_feat, s));
     return TM_OK;
 }
 
-// Uploads the instance segments and sizes the search buffers.
-int plan_search_prepare(tm_plan* p, const int64_t* seg, int64_t nseg, int32_t topk, bool ranked, SearchBufs** out,
-                        hipStream_t s) {
+int plan_block_estimates(const tm_plan* p, double* d_est, hipStream_t s) {
+    if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
+    if (!d_est) return set_error(TM_EINVAL, "null output");
+    tm_plan* q = const_cast<tm_plan*>(p);
+    SearchBufs& b = q->sb;
+    const int64_t n = p->cp.hdr.n;
+    const int rc = ensure_rank_bufs(b, n, 0, s);
+    if (rc != TM_OK) return rc;
+    TM_HIP(launch_chain_stats(p->d_cands, nullptr, n, p->cp.max_vol, p->d_hdr->halo, b.cross, s));
+    if (n > 0)
+        TM_HIP(hipMemcpyAsync(d_est, chain_estimates(b.cross, n), (size_t)n * 2 * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+    return TM_OK;
+}
+
+int plan_search_prepare(tm_plan* p, const int64_t* seg, int64_t nseg, int32_t prefilter, int32_t topk, bool ranked,
+                        SearchBufs** out, hipStream_t s) {
     if (!p || !p->loaded) return set_error(TM_EINVAL, "plan not loaded");
     if (nseg < 1 || !seg) return set_error(TM_EINVAL, "no segments");
     const int64_t n = p->cp.hdr.n;
     if (seg[0] != 0 || seg[nseg] != n) return set_error(TM_EINVAL, "segments must cover the loaded batch");
-    for (int64_t i = 0; i < nseg; ++i)
+    for (int64_t i = 0; i < nseg; ++i) {
         if (seg[i + 1] < seg[i]) return set_error(TM_EINVAL, "segment %lld is not ordered", (long long)i);
+        if (seg[i + 1] - seg[i] > INT32_MAX) return set_error(TM_EINVAL, "segment %lld is too long", (long long)i);
+    }
     if (ranked && (topk < 1 || topk > 4096)) return set_error(TM_EINVAL, "topk %d not in 1..4096", topk);
+    if (ranked && prefilter != 0 && (prefilter < topk || prefilter > 65536))
+        return set_error(TM_EINVAL, "prefilter %d not 0 or in topk..65536", prefilter);
     SearchBufs& b = p->sb;
     const int64_t nsel = ranked ? nseg * (int64_t)topk : 0;
+    const int64_t npre = ranked ? nseg * (int64_t)prefilter : 0;
     // survivors' tables, then their item table
     const int64_t words = nsel * (std::max<int64_t>(p->cp.max_all_words, 1) + p->cp.max_citems) + 4;
     auto grow = [&](bool need) -> int {
@@ -972,24 +1005,16 @@ int plan_search_prepare(tm_plan* p, const int64_t* seg, int64_t nseg, int32_t to
         return TM_OK;
     };
     if (ranked) {
-        if (b.cap_n < n) {
-            int rc = grow(true);
-            if (rc != TM_OK) return rc;
-            if (b.X) (void)hipFree(b.X);
-            if (b.Y) (void)hipFree(b.Y);
-            if (b.score) (void)hipFree(b.score);
-            if (b.scratch) (void)hipFree(b.scratch);
-            if (b.cross) (void)hipFree(b.cross);
-            b.X = nullptr;
-            b.Y = b.score = b.scratch = b.cross = nullptr;
-            b.cap_n = 0;
-            if (hipMalloc((void**)&b.X, (size_t)std::max<int64_t>(n, 1) * kFeat * 2) != hipSuccess ||
-                hipMalloc((void**)&b.Y, (size_t)std::max<int64_t>(n, 1) * kOut * 4) != hipSuccess ||
-                hipMalloc((void**)&b.score, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
-                hipMalloc((void**)&b.scratch, (size_t)std::max<int64_t>(n, 1) * 4) != hipSuccess ||
-                hipMalloc((void**)&b.cross, (size_t)std::max<int64_t>(n, 1) * (2 * kMaxMrankCross + 4) * 4) != hipSuccess)
-                return set_error(TM_ENOMEM, "score buffers");
-            b.cap_n = n;
+        int rc = ensure_rank_bufs(b, n, npre, s);
+        if (rc != TM_OK) return rc;
+        if (b.cap_pre < npre) {
+            TM_HIP(hipStreamSynchronize(s));
+            if (b.pre) (void)hipFree(b.pre);
+            b.pre = nullptr;
+            b.cap_pre = 0;
+            if (hipMalloc((void**)&b.pre, (size_t)npre * 8) != hipSuccess)
+                return set_error(TM_ENOMEM, "prefilter buffer");
+            b.cap_pre = npre;
         }
         if (b.cap_sel < nsel || b.cap_words < words) {
             int rc = grow(true);
@@ -1086,7 +1111,7 @@ int plan_exhaustive_search(tm_plan* p, const int64_t* seg, int64_t nseg, int64_t
                            tm_stencil_cost* d_best_cost, hipStream_t s) {
     if (!d_best) return set_error(TM_EINVAL, "null output");
     SearchBufs* sb = nullptr;
-    int rc = plan_search_prepare(p, seg, nseg, 0, false, &sb, s);
+    int rc = plan_search_prepare(p, seg, nseg, 0, 0, false, &sb, s);
     if (rc == TM_OK) rc = plan_ensure_arena(p, s);
     if (rc != TM_OK) return rc;
     const int grid = count_grid(p->cp.cnt_words, p->cp.items, p->wg_per_cu);

@@ -27,10 +27,12 @@ struct Compiled {
 
 // Device buffers of a search over a loaded plan (grown on demand).
 struct SearchBufs {
-    int64_t cap_n = 0, cap_sel = 0, cap_seg = 0, cap_words = 0, cap_all = 0;
+    int64_t cap_n = 0, cap_sc = 0, cap_pre = 0, cap_sel = 0, cap_seg = 0, cap_words = 0, cap_all = 0;
     uint16_t* X = nullptr;          // [n][kFeat] bf16 features
-    float *Y = nullptr, *score = nullptr, *scratch = nullptr;
-    float* cross = nullptr;         // [n][16] crossing fractions, then [n][2] fp64 block-model estimates
+    float* Y = nullptr;             // [n][kOut] network outputs
+    float* score = nullptr;         // [cap_sc] ranking scores (both stages)
+    float* cross = nullptr;         // [cap_sc][16] crossing fractions, then [cap_sc][2] fp64 estimates
+    int64_t* pre = nullptr;         // [nseg*prefilter] candidates kept by the network's scores
     int64_t* seg = nullptr;         // [nseg+1] instance segments
     int64_t* sel = nullptr;         // [nseg*k] chosen candidate indices
     DevCand* sub = nullptr;         // [nseg*k] survivors
@@ -92,8 +94,9 @@ const int32_t* plan_halo(const tm_plan* p);
 const DevHeader* plan_hdr(const tm_plan* p);
 int64_t plan_cells_per_item(const tm_plan* p);
 int plan_features(const tm_plan* p, float* d_feat, hipStream_t s);
-int plan_search_prepare(tm_plan* p, const int64_t* seg, int64_t nseg, int32_t topk, bool ranked, SearchBufs** out,
-                        hipStream_t s);
+int plan_block_estimates(const tm_plan* p, double* d_est, hipStream_t s);
+int plan_search_prepare(tm_plan* p, const int64_t* seg, int64_t nseg, int32_t prefilter, int32_t topk, bool ranked,
+                        SearchBufs** out, hipStream_t s);
 hipError_t plan_eval_sub(tm_plan* p, SearchBufs* sb, hipStream_t s);
 int plan_exhaustive_search(tm_plan* p, const int64_t* seg, int64_t nseg, int64_t* d_best,
                            tm_stencil_cost* d_best_cost, hipStream_t s);

@@ -72,10 +72,11 @@ struct RankerBuffers {
 };
 
 constexpr int kMaxMrankCross = 8;  // node-crossing fractions kept per candidate
-// The block-model estimates (ghost cells, inter-node ghost cells) enter the features
-// as log2(1 + est) / kBaseScale at kBaseFeat[h]; the network learns the residual of
-// log2(1 + exact bytes) over kBaseScale * feature, so the estimate keeps its fp32
-// precision instead of passing through bf16.
+// The descriptor estimate of the ghost cells enters the features as
+// log2(1 + est) / kBaseScale at kBaseFeat[0] (feature kBaseFeat[1], the inter-node
+// head's base, is 0); the network learns the residual of log2(1 + exact bytes) over
+// kBaseScale * feature, so the estimate keeps its fp32 precision instead of passing
+// through bf16.
 constexpr int kBaseFeat[kOut] = {23, 60};
 constexpr float kBaseScale = 32.f;
 // Per-candidate chain statistics: 2 * kMaxMrankCross floats, then 2 doubles (estimates).
@@ -84,9 +85,15 @@ inline double* chain_estimates(float* cross, int64_t n) {
     return reinterpret_cast<double*>(cross + n * kCrossFloats);  // 64n bytes in: 8-byte aligned
 }
 
-hipError_t launch_features(const DevCand* cands, int64_t n, int32_t max_vol, const int32_t* d_halo, float* cross,
-                           uint16_t* X,
+// Features of n candidates: bf16 rows X, fp32 copies f32 (nullable), and the
+// descriptor estimate est[2i] (est[2i+1] = 0).
+hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_halo, double* est, uint16_t* X,
                            float* f32, hipStream_t s);
+// Chain statistics and block-model estimates of entries 0..n-1: candidate idx[i]
+// (negative: skipped) or i without idx; outputs at entry i of cross and
+// chain_estimates(cross, n).
+hipError_t launch_chain_stats(const DevCand* cands, const int64_t* idx, int64_t n, int32_t max_vol,
+                              const int32_t* d_halo, float* cross, hipStream_t s);
 hipError_t launch_mlp_forward(const uint16_t* X, int64_t n, const RankerWeights& W, float* Y, uint16_t* H1,
                               uint16_t* H2, uint16_t* H3, hipStream_t s);
 hipError_t launch_backward(const RankerBuffers& B, const RankerWeights& W, int64_t n, float s0, float s1,
@@ -94,8 +101,13 @@ hipError_t launch_backward(const RankerBuffers& B, const RankerWeights& W, int64
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t count, float lr, float b1, float b2,
                        float eps, int64_t t, const RankerWeights& W, hipStream_t s);
 hipError_t launch_publish(const float* p, int64_t count, const RankerWeights& W, hipStream_t s);
-hipError_t launch_topk(const float* score, const int64_t* seg, int64_t nseg, int k, float margin, float* scratch,
-                       int64_t* sel, hipStream_t s);
+// The k smallest (score, index) entries of each segment (k_select): sel[s*k ..)
+// in index order, -1 after; stride > 0 takes segment s as the first
+// min(stride, seg[s+1] - seg[s]) entries from s * stride; remap (nullable) maps an
+// entry to the index written.
+hipError_t launch_select(const float* score, const int64_t* seg, int64_t nseg, int64_t stride, int k, float margin,
+                         const int64_t* remap, int64_t* sel, hipStream_t s);
+// Scores from the heads Y (nullable: the estimates alone) and the estimates est.
 hipError_t launch_combine(const float* Y, const double* est, int64_t n, const float* mu, const float* sigma,
                           float lambda, float* s, hipStream_t st);
 hipError_t launch_gather(const DevCand* cands, const int64_t* sel, int64_t nsel, int k, int64_t cells_per_item,

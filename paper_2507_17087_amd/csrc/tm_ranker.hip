@@ -36,7 +36,7 @@ __device__ __forceinline__ f32x4 mfma16(u16x8 a, u16x8 b, f32x4 c) {
 
 __device__ __forceinline__ float lg2(double x) { return (float)log2(x); }
 
-// Per-candidate chain statistics for the ranker features:
+// Per-candidate chain statistics (the second stage of a ranked search):
 //   cross[0..8)   per final dim j: fraction of adjacent coordinate pairs (a, a+e_j)
 //                 whose owners sit on different nodes;
 //   cross[8..16)  the same for different processors;
@@ -104,7 +104,8 @@ __device__ __forceinline__ void boundary_terms(int32_t v, const int32_t (&a)[kMa
     }
 }
 
-__global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__ cands, int64_t n,
+__global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__ cands,
+                                                     const int64_t* __restrict__ idx, int64_t n,
                                                      const int32_t* __restrict__ halo, float* __restrict__ cross,
                                                      double* __restrict__ est, int32_t vmin, int32_t vmax,
                                                      int32_t vcap) {
@@ -125,13 +126,16 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
     __shared__ float s_cross[2 * kMaxMrankCross];  // this candidate's crossing fractions
     __shared__ float s_rt[kRecipSlots];             // reciprocals of the inverse chain's divisors
     const int nw = blockDim.x >> 6;
-    for (int64_t ci = blockIdx.x; ci < n; ci += gridDim.x) {
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        // entry i: candidate idx[i] (skipped when negative), or i without idx
+        const int64_t ci = idx ? wave_uniform64(idx[i]) : i;
+        if (ci < 0) continue;
         // this launch takes the candidates of volume in (vmin, vmax]; the one whose
         // vmax is kCrossMax also writes the zeros of those above it
         const int32_t v0 = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)cands[ci].vol);
         if (v0 > kCrossMax && vmax == kCrossMax) {
-            if (threadIdx.x < 2 * kMaxMrankCross) cross[ci * 2 * kMaxMrankCross + threadIdx.x] = 0.f;
-            if (threadIdx.x < 2) est[ci * 2 + threadIdx.x] = 0.0;
+            if (threadIdx.x < 2 * kMaxMrankCross) cross[i * 2 * kMaxMrankCross + threadIdx.x] = 0.f;
+            if (threadIdx.x < 2) est[i * 2 + threadIdx.x] = 0.0;
             continue;
         }
         if (v0 <= vmin || v0 > vmax) continue;
@@ -268,8 +272,8 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
                 fn = (float)dn * inv;
                 fp = (float)dp * inv;
             }
-            cross[ci * 2 * kMaxMrankCross + j] = fn;
-            cross[ci * 2 * kMaxMrankCross + kMaxMrankCross + j] = fp;
+            cross[i * 2 * kMaxMrankCross + j] = fn;
+            cross[i * 2 * kMaxMrankCross + kMaxMrankCross + j] = fp;
             s_cross[j] = fn;
             s_cross[kMaxMrankCross + j] = fp;
         }
@@ -330,16 +334,49 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
         if (threadIdx.x < 2) {
             double e = 0;
             for (int w = 0; w < nwv; ++w) e += dred[w][threadIdx.x];
-            est[ci * 2 + threadIdx.x] = e;
+            est[i * 2 + threadIdx.x] = e;
         }
     }
 }
 
-// One thread per candidate; writes kFeat bf16 values (row of X) and, when
-// feat_f32 is given, the same values in fp32.
+// Descriptor estimate of the ghost cells, from the shapes alone: if every change of
+// the final coordinates projected from a launch dim changes the processor (a
+// bijective chain), the processor changes along launch dim d at l - 1 coordinate
+// boundaries when a final dim of size > 1 is projected onto it cyclically, and
+// otherwise at the interior block starts of its block-projected final dims (at most
+// the sum of their sizes less one each, and at most l - 1); every boundary puts 2h
+// cells of each cross-section into the halo.  Exact for bijective chains with one
+// final dim per launch dim whose blocks are at least h wide.
+__device__ __forceinline__ double descriptor_estimate(const DevCand& c, const int32_t* __restrict__ halo) {
+    const int k = c.lrank, fr = c.frank;
+    double cells = 0;
+#pragma unroll
+    for (int d = 0; d < TM_MAX_LRANK; ++d) {
+        if (d >= k) continue;
+        const int64_t l = c.extent[d];
+        int64_t nb = 0;
+        bool cyc = false;
+#pragma unroll
+        for (int j = 0; j < TM_MAX_MRANK; ++j) {
+            if (j >= fr || c.proj_src[j] != d) continue;
+            if (c.proj_mode[j] != TM_BLOCK) cyc = cyc || c.fshape[j] > 1;
+            else nb += c.fshape[j] - 1;
+        }
+        nb = cyc ? l - 1 : (nb < l - 1 ? nb : l - 1);
+        double face = 1;
+#pragma unroll
+        for (int e = 0; e < TM_MAX_LRANK; ++e)
+            if (e < k && e != d) face *= (double)c.extent[e];
+        cells += 2.0 * halo[d] * (double)nb * face;
+    }
+    return cells;
+}
+
+// One thread per candidate; writes kFeat bf16 values (row of X), the descriptor
+// estimate (est[2i]; est[2i+1] = 0: no inter-node base) and, when feat_f32 is
+// given, the features in fp32.
 __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ cands, int64_t n,
-                                                  const int32_t* __restrict__ halo,
-                                                  const float* __restrict__ cross, const double* __restrict__ est,
+                                                  const int32_t* __restrict__ halo, double* __restrict__ est,
                                                   uint16_t* __restrict__ X, float* __restrict__ feat_f32) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -414,29 +451,12 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
     f[53] = fr / 8.f;
     f[58] = c.gbits / 3.f;
     f[59] = 1.f;
-    // node / processor crossings per launch dim (largest over the final dims it
-    // projects onto) and block-model estimates of the ghost cells, total and
-    // inter-node, in the log space of the targets
-    float cn[TM_MAX_LRANK] = {0.f, 0.f, 0.f, 0.f}, cp[TM_MAX_LRANK] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int j = 0; j < kMaxMrankCross; ++j) {
-        if (j < fr) {
-            const int src = c.proj_src[j];
-            const float xn = cross[i * 2 * kMaxMrankCross + j];
-            const float xp = cross[i * 2 * kMaxMrankCross + kMaxMrankCross + j];
-#pragma unroll
-            for (int d = 0; d < TM_MAX_LRANK; ++d) {
-                cn[d] = src == d ? fmaxf(cn[d], xn) : cn[d];
-                cp[d] = src == d ? fmaxf(cp[d], xp) : cp[d];
-            }
-        }
-    }
-    f[kBaseFeat[0]] = lg2(1.0 + est[i * 2]) / kBaseScale;
-    f[kBaseFeat[1]] = lg2(1.0 + est[i * 2 + 1]) / kBaseScale;
-    for (int d = 0; d < 3; ++d) {
-        f[61 + d] = cn[d];
-        f[36 + d] = cp[d];
-    }
+    // the descriptor estimate of the ghost cells in the log space of the target (the
+    // inter-node head has no base: feature kBaseFeat[1] stays 0)
+    const double e0 = descriptor_estimate(c, halo);
+    est[i * 2] = e0;
+    est[i * 2 + 1] = 0.0;
+    f[kBaseFeat[0]] = lg2(1.0 + e0) / kBaseScale;
     uint16_t* row = X + i * kFeat;
 #pragma unroll
     for (int t = 0; t < kFeat; ++t) {
@@ -785,74 +805,149 @@ __global__ __launch_bounds__(256) void k_publish(const float* __restrict__ p, in
     publish_param(i, p[i], W);
 }
 
-// ------------------------------------------------------------------ top-k per segment
+// ------------------------------------------------------------------ k smallest per segment
 //
-// One workgroup per segment: k rounds of a block-wide argmin over (score, index),
-// the winner marked taken (NaN) in the scratch copy.  Output: global candidate
-// indices, ascending by (score, index); -1 past the end of a shorter segment.
+// One workgroup per segment chooses its k smallest (score, index) pairs by a radix
+// select over the scores' order-preserving 32-bit keys: three passes of 11, 11 and
+// 10 bits, each a histogram in LDS of the keys that share the digits found so far,
+// give the k-th smallest key T and how many of the k equal it; one pass in index
+// order then takes every key below T and the lowest-indexed keys equal to T.  The
+// chosen entries are written in index order, then -1 up to k.  Segment s is
+// [seg[s], seg[s+1]), or with stride > 0 the first min(stride, seg[s+1] - seg[s])
+// entries from s * stride.  margin > 0 keeps of the chosen only those scoring at
+// most `margin` above the segment's best.  remap (nullable) gives the index written
+// for entry e (else e).  Scores are finite or +inf.
 
-__global__ __launch_bounds__(256) void k_topk(const float* __restrict__ score, const int64_t* __restrict__ seg,
-                                              int k, float margin, float* __restrict__ scratch,
-                                              int64_t* __restrict__ sel) {
-    __shared__ float sv[256];
-    __shared__ int64_t si[256];
-    const int64_t a = seg[blockIdx.x], e = seg[blockIdx.x + 1];
-    for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) scratch[i] = score[i];
+__device__ __forceinline__ uint32_t order_key(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+constexpr int kSelThreads = 256;
+constexpr int kSelBins = 2048;  // 8 per thread
+
+__global__ __launch_bounds__(kSelThreads) void k_select(const float* __restrict__ score,
+                                                        const int64_t* __restrict__ seg, int64_t stride, int k,
+                                                        float margin, const int64_t* __restrict__ remap,
+                                                        int64_t* __restrict__ sel) {
+    __shared__ uint32_t hist[kSelBins];
+    __shared__ uint32_t wa[kSelThreads / 64], wb[kSelThreads / 64];
+    __shared__ float wmin[kSelThreads / 64];
+    __shared__ uint32_t s_bin, s_below;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int nwv = kSelThreads / 64;
+    const int64_t s = blockIdx.x;
+    const int64_t len_s = seg[s + 1] - seg[s];
+    const int64_t a = stride > 0 ? s * stride : seg[s];
+    const uint32_t len = (uint32_t)(stride > 0 ? (len_s < stride ? len_s : stride) : len_s);
+    int64_t* out = sel + s * (int64_t)k;
+    const uint64_t lt_mask = (1ull << lane) - 1;
+    // the segment's best score (the margin's reference)
+    float best = INFINITY;
+    for (uint32_t i = tid; i < len; i += kSelThreads) best = fminf(best, score[a + i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) best = fminf(best, __shfl_xor(best, o, 64));
+    if (lane == 0) wmin[wv] = best;
     __syncthreads();
-    const float taken = __builtin_nanf("");  // never wins a comparison
-    float best = 0.f;
-    for (int round = 0; round < k; ++round) {
-        float bv = INFINITY;
-        int64_t bi = INT64_MAX;
-        for (int64_t i = a + threadIdx.x; i < e; i += blockDim.x) {
-            const float s = scratch[i];
-            if (s < bv || (s == bv && i < bi)) {
-                bv = s;
-                bi = i;
-            }
-        }
-        sv[threadIdx.x] = bv;
-        si[threadIdx.x] = bi;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) {
-                const float ov = sv[threadIdx.x + w];
-                const int64_t oi = si[threadIdx.x + w];
-                if (ov < sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
-                    sv[threadIdx.x] = ov;
-                    si[threadIdx.x] = oi;
-                }
+#pragma unroll
+    for (int w = 0; w < nwv; ++w) best = fminf(best, wmin[w]);
+    // the k-th smallest key T; rem = how many of the chosen have key T
+    const bool all = len <= (uint32_t)k;
+    uint32_t prefix = 0, pmask = 0, rem = all ? len : (uint32_t)k;
+    if (!all) {
+        for (int pass = 0; pass < 3; ++pass) {
+            const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
+            const uint32_t dmask = pass == 2 ? 0x3ffu : 0x7ffu;
+            for (int b = tid; b < kSelBins; b += kSelThreads) hist[b] = 0;
+            __syncthreads();
+            for (uint32_t i = tid; i < len; i += kSelThreads) {
+                const uint32_t kk = order_key(score[a + i]);
+                if ((kk & pmask) == prefix) atomicAdd(&hist[(kk >> shift) & dmask], 1u);
             }
             __syncthreads();
+            uint32_t c[8], tsum = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                c[q] = hist[tid * 8 + q];
+                tsum += c[q];
+            }
+            uint32_t incl = tsum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t u = __shfl_up(incl, o, 64);
+                incl += lane >= o ? u : 0u;
+            }
+            if (lane == 63) wa[wv] = incl;
+            __syncthreads();
+            uint32_t run = incl - tsum;
+            for (int w = 0; w < wv; ++w) run += wa[w];
+            // exactly one bin has run < rem <= run + count
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (run < rem && run + c[q] >= rem) {
+                    s_bin = (uint32_t)(tid * 8 + q);
+                    s_below = run;
+                }
+                run += c[q];
+            }
+            __syncthreads();
+            prefix |= s_bin << shift;
+            pmask |= dmask << shift;
+            rem -= s_below;
+            __syncthreads();  // s_bin, s_below and hist are rewritten by the next pass
         }
-        const int64_t win = si[0];
-        const float wv = sv[0];
-        __syncthreads();
-        if (round == 0) best = wv;
-        // segment exhausted, or (margin > 0) the next pick scores more than `margin`
-        // above the segment's best: the remaining slots stay empty
-        if (win == INT64_MAX || (margin > 0.f && round > 0 && wv > best + margin)) {
-            for (int rr = round + threadIdx.x; rr < k; rr += blockDim.x) sel[blockIdx.x * (int64_t)k + rr] = -1;
-            break;
-        }
-        if (threadIdx.x == 0) {
-            sel[blockIdx.x * (int64_t)k + round] = win;
-            scratch[win] = taken;
-        }
-        __syncthreads();
     }
+    // in index order: keys below T, then the first rem keys equal to T
+    const uint32_t T = prefix;
+    uint32_t seen_eq = 0, written = 0;
+    for (uint32_t i0 = 0; i0 < len; i0 += kSelThreads) {
+        const uint32_t i = i0 + tid;
+        bool in = false, eq = false;
+        float sv = INFINITY;
+        if (i < len) {
+            sv = score[a + i];
+            const uint32_t kk = order_key(sv);
+            in = all || kk < T;
+            eq = !all && kk == T;
+        }
+        const uint64_t beq = __ballot(eq);
+        if (lane == 0) wa[wv] = (uint32_t)__popcll(beq);
+        __syncthreads();
+        uint32_t eq_rank = (uint32_t)__popcll(beq & lt_mask), chunk_eq = 0;
+#pragma unroll
+        for (int w = 0; w < nwv; ++w) {
+            eq_rank += w < wv ? wa[w] : 0u;
+            chunk_eq += wa[w];
+        }
+        const bool take = (in || (eq && seen_eq + eq_rank < rem)) && (margin <= 0.f || sv <= best + margin);
+        const uint64_t bt = __ballot(take);
+        if (lane == 0) wb[wv] = (uint32_t)__popcll(bt);
+        __syncthreads();
+        uint32_t pos = (uint32_t)__popcll(bt & lt_mask), chunk_t = 0;
+#pragma unroll
+        for (int w = 0; w < nwv; ++w) {
+            pos += w < wv ? wb[w] : 0u;
+            chunk_t += wb[w];
+        }
+        if (take && written + pos < (uint32_t)k) out[written + pos] = remap ? remap[a + i] : a + i;
+        written += chunk_t;
+        seen_eq += chunk_eq;
+        __syncthreads();  // wa, wb are rewritten by the next chunk
+    }
+    for (int64_t r = (int64_t)written + tid; r < k; r += kSelThreads) out[r] = -1;
 }
 
 // Ranking score: predicted log2(1 + bytes) + lambda * predicted log2(1 + inter-node
 // bytes), each = estimate base (the same fp32 value training used) + un-standardised
-// residual head; +inf when that is not finite.
+// residual head; without Y the estimates alone; +inf when that is not finite.
 __global__ void k_combine(const float* __restrict__ Y, const double* __restrict__ est, int64_t n, float mu0,
                           float s0, float mu1, float s1, float lambda, float* __restrict__ s) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float b0 = kBaseScale * (lg2(1.0 + est[i * 2]) / kBaseScale);
     const float b1 = kBaseScale * (lg2(1.0 + est[i * 2 + 1]) / kBaseScale);
-    const float v = (b0 + mu0 + s0 * Y[i * kOut]) + lambda * (b1 + mu1 + s1 * Y[i * kOut + 1]);
+    const float p0 = Y ? b0 + mu0 + s0 * Y[i * kOut] : b0, p1 = Y ? b1 + mu1 + s1 * Y[i * kOut + 1] : b1;
+    const float v = p0 + lambda * p1;
     // a non-finite score (diverged or corrupt parameters) ranks last, by index, so
     // such candidates stay selectable and every instance keeps its survivors
     s[i] = __builtin_isfinite(v) ? v : INFINITY;
@@ -990,14 +1085,21 @@ __global__ void k_pick_costs(const int64_t* __restrict__ best, const int64_t* __
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_features(const DevCand* cands, int64_t n, int32_t max_vol, const int32_t* d_halo, float* cross,
-                           uint16_t* X, float* f32, hipStream_t s) {
+hipError_t launch_features(const DevCand* cands, int64_t n, const int32_t* d_halo, double* est, uint16_t* X,
+                           float* f32, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cands, n, d_halo, est, X, f32);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_stats(const DevCand* cands, const int64_t* idx, int64_t n, int32_t max_vol,
+                              const int32_t* d_halo, float* cross, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t g = n < 65536 ? n : 65536;
     double* est = chain_estimates(cross, n);
     // the owner table of a candidate lives in LDS: most candidates are small, so a
     // first launch with a small table (more workgroups per CU) takes the volumes up to
-    // kStatsSmallVol, and a second one, sized for the batch's largest, the rest
+    // kStatsSmallVol, and a second one, sized for the batch's largest, the rest;
     // large batches of small candidates: one-wave workgroups, four times as many
     // candidates in flight per CU (each candidate's work is a few hundred keys)
     const int bs = n >= kSmallBlockBatch ? 64 : 256;
@@ -1008,16 +1110,14 @@ hipError_t launch_features(const DevCand* cands, int64_t n, int32_t max_vol, con
         return (size_t)(((vcap + 3) & ~3) + std::max(2 * tcap, kStatsStage)) * 4;
     };
     if (vtop <= kStatsSmallVol) {
-        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(bs), lds_bytes(vtop), s, cands, n, d_halo, cross,
-                           est, 0, kCrossMax, vtop);
+        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(bs), lds_bytes(vtop), s, cands, idx, n, d_halo,
+                           cross, est, 0, kCrossMax, vtop);
     } else {
-        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(bs), lds_bytes(kStatsSmallVol), s, cands, n,
+        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(bs), lds_bytes(kStatsSmallVol), s, cands, idx, n,
                            d_halo, cross, est, 0, kStatsSmallVol, kStatsSmallVol);
-        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(bs), lds_bytes(vtop), s, cands, n, d_halo, cross,
-                           est, kStatsSmallVol, kCrossMax, vtop);
+        hipLaunchKernelGGL(k_chain_stats, dim3((unsigned)g), dim3(bs), lds_bytes(vtop), s, cands, idx, n, d_halo,
+                           cross, est, kStatsSmallVol, kCrossMax, vtop);
     }
-    hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cands, n, d_halo, cross, est,
-                       X, f32);
     return hipGetLastError();
 }
 
@@ -1078,10 +1178,11 @@ hipError_t launch_publish(const float* p, int64_t count, const RankerWeights& W,
     return hipGetLastError();
 }
 
-hipError_t launch_topk(const float* score, const int64_t* seg, int64_t nseg, int k, float margin, float* scratch,
-                       int64_t* sel, hipStream_t s) {
+hipError_t launch_select(const float* score, const int64_t* seg, int64_t nseg, int64_t stride, int k, float margin,
+                         const int64_t* remap, int64_t* sel, hipStream_t s) {
     if (nseg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_topk, dim3((unsigned)nseg), dim3(256), 0, s, score, seg, k, margin, scratch, sel);
+    hipLaunchKernelGGL(k_select, dim3((unsigned)nseg), dim3(kSelThreads), 0, s, score, seg, stride, k, margin, remap,
+                       sel);
     return hipGetLastError();
 }
 

@@ -442,8 +442,8 @@ int tm_ranker_load(const char* path, tm_ranker** out) {
 
 namespace tmk {
 
-int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t topk, float lambda,
-                       float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, hipStream_t s);
+int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t prefilter, int32_t topk,
+                       float lambda, float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, hipStream_t s);
 
 }  // namespace tmk
 
@@ -451,28 +451,46 @@ extern "C" int tm_ranker_features(const tm_plan* p, float* d_feat, void* stream)
     return tmk::plan_features(p, d_feat, (hipStream_t)stream);
 }
 
-extern "C" int tm_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t topk, float lambda,
-                         float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, void* stream) {
+extern "C" int tm_ranker_block_estimates(const tm_plan* p, double* d_est, void* stream) {
+    return tmk::plan_block_estimates(p, d_est, (hipStream_t)stream);
+}
+
+extern "C" int tm_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t prefilter, int32_t topk,
+                         float lambda, float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, void* stream) {
     if (!r) return tmk::plan_exhaustive_search(p, seg, nseg, d_best, d_best_cost, (hipStream_t)stream);
     if (!(margin >= 0.f)) return tmk::set_error(TM_EINVAL, "margin must be >= 0");
-    return tmk::plan_ranked_search(p, r, seg, nseg, topk, lambda, margin, d_best, d_best_cost, (hipStream_t)stream);
+    return tmk::plan_ranked_search(p, r, seg, nseg, prefilter, topk, lambda, margin, d_best, d_best_cost,
+                                   (hipStream_t)stream);
 }
 
 namespace tmk {
 
-int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t topk, float lambda,
-                       float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, hipStream_t s) {
+int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nseg, int32_t prefilter, int32_t topk,
+                       float lambda, float margin, int64_t* d_best, tm_stencil_cost* d_best_cost, hipStream_t s) {
+    if (!d_best) return set_error(TM_EINVAL, "null output");
     SearchBufs* sb = nullptr;
-    int rc = plan_search_prepare(p, seg, nseg, topk, true, &sb, s);
+    int rc = plan_search_prepare(p, seg, nseg, prefilter, topk, true, &sb, s);
     if (rc != TM_OK) return rc;
     const int64_t n = plan_size(p);
     const int64_t nsel = nseg * topk;
-    // scores of every candidate
-    hipError_t e = launch_features(plan_cands(p), n, plan_max_vol(p), plan_halo(p), sb->cross, sb->X, nullptr, s);
+    // the network's score of every candidate: descriptor features, forward, residuals
+    // over the descriptor estimate
+    hipError_t e = launch_features(plan_cands(p), n, plan_halo(p), chain_estimates(sb->cross, n), sb->X, nullptr, s);
     if (e == hipSuccess) e = launch_mlp_forward(sb->X, n, r->W, sb->Y, nullptr, nullptr, nullptr, s);
     if (e == hipSuccess) e = launch_combine(sb->Y, chain_estimates(sb->cross, n), n, r->mu, r->sigma, lambda, sb->score, s);
-    // top-k per instance, then the survivors' exact costs
-    if (e == hipSuccess) e = launch_topk(sb->score, sb->seg, nseg, topk, margin, sb->scratch, sb->sel, s);
+    if (prefilter > 0) {
+        // the network keeps `prefilter` per instance; their block-model estimates (chain
+        // statistics) choose the topk
+        const int64_t m = nseg * (int64_t)prefilter;
+        if (e == hipSuccess) e = launch_select(sb->score, sb->seg, nseg, 0, prefilter, 0.f, nullptr, sb->pre, s);
+        if (e == hipSuccess) e = launch_chain_stats(plan_cands(p), sb->pre, m, plan_max_vol(p), plan_halo(p), sb->cross, s);
+        if (e == hipSuccess)
+            e = launch_combine(nullptr, chain_estimates(sb->cross, m), m, r->mu, r->sigma, lambda, sb->score, s);
+        if (e == hipSuccess) e = launch_select(sb->score, sb->seg, nseg, prefilter, topk, margin, sb->pre, sb->sel, s);
+    } else if (e == hipSuccess) {
+        e = launch_select(sb->score, sb->seg, nseg, 0, topk, margin, nullptr, sb->sel, s);
+    }
+    // the survivors' exact costs
     if (e == hipSuccess)
         e = launch_gather(plan_cands(p), sb->sel, nsel, topk, plan_cells_per_item(p), sb->sub, sb->map, sb->sub_seg,
                           sb->sub_hdr, plan_hdr(p), s);
