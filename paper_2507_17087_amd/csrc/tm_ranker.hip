@@ -339,6 +339,78 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
     }
 }
 
+// The descriptor fields the features read, fetched with 16-byte loads: each group
+// below starts at a 16-byte aligned offset of DevCand (checked here), so a thread
+// issues 15 vector loads per candidate instead of one load per field.
+static_assert(offsetof(DevCand, lrank) == 0 && offsetof(DevCand, nops) == 4 && offsetof(DevCand, nodes) == 8 &&
+                  offsetof(DevCand, gpus) == 12 && offsetof(DevCand, gbits) == 16 && offsetof(DevCand, frank) == 20,
+              "descriptor header");
+static_assert(offsetof(DevCand, extent) == 32, "extents");
+static_assert(offsetof(DevCand, fshape) % 16 == 0 && TM_MAX_MRANK == 8, "final shape");
+static_assert(offsetof(DevCand, proj_mode) == offsetof(DevCand, proj_src) + 8 && offsetof(DevCand, proj_src) % 16 == 0,
+              "projections");
+static_assert(offsetof(DevCand, op_kind) % 16 == 0 && offsetof(DevCand, op_a) % 16 == 0 &&
+                  offsetof(DevCand, op_b) % 16 == 0 && offsetof(DevCand, op_nf) % 16 == 0 &&
+                  offsetof(DevCand, op_f) % 16 == 0 && TM_MAX_OPS == 8 && TM_MAX_LRANK == 4,
+              "ops");
+
+struct FeatDesc {
+    int k, nops, nodes, gpus, gbits, fr;
+    int64_t ext[TM_MAX_LRANK];
+    int32_t fsh[TM_MAX_MRANK];
+    int32_t psrc[TM_MAX_MRANK], pmode[TM_MAX_MRANK];
+    int32_t kind[TM_MAX_OPS], opa[4], opb[TM_MAX_OPS];
+    int tdec, nf;
+    int32_t F[TM_MAX_LRANK];  // the factors of the first decompose (1 past nf)
+};
+
+__device__ __forceinline__ FeatDesc load_feat_desc(const DevCand* c) {
+    const int4* q = reinterpret_cast<const int4*>(c);
+    auto at = [&](size_t off) { return q[off / 16]; };
+    FeatDesc d;
+    const int4 h0 = at(0), h1 = at(16);
+    d.k = h0.x, d.nops = h0.y, d.nodes = h0.z, d.gpus = h0.w, d.gbits = h1.x, d.fr = h1.y;
+    const int4 e0 = at(32), e1 = at(48);
+    d.ext[0] = (int64_t)(((uint64_t)(uint32_t)e0.y << 32) | (uint32_t)e0.x);
+    d.ext[1] = (int64_t)(((uint64_t)(uint32_t)e0.w << 32) | (uint32_t)e0.z);
+    d.ext[2] = (int64_t)(((uint64_t)(uint32_t)e1.y << 32) | (uint32_t)e1.x);
+    d.ext[3] = (int64_t)(((uint64_t)(uint32_t)e1.w << 32) | (uint32_t)e1.z);
+    const int4 f0 = at(offsetof(DevCand, fshape)), f1 = at(offsetof(DevCand, fshape) + 16);
+    const int32_t fs[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+    const int4 pj = at(offsetof(DevCand, proj_src));
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        d.fsh[j] = fs[j];
+        d.psrc[j] = (int32_t)(int8_t)(((j < 4 ? pj.x : pj.y) >> (8 * (j & 3))) & 0xff);
+        d.pmode[j] = (int32_t)(int8_t)(((j < 4 ? pj.z : pj.w) >> (8 * (j & 3))) & 0xff);
+    }
+    const int4 k0 = at(offsetof(DevCand, op_kind)), k1 = at(offsetof(DevCand, op_kind) + 16);
+    const int4 b0 = at(offsetof(DevCand, op_b)), b1 = at(offsetof(DevCand, op_b) + 16);
+    const int4 n0 = at(offsetof(DevCand, op_nf)), n1 = at(offsetof(DevCand, op_nf) + 16);
+    const int4 a0 = at(offsetof(DevCand, op_a));
+    const int32_t kk[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+    const int32_t bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+    const int32_t nn[8] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+    d.opa[0] = a0.x, d.opa[1] = a0.y, d.opa[2] = a0.z, d.opa[3] = a0.w;
+    d.tdec = -1;
+    d.nf = 0;
+#pragma unroll
+    for (int t = TM_MAX_OPS - 1; t >= 0; --t) {
+        d.kind[t] = kk[t];
+        d.opb[t] = bb[t];
+        if (t < d.nops && kk[t] == TM_DECOMPOSE) {
+            d.tdec = t;
+            d.nf = nn[t];
+        }
+    }
+    const int4 fv = q[(offsetof(DevCand, op_f) + 16 * (d.tdec >= 0 ? d.tdec : 0)) / 16];
+    d.F[0] = 0 < d.nf ? fv.x : 1;
+    d.F[1] = 1 < d.nf ? fv.y : 1;
+    d.F[2] = 2 < d.nf ? fv.z : 1;
+    d.F[3] = 3 < d.nf ? fv.w : 1;
+    return d;
+}
+
 // Descriptor estimate of the ghost cells, from the shapes alone: if every change of
 // the final coordinates projected from a launch dim changes the processor (a
 // bijective chain), the processor changes along launch dim d at l - 1 coordinate
@@ -347,47 +419,50 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
 // the sum of their sizes less one each, and at most l - 1); every boundary puts 2h
 // cells of each cross-section into the halo.  Exact for bijective chains with one
 // final dim per launch dim whose blocks are at least h wide.
-__device__ __forceinline__ double descriptor_estimate(const DevCand& c, const int32_t* __restrict__ halo) {
-    const int k = c.lrank, fr = c.frank;
+__device__ __forceinline__ double descriptor_estimate(const FeatDesc& c, const int32_t* __restrict__ halo) {
     double cells = 0;
 #pragma unroll
     for (int d = 0; d < TM_MAX_LRANK; ++d) {
-        if (d >= k) continue;
-        const int64_t l = c.extent[d];
+        if (d >= c.k) continue;
+        const int64_t l = c.ext[d];
         int64_t nb = 0;
         bool cyc = false;
 #pragma unroll
         for (int j = 0; j < TM_MAX_MRANK; ++j) {
-            if (j >= fr || c.proj_src[j] != d) continue;
-            if (c.proj_mode[j] != TM_BLOCK) cyc = cyc || c.fshape[j] > 1;
-            else nb += c.fshape[j] - 1;
+            if (j >= c.fr || c.psrc[j] != d) continue;
+            if (c.pmode[j] != TM_BLOCK) cyc = cyc || c.fsh[j] > 1;
+            else nb += c.fsh[j] - 1;
         }
         nb = cyc ? l - 1 : (nb < l - 1 ? nb : l - 1);
         double face = 1;
 #pragma unroll
         for (int e = 0; e < TM_MAX_LRANK; ++e)
-            if (e < k && e != d) face *= (double)c.extent[e];
+            if (e < c.k && e != d) face *= (double)c.ext[e];
         cells += 2.0 * halo[d] * (double)nb * face;
     }
     return cells;
 }
 
-// One thread per candidate; writes kFeat bf16 values (row of X), the descriptor
-// estimate (est[2i]; est[2i+1] = 0: no inter-node base) and, when feat_f32 is
-// given, the features in fp32.
+// log2 in fp32 for the features other than the estimate's (they are compared with
+// the fp64 reference at 1e-5 and stored in bf16)
+__device__ __forceinline__ float lg2f(float x) { return log2f(x); }
+
+// One thread per candidate; writes kFeat bf16 values (row of X, eight 16-byte
+// stores), the descriptor estimate (est[2i]; est[2i+1] = 0: no inter-node base)
+// and, when feat_f32 is given, the features in fp32.
 __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ cands, int64_t n,
                                                   const int32_t* __restrict__ halo, double* __restrict__ est,
                                                   uint16_t* __restrict__ X, float* __restrict__ feat_f32) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const DevCand& c = cands[i];
+    const FeatDesc c = load_feat_desc(cands + i);
     // every index into f and the small arrays below is static once the loops are
     // unrolled (bounded by the ABI's maxima, the candidate's counts as predicates), so
     // all of them live in registers
     float f[kFeat];
 #pragma unroll
     for (int t = 0; t < kFeat; ++t) f[t] = 0.f;
-    const int k = c.lrank, fr = c.frank, nops = c.nops;
+    const int k = c.k, fr = c.fr, nops = c.nops, nf = c.nf;
 #pragma unroll
     for (int d = 0; d < TM_MAX_LRANK; ++d) f[d] = d == k - 1 ? 1.f : 0.f;
     // blocks per launch dim: the product of the final extents it projects onto
@@ -395,73 +470,74 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
 #pragma unroll
     for (int j = 0; j < TM_MAX_MRANK; ++j) {
         if (j < fr) {
-            const int src = c.proj_src[j];
-            const double sh = (double)c.fshape[j];
+            const int src = c.psrc[j];
+            const double sh = (double)c.fsh[j];
 #pragma unroll
             for (int d = 0; d < TM_MAX_LRANK; ++d) blocks[d] *= src == d ? sh : 1.0;
         }
     }
-    // the factors of the first decompose
-    int tdec = -1;
-    for (int t = 0; t < nops; ++t)
-        if (c.op_kind[t] == TM_DECOMPOSE) {
-            tdec = t;
-            break;
-        }
-    const int nf = tdec >= 0 ? c.op_nf[tdec] : 0;
-    int32_t F[TM_MAX_LRANK];
+    int32_t hl[TM_MAX_LRANK];
 #pragma unroll
-    for (int m = 0; m < TM_MAX_LRANK; ++m) F[m] = m < nf ? c.op_f[tdec >= 0 ? tdec : 0][m] : 1;
+    for (int d = 0; d < TM_MAX_LRANK; ++d) hl[d] = d < k ? halo[d] : 0;
     double vol_f = 0;
 #pragma unroll
     for (int d = 0; d < TM_MAX_LRANK; ++d) {
         if (d < k) {
-            const double l = (double)c.extent[d];
-            f[4 + d] = lg2(l) / 10.f;
-            f[15 + d] = lg2(blocks[d]) / 9.f;
-            f[19 + d] = (lg2(l) - lg2(blocks[d])) / 10.f;
-            if (d < nf) vol_f += 2.0 * halo[d] * (F[d] - 1.0) / l;
-            f[54 + d] = halo[d] / 4.f;
+            const double l = (double)c.ext[d];
+            const float ll = lg2f((float)l), lb = lg2f((float)blocks[d]);
+            f[4 + d] = ll / 10.f;
+            f[15 + d] = lb / 9.f;
+            f[19 + d] = (ll - lb) / 10.f;
+            if (d < nf) vol_f += 2.0 * hl[d] * (c.F[d] - 1.0) / l;
+            f[54 + d] = hl[d] / 4.f;
         }
     }
-    f[8] = lg2((double)c.nodes) / 6.f;
-    f[9] = lg2((double)c.gpus) / 3.f;
-    f[10] = lg2((double)c.nodes * c.gpus) / 9.f;
+    f[8] = lg2f((float)c.nodes) / 6.f;
+    f[9] = lg2f((float)c.gpus) / 3.f;
+    f[10] = lg2f((float)c.nodes * (float)c.gpus) / 9.f;
 #pragma unroll
     for (int m = 0; m < TM_MAX_LRANK; ++m)
-        if (m < nf) f[11 + m] = lg2((double)F[m]) / 9.f;
-    f[24] = lg2(1.0 + vol_f) / 4.f;
+        if (m < nf) f[11 + m] = lg2f((float)c.F[m]) / 9.f;
+    f[24] = lg2f((float)(1.0 + vol_f)) / 4.f;
 #pragma unroll
     for (int t = 0; t < TM_MAX_OPS; ++t) {
         if (t < nops) {
-            const int kd = c.op_kind[t];
+            const int kd = c.kind[t];
 #pragma unroll
             for (int q = 0; q < 5; ++q) f[25 + q] += kd == q + 1 ? 0.25f : 0.f;
             if (t < 6) {
                 f[30 + t] = kd / 5.f;
-                if (t < 3) f[39 + t] = c.op_a[t] / 8.f;
-                f[42 + t] = kd == TM_DECOMPOSE ? 0.f : lg2(1.0 + (double)c.op_b[t]) / 9.f;
+                if (t < 3) f[39 + t] = c.opa[t] / 8.f;
+                f[42 + t] = kd == TM_DECOMPOSE ? 0.f : lg2f(1.f + (float)c.opb[t]) / 9.f;
             }
         }
     }
-    f[48] = (nops > 0 && c.op_kind[0] == TM_SWAP) ? 1.f : 0.f;
+    f[48] = (nops > 0 && c.kind[0] == TM_SWAP) ? 1.f : 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-        if (j < fr) f[49 + j] = c.proj_mode[j] ? 1.f : 0.f;
+        if (j < fr) f[49 + j] = c.pmode[j] ? 1.f : 0.f;
     f[53] = fr / 8.f;
     f[58] = c.gbits / 3.f;
     f[59] = 1.f;
     // the descriptor estimate of the ghost cells in the log space of the target (the
     // inter-node head has no base: feature kBaseFeat[1] stays 0)
-    const double e0 = descriptor_estimate(c, halo);
-    est[i * 2] = e0;
-    est[i * 2 + 1] = 0.0;
+    const double e0 = descriptor_estimate(c, hl);
+    *reinterpret_cast<double2*>(est + i * 2) = make_double2(e0, 0.0);
     f[kBaseFeat[0]] = lg2(1.0 + e0) / kBaseScale;
-    uint16_t* row = X + i * kFeat;
+    uint4* row = reinterpret_cast<uint4*>(X + i * kFeat);
 #pragma unroll
-    for (int t = 0; t < kFeat; ++t) {
-        row[t] = f2bf(f[t]);
-        if (feat_f32) feat_f32[i * kFeat + t] = f[t];
+    for (int t = 0; t < kFeat / 8; ++t) {
+        uint4 w;
+        w.x = (uint32_t)f2bf(f[8 * t]) | ((uint32_t)f2bf(f[8 * t + 1]) << 16);
+        w.y = (uint32_t)f2bf(f[8 * t + 2]) | ((uint32_t)f2bf(f[8 * t + 3]) << 16);
+        w.z = (uint32_t)f2bf(f[8 * t + 4]) | ((uint32_t)f2bf(f[8 * t + 5]) << 16);
+        w.w = (uint32_t)f2bf(f[8 * t + 6]) | ((uint32_t)f2bf(f[8 * t + 7]) << 16);
+        row[t] = w;
+    }
+    if (feat_f32) {
+        float4* fo = reinterpret_cast<float4*>(feat_f32 + i * kFeat);
+#pragma unroll
+        for (int t = 0; t < kFeat / 4; ++t) fo[t] = make_float4(f[4 * t], f[4 * t + 1], f[4 * t + 2], f[4 * t + 3]);
     }
 }
 
@@ -470,9 +546,12 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
 // A workgroup (4 waves) takes 64 rows.  Activations stay in LDS (bf16, padded row
 // stride); wave w computes output columns [64w, 64w + 64) of each hidden layer as
 // 4 x 4 MFMA tiles, reading weight fragments straight from the transposed bf16
-// weights Wt[n][k] (16 contiguous bytes per lane).  Epilogue: bias, ReLU, round to
-// bf16; optionally the activations are stored for the backward pass.  The head
-// (256 -> 2) is a pair of FP32 dot products per row.
+// weights Wt[n][k] (16 contiguous bytes per lane).  The tiles are computed
+// transposed (weights as the first operand), so a lane ends with four consecutive
+// columns of one row: the epilogue (bias, ReLU, round to bf16) writes them to LDS
+// as one 8-byte store; optionally the activations are stored for the backward pass.
+// The head (256 -> 2) is one more MFMA tile per wave against the two weight columns
+// staged in LDS (the other 14 columns zero): bf16 products summed in fp32.
 
 constexpr int kRowsFwd = 64;
 constexpr int kLdsStride = kWidth + 8;  // bf16 elements per LDS row (breaks bank aliasing)
@@ -487,7 +566,9 @@ __device__ __forceinline__ void layer_fwd(const uint16_t* __restrict__ in_lds, u
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
-#pragma unroll
+    // two k-steps in flight: at most 256 registers, so two workgroups (their LDS
+    // allows two) share a CU
+#pragma unroll 2
     for (int k0 = 0; k0 < KIN; k0 += 32) {
         u16x8 bf[4];
 #pragma unroll
@@ -499,21 +580,22 @@ __device__ __forceinline__ void layer_fwd(const uint16_t* __restrict__ in_lds, u
         for (int a = 0; a < 4; ++a) {
             const u16x8 af = *reinterpret_cast<const u16x8*>(in_lds + (a * 16 + r16) * kLdsStride + k0 + kq);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(af, bf[b], acc[a][b]);
+            for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(bf[b], af, acc[a][b]);
         }
     }
+    // acc[a][b][r]: row a*16 + r16, column wid*64 + b*16 + (lane>>4)*4 + r
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        const int col = wid * 64 + b * 16 + r16;
-        const float bb = bias[col];
+        const int col0 = wid * 64 + b * 16 + (lane >> 4) * 4;
+        const float b0 = bias[col0], b1 = bias[col0 + 1], b2 = bias[col0 + 2], b3 = bias[col0 + 3];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = a * 16 + (lane >> 4) * 4 + r;
-                const float v = fmaxf(acc[a][b][r] + bb, 0.f);
-                out_lds[row * kLdsStride + col] = f2bf(v);
-            }
+        for (int a = 0; a < 4; ++a) {
+            const int row = a * 16 + r16;
+            uint2 w;
+            w.x = (uint32_t)f2bf(fmaxf(acc[a][b][0] + b0, 0.f)) | ((uint32_t)f2bf(fmaxf(acc[a][b][1] + b1, 0.f)) << 16);
+            w.y = (uint32_t)f2bf(fmaxf(acc[a][b][2] + b2, 0.f)) | ((uint32_t)f2bf(fmaxf(acc[a][b][3] + b3, 0.f)) << 16);
+            *reinterpret_cast<uint2*>(out_lds + row * kLdsStride + col0) = w;
+        }
     }
 }
 
@@ -534,7 +616,11 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t* __restrict_
                                                      uint16_t* __restrict__ H3) {
     __shared__ __attribute__((aligned(16))) uint16_t sa[kRowsFwd * kLdsStride];
     __shared__ __attribute__((aligned(16))) uint16_t sb[kRowsFwd * kLdsStride];
+    __shared__ __attribute__((aligned(16))) uint16_t s_w4[kOut * kWidth];  // head weights, transposed
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (int i = tid; i < kOut * kWidth; i += 256) s_w4[(i % kOut) * kWidth + i / kOut] = W.w4[i];
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    const float hb = r16 < kOut ? W.b4[r16] : 0.f;
     for (int64_t row0 = (int64_t)blockIdx.x * kRowsFwd; row0 < n; row0 += (int64_t)gridDim.x * kRowsFwd) {
         __syncthreads();
         // X tile -> sa (64 x 64 bf16), zero rows past n
@@ -554,14 +640,24 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t* __restrict_
         layer_fwd<kWidth>(sa, sb, W.w3t, W.b3, lane, wid);
         __syncthreads();
         if (H3) store_act(sb, H3, row0, n, tid);
-        // head: thread t -> row t/4, output (t/2)%2, half (t%2) of the k range
+        // head: wave w takes rows 16w..16w+15; B columns 0, 1 are the two heads
         {
-            const int r = tid >> 2, h = (tid >> 1) & 1, half = tid & 1;
-            float s = 0.f;
-            for (int k = half * (kWidth / 2); k < (half + 1) * (kWidth / 2); ++k)
-                s += bf2f(sb[r * kLdsStride + k]) * bf2f(W.w4[k * kOut + h]);
-            s += __shfl_xor(s, 1, 64);
-            if (half == 0 && row0 + r < n) Y[(row0 + r) * kOut + h] = s + W.b4[h];
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int k0 = 0; k0 < kWidth; k0 += 32) {
+                const u16x8 af = *reinterpret_cast<const u16x8*>(sb + (wid * 16 + r16) * kLdsStride + k0 + kq);
+                const u16x8 wf = *reinterpret_cast<const u16x8*>(s_w4 + (r16 < kOut ? r16 : 0) * kWidth + k0 + kq);
+                acc = mfma16(af, r16 < kOut ? wf : zero, acc);
+            }
+            // acc[r]: row wid*16 + (lane>>4)*4 + r, output r16
+            if (r16 < kOut) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row0 + wid * 16 + (lane >> 4) * 4 + r;
+                    if (row < n) Y[row * kOut + r16] = acc[r] + hb;
+                }
+            }
         }
     }
 }
