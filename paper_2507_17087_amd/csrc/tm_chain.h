@@ -209,6 +209,17 @@ __device__ inline void owner_keys(const DevCand& c, const float* __restrict__ rt
     }
 }
 
+// owner_keys with the keys per thread chosen by the range's length: slots past the
+// range repeat its last index, so a range of at most nt (2 nt) coordinates takes one
+// (two) per thread.  The length is the same in every lane.
+__device__ inline void owner_keys_sized(const DevCand& c, const float* __restrict__ rt, int32_t* __restrict__ out,
+                                        int32_t vbase, int32_t v0, int32_t v1, int32_t keep, int tid, int nt) {
+    const int32_t len = v1 - v0;
+    if (len <= nt) owner_keys<1>(c, rt, out, vbase, v0, v1, keep, tid, nt);
+    else if (len <= 2 * nt) owner_keys<2>(c, rt, out, vbase, v0, v1, keep, tid, nt);
+    else owner_keys<4>(c, rt, out, vbase, v0, v1, keep, tid, nt);
+}
+
 // Contribution of coordinate x of launch dim d to the linear final index.
 __device__ inline int32_t coord_value(const DevCand& c, int d, int64_t x) {
     int32_t v = 0;

@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void k_build_tables(const DevHeader* __restric
         const int32_t keep = hdr->node_level ? ~((1 << sc.gbits) - 1) : -1;
         const int32_t v0 = split ? (int32_t)((int64_t)sc.vol * dlo / K) : 0;
         const int32_t v1 = split ? (int32_t)((int64_t)sc.vol * (dlo + 1) / K) : sc.vol;
-        owner_keys<4>(sc, s_rt, base, 0, v0, v1, keep, tid, blockDim.x);
+        owner_keys_sized(sc, s_rt, base, 0, v0, v1, keep, tid, blockDim.x);
         for (int d = dlo; d < dhi; ++d) {
             if (d > dlo) lds_sync(nw);  // the previous dim's staged table is no longer read
             const int64_t l = sc.extent[d];

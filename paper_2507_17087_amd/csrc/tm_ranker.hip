@@ -38,7 +38,9 @@ __device__ __forceinline__ float lg2(double x) { return (float)log2(x); }
 
 // Per-candidate chain statistics (the second stage of a ranked search):
 //   cross[0..8)   per final dim j: fraction of adjacent coordinate pairs (a, a+e_j)
-//                 whose owners sit on different nodes;
+//                 whose owners sit on different nodes (0 for a candidate whose
+//                 launch dims are each block-projected onto one final dim: its
+//                 estimate does not use them);
 //   cross[8..16)  the same for different processors;
 //   est[0..2)     block-model estimate of the ghost cells and of the inter-node
 //                 ones.  When every launch dim is projected (block) onto exactly one
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
             hj[j] = j < fr ? wave_uniform(halo[d]) : 0;
             lj[j] = j < fr ? wave_uniform64(sc.extent[d]) : 1;
         }
-        owner_keys<4>(sc, s_rt, key, 0, 0, vol, -1, tid, blockDim.x);
+        owner_keys_sized(sc, s_rt, key, 0, 0, vol, -1, tid, blockDim.x);
         // the block tables fit when the blocks are few and the extents below 2^31
         bool tab = simple && off <= tcap;
 #pragma unroll
@@ -197,9 +199,10 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
             }
         }
         lds_sync(nw);  // owner keys and block tables ready
-        // one pass over the final coordinates: per final dim j, the adjacent pairs
-        // (v, v + e_j) and how many of them change owner / node (crossing fractions);
-        // with simple projections also the block-model estimate: every v that starts
+        // one pass over the final coordinates: without simple projections, per final
+        // dim j, the adjacent pairs (v, v + e_j) and how many of them change owner /
+        // node (the crossing fractions, which only that estimate uses); with simple
+        // projections the block-model estimate: every v that starts
         // a non-empty block along j (a_j >= 1) is a cell boundary b, seen by the
         // min(h, b) + min(h, l - b) cells within the halo of it times the area of the
         // face (the product of the other dims' block widths), counted where the owners
@@ -211,7 +214,8 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
 #pragma unroll
         for (int j = 0; j < kMaxMrankCross; ++j) ch[j] = 0;
         double tot = 0, inter = 0;
-        for (int32_t v = tid; v < vol; v += blockDim.x) {
+        const bool need_cross = !simple;
+        for (int32_t v = tid; v < vol && (need_cross || tab); v += blockDim.x) {
             int32_t a[kMaxMrankCross];
             uint32_t rem = (uint32_t)v;
 #pragma unroll
@@ -220,12 +224,14 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
                 a[j] = j < fr ? (int32_t)(rem - __umul24(q, (uint32_t)fs[j])) : 0;
                 rem = q;
             }
-            const int32_t kv = key[v];
+            if (need_cross) {
+                const int32_t kv = key[v];
 #pragma unroll
-            for (int j = 0; j < kMaxMrankCross; ++j) {
-                if (j < nj && a[j] < fs[j] - 1) {
-                    const int32_t kn = key[v + fst[j]];
-                    ch[j] += ((kn != kv) << 16) | ((kn >> gb) != (kv >> gb));
+                for (int j = 0; j < kMaxMrankCross; ++j) {
+                    if (j < nj && a[j] < fs[j] - 1) {
+                        const int32_t kn = key[v + fst[j]];
+                        ch[j] += ((kn != kv) << 16) | ((kn >> gb) != (kv >> gb));
+                    }
                 }
             }
             if (tab) boundary_terms<true>(v, a, fr, fs, fst, toff, hj, lj, bft, aLt, key, gb, tot, inter);
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
         // the counts summed within each wave by shuffles, then over the waves
 #pragma unroll
         for (int j = 0; j < kMaxMrankCross; ++j) {
-            if (j < nj) {
+            if (j < nj && need_cross) {
 #pragma unroll
                 for (int o2 = 32; o2 > 0; o2 >>= 1) ch[j] += __shfl_xor(ch[j], o2, 64);
                 if (lane == 0) {
@@ -259,7 +265,7 @@ __global__ __launch_bounds__(256) void k_chain_stats(const DevCand* __restrict__
         if (tid < kMaxMrankCross) {
             const int j = tid;
             float fn = 0.f, fp = 0.f;
-            if (j < nj) {
+            if (j < nj && need_cross) {
                 // pairs (v, v + e_j): the coordinates with a_j < S_j - 1
                 const int32_t Sj = sc.fshape[j];
                 const int pairs = (Sj - 1) * (vol / Sj);
