@@ -110,9 +110,11 @@ hipError_t launch_select(const float* score, const int64_t* seg, int64_t nseg, i
 // Scores from the heads Y (nullable: the estimates alone) and the estimates est.
 hipError_t launch_combine(const float* Y, const double* est, int64_t n, const float* mu, const float* sigma,
                           float lambda, float* s, hipStream_t st);
+// The sub-batch of the selected candidates (sel[nsel], -1 skipped); sizes: scratch
+// of 2 * nsel int64 (their table words and counting items).
 hipError_t launch_gather(const DevCand* cands, const int64_t* sel, int64_t nsel, int k, int64_t cells_per_item,
                          DevCand* sub, int64_t* map, int64_t* seg_out, DevHeader* hdr, const DevHeader* proto,
-                         hipStream_t s);
+                         int64_t* sizes, hipStream_t s);
 hipError_t launch_map_best(const int64_t* sub_best, const int64_t* seg, const int64_t* map,
                            const tm_stencil_cost* sub_cost, int64_t nseg, const int64_t* orig_seg, int64_t* best,
                            tm_stencil_cost* best_cost, hipStream_t s);

@@ -549,9 +549,10 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
 
 // ------------------------------------------------------------------ fused forward
 //
-// A workgroup (4 waves) takes 64 rows.  Activations stay in LDS (bf16, padded row
-// stride); wave w computes output columns [64w, 64w + 64) of each hidden layer as
-// 4 x 4 MFMA tiles, reading weight fragments straight from the transposed bf16
+// A workgroup of the forward pass (4 waves) takes 64 rows.  Activations stay in LDS
+// (bf16, padded row stride); wave w computes output columns [64w, 64w + 64) of
+// each hidden layer as 4 x 4 MFMA tiles (128-row workgroups of 8 waves, two per
+// column block, measured 6 % slower), reading weight fragments straight from the transposed bf16
 // weights Wt[n][k] (16 contiguous bytes per lane).  The tiles are computed
 // transposed (weights as the first operand), so a lane ends with four consecutive
 // columns of one row: the epilogue (bias, ReLU, round to bf16) writes them to LDS
@@ -559,7 +560,9 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
 // The head (256 -> 2) is one more MFMA tile per wave against the two weight columns
 // staged in LDS (the other 14 columns zero): bf16 products summed in fp32.
 
-constexpr int kRowsFwd = 64;
+constexpr int kRowsFwd = 64;    // rows per workgroup of the backward-data kernel
+constexpr int kRowsMlp = 64;    // rows per workgroup of the forward pass
+constexpr int kMlpThreads = 256;
 constexpr int kLdsStride = kWidth + 8;  // bf16 elements per LDS row (breaks bank aliasing)
 
 template <int KIN>
@@ -607,8 +610,8 @@ __device__ __forceinline__ void layer_fwd(const uint16_t* __restrict__ in_lds, u
 
 __device__ __forceinline__ void store_act(const uint16_t* __restrict__ lds_act, uint16_t* __restrict__ g,
                                           int64_t row0, int64_t n, int tid) {
-    // 64 rows x 256 bf16: each thread moves 8 bf16 per step
-    for (int i = tid; i < kRowsFwd * (kWidth / 8); i += 256) {
+    // kRowsMlp rows x 256 bf16: each thread moves 8 bf16 per step
+    for (int i = tid; i < kRowsMlp * (kWidth / 8); i += kMlpThreads) {
         const int r = i / (kWidth / 8), c8 = (i % (kWidth / 8)) * 8;
         if (row0 + r < n)
             *reinterpret_cast<u16x8*>(g + (row0 + r) * kWidth + c8) =
@@ -616,34 +619,35 @@ __device__ __forceinline__ void store_act(const uint16_t* __restrict__ lds_act, 
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t* __restrict__ X, int64_t n,
-                                                     const RankerWeights W, float* __restrict__ Y,
-                                                     uint16_t* __restrict__ H1, uint16_t* __restrict__ H2,
-                                                     uint16_t* __restrict__ H3) {
-    __shared__ __attribute__((aligned(16))) uint16_t sa[kRowsFwd * kLdsStride];
-    __shared__ __attribute__((aligned(16))) uint16_t sb[kRowsFwd * kLdsStride];
+__global__ __launch_bounds__(kMlpThreads) void k_mlp_forward(const uint16_t* __restrict__ X, int64_t n,
+                                                             const RankerWeights W, float* __restrict__ Y,
+                                                             uint16_t* __restrict__ H1, uint16_t* __restrict__ H2,
+                                                             uint16_t* __restrict__ H3) {
+    __shared__ __attribute__((aligned(16))) uint16_t sa[kRowsMlp * kLdsStride];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[kRowsMlp * kLdsStride];
     __shared__ __attribute__((aligned(16))) uint16_t s_w4[kOut * kWidth];  // head weights, transposed
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    for (int i = tid; i < kOut * kWidth; i += 256) s_w4[(i % kOut) * kWidth + i / kOut] = W.w4[i];
+    const int cb = wid & 3, rb = (wid >> 2) * 64 * kLdsStride;  // column block; row half
+    for (int i = tid; i < kOut * kWidth; i += kMlpThreads) s_w4[(i % kOut) * kWidth + i / kOut] = W.w4[i];
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
     const float hb = r16 < kOut ? W.b4[r16] : 0.f;
-    for (int64_t row0 = (int64_t)blockIdx.x * kRowsFwd; row0 < n; row0 += (int64_t)gridDim.x * kRowsFwd) {
+    for (int64_t row0 = (int64_t)blockIdx.x * kRowsMlp; row0 < n; row0 += (int64_t)gridDim.x * kRowsMlp) {
         __syncthreads();
-        // X tile -> sa (64 x 64 bf16), zero rows past n
-        for (int i = tid; i < kRowsFwd * (kFeat / 8); i += 256) {
+        // X tile -> sa (kRowsMlp x 64 bf16), zero rows past n
+        for (int i = tid; i < kRowsMlp * (kFeat / 8); i += kMlpThreads) {
             const int r = i / (kFeat / 8), c8 = (i % (kFeat / 8)) * 8;
             u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
             if (row0 + r < n) v = *reinterpret_cast<const u16x8*>(X + (row0 + r) * kFeat + c8);
             *reinterpret_cast<u16x8*>(sa + r * kLdsStride + c8) = v;
         }
         __syncthreads();
-        layer_fwd<kFeat>(sa, sb, W.w1t, W.b1, lane, wid);
+        layer_fwd<kFeat>(sa + rb, sb + rb, W.w1t, W.b1, lane, cb);
         __syncthreads();
         if (H1) store_act(sb, H1, row0, n, tid);
-        layer_fwd<kWidth>(sb, sa, W.w2t, W.b2, lane, wid);
+        layer_fwd<kWidth>(sb + rb, sa + rb, W.w2t, W.b2, lane, cb);
         __syncthreads();
         if (H2) store_act(sa, H2, row0, n, tid);
-        layer_fwd<kWidth>(sa, sb, W.w3t, W.b3, lane, wid);
+        layer_fwd<kWidth>(sa + rb, sb + rb, W.w3t, W.b3, lane, cb);
         __syncthreads();
         if (H3) store_act(sb, H3, row0, n, tid);
         // head: wave w takes rows 16w..16w+15; B columns 0, 1 are the two heads
@@ -1057,9 +1061,11 @@ __global__ void k_combine(const float* __restrict__ Y, const double* __restrict_
 
 // ------------------------------------------------------------------ survivors
 
-// Builds the sub-batch of selected candidates on the device, in two launches.
-// k_gather (one workgroup) lays out their tables and work items by prefix sums over
-// the selection (wave scans, then the waves' totals), writes the sub-batch entry j of
+// Builds the sub-batch of selected candidates on the device, in three launches.
+// k_gather_sizes reads each selected candidate's table words and counting items;
+// k_gather (one workgroup, 16 consecutive entries per thread) lays out their tables
+// and work items by prefix sums over the selection (per-thread sums, wave scans,
+// then the waves' totals), writes the sub-batch entry j of
 // every selected candidate -- map[j] = its original index and the three fields that
 // change (arena_off, item_first, citems) -- the sub-batch segments and header;
 // k_gather_copy then copies the rest of the descriptors, word by word across the
@@ -1079,27 +1085,46 @@ __device__ __forceinline__ int64_t wave_incl_scan(int64_t v, int lane) {
     return v;
 }
 
-__global__ __launch_bounds__(1024) void k_gather(const DevCand* __restrict__ cands, const int64_t* __restrict__ sel,
-                                                 int64_t nsel, int k, int64_t cells_per_item,
-                                                 DevCand* __restrict__ sub, int64_t* __restrict__ map,
-                                                 int64_t* __restrict__ seg_out, DevHeader* __restrict__ hdr,
-                                                 const DevHeader* __restrict__ proto) {
+// Sizes of the selected candidates, one thread per entry: sizes[2s] = the table
+// words of candidate sel[s] (-1 when sel[s] < 0), sizes[2s+1] = its counting items.
+__global__ void k_gather_sizes(const DevCand* __restrict__ cands, const int64_t* __restrict__ sel, int64_t nsel,
+                               int64_t cells_per_item, int64_t* __restrict__ sizes) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= nsel) return;
+    const int64_t ci = sel[s];
+    int64_t w = -1, it = 0;
+    if (ci >= 0) {
+        const DevCand& c = cands[ci];
+        w = c.words;
+        it = count_items(c, cells_per_item);
+    }
+    sizes[2 * s] = w;
+    sizes[2 * s + 1] = it;
+}
+
+constexpr int kGatherPer = 16;  // consecutive entries per thread of k_gather
+
+__global__ __launch_bounds__(1024) void k_gather(const int64_t* __restrict__ sel, const int64_t* __restrict__ sizes,
+                                                 int64_t nsel, int k, DevCand* __restrict__ sub,
+                                                 int64_t* __restrict__ map, int64_t* __restrict__ seg_out,
+                                                 DevHeader* __restrict__ hdr, const DevHeader* __restrict__ proto) {
     __shared__ int64_t s_tot[16][3];  // per wave: words, items, present
     __shared__ int64_t carry[3];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
     if (tid < 3) carry[tid] = 0;
     __syncthreads();
-    for (int64_t base = 0; base < nsel; base += blockDim.x) {
-        const int64_t s = base + tid;
+    const int64_t span = (int64_t)blockDim.x * kGatherPer;
+    for (int64_t base = 0; base < nsel; base += span) {
+        // this thread's entries s0 .. s0 + kGatherPer - 1: their totals, then a
+        // block-wide scan of the totals, then the entries in order
+        const int64_t s0 = base + (int64_t)tid * kGatherPer;
         int64_t words = 0, items = 0, present = 0;
-        int64_t ci = -1;
-        if (s < nsel) {
-            ci = sel[s];
-            if (ci >= 0) {
-                const DevCand& c = cands[ci];
-                words = c.words;
-                items = count_items(c, cells_per_item);
-                present = 1;
+        for (int q = 0; q < kGatherPer && s0 + q < nsel; ++q) {
+            const int64_t w = sizes[2 * (s0 + q)];
+            if (w >= 0) {
+                words += w;
+                items += sizes[2 * (s0 + q) + 1];
+                ++present;
             }
         }
         const int64_t iw = wave_incl_scan(words, lane), ii = wave_incl_scan(items, lane),
@@ -1110,21 +1135,28 @@ __global__ __launch_bounds__(1024) void k_gather(const DevCand* __restrict__ can
             s_tot[wid][2] = ic;
         }
         __syncthreads();
-        int64_t pw = carry[0], pi = carry[1], pc = carry[2];
+        int64_t pw = carry[0] + iw - words, pi = carry[1] + ii - items, pc = carry[2] + ic - present;
         for (int w = 0; w < wid; ++w) {
             pw += s_tot[w][0];
             pi += s_tot[w][1];
             pc += s_tot[w][2];
         }
-        if (present) {
-            const int64_t j = pc + ic - 1;
-            map[j] = ci;
-            sub[j].arena_off = pw + iw - words;
-            sub[j].item_first = pi + ii - items;
-            sub[j].citems = (int32_t)items;
+        for (int q = 0; q < kGatherPer && s0 + q < nsel; ++q) {
+            const int64_t s = s0 + q;
+            // segment starts: first slot of each segment of k
+            if (s % k == 0) seg_out[s / k] = pc;
+            const int64_t w = sizes[2 * s];
+            if (w >= 0) {
+                const int64_t it = sizes[2 * s + 1];
+                map[pc] = sel[s];
+                sub[pc].arena_off = pw;
+                sub[pc].item_first = pi;
+                sub[pc].citems = (int32_t)it;
+                pw += w;
+                pi += it;
+                ++pc;
+            }
         }
-        // segment starts: first slot of each segment of k
-        if (s < nsel && (s % k) == 0) seg_out[s / k] = pc + ic - present;
         __syncthreads();  // every thread has read carry and s_tot
         if (tid < 3) {
             int64_t t = 0;
@@ -1226,9 +1258,9 @@ hipError_t launch_chain_stats(const DevCand* cands, const int64_t* idx, int64_t 
 hipError_t launch_mlp_forward(const uint16_t* X, int64_t n, const RankerWeights& W, float* Y, uint16_t* H1,
                               uint16_t* H2, uint16_t* H3, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    int64_t grid = (n + kRowsFwd - 1) / kRowsFwd;
+    int64_t grid = (n + kRowsMlp - 1) / kRowsMlp;
     if (grid > 8192) grid = 8192;
-    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)grid), dim3(256), 0, s, X, n, W, Y, H1, H2, H3);
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)grid), dim3(kMlpThreads), 0, s, X, n, W, Y, H1, H2, H3);
     return hipGetLastError();
 }
 
@@ -1298,9 +1330,11 @@ hipError_t launch_combine(const float* Y, const double* est, int64_t n, const fl
 
 hipError_t launch_gather(const DevCand* cands, const int64_t* sel, int64_t nsel, int k, int64_t cells_per_item,
                          DevCand* sub, int64_t* map, int64_t* seg_out, DevHeader* hdr, const DevHeader* proto,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_gather, dim3(1), dim3(1024), 0, s, cands, sel, nsel, k, cells_per_item, sub, map, seg_out,
-                       hdr, proto);
+                         int64_t* sizes, hipStream_t s) {
+    if (nsel > 0)
+        hipLaunchKernelGGL(k_gather_sizes, dim3((unsigned)((nsel + 255) / 256)), dim3(256), 0, s, cands, sel, nsel,
+                           cells_per_item, sizes);
+    hipLaunchKernelGGL(k_gather, dim3(1), dim3(1024), 0, s, sel, sizes, nsel, k, sub, map, seg_out, hdr, proto);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nsel <= 0) return e;
     const int64_t blocks = (nsel * kDescWords + 255) / 256;

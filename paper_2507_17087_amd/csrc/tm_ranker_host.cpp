@@ -490,10 +490,12 @@ int plan_ranked_search(tm_plan* p, tm_ranker* r, const int64_t* seg, int64_t nse
     } else if (e == hipSuccess) {
         e = launch_select(sb->score, sb->seg, nseg, 0, topk, margin, nullptr, sb->sel, s);
     }
-    // the survivors' exact costs
+    // the survivors' exact costs (their cost rows serve the gather as scratch first:
+    // 32 bytes per survivor, 16 used)
+    static_assert(sizeof(tm_stencil_cost) >= 2 * sizeof(int64_t), "gather scratch");
     if (e == hipSuccess)
         e = launch_gather(plan_cands(p), sb->sel, nsel, topk, plan_cells_per_item(p), sb->sub, sb->map, sb->sub_seg,
-                          sb->sub_hdr, plan_hdr(p), s);
+                          sb->sub_hdr, plan_hdr(p), reinterpret_cast<int64_t*>(sb->sub_out), s);
     if (e == hipSuccess) e = plan_eval_sub(p, sb, s);
     if (e == hipSuccess) e = launch_select_segments(sb->sub_out, sb->sub_seg, nseg, sb->sub_best, s, sb->map);
     if (e == hipSuccess)
