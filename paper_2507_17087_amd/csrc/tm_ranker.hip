@@ -1063,7 +1063,7 @@ __global__ void k_combine(const float* __restrict__ Y, const double* __restrict_
 
 // Builds the sub-batch of selected candidates on the device, in three launches.
 // k_gather_sizes reads each selected candidate's table words and counting items;
-// k_gather (one workgroup, 16 consecutive entries per thread) lays out their tables
+// k_gather (one workgroup, 4 consecutive entries per thread) lays out their tables
 // and work items by prefix sums over the selection (per-thread sums, wave scans,
 // then the waves' totals), writes the sub-batch entry j of
 // every selected candidate -- map[j] = its original index and the three fields that
@@ -1102,7 +1102,7 @@ __global__ void k_gather_sizes(const DevCand* __restrict__ cands, const int64_t*
     sizes[2 * s + 1] = it;
 }
 
-constexpr int kGatherPer = 16;  // consecutive entries per thread of k_gather
+constexpr int kGatherPer = 4;  // consecutive entries per thread of k_gather
 
 __global__ __launch_bounds__(1024) void k_gather(const int64_t* __restrict__ sel, const int64_t* __restrict__ sizes,
                                                  int64_t nsel, int k, DevCand* __restrict__ sub,
