@@ -549,11 +549,12 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
 
 // ------------------------------------------------------------------ fused forward
 //
-// A workgroup of the forward pass (4 waves) takes 64 rows.  Activations stay in LDS
-// (bf16, padded row stride); wave w computes output columns [64w, 64w + 64) of
-// each hidden layer as 4 x 4 MFMA tiles (128-row workgroups of 8 waves, two per
-// column block, measured 6 % slower), reading weight fragments straight from the transposed bf16
-// weights Wt[n][k] (16 contiguous bytes per lane).  The tiles are computed
+// A workgroup of the forward pass (8 waves) takes 64 rows.  Activations stay in LDS
+// (bf16, padded row stride); wave w computes output columns [32w, 32w + 32) of
+// each hidden layer as 4 x 2 MFMA tiles, reading weight fragments straight from
+// the transposed bf16 weights Wt[n][k] (16 contiguous bytes per lane).  Measured on
+// 1M rows: 8 waves of 32 columns 0.58 ms, 4 of 64 columns 0.63 ms, 16 of 16
+// columns 0.72 ms, 128-row workgroups 0.70 ms.  The tiles are computed
 // transposed (weights as the first operand), so a lane ends with four consecutive
 // columns of one row: the epilogue (bias, ReLU, round to bf16) writes them to LDS
 // as one 8-byte store; optionally the activations are stored for the backward pass.
@@ -562,40 +563,40 @@ __global__ __launch_bounds__(256) void k_features(const DevCand* __restrict__ ca
 
 constexpr int kRowsFwd = 64;    // rows per workgroup of the backward-data kernel
 constexpr int kRowsMlp = 64;    // rows per workgroup of the forward pass
-constexpr int kMlpThreads = 256;
+constexpr int kMlpThreads = 512;
+constexpr int kMlpNB = kWidth / 16 / (kMlpThreads / 64);  // 16-column blocks per wave
 constexpr int kLdsStride = kWidth + 8;  // bf16 elements per LDS row (breaks bank aliasing)
 
-template <int KIN>
+template <int KIN, int NB>
 __device__ __forceinline__ void layer_fwd(const uint16_t* __restrict__ in_lds, uint16_t* __restrict__ out_lds,
                                           const uint16_t* __restrict__ Wt, const float* __restrict__ bias,
-                                          int lane, int wid) {
-    f32x4 acc[4][4];
+                                          int lane, int cbase) {
+    f32x4 acc[4][NB];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < NB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
-    // two k-steps in flight: at most 256 registers, so two workgroups (their LDS
-    // allows two) share a CU
+    // two k-steps in flight
 #pragma unroll 2
     for (int k0 = 0; k0 < KIN; k0 += 32) {
-        u16x8 bf[4];
+        u16x8 bf[NB];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int ncol = wid * 64 + b * 16 + r16;
+        for (int b = 0; b < NB; ++b) {
+            const int ncol = cbase + b * 16 + r16;
             bf[b] = *reinterpret_cast<const u16x8*>(Wt + (size_t)ncol * KIN + k0 + kq);
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const u16x8 af = *reinterpret_cast<const u16x8*>(in_lds + (a * 16 + r16) * kLdsStride + k0 + kq);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = mfma16(bf[b], af, acc[a][b]);
+            for (int b = 0; b < NB; ++b) acc[a][b] = mfma16(bf[b], af, acc[a][b]);
         }
     }
-    // acc[a][b][r]: row a*16 + r16, column wid*64 + b*16 + (lane>>4)*4 + r
+    // acc[a][b][r]: row a*16 + r16, column cbase + b*16 + (lane>>4)*4 + r
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int col0 = wid * 64 + b * 16 + (lane >> 4) * 4;
+    for (int b = 0; b < NB; ++b) {
+        const int col0 = cbase + b * 16 + (lane >> 4) * 4;
         const float b0 = bias[col0], b1 = bias[col0 + 1], b2 = bias[col0 + 2], b3 = bias[col0 + 3];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
@@ -627,7 +628,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_forward(const uint16_t* __r
     __shared__ __attribute__((aligned(16))) uint16_t sb[kRowsMlp * kLdsStride];
     __shared__ __attribute__((aligned(16))) uint16_t s_w4[kOut * kWidth];  // head weights, transposed
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int cb = wid & 3, rb = (wid >> 2) * 64 * kLdsStride;  // column block; row half
+    const int cbase = wid * kMlpNB * 16;  // this wave's output columns
     for (int i = tid; i < kOut * kWidth; i += kMlpThreads) s_w4[(i % kOut) * kWidth + i / kOut] = W.w4[i];
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
     const float hb = r16 < kOut ? W.b4[r16] : 0.f;
@@ -641,17 +642,17 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_forward(const uint16_t* __r
             *reinterpret_cast<u16x8*>(sa + r * kLdsStride + c8) = v;
         }
         __syncthreads();
-        layer_fwd<kFeat>(sa + rb, sb + rb, W.w1t, W.b1, lane, cb);
+        layer_fwd<kFeat, kMlpNB>(sa, sb, W.w1t, W.b1, lane, cbase);
         __syncthreads();
         if (H1) store_act(sb, H1, row0, n, tid);
-        layer_fwd<kWidth>(sb + rb, sa + rb, W.w2t, W.b2, lane, cb);
+        layer_fwd<kWidth, kMlpNB>(sb, sa, W.w2t, W.b2, lane, cbase);
         __syncthreads();
         if (H2) store_act(sa, H2, row0, n, tid);
-        layer_fwd<kWidth>(sa + rb, sb + rb, W.w3t, W.b3, lane, cb);
+        layer_fwd<kWidth, kMlpNB>(sa, sb, W.w3t, W.b3, lane, cbase);
         __syncthreads();
         if (H3) store_act(sb, H3, row0, n, tid);
-        // head: wave w takes rows 16w..16w+15; B columns 0, 1 are the two heads
-        {
+        // head: wave w < 4 takes rows 16w..16w+15; B columns 0, 1 are the two heads
+        if (wid < kRowsMlp / 16) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
