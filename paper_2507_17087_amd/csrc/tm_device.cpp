@@ -327,7 +327,7 @@ static int eval_stencil(const tm_candidate* c, int64_t n, const tm_stencil* st, 
         hipError_t e = launch_build_tables(db.hdr, db.cands, n, db.arena, 1, s, d_out, db.counter);
         if (e == hipSuccess)
             e = launch_count(db.hdr, db.cands, db.arena, db.counter, d_out, grid, cp.cnt_words, s, fin, nullptr);
-        if (e == hipSuccess && !fin) e = launch_finalize_select(db.hdr, d_out, nullptr, s);
+        if (e == hipSuccess && !fin) e = launch_finalize_select(db.hdr, d_out, nullptr, n, s);
         if (e != hipSuccess) rc = set_error(TM_EDEVICE, "stencil launch: %s", hipGetErrorString(e));
     }
     free_batch(db, s);
@@ -614,7 +614,7 @@ static hipError_t plan_enqueue(tm_plan* p, int stage, tm_stencil_cost* out, int6
     }
     // stage 2 on its own repeats the selection (idempotent); the whole run needs it
     // only when the counting launch did not do it
-    if (stage == 2 || (stage < 0 && !fin)) e = launch_finalize_select(p->d_hdr, out, best, s);
+    if (stage == 2 || (stage < 0 && !fin)) e = launch_finalize_select(p->d_hdr, out, best, cp.hdr.n, s);
     return e;
 }
 
@@ -1103,7 +1103,7 @@ hipError_t plan_eval_sub(tm_plan* p, SearchBufs* sb, hipStream_t s) {
         e = launch_count(sb->sub_hdr, sb->sub, sb->sub_arena, sb->sub_counter, sb->sub_out, grid, cp.cnt_words, s,
                          nsel <= kFinInCount, nullptr);
     }
-    if (e == hipSuccess && nsel > kFinInCount) e = launch_finalize_select(sb->sub_hdr, sb->sub_out, nullptr, s);
+    if (e == hipSuccess && nsel > kFinInCount) e = launch_finalize_select(sb->sub_hdr, sb->sub_out, nullptr, nsel, s);
     return e;
 }
 

@@ -139,7 +139,10 @@ hipError_t launch_count(const DevHeader* hdr, const DevCand* cands, const int32_
 constexpr int64_t kFinInCount = 2048;
 hipError_t launch_class_tuples(const DevCand* cands, int64_t n, const int32_t* arena, unsigned long long* total,
                                hipStream_t s);
-hipError_t launch_finalize_select(const DevHeader* hdr, tm_stencil_cost* out, int64_t* best,
+// n_max: an upper bound on the header's candidate count; without best, batches above
+// kFinBytesGrid candidates take their bytes in a grid-wide launch.
+constexpr int64_t kFinBytesGrid = 65536;
+hipError_t launch_finalize_select(const DevHeader* hdr, tm_stencil_cost* out, int64_t* best, int64_t n_max,
                                   hipStream_t s);
 hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* seg, int64_t nseg,
                                   int64_t* best, hipStream_t s, const int64_t* key = nullptr);

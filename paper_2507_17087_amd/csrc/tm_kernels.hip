@@ -580,8 +580,27 @@ __global__ __launch_bounds__(1024) void k_finalize_select(const DevHeader* __res
     finalize_select_block(hdr, out, best, sb, si, sx);
 }
 
-hipError_t launch_finalize_select(const DevHeader* hdr, tm_stencil_cost* out, int64_t* best, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_select, dim3(1), dim3(1024), 0, s, hdr, out, best);
+// Bytes from cell counts only (no selection), grid-stride over the candidates.
+__global__ __launch_bounds__(256) void k_finalize_bytes(const DevHeader* __restrict__ hdr,
+                                                        tm_stencil_cost* __restrict__ out) {
+    const int64_t n = hdr->n, eb = hdr->elem_bytes;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t* o = reinterpret_cast<int64_t*>(&out[i]);
+        const int64_t gc = __hip_atomic_load(o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t ic = __hip_atomic_load(o + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        o[2] = gc * eb;
+        o[3] = ic * eb;
+    }
+}
+
+hipError_t launch_finalize_select(const DevHeader* hdr, tm_stencil_cost* out, int64_t* best, int64_t n_max,
+                                  hipStream_t s) {
+    if (!best && n_max > kFinBytesGrid) {
+        const int64_t g = std::min<int64_t>((n_max + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_finalize_bytes, dim3((unsigned)g), dim3(256), 0, s, hdr, out);
+    } else {
+        hipLaunchKernelGGL(k_finalize_select, dim3(1), dim3(1024), 0, s, hdr, out, best);
+    }
     return hipGetLastError();
 }
 

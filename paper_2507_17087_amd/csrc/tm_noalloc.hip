@@ -82,7 +82,7 @@ extern "C" int tm_eval_stencil_batch_noalloc(const tm_candidate* c, int64_t n, c
     if (e == hipSuccess)
         e = launch_count(hdr, cands, arena, counter, d_out, count_grid(cp.cnt_words, cp.items, 0), cp.cnt_words, s,
                          fin, nullptr);
-    if (e == hipSuccess && !fin) e = launch_finalize_select(hdr, d_out, nullptr, s);
+    if (e == hipSuccess && !fin) e = launch_finalize_select(hdr, d_out, nullptr, n, s);
     if (e != hipSuccess) return set_error(TM_EDEVICE, "stencil launch (no allocation): %s", hipGetErrorString(e));
     return TM_OK;
 }
