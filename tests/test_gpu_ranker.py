@@ -337,6 +337,34 @@ def test_topk_selection(tm, held_out, k):
     r.close()
 
 
+@pytest.mark.parametrize("k", [1, 100, 4096])
+def test_topk_selection_one_long_segment(tm, held_out, k):
+    """The selection over one segment of every held-out candidate (several hundred
+    thousand entries: many passes of the workgroup over its segment, long runs of
+    equal scores): the search returns the cheapest of the k smallest (score, index)
+    pairs, as known on the host."""
+    import torch
+    say(f"top-{k} selection over one long segment")
+    inst, cands, seg, plan, ce = held_out
+    r = tm.Ranker(seed=4)
+    r.set_params(torch.zeros(tm.tm_ranker_param_count(), dtype=torch.float32, device="cuda"))
+    mu0 = np.float32(r.scaling()[0])
+    feat = tm.tm_ranker_features(plan).cpu().numpy()
+    score = np.float32(32) * feat[:, 23].astype(np.float32) + mu0
+    one = np.array([0, len(cands)], np.int64)
+    b, c = tm.tm_search(plan, r, one, topk=k, lam=0.0)
+    out = torch.empty((len(cands), 4), dtype=torch.int64, device="cuda")
+    plan.run(out)
+    torch.cuda.synchronize()
+    allc, b, c = out.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy()
+    say(f"  {len(cands)} entries, {len(np.unique(score))} distinct scores")
+    sel = _k_smallest(score, 0, len(cands), k)
+    sub = allc[sel]
+    best = sel[np.lexsort((sel, sub[:, 3], sub[:, 2]))[0]]
+    assert b[0] == best and tuple(c[0]) == tuple(allc[best])
+    r.close()
+
+
 @pytest.mark.parametrize("pre,k", [(40, 5), (300, 17)])
 def test_two_stage_selection(tm, held_out, pre, k):
     """The two-stage search's selections, checked through its result: with an
