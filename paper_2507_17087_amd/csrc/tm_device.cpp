@@ -32,8 +32,8 @@ constexpr int64_t kMaxCellsPerItem = int64_t(1) << 26;
 // Map launches: one workgroup per block of map_rows_per_block(L) rows, up to this many
 // (more blocks are taken grid-stride).
 constexpr int64_t kMapMaxGrid = int64_t(1) << 20;
-static int map_grid(int64_t rows, int32_t L) {
-    const int64_t rpb = map_rows_per_block(L);
+static int map_grid(int64_t rows, int32_t L, int32_t lds_words) {
+    const int64_t rpb = map_rows_per_block(L, map_narrow(lds_words));
     return (int)std::max<int64_t>(1, std::min<int64_t>((rows + rpb - 1) / rpb, kMapMaxGrid));
 }
 
@@ -301,7 +301,7 @@ extern "C" int tm_proc_map(const tm_candidate* c, int32_t* d_map, int64_t len, v
     DeviceBatch db;
     rc = upload_batch(cp, db, s);
     if (rc == TM_OK) {
-        const int grid = map_grid(cp.cands[0].rows, cp.cands[0].L);
+        const int grid = map_grid(cp.cands[0].rows, cp.cands[0].L, cp.max_words);
         hipError_t e = launch_build_tables(db.hdr, db.cands, 1, db.arena, 0, s);
         if (e == hipSuccess) e = launch_map(db.cands, 1, db.arena, nullptr, 0, d_map, grid, cp.max_words, s);
         if (e != hipSuccess) rc = set_error(TM_EDEVICE, "map launch: %s", hipGetErrorString(e));
@@ -637,7 +637,7 @@ static int capture(tm_plan* p, int stage, tm_stencil_cost* out, int64_t* best, i
 // Map grid for a device-side index: the largest over the loaded candidates.
 static int plan_map_grid(const tm_plan* p) {
     int grid = 1;
-    for (auto& d : p->cp.cands) grid = std::max(grid, map_grid(d.rows, d.L));
+    for (auto& d : p->cp.cands) grid = std::max(grid, map_grid(d.rows, d.L, p->cp.max_words));
     return grid;
 }
 
@@ -793,7 +793,7 @@ extern "C" int tm_plan_materialize(tm_plan* p, const int64_t* d_index, int64_t h
     if (!d_index) {
         if (host_index < 0 || host_index >= cp.hdr.n) return set_error(TM_EINVAL, "index %lld", (long long)host_index);
         need = cp.cands[(size_t)host_index].npoints;
-        grid = map_grid(cp.cands[(size_t)host_index].rows, cp.cands[(size_t)host_index].L);
+        grid = map_grid(cp.cands[(size_t)host_index].rows, cp.cands[(size_t)host_index].L, cp.max_words);
     } else {
         grid = plan_map_grid(p);
     }

@@ -98,10 +98,15 @@ __host__ __device__ inline int64_t class_cap(const DevCand& c, int d, int h) {
     return r < l ? r : l;
 }
 
-// Map kernel: rows per workgroup block, about 4,096 points (16 KB) of int32 map.
+// Map kernel: when the staged tables are small (many workgroups fit a CU), one-wave
+// workgroups taking blocks of about 1,024 points (4 KB of int32 map); else four-wave
+// workgroups taking about 4,096 points (16 KB).
 constexpr int32_t kMapMaxRowsPerBlock = 64;
-__host__ __device__ inline int32_t map_rows_per_block(int32_t L) {
-    const int32_t r = (4096 + (L > 0 ? L : 1) - 1) / (L > 0 ? L : 1);
+constexpr int32_t kMapNarrowWords = 2048;
+__host__ __device__ inline bool map_narrow(int32_t lds_words) { return lds_words <= kMapNarrowWords; }
+__host__ __device__ inline int32_t map_rows_per_block(int32_t L, bool narrow) {
+    const int32_t pts = narrow ? 1024 : 4096;
+    const int32_t r = (pts + (L > 0 ? L : 1) - 1) / (L > 0 ? L : 1);
     return r < 1 ? 1 : (r > kMapMaxRowsPerBlock ? kMapMaxRowsPerBlock : r);
 }
 

@@ -664,20 +664,26 @@ hipError_t launch_select_segments(const tm_stencil_cost* costs, const int64_t* s
 // 6.80 TB/s, 16 KB 6.05, 4 KB 5.71, non-temporal stores 5.75 at 16 KB; a plain
 // device fill of the same bytes 6.58.
 
-__global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, int64_t n,
-                                             const int32_t* __restrict__ arena,
-                                             const int64_t* __restrict__ d_index, int64_t index,
-                                             int32_t* __restrict__ out) {
+template <int NT>
+__global__ __launch_bounds__(NT) void k_map(const DevCand* __restrict__ cands, int64_t n,
+                                            const int32_t* __restrict__ arena,
+                                            const int64_t* __restrict__ d_index, int64_t index,
+                                            int32_t* __restrict__ out) {
     extern __shared__ __attribute__((aligned(16))) int32_t lds[];  // 16-byte aligned: ds_read_b128 of staged tables
     // a short prologue (many small workgroups): the descriptor's fields are read in
     // place; the tables and the first block's row bases are ready behind one barrier
     __shared__ int32_t s_base[kMapMaxRowsPerBlock];
+    static_assert(NT >= kMapMaxRowsPerBlock, "a thread per row base");
     const int64_t ci = d_index ? uniform64(*d_index) : index;
     if (ci < 0 || ci >= n) return;  // no candidate selected (empty batch)
     const DevCand* __restrict__ c = &cands[ci];
     const int32_t words = uniform32(c->lds_words);
     const int32_t* G = arena + uniform64(c->arena_off);  // outer tables (and a last-dim table that did not fit)
-    stage_words(lds, G, (words + 3) & ~3);
+    {
+        const i32x4* s4 = reinterpret_cast<const i32x4*>(G);
+        i32x4* d4 = reinterpret_cast<i32x4*>(lds);
+        for (int32_t i = threadIdx.x; i < (words + 3) >> 2; i += NT) d4[i] = s4[i];
+    }
     const int K = uniform32(c->lrank);
     const int32_t L = uniform32(c->L);
     const int64_t rows = uniform64(c->rows);
@@ -692,7 +698,7 @@ __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, 
     }
     const int32_t* T = lds;
     const int tid = threadIdx.x;
-    const int32_t rpb = map_rows_per_block(L);
+    const int32_t rpb = map_rows_per_block(L, NT == 64);
     const bool vec = (L & 3) == 0 && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
     const int64_t stride = (int64_t)gridDim.x * rpb;
     for (int64_t r0 = (int64_t)blockIdx.x * rpb; r0 < rows; r0 += stride) {
@@ -712,7 +718,7 @@ __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, 
         if (vec) {
             const uint32_t pr = (uint32_t)L >> 2;  // 16-byte pieces per row
             const uint32_t np = (uint32_t)nr * pr;
-            for (uint32_t j = tid; j < np; j += 256) {
+            for (uint32_t j = tid; j < np; j += NT) {
                 const uint32_t rl = j / pr;
                 const int32_t x = (int32_t)(j - rl * pr) * 4;
                 const int32_t base = s_base[rl];
@@ -725,7 +731,7 @@ __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, 
             }
         } else {
             const uint32_t np = (uint32_t)nr * (uint32_t)L;
-            for (uint32_t j = tid; j < np; j += 256) {
+            for (uint32_t j = tid; j < np; j += NT) {
                 const uint32_t rl = j / (uint32_t)L;
                 const int32_t x = (int32_t)(j - rl * (uint32_t)L);
                 const int32_t key = T[s_base[rl] + (CL[x] & kValMask)];
@@ -738,8 +744,12 @@ __global__ __launch_bounds__(256) void k_map(const DevCand* __restrict__ cands, 
 
 hipError_t launch_map(const DevCand* cands, int64_t n, const int32_t* arena, const int64_t* d_index,
                       int64_t index, int32_t* out, int grid, int lds_words, hipStream_t s) {
-    hipLaunchKernelGGL(k_map, dim3(grid), dim3(256), (size_t)lds_words * 4, s, cands, n, arena, d_index, index,
-                       out);
+    if (map_narrow(lds_words))
+        hipLaunchKernelGGL(k_map<64>, dim3(grid), dim3(64), (size_t)lds_words * 4, s, cands, n, arena, d_index,
+                           index, out);
+    else
+        hipLaunchKernelGGL(k_map<256>, dim3(grid), dim3(256), (size_t)lds_words * 4, s, cands, n, arena, d_index,
+                           index, out);
     return hipGetLastError();
 }
 
