@@ -565,6 +565,7 @@ constexpr int kRowsFwd = 64;    // rows per workgroup of the backward-data kerne
 constexpr int kRowsMlp = 64;    // rows per workgroup of the forward pass
 constexpr int kMlpThreads = 512;
 constexpr int kMlpNB = kWidth / 16 / (kMlpThreads / 64);  // 16-column blocks per wave
+constexpr int kMlpInferCus = 256;  // persistent inference workgroups (one per CU)
 constexpr int kLdsStride = kWidth + 8;  // bf16 elements per LDS row (breaks bank aliasing)
 
 template <int KIN, int NB>
@@ -662,6 +663,103 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_forward(const uint16_t* __r
                 acc = mfma16(af, r16 < kOut ? wf : zero, acc);
             }
             // acc[r]: row wid*16 + (lane>>4)*4 + r, output r16
+            if (r16 < kOut) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row0 + wid * 16 + (lane >> 4) * 4 + r;
+                    if (row < n) Y[row * kOut + r16] = acc[r] + hb;
+                }
+            }
+        }
+    }
+}
+
+// Inference over many rows (no activations stored): a persistent workgroup per CU
+// keeps its waves' weight fragments in registers for every row tile it takes, so
+// the weights are read from L2 once per workgroup instead of once per tile.
+template <int KIN>
+__device__ __forceinline__ void load_wfrag(u16x8 (&wf)[KIN / 32][kMlpNB], const uint16_t* __restrict__ Wt, int lane,
+                                           int cbase) {
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll
+    for (int ks = 0; ks < KIN / 32; ++ks)
+#pragma unroll
+        for (int b = 0; b < kMlpNB; ++b)
+            wf[ks][b] = *reinterpret_cast<const u16x8*>(Wt + (size_t)(cbase + b * 16 + r16) * KIN + ks * 32 + kq);
+}
+
+template <int KIN>
+__device__ __forceinline__ void layer_reg(const uint16_t* __restrict__ in_lds, uint16_t* __restrict__ out_lds,
+                                          const u16x8 (&wf)[KIN / 32][kMlpNB], const float* __restrict__ bias,
+                                          int lane, int cbase) {
+    f32x4 acc[4][kMlpNB];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < kMlpNB; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll
+    for (int ks = 0; ks < KIN / 32; ++ks) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const u16x8 af = *reinterpret_cast<const u16x8*>(in_lds + (a * 16 + r16) * kLdsStride + ks * 32 + kq);
+#pragma unroll
+            for (int b = 0; b < kMlpNB; ++b) acc[a][b] = mfma16(wf[ks][b], af, acc[a][b]);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < kMlpNB; ++b) {
+        const int col0 = cbase + b * 16 + (lane >> 4) * 4;
+        const float b0 = bias[col0], b1 = bias[col0 + 1], b2 = bias[col0 + 2], b3 = bias[col0 + 3];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int row = a * 16 + r16;
+            uint2 w;
+            w.x = (uint32_t)f2bf(fmaxf(acc[a][b][0] + b0, 0.f)) | ((uint32_t)f2bf(fmaxf(acc[a][b][1] + b1, 0.f)) << 16);
+            w.y = (uint32_t)f2bf(fmaxf(acc[a][b][2] + b2, 0.f)) | ((uint32_t)f2bf(fmaxf(acc[a][b][3] + b3, 0.f)) << 16);
+            *reinterpret_cast<uint2*>(out_lds + row * kLdsStride + col0) = w;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kMlpThreads) void k_mlp_infer(const uint16_t* __restrict__ X, int64_t n,
+                                                           const RankerWeights W, float* __restrict__ Y) {
+    __shared__ __attribute__((aligned(16))) uint16_t sa[kRowsMlp * kLdsStride];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[kRowsMlp * kLdsStride];
+    __shared__ __attribute__((aligned(16))) uint16_t s_w4[kOut * kWidth];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int cbase = wid * kMlpNB * 16;
+    for (int i = tid; i < kOut * kWidth; i += kMlpThreads) s_w4[(i % kOut) * kWidth + i / kOut] = W.w4[i];
+    u16x8 w1[kFeat / 32][kMlpNB], w2[kWidth / 32][kMlpNB], w3[kWidth / 32][kMlpNB];
+    load_wfrag<kFeat>(w1, W.w1t, lane, cbase);
+    load_wfrag<kWidth>(w2, W.w2t, lane, cbase);
+    load_wfrag<kWidth>(w3, W.w3t, lane, cbase);
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    const float hb = r16 < kOut ? W.b4[r16] : 0.f;
+    for (int64_t row0 = (int64_t)blockIdx.x * kRowsMlp; row0 < n; row0 += (int64_t)gridDim.x * kRowsMlp) {
+        __syncthreads();
+        for (int i = tid; i < kRowsMlp * (kFeat / 8); i += kMlpThreads) {
+            const int r = i / (kFeat / 8), c8 = (i % (kFeat / 8)) * 8;
+            u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (row0 + r < n) v = *reinterpret_cast<const u16x8*>(X + (row0 + r) * kFeat + c8);
+            *reinterpret_cast<u16x8*>(sa + r * kLdsStride + c8) = v;
+        }
+        __syncthreads();
+        layer_reg<kFeat>(sa, sb, w1, W.b1, lane, cbase);
+        __syncthreads();
+        layer_reg<kWidth>(sb, sa, w2, W.b2, lane, cbase);
+        __syncthreads();
+        layer_reg<kWidth>(sa, sb, w3, W.b3, lane, cbase);
+        __syncthreads();
+        if (wid < kRowsMlp / 16) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int k0 = 0; k0 < kWidth; k0 += 32) {
+                const u16x8 af = *reinterpret_cast<const u16x8*>(sb + (wid * 16 + r16) * kLdsStride + k0 + kq);
+                const u16x8 wf = *reinterpret_cast<const u16x8*>(s_w4 + (r16 < kOut ? r16 : 0) * kWidth + k0 + kq);
+                acc = mfma16(af, r16 < kOut ? wf : zero, acc);
+            }
             if (r16 < kOut) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -1260,6 +1358,11 @@ hipError_t launch_mlp_forward(const uint16_t* X, int64_t n, const RankerWeights&
                               uint16_t* H2, uint16_t* H3, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     int64_t grid = (n + kRowsMlp - 1) / kRowsMlp;
+    if (!H1 && !H2 && !H3 && grid > 4 * kMlpInferCus) {
+        // inference over many rows: persistent workgroups, weights in registers
+        hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)kMlpInferCus), dim3(kMlpThreads), 0, s, X, n, W, Y);
+        return hipGetLastError();
+    }
     if (grid > 8192) grid = 8192;
     hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)grid), dim3(kMlpThreads), 0, s, X, n, W, Y, H1, H2, H3);
     return hipGetLastError();
