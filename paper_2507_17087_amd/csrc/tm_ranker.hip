@@ -1,7 +1,8 @@
-// tm_ranker.hip -- learned ranker kernels (gfx950): candidate features, a 3-layer
-// BF16 MLP (MFMA v_mfma_f32_16x16x32_bf16, FP32 accumulation) forward / backward,
-// Adam, per-segment top-k, and the on-device gather of the survivors for exact
-// re-evaluation.
+// tm_ranker.hip -- learned ranker kernels (gfx950): descriptor features, a 3-layer
+// BF16 MLP (MFMA v_mfma_f32_16x16x32_bf16, FP32 accumulation) inference / forward /
+// backward, Adam, the chain statistics and block-model estimates of a ranked
+// search's second stage, per-segment k-smallest selection, and the on-device gather
+// of the survivors for exact re-evaluation.
 //
 // MFMA fragment layout used throughout (16x16x32, one wave): lane l holds row
 // (l % 16) of A and column (l % 16) of B, eight consecutive k values starting at
