@@ -737,21 +737,27 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_infer(const uint16_t* __res
     load_wfrag<kWidth>(w3, W.w3t, lane, cbase);
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
     const float hb = r16 < kOut ? W.b4[r16] : 0.f;
-    for (int64_t row0 = (int64_t)blockIdx.x * kRowsMlp; row0 < n; row0 += (int64_t)gridDim.x * kRowsMlp) {
-        __syncthreads();
-        for (int i = tid; i < kRowsMlp * (kFeat / 8); i += kMlpThreads) {
-            const int r = i / (kFeat / 8), c8 = (i % (kFeat / 8)) * 8;
-            u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (row0 + r < n) v = *reinterpret_cast<const u16x8*>(X + (row0 + r) * kFeat + c8);
-            *reinterpret_cast<u16x8*>(sa + r * kLdsStride + c8) = v;
-        }
-        __syncthreads();
+    // one 16-byte piece of a 64 x 64 feature tile per thread; the next tile's piece is
+    // loaded while the current tile runs through the layers
+    static_assert(kRowsMlp * (kFeat / 8) == kMlpThreads, "one feature piece per thread");
+    const int xr = tid / (kFeat / 8), xc = (tid % (kFeat / 8)) * 8;
+    const int64_t step = (int64_t)gridDim.x * kRowsMlp;
+    auto x_piece = [&](int64_t r0) {
+        u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (r0 + xr < n) v = *reinterpret_cast<const u16x8*>(X + (r0 + xr) * kFeat + xc);
+        return v;
+    };
+    *reinterpret_cast<u16x8*>(sa + xr * kLdsStride + xc) = x_piece((int64_t)blockIdx.x * kRowsMlp);
+    for (int64_t row0 = (int64_t)blockIdx.x * kRowsMlp; row0 < n; row0 += step) {
+        __syncthreads();  // this tile's features in sa; the previous head is done with sb
+        const u16x8 xn = x_piece(row0 + step);
         layer_reg<kFeat>(sa, sb, w1, W.b1, lane, cbase);
         __syncthreads();
         layer_reg<kWidth>(sb, sa, w2, W.b2, lane, cbase);
         __syncthreads();
         layer_reg<kWidth>(sa, sb, w3, W.b3, lane, cbase);
-        __syncthreads();
+        __syncthreads();  // sa is free: the next tile's features go in
+        *reinterpret_cast<u16x8*>(sa + xr * kLdsStride + xc) = xn;
         if (wid < kRowsMlp / 16) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
